@@ -1,0 +1,241 @@
+"""CPU FP64 oracle of the M2NuFFT estimator (arXiv 2407.01943).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The GPU library never imports this
+package and shares no code with it.
+
+The arithmetic lives in ``m2n_oracle.c`` (plain C, FP64, OpenMP), built into
+``liboracle.so`` by ``oracle/build.py``; this module marshals numpy arrays and
+adds the two one-line steps that are clearer in numpy:
+
+* ``psd``: P(A_i) = sum_k d_k |J_k(A_i)|^2 with d_k = 1/K (Sec. 3.2, the
+  estimator of the integrated spectrum; Table 3 step 5);
+* ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order.
+
+Parity pins: tests/test_oracle_pins.py.  Readings where the paper is silent
+(sign of a taper, the suboptimality estimate) are stated at each function.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, ERR_ARG, ERR_T_ORDER, ERR_NOT_PD, ERR_NO_CONVERGE = 0, -1, -2, -3, -4
+
+_d = ctypes.POINTER(ctypes.c_double)
+_l = ctypes.POINTER(ctypes.c_long)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.or_validate.restype = ctypes.c_int
+        L.or_validate.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.or_sinpi.restype = ctypes.c_double
+        L.or_sinpi.argtypes = [ctypes.c_double]
+        L.or_gpss_matrix.restype = None
+        L.or_gpss_matrix.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d]
+        L.or_band_matrix.restype = None
+        L.or_band_matrix.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, _d, _d]
+        L.or_apply_sinc.restype = None
+        L.or_apply_sinc.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_long, _d]
+        L.or_cholesky.restype = ctypes.c_long
+        L.or_cholesky.argtypes = [_d, ctypes.c_long]
+        L.or_reduce.restype = None
+        L.or_reduce.argtypes = [_d, _d, ctypes.c_long, _d]
+        L.or_jacobi.restype = ctypes.c_int
+        L.or_jacobi.argtypes = [_d, ctypes.c_long, _d, _d, ctypes.c_int]
+        L.or_lanczos.restype = ctypes.c_int
+        L.or_lanczos.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, _d, _d,
+                                 ctypes.c_uint64]
+        L.or_gpss_tapers.restype = ctypes.c_long
+        L.or_gpss_tapers.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, _d, _d]
+        L.or_nudft.restype = None
+        L.or_nudft.argtypes = [_d, _d, _d, ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double, _l, ctypes.c_long, _d, _d]
+        L.or_ehat_direct.restype = None
+        L.or_ehat_direct.argtypes = [_d, _d, _d, ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _l,
+                                     ctypes.c_long, _d, _d]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_d)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def validate(t, fmax, fw, K):
+    t = _f64(t)
+    return lib().or_validate(_p(t), t.shape[0], fmax, fw, K)
+
+
+def sinpi(u: float) -> float:
+    """sin(pi u) with exact zeros at integers (argument reduction by 2)."""
+    return lib().or_sinpi(float(u))
+
+
+def gpss_matrix(t, f):
+    """R_{nm} = sin(2 pi f (t_n - t_m)) / (pi (t_n - t_m)); diagonal 2 f.
+
+    With f = f_max this is R(B) (Sec. 2.1); with f = f_w it is R(A0) for a
+    band centred at 0 (Sec. 3.2).
+    """
+    t = _f64(t)
+    N = t.shape[0]
+    R = np.empty((N, N))
+    lib().or_gpss_matrix(_p(t), N, float(f), _p(R))
+    return R
+
+
+def band_matrix(t, fc, fw):
+    """Complex R(A) of the band |f - fc| <= fw (Sec. 2.3)."""
+    t = _f64(t)
+    N = t.shape[0]
+    re, im = np.empty((N, N)), np.empty((N, N))
+    lib().or_band_matrix(_p(t), N, float(fc), float(fw), _p(re), _p(im))
+    return re + 1j * im
+
+
+def apply_sinc(t, f, V):
+    """R(f) @ V without storing R(f) (V is N x nv)."""
+    t = _f64(t)
+    V = _f64(V)
+    squeeze = V.ndim == 1
+    if squeeze:
+        V = V[:, None].copy()
+    Y = np.empty_like(V)
+    lib().or_apply_sinc(_p(t), t.shape[0], float(f), _p(V), V.shape[1], _p(Y))
+    return Y[:, 0] if squeeze else Y
+
+
+def cholesky(A):
+    A = _f64(A).copy()
+    st = lib().or_cholesky(_p(A), A.shape[0])
+    if st < 0:
+        raise OracleError(ERR_NOT_PD, f"cholesky (pivot {-st - 1})")
+    return A
+
+
+def reduce(L, RA):
+    L, RA = _f64(L), _f64(RA)
+    C = np.empty_like(RA)
+    lib().or_reduce(_p(L), _p(RA), L.shape[0], _p(C))
+    return C
+
+
+def jacobi_eigh(A, max_sweeps=100):
+    """Eigen-decomposition by cyclic Jacobi; eigenvalues descending."""
+    A = _f64(A).copy()
+    N = A.shape[0]
+    ev, V = np.empty(N), np.empty((N, N))
+    st = lib().or_jacobi(_p(A), N, _p(ev), _p(V), max_sweeps)
+    if st < 0:
+        raise OracleError(st, "jacobi")
+    return ev, V
+
+
+def gpss_tapers(t, fmax, fw, K, method="auto"):
+    """The K largest solutions of R(A0) w = lambda R(B) w (Sec. 3.2), with
+    w_k^T R(B) w_k = 2 f_w (Sec. 2.2) and the sign reading of fix_sign.
+
+    method: "jacobi" (dense reduction + cyclic Jacobi), "lanczos", or "auto"
+    (Jacobi up to N = 600).  Returns (w [K, N], lam [K]).
+    """
+    t = _f64(t)
+    N = t.shape[0]
+    m = {"jacobi": 0, "lanczos": 1}.get(method, 0 if N <= 600 else 1)
+    w, lam = np.empty((K, N)), np.empty(K)
+    st = lib().or_gpss_tapers(_p(t), N, float(fmax), float(fw), int(K), m, _p(w), _p(lam))
+    if st < 0:
+        raise OracleError(st, "gpss_tapers")
+    return w, lam
+
+
+def nudft(t, x, w, f_lo, df, I=None, bands=None):
+    """J_k(i) = sum_n w_k(t_n) x_n exp(-j 2 pi (f_lo + i df) t_n) by direct
+    summation (Sec. 3.2 eigencoefficients; Table 3 step 4).  Real tapers, so
+    w^* = w.  Returns complex [K, len(bands)]."""
+    t, x, w = _f64(t), _f64(x), _f64(np.atleast_2d(w))
+    K, N = w.shape
+    if bands is None:
+        bands = np.arange(I, dtype=np.int64)
+    bands = np.ascontiguousarray(bands, dtype=np.int64)
+    nb = bands.shape[0]
+    re, im = np.empty((K, nb)), np.empty((K, nb))
+    lib().or_nudft(_p(t), _p(x), _p(w), N, K, float(f_lo), float(df),
+                   bands.ctypes.data_as(_l), nb, _p(re), _p(im))
+    return re + 1j * im
+
+
+def psd(J, weights=None):
+    """P(A_i) = sum_k d_k |J_k(A_i)|^2, d_k = 1/K unless given (Sec. 3.2)."""
+    K = J.shape[0]
+    d = np.full(K, 1.0 / K) if weights is None else np.asarray(weights, dtype=np.float64)
+    return (d[:, None] * np.abs(J) ** 2).sum(axis=0)
+
+
+def ehat(t, w, lam, fmax, fw, f_lo, df, I=None, bands=None):
+    """Suboptimality estimate (Appendix B with Sec. 3.5):
+    D_k(i) = (E_i w_k)^* R(B) (E_i w_k), lambda_hat = 2 f_w lambda_k / D_k(i),
+    Ehat_i = (1/K) sum_k |lambda_k - lambda_hat_k(i)|.
+    Returns (E [nb], D [K, nb])."""
+    t, w, lam = _f64(t), _f64(np.atleast_2d(w)), _f64(lam)
+    K, N = w.shape
+    if bands is None:
+        bands = np.arange(I, dtype=np.int64)
+    bands = np.ascontiguousarray(bands, dtype=np.int64)
+    nb = bands.shape[0]
+    D, E = np.empty((K, nb)), np.empty(nb)
+    lib().or_ehat_direct(_p(t), _p(w), _p(lam), N, K, float(fmax), float(fw),
+                         float(f_lo), float(df), bands.ctypes.data_as(_l), nb,
+                         _p(D), _p(E))
+    return E, D
+
+
+def lanczos(t, fw, K, L=None, cdiag=1.0, mmax=400, tol=1e-14, seed=0x5EED):
+    """Top-K eigenpairs of L^{-1} R(A0) L^{-T} (L None: R(B) = cdiag I)."""
+    t = _f64(t)
+    N = t.shape[0]
+    ev, y = np.empty(K), np.empty((N, K))
+    Lp = _p(_f64(L)) if L is not None else ctypes.cast(None, _d)
+    st = lib().or_lanczos(_p(t), N, float(fw), Lp, float(cdiag), K, int(mmax),
+                          float(tol), _p(ev), _p(y), seed)
+    if st < 0:
+        raise OracleError(st, "lanczos")
+    return ev, y
+
+
+def m2nufft(t, x, fmax, fw, K, f_lo, df, I, bands=None, method="auto",
+            with_ehat=True):
+    """Table 3 with one sub-band and the GEP branch at f_c0 = 0:
+    step 3 tapers, step 4 eigencoefficients, step 5 average; plus Ehat."""
+    w, lam = gpss_tapers(t, fmax, fw, K, method=method)
+    J = nudft(t, x, w, f_lo, df, I=I, bands=bands)
+    P = psd(J)
+    out = {"w": w, "lam": lam, "J": J, "P": P}
+    if with_ehat:
+        out["E"], out["D"] = ehat(t, w, lam, fmax, fw, f_lo, df, I=I, bands=bands)
+    return out

@@ -1,0 +1,337 @@
+"""Pins of the CPU FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own code: each one compares it with a
+closed form, a library routine on a special case, an exact rational
+computation, a brute force, or an invariant the paper states.  A plausible
+slip in the oracle (dropped term, wrong sign or index, transposed operand,
+wrong normalisation) fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.signal.windows as sw
+
+import workloads as W
+
+
+# --------------------------------------------------------------------------
+# sin(pi u) reduction and the GPSS matrices (Sec. 2.1 R(B), Sec. 2.3 R(A))
+# --------------------------------------------------------------------------
+
+def test_sinpi_exact_zero_at_integers_and_matches_mpmath(orc):
+    import mpmath
+    mpmath.mp.dps = 40
+    for u in [0.0, 1.0, -1.0, 2.0, 7.0, -12345.0, 2.0 ** 40]:
+        assert orc.sinpi(u) == 0.0
+    rng = np.random.default_rng(0)
+    for u in np.concatenate([rng.uniform(-50, 50, 200), [0.5, -0.5, 1.5, 1e-9, 3.25]]):
+        ref = float(mpmath.sin(mpmath.pi * mpmath.mpf(float(u))))
+        assert abs(orc.sinpi(u) - ref) <= 4e-16 * max(abs(ref), 1e-300) + 1e-300
+
+
+def test_gpss_matrix_entries_against_mpmath(orc):
+    import mpmath
+    mpmath.mp.dps = 40
+    s = W.scheme_jitter()
+    R = orc.gpss_matrix(s.t, 0.5)
+    assert np.array_equal(R, R.T)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        n, m = rng.integers(0, s.N, 2)
+        tau = mpmath.mpf(float(s.t[n])) - mpmath.mpf(float(s.t[m]))
+        tau = mpmath.mpf(float(tau))          # the difference is rounded once, as in FP64
+        ref = 1.0 if n == m else float(mpmath.sin(2 * mpmath.pi * 0.5 * tau) / (mpmath.pi * tau))
+        assert abs(R[n, m] - ref) <= 1e-15
+    np.testing.assert_array_equal(np.diag(R), 1.0)
+
+
+def test_lattice_signal_band_matrix_is_identity(orc):
+    # Appendix B: integer lattice, f_s = 1, f_max = 1/2  =>  R(B) = I exactly
+    s = W.small_gapped()
+    R = orc.gpss_matrix(s.t, 0.5)
+    assert np.array_equal(R, np.eye(s.N))
+    # also for a lattice of spacing 2 with f_max = 1/2 (2 f_max beta = 2)
+    R2 = orc.gpss_matrix(2.0 * s.t, 0.5)
+    assert np.array_equal(R2, np.eye(s.N))
+
+
+def test_band_matrix_shift_identity(orc):
+    # Sec. 3.5: R(A0) = E_i^* R(A_i) E_i with E_i = diag(exp(j 2 pi df_i t_n))
+    s = W.scheme_arithmetic()
+    fw, fci = 0.05, 0.137
+    RA0 = orc.band_matrix(s.t, 0.0, fw)
+    RAi = orc.band_matrix(s.t, fci, fw)
+    E = np.diag(np.exp(2j * np.pi * fci * s.t))
+    np.testing.assert_allclose(E.conj().T @ RAi @ E, RA0, atol=1e-14)
+    np.testing.assert_allclose(RA0.imag, 0.0, atol=0)
+    np.testing.assert_allclose(RA0.real, orc.gpss_matrix(s.t, fw), atol=0)
+
+
+def test_apply_sinc_matches_dense(orc):
+    s = W.small_gapped()
+    V = np.random.default_rng(2).standard_normal((s.N, 3))
+    Y = orc.apply_sinc(s.t, s.fw, V)          # integer t: lag-table path
+    np.testing.assert_allclose(Y, orc.gpss_matrix(s.t, s.fw) @ V, rtol=0, atol=1e-13)
+    j = W.scheme_jitter()
+    V = np.random.default_rng(3).standard_normal((j.N, 2))
+    np.testing.assert_allclose(orc.apply_sinc(j.t, 0.3, V),
+                               orc.gpss_matrix(j.t, 0.3) @ V, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# linear algebra against LAPACK (numpy) on the same matrices
+# --------------------------------------------------------------------------
+
+def test_cholesky_and_reduce_against_lapack(orc):
+    s = W.scheme_jitter()
+    RB = orc.gpss_matrix(s.t, 0.5)
+    L = orc.cholesky(RB)
+    np.testing.assert_allclose(L, np.linalg.cholesky(RB), atol=1e-13)
+    RA = orc.gpss_matrix(s.t, 0.05)
+    C = orc.reduce(L, RA)
+    np.testing.assert_allclose(L @ C @ L.T, RA, atol=1e-13)
+    Li = np.linalg.inv(np.linalg.cholesky(RB))
+    np.testing.assert_allclose(C, Li @ RA @ Li.T, atol=1e-12)
+
+
+def test_cholesky_reports_non_pd(orc):
+    # duplicated sampling time: R(B) is singular
+    t = np.array([0.0, 1.0, 1.0, 2.0])
+    with pytest.raises(orc.OracleError):
+        orc.cholesky(orc.gpss_matrix(t, 0.5))
+    assert orc.validate(t, 0.5, 0.1, 2) == orc.ERR_T_ORDER
+
+
+def test_jacobi_against_lapack(orc):
+    s = W.scheme_missing()
+    C = orc.gpss_matrix(s.t, 0.05)
+    ev, V = orc.jacobi_eigh(C)
+    ref = np.linalg.eigvalsh(C)[::-1]
+    np.testing.assert_allclose(ev, ref, atol=1e-14)
+    np.testing.assert_allclose(V @ np.diag(ev) @ V.T, C, atol=1e-13)
+    np.testing.assert_allclose(V.T @ V, np.eye(s.N), atol=1e-13)
+
+
+def test_lanczos_matches_jacobi(orc):
+    s = W.gapped_scaled(512, 5, 1024, seed=21)
+    w_j, lam_j = orc.gpss_tapers(s.t, 0.5, s.fw, 5, method="jacobi")
+    w_l, lam_l = orc.gpss_tapers(s.t, 0.5, s.fw, 5, method="lanczos")
+    np.testing.assert_allclose(lam_l, lam_j, atol=1e-13)
+    np.testing.assert_allclose(w_l, w_j, atol=1e-9)
+    # general (dense, non-diagonal R(B)) Lanczos path too
+    # (f_w chosen so the top eigenvalues are separated by >= 5e-4: a taper is
+    # only determined to ~eps/gap)
+    j = W.scheme_jitter(n=200)
+    w_j, lam_j = orc.gpss_tapers(j.t, 0.5, 0.0125, 4, method="jacobi")
+    w_l, lam_l = orc.gpss_tapers(j.t, 0.5, 0.0125, 4, method="lanczos")
+    np.testing.assert_allclose(lam_l, lam_j, atol=1e-13)
+    np.testing.assert_allclose(w_l, w_j, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# P1: closed forms at N = 1 and N = 2
+# --------------------------------------------------------------------------
+
+def test_tapers_closed_form_n1(orc):
+    fmax, fw, x = 0.5, 0.125, 1.7
+    w, lam = orc.gpss_tapers(np.array([3.25]), fmax, fw, 1)
+    assert abs(lam[0] - fw / fmax) < 1e-16
+    assert abs(w[0, 0] - math.sqrt(fw / fmax)) < 1e-16
+    J = orc.nudft(np.array([3.25]), np.array([x]), w, -0.5, 1 / 8, I=8)
+    np.testing.assert_allclose(orc.psd(J), (fw / fmax) * x * x, rtol=1e-15)
+
+
+def test_tapers_closed_form_n2(orc):
+    t = np.array([0.0, 0.7])
+    fmax, fw = 0.5, 0.2
+    sB = math.sin(2 * math.pi * fmax * 0.7) / (math.pi * 0.7)
+    sA = math.sin(2 * math.pi * fw * 0.7) / (math.pi * 0.7)
+    lp, lm = (2 * fw + sA) / (2 * fmax + sB), (2 * fw - sA) / (2 * fmax - sB)
+    w, lam = orc.gpss_tapers(t, fmax, fw, 2)
+    order = [0, 1] if lp >= lm else [1, 0]
+    pairs = [(lp, math.sqrt(fw / (2 * fmax + sB)) * np.array([1.0, 1.0])),
+             (lm, math.sqrt(fw / (2 * fmax - sB)) * np.array([1.0, -1.0]))]
+    for k, idx in enumerate(order):
+        assert abs(lam[k] - pairs[idx][0]) < 1e-15
+        np.testing.assert_allclose(w[k], pairs[idx][1], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# P2: GPSS on a gap-free unit grid with f_max = 1/2 are the DPSS
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,NW,K", [(64, 2.5, 4), (128, 3.0, 5)])
+def test_gpss_reduce_to_dpss(orc, N, NW, K):
+    t = np.arange(N, dtype=np.float64)
+    fw = NW / N
+    w, lam = orc.gpss_tapers(t, 0.5, fw, K)
+    v, ratios = sw.dpss(N, NW, Kmax=K, sym=True, norm=2, return_ratios=True)
+    np.testing.assert_allclose(lam, ratios, atol=1e-12)
+    # same sign convention as the Slepian sequences: even sum > 0, odd start > 0
+    np.testing.assert_allclose(w, math.sqrt(2 * fw) * v, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# P3: uniform / lattice closed form of the eigencoefficients by FFT
+# --------------------------------------------------------------------------
+
+def test_nudft_lattice_closed_form_fft(orc):
+    s = W.small_gapped()
+    K, I = 3, s.I
+    w = np.random.default_rng(4).standard_normal((K, s.N))
+    J = orc.nudft(s.t, s.x, w, s.f_lo, s.df, I=I)
+    # f_lo = -1/2, df = 1/I, integer t < I: J = FFT_I of (w x e^{j pi t}) on the grid
+    g = np.zeros((K, I), dtype=complex)
+    ti = s.t.astype(np.int64)
+    g[:, ti] = w * s.x * np.exp(1j * np.pi * s.t)
+    np.testing.assert_allclose(J, np.fft.fft(g, axis=1), atol=1e-12)
+
+
+def test_nudft_phase_is_exact_for_large_times(orc):
+    # the phase (f_lo + i df) t_n is evaluated exactly in rationals here
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.uniform(7.0e4, 8.2e4, 12))
+    x = rng.standard_normal(12)
+    w = np.ones((1, 12))
+    f_lo, df = -0.5 + 1.0 / 3.0, 1.0 / 262144.0
+    bands = np.array([0, 1, 12345, 262143], dtype=np.int64)
+    J = orc.nudft(t, x, w, f_lo, df, bands=bands)[0]
+    for b, i in enumerate(bands):
+        acc = 0j
+        for n in range(12):
+            ph = (Fraction(f_lo) + i * Fraction(df)) * Fraction(float(t[n]))
+            r = float(ph - math.floor(ph))
+            acc += x[n] * complex(math.cos(2 * math.pi * r), -math.sin(2 * math.pi * r))
+        assert abs(J[b] - acc) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# invariants the paper states
+# --------------------------------------------------------------------------
+
+def test_eigenvalues_in_unit_interval_and_trace(orc):
+    # P5: 0 <= lambda <= 1 (Sec. 3.5); with R(B) = I the full spectrum sums to
+    # tr R(A0) = 2 f_w N
+    s = W.small_gapped()
+    RA = orc.gpss_matrix(s.t, s.fw)
+    ev, _ = orc.jacobi_eigh(RA)
+    assert ev.min() > -1e-14 and ev.max() < 1 + 1e-14
+    assert abs(ev.sum() - 2 * s.fw * s.N) < 1e-12
+    j = W.scheme_jitter()
+    L = orc.cholesky(orc.gpss_matrix(j.t, 0.5))
+    evj, _ = orc.jacobi_eigh(orc.reduce(L, orc.gpss_matrix(j.t, 0.05)))
+    assert evj.min() > -1e-13 and evj.max() < 1 + 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["jitter", "missing", "arithmetic", "uniform"])
+def test_normalisation_and_variance_factor(orc, scheme):
+    # P6: w_k^T R(B) w_l = 2 f_w delta_kl (Sec. 2.2), so the variance bound
+    # factor V = (1/K^2) sum |w_k^T R(B) w_l|^2 = (2 f_w)^2 / K
+    s = W.by_name(scheme)
+    w, lam = orc.gpss_tapers(s.t, s.fmax, s.fw, s.K)
+    G = w @ orc.gpss_matrix(s.t, s.fmax) @ w.T
+    np.testing.assert_allclose(G, 2 * s.fw * np.eye(s.K), atol=1e-13)
+    V = (G ** 2).sum() / s.K ** 2
+    assert abs(V - (2 * s.fw) ** 2 / s.K) < 1e-14
+    # and they solve the GEP: R(A0) w = lambda R(B) w
+    RA, RB = orc.gpss_matrix(s.t, s.fw), orc.gpss_matrix(s.t, s.fmax)
+    np.testing.assert_allclose(RA @ w.T, (RB @ w.T) * lam, atol=1e-12)
+    # lambdas are the K largest generalized eigenvalues (LAPACK on the pencil)
+    Lc = np.linalg.cholesky(RB)
+    Li = np.linalg.inv(Lc)
+    ref = np.linalg.eigvalsh(Li @ RA @ Li.T)[::-1][:s.K]
+    np.testing.assert_allclose(lam, ref, atol=1e-12)
+
+
+def test_parseval_on_lattice(orc):
+    # P8: integer t, df = 1/M, M >= span: (1/M) sum_i |J_k(i)|^2 = sum_n |w_k x_n|^2
+    s = W.small_gapped()
+    M = 256
+    w = np.random.default_rng(6).standard_normal((2, s.N))
+    J = orc.nudft(s.t, s.x, w, -0.5, 1.0 / M, I=M)
+    np.testing.assert_allclose((np.abs(J) ** 2).sum(1) / M, ((w * s.x) ** 2).sum(1), rtol=1e-13)
+
+
+def test_symmetry_real_data(orc):
+    # P9: real x and w, f_lo = -1/2, df = 1/I, integer t: P_{I-i} = P_i
+    s = W.small_gapped()
+    out = orc.m2nufft(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I, with_ehat=False)
+    P = out["P"]
+    np.testing.assert_allclose(P[1:], P[1:][::-1], rtol=1e-12, atol=1e-15)
+
+
+def test_ehat_zero_on_lattice_and_at_nominal_band(orc):
+    # P4 (Appendix B): on the lattice with f_max = 1/2, R(B) = I and Ehat = 0
+    s = W.small_gapped()
+    out = orc.m2nufft(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I)
+    assert np.abs(out["E"]).max() < 1e-14
+    np.testing.assert_allclose(out["D"], 2 * s.fw, rtol=1e-13)
+    # P10: at df_i = 0 the shifted taper is the nominal one, D = 2 f_w, Ehat = 0
+    for name in ["jitter", "missing", "arithmetic"]:
+        j = W.by_name(name)
+        w, lam = orc.gpss_tapers(j.t, j.fmax, j.fw, j.K)
+        E, D = orc.ehat(j.t, w, lam, j.fmax, j.fw, -0.5, 1.0 / 64, bands=np.array([32]))
+        assert abs(E[0]) < 1e-13
+        np.testing.assert_allclose(D[:, 0], 2 * j.fw, rtol=1e-12)
+        E_all, _ = orc.ehat(j.t, w, lam, j.fmax, j.fw, -0.5, 1.0 / 64, I=64)
+        assert E_all.min() >= 0.0
+
+
+def test_ehat_equals_exact_suboptimality_on_lattice(orc):
+    # P4/P12 brute force: per-band GEP R(A_i) w = lambda R(B) w on a tiny lattice
+    # has the same eigenvalues as at A0, so the exact E_i is 0 like Ehat
+    s = W.small_gapped()
+    t = s.t[:40]
+    fw, K = 0.1, 3
+    w, lam = orc.gpss_tapers(t, 0.5, fw, K)
+    for fci in [0.0, 0.1, -0.23, 0.4]:
+        RAi = orc.band_matrix(t, fci, fw)     # R(B) = I here
+        ev = np.linalg.eigvalsh(RAi)[::-1][:K]
+        np.testing.assert_allclose(ev, lam, atol=1e-13)
+
+
+def test_ehat_nonlattice_matches_rayleigh_quotient(orc):
+    # Appendix B: lambda_hat = (E w)^* R(A_i) (E w) / (E w)^* R(B) (E w), using
+    # the complex band matrix directly (independent of the 2 f_w lambda form)
+    s = W.scheme_missing()
+    w, lam = orc.gpss_tapers(s.t, s.fmax, s.fw, s.K)
+    RB = orc.gpss_matrix(s.t, s.fmax)
+    bands = np.array([5, 20, 40, 60], dtype=np.int64)
+    E, D = orc.ehat(s.t, w, lam, s.fmax, s.fw, -0.5, 1.0 / 64, bands=bands)
+    for b, i in enumerate(bands):
+        fci = -0.5 + i / 64.0
+        Ei = np.exp(2j * np.pi * fci * s.t)
+        RAi = orc.band_matrix(s.t, fci, s.fw)
+        lh = []
+        for k in range(s.K):
+            z = Ei * w[k]
+            lh.append((z.conj() @ RAi @ z).real / (z.conj() @ RB @ z).real)
+        np.testing.assert_allclose(D[:, b], [(Ei * w[k]).conj() @ RB @ (Ei * w[k]) for k in range(s.K)],
+                                   rtol=1e-12)
+        assert abs(E[b] - np.mean(np.abs(lam - np.array(lh)))) < 1e-12
+
+
+def test_unbiased_for_white_noise(orc):
+    # P7 (Sec. 3.3): E[P(A_i)] = 2 f_w sigma^2 for white noise on the lattice
+    s = W.small_gapped()
+    w, lam = orc.gpss_tapers(s.t, s.fmax, s.fw, s.K)
+    bands = np.arange(0, s.I, 8, dtype=np.int64)
+    acc = []
+    for m in range(300):
+        x = W.white_noise(s.N, 7000 + m, sigma=1.3)
+        acc.append(orc.psd(orc.nudft(s.t, x, w, s.f_lo, s.df, bands=bands)).mean())
+    acc = np.array(acc)
+    target = 2 * s.fw * 1.3 ** 2
+    se = acc.std(ddof=1) / math.sqrt(len(acc))
+    assert abs(acc.mean() - target) < 4 * se
+
+
+def test_sinusoid_peak_band(orc):
+    # P14: the strongest sinusoid (f = 0.05) dominates the bands around +-0.05
+    s = W.small_gapped()
+    out = orc.m2nufft(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I, with_ehat=False)
+    top = np.argmax(out["P"])
+    fc = s.f_lo + top * s.df
+    assert abs(abs(fc) - 0.05) <= s.fw
