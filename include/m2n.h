@@ -1,0 +1,150 @@
+/*
+ * m2n.h -- C-ABI of the MI355X M2NuFFT library (libm2n.so).
+ *
+ * The estimator (Cui, Brinkmann & Worrell, M2NuFFT, arXiv 2407.01943) for a
+ * gapped or nonuniformly sampled series x(t_n), n = 1..N, with signal band
+ * B = [-f_max, f_max], nominal analysis band A0 = [-f_w, f_w] and I analysis
+ * bands A_i centred at f_lo + i*df:
+ *
+ *   tapers     R(A0) w_k = lambda_k R(B) w_k, the K largest, scaled so that
+ *              w_k^T R(B) w_k = 2 f_w              (Sec. 3.2 GEP at A0, Sec. 2.2
+ *                                                   normalisation; Table 3 step 3)
+ *   eigcoeffs  J_k(A_i) = sum_n w_k(t_n) x(t_n) exp(-j 2 pi (f_lo + i df) t_n)
+ *                                                  (Sec. 3.2; Table 3 step 4)
+ *   psd        P(A_i) = sum_k d_k |J_k(A_i)|^2, d_k = 1/K by default
+ *                                                  (Sec. 3.2; Table 3 step 5)
+ *   ehat       Ehat_i = (1/K) sum_k |lambda_k - 2 f_w lambda_k / D_k(i)|,
+ *              D_k(i) = (E_i w_k)^* R(B) (E_i w_k)  (Sec. 3.5 with the
+ *                                                   Appendix B Rayleigh quotient)
+ *
+ * R(B)_{nm} = sin(2 pi f_max tau)/(pi tau), R(A0)_{nm} = sin(2 pi f_w tau)/(pi tau),
+ * tau = t_n - t_m (Sec. 2.1, Sec. 2.3); the diagonals are 2 f_max and 2 f_w.
+ *
+ * Conventions for every call below
+ *  - Every array argument is a DEVICE pointer (HIP device memory of the
+ *    context's device) owned by the caller; the library never frees it and
+ *    keeps no reference after the call's stream work has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Layouts are row-major: tapers w are K x N (taper k at w + k*N), the
+ *    eigencoefficients J are K x I complex (interleaved re, im).
+ *  - Sizes are int64_t; N >= 1, 1 <= K <= min(N, 64), 1 <= I <= 2^23.
+ *  - Errors are returned as m2n_status codes; nothing aborts and no C++
+ *    exception crosses the ABI.  m2n_last_error() gives a text for the last
+ *    failure on the calling thread.
+ *  - A context is not thread-safe: one host thread at a time per context.
+ */
+#ifndef M2N_H
+#define M2N_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct m2n_ctx m2n_ctx;
+
+typedef enum {
+    M2N_OK = 0,
+    M2N_ERR_ARG = -1,          /* bad size, NULL pointer or non-finite value     */
+    M2N_ERR_T_ORDER = -2,      /* sampling times not strictly increasing         */
+    M2N_ERR_NOT_PD = -3,       /* R(B) not numerically positive definite         */
+    M2N_ERR_NO_CONVERGE = -4,  /* eigen-solver did not reach its tolerance       */
+    M2N_ERR_OOM = -5,          /* device allocation or memory budget exceeded    */
+    M2N_ERR_HIP = -6,          /* a HIP runtime call failed                      */
+    M2N_ERR_NOT_READY = -7,    /* queue: request still in flight                 */
+    M2N_ERR_UNSUPPORTED = -8,  /* valid input outside what this build implements */
+    M2N_ERR_CANCELLED = -9     /* queue: request cancelled by queue destruction  */
+} m2n_status;
+
+typedef enum { M2N_FP32 = 1, M2N_FP64 = 2 } m2n_prec;
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * library's own workspace (0 = no cap).  On success *out owns all plans,
+ * caches and workspace until m2n_destroy. */
+int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx **out);
+
+/* Free everything the context owns (waits for its streams' work first). */
+void m2n_destroy(m2n_ctx *ctx);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char *m2n_last_error(void);
+
+/* Bytes of device workspace the context currently holds. */
+size_t m2n_workspace_bytes(const m2n_ctx *ctx);
+
+/*
+ * gpss_tapers -- Table 3 step 3, GEP branch (Sec. 3.2): the K largest
+ * generalized eigenpairs of R(A0) w = lambda R(B) w at f_c0 = 0.
+ *
+ *   t       [N]     device, FP64, strictly increasing sampling times
+ *   fmax            signal band half-width, > f_w
+ *   fw              nominal band half-width, > 0
+ *   fc0             nominal band centre; only 0 is implemented (else
+ *                   M2N_ERR_UNSUPPORTED)
+ *   w       [K*N]   device, FP64 out: taper k at w + k*N, w_k^T R(B) w_k = 2 f_w;
+ *                   sign: the larger in magnitude of sum_n w_k(t_n) and
+ *                   sum_n (tbar - t_n) w_k(t_n) is positive, tbar = (t_1+t_N)/2
+ *   lambda  [K]     device, FP64 out, descending, in [0, 1]
+ *
+ * Blocks the calling thread until the tapers are on the device (the solver
+ * reads back its convergence test).  Errors: M2N_ERR_T_ORDER, M2N_ERR_NOT_PD
+ * (Cholesky pivot <= 0; no silent regularisation), M2N_ERR_NO_CONVERGE.
+ */
+int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
+                double fmax, double fw, double fc0, int K,
+                double *w, double *lambda);
+
+/*
+ * m2nufft_eigcoeffs -- Table 3 step 4 (Sec. 3.2 eigencoefficients) as a
+ * type-1 NuFFT of the K tapered sequences onto the I band centres.
+ *
+ *   t, x    [N]     device, FP64; t strictly increasing
+ *   w       [K*N]   device, FP64 tapers (any real tapers, e.g. from gpss_tapers)
+ *   f_lo, df        band centres f_lo + i*df, i = 0..I-1 (df > 0)
+ *   prec            M2N_FP32: spread/FFT/average in FP32 (J is float2);
+ *                   M2N_FP64: all FP64 (J is double2)
+ *   nufft_tol       requested relative accuracy of the NuFFT (<= 0: 1e-6 for
+ *                   FP32, 1e-12 for FP64); sets the kernel width
+ *   J       [K*I]   device out, complex, J + (k*I + i)
+ *
+ * Stream-ordered and asynchronous once the plan for (I, prec, tol) exists
+ * (the first call for a plan allocates and fills its tables).
+ */
+int m2nufft_eigcoeffs(m2n_ctx *ctx, void *stream, const double *t,
+                      const double *x, int64_t N, const double *w, int K,
+                      double f_lo, double df, int64_t I, int prec,
+                      double nufft_tol, void *J);
+
+/*
+ * m2nufft_psd -- Table 3 steps 4 and 5 fused, plus the suboptimality
+ * estimate of Appendix B.
+ *
+ *   t, x, w, f_lo, df, I, prec, nufft_tol   as in m2nufft_eigcoeffs
+ *   lambda  [K]     device, FP64 eigenvalues of the tapers (needed for E)
+ *   fmax, fw        band parameters the tapers were built for (needed for E)
+ *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
+ *   P       [I]     device out, float (FP32) or double (FP64)
+ *   E       [I]     device out or NULL; implemented when R(B) is a multiple
+ *                   of the identity (t on a lattice of spacing beta with
+ *                   2 f_max beta a positive integer), else M2N_ERR_UNSUPPORTED
+ *   J       [K*I]   device out or NULL, as in m2nufft_eigcoeffs
+ *
+ * Stream-ordered and asynchronous once the plan exists.
+ */
+int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
+                int64_t N, const double *w, const double *lambda, int K,
+                double fmax, double fw, double f_lo, double df, int64_t I,
+                int prec, double nufft_tol, const double *weights, void *P,
+                void *E, void *J);
+
+/* Wait for `stream` and report the first device-side data error flagged by
+ * the library's kernels since the last check (M2N_ERR_ARG for non-finite t). */
+int m2n_check(m2n_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* M2N_H */

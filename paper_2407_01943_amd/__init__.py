@@ -1,0 +1,175 @@
+"""Python binding of libm2n.so, the MI355X M2NuFFT library (C-ABI in
+include/m2n.h).  Argument marshalling only: torch provides device memory and
+the current stream, every computation runs in the library's HIP kernels.
+
+The functions keep the C-ABI names:
+
+    gpss_tapers(ctx, t, fmax, fw, K, fc0=0.0)            -> (w [K, N], lam [K])
+    m2nufft_eigcoeffs(ctx, t, x, w, f_lo, df, I, prec)   -> J [K, I] complex
+    m2nufft_psd(ctx, t, x, w, lam, fmax, fw, f_lo, df, I, prec, ...) -> dict
+
+If libm2n.so is missing or cannot be loaded the import fails: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libm2n.so")
+
+M2N_OK = 0
+M2N_ERR_ARG = -1
+M2N_ERR_T_ORDER = -2
+M2N_ERR_NOT_PD = -3
+M2N_ERR_NO_CONVERGE = -4
+M2N_ERR_OOM = -5
+M2N_ERR_HIP = -6
+M2N_ERR_NOT_READY = -7
+M2N_ERR_UNSUPPORTED = -8
+M2N_ERR_CANCELLED = -9
+M2N_FP32 = 1
+M2N_FP64 = 2
+
+EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes",
+            "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check"]
+
+
+class M2NError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, d, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    L.m2n_create.argtypes = [i, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.m2n_create.restype = i
+    L.m2n_destroy.argtypes = [vp]
+    L.m2n_destroy.restype = None
+    L.m2n_last_error.argtypes = []
+    L.m2n_last_error.restype = ctypes.c_char_p
+    L.m2n_workspace_bytes.argtypes = [vp]
+    L.m2n_workspace_bytes.restype = ctypes.c_size_t
+    L.m2n_check.argtypes = [vp, vp]
+    L.m2n_check.restype = i
+    L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
+    L.gpss_tapers.restype = i
+    L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
+    L.m2nufft_eigcoeffs.restype = i
+    L.m2nufft_psd.argtypes = [vp, vp, vp, vp, i64, vp, vp, i, d, d, d, d, i64, i, d,
+                              vp, vp, vp, vp]
+    L.m2nufft_psd.restype = i
+    return L
+
+
+lib = _load()
+
+
+def _err(code, where):
+    if code != M2N_OK:
+        raise M2NError(code, where, lib.m2n_last_error().decode(errors="replace"))
+
+
+def _ptr(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype=torch.float64):
+    assert x.is_cuda and x.dtype == dtype and x.is_contiguous(), (x.device, x.dtype)
+    return x
+
+
+class Context:
+    """Owns one m2n_ctx (plans, caches, workspace) on a HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _err(lib.m2n_create(device, hbm_budget_bytes, ctypes.byref(h)), "m2n_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib.m2n_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        return lib.m2n_workspace_bytes(self.handle)
+
+    def check(self, stream=None):
+        _err(lib.m2n_check(self.handle, _stream(stream)), "m2n_check")
+
+
+def gpss_tapers(ctx: Context, t, fmax, fw, K, fc0=0.0, stream=None, out=None):
+    """Table 3 step 3 (GEP branch): the K largest GPSS tapers at A0."""
+    t = _dev(t)
+    N = t.shape[0]
+    if out is None:
+        w = torch.empty((K, N), dtype=torch.float64, device=t.device)
+        lam = torch.empty((K,), dtype=torch.float64, device=t.device)
+    else:
+        w, lam = out
+    _err(lib.gpss_tapers(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw),
+                         float(fc0), int(K), _ptr(w), _ptr(lam)), "gpss_tapers")
+    return w, lam
+
+
+def m2nufft_eigcoeffs(ctx: Context, t, x, w, f_lo, df, I, prec=M2N_FP64, nufft_tol=0.0,
+                      stream=None, out=None, check=True):
+    """Table 3 step 4: J_k(A_i) for all bands (complex [K, I])."""
+    t, x, w = _dev(t), _dev(x), _dev(w)
+    K, N = w.shape
+    cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
+    J = torch.empty((K, I), dtype=cdt, device=t.device) if out is None else out
+    _err(lib.m2nufft_eigcoeffs(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w),
+                               K, float(f_lo), float(df), int(I), int(prec), float(nufft_tol),
+                               _ptr(J)), "m2nufft_eigcoeffs")
+    if check:
+        ctx.check(stream)
+    return J
+
+
+def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64,
+                nufft_tol=0.0, weights=None, want_E=True, want_J=False, stream=None,
+                out=None, check=True):
+    """Table 3 steps 4-5 fused, plus the Appendix B suboptimality estimate.
+    Returns {"P": [I], "E": [I] or None, "J": [K, I] or None}."""
+    t, x, w = _dev(t), _dev(x), _dev(w)
+    K, N = w.shape
+    rdt = torch.float32 if prec == M2N_FP32 else torch.float64
+    cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
+    if out is None:
+        P = torch.empty((I,), dtype=rdt, device=t.device)
+        E = torch.empty((I,), dtype=rdt, device=t.device) if want_E else None
+        J = torch.empty((K, I), dtype=cdt, device=t.device) if want_J else None
+    else:
+        P, E, J = out
+    if lam is not None:
+        lam = _dev(lam)
+    if weights is not None:
+        weights = _dev(weights)
+    _err(lib.m2nufft_psd(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w),
+                         _ptr(lam), K, float(fmax), float(fw), float(f_lo), float(df), int(I),
+                         int(prec), float(nufft_tol), _ptr(weights), _ptr(P), _ptr(E), _ptr(J)),
+         "m2nufft_psd")
+    if check:
+        ctx.check(stream)
+    return {"P": P, "E": E, "J": J}

@@ -1,0 +1,195 @@
+// C-ABI entry points, context, workspace and error state.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "m2n_common.hpp"
+
+namespace m2n {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int Ctx::alloc(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (budget && held + bytes > budget) {
+        set_error("device memory budget exceeded (%zu + %zu > %zu bytes)", held, bytes, budget);
+        return M2N_ERR_OOM;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? M2N_ERR_OOM : M2N_ERR_HIP;
+    }
+    b.p = p;
+    b.bytes = bytes;
+    held += bytes;
+    return M2N_OK;
+}
+
+void Ctx::release(DevBuf& b) {
+    if (b.p) {
+        (void)hipFree(b.p);
+        held -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+int Ctx::workspace(const char* name, size_t bytes, void** out) {
+    DevBuf& b = ws[name];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            // earlier work queued on any stream may still read the old buffer
+            M2N_HIP(hipDeviceSynchronize());
+            release(b);
+        }
+        size_t want = bytes + bytes / 4;
+        M2N_TRY(alloc(b, want));
+    }
+    *out = b.p;
+    return M2N_OK;
+}
+
+}  // namespace m2n
+
+using namespace m2n;
+
+struct m2n_ctx : public m2n::Ctx {};
+
+extern "C" {
+
+const char* m2n_last_error(void) { return g_err; }
+
+int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx** out) {
+    if (!out) {
+        set_error("out is NULL");
+        return M2N_ERR_ARG;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    M2N_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) {
+        set_error("device %d out of range (%d devices)", hip_device, ndev);
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(hip_device));
+    auto* c = new (std::nothrow) m2n_ctx();
+    if (!c) {
+        set_error("host allocation failed");
+        return M2N_ERR_OOM;
+    }
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    void* e = nullptr;
+    if (hipMalloc(&e, 256) != hipSuccess) {
+        delete c;
+        set_error("hipMalloc of the error word failed");
+        return M2N_ERR_HIP;
+    }
+    (void)hipMemset(e, 0, 256);
+    c->dev_err = (unsigned*)e;
+    *out = c;
+    return M2N_OK;
+}
+
+void m2n_destroy(m2n_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->plans) {
+        ctx->release(kv.second->tw_fft);
+        ctx->release(kv.second->tw_lo);
+        ctx->release(kv.second->tw_hi);
+        ctx->release(kv.second->inv_phihat);
+    }
+    for (auto& kv : ctx->ws) ctx->release(kv.second);
+    if (ctx->dev_err) (void)hipFree(ctx->dev_err);
+    delete ctx;
+}
+
+size_t m2n_workspace_bytes(const m2n_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+int m2n_check(m2n_ctx* ctx, void* stream) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    M2N_HIP(hipStreamSynchronize((hipStream_t)stream));
+    unsigned v = 0;
+    M2N_HIP(hipMemcpy(&v, ctx->dev_err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (v) {
+        unsigned z = 0;
+        M2N_HIP(hipMemcpy(ctx->dev_err, &z, sizeof(unsigned), hipMemcpyHostToDevice));
+        if (v & DEVERR_NONFINITE) {
+            set_error("non-finite sampling time or sample value");
+            return M2N_ERR_ARG;
+        }
+        if (v & DEVERR_E_UNSUPPORTED) {
+            set_error("Ehat is implemented only when R(B) is a multiple of the identity "
+                      "(integer t and integer 2 f_max)");
+            return M2N_ERR_UNSUPPORTED;
+        }
+    }
+    return M2N_OK;
+}
+
+int gpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw,
+                double fc0, int K, double* w, double* lambda) {
+    if (!ctx || !t || !w || !lambda) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    if (N < 1 || K < 1 || K > 64 || K > N) {
+        set_error("need 1 <= K <= min(N, 64) (N = %lld, K = %d)", (long long)N, K);
+        return M2N_ERR_ARG;
+    }
+    if (!std::isfinite(fmax) || !std::isfinite(fw) || !(fw > 0.0) || !(fw < fmax)) {
+        set_error("need 0 < fw < fmax (fw = %g, fmax = %g)", fw, fmax);
+        return M2N_ERR_ARG;
+    }
+    if (fc0 != 0.0) {
+        set_error("only f_c0 = 0 is implemented");
+        return M2N_ERR_UNSUPPORTED;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
+}
+
+int m2nufft_eigcoeffs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
+                      const double* w, int K, double f_lo, double df, int64_t I, int prec,
+                      double nufft_tol, void* J) {
+    if (!ctx || !J) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
+                     nullptr, nullptr, 0.0, 0.0, nullptr, nullptr, J);
+}
+
+int m2nufft_psd(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
+                const double* w, const double* lambda, int K, double fmax, double fw,
+                double f_lo, double df, int64_t I, int prec, double nufft_tol,
+                const double* weights, void* P, void* E, void* J) {
+    if (!ctx || !P) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
+                     weights, lambda, fmax, fw, P, E, J);
+}
+
+}  // extern "C"

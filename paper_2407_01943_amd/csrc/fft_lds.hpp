@@ -1,0 +1,96 @@
+// Batched power-of-two complex FFTs held in LDS (Stockham autosort).
+//
+// Forward transform X[m] = sum_j x[j] exp(-2 pi i j m / N).  NB transforms of
+// length N live in LDS at buf[b * LD + j].  One radix-RAD Stockham stage with
+// current span p (p = 1, RAD, RAD^2, ...) takes, for every j < N/RAD with
+// k = j mod p, the inputs x[j + t N/RAD] (t < RAD), multiplies input t by
+// exp(-2 pi i t k / (p RAD)), applies the length-RAD DFT and stores output q
+// at (j - k) RAD + k + q p.  After all stages the result is in natural order.
+// Every stage stages its inputs in registers, so a single LDS buffer suffices
+// (barrier between the loads and the stores).  Twiddles come from a table
+// tw[j] = exp(-2 pi i j / Nt) in global memory (cached), with Nt a multiple
+// of N; `tws` = Nt / N.
+#pragma once
+
+#include "m2n_common.hpp"
+
+namespace m2n {
+
+template <typename R>
+__device__ __forceinline__ void dft2(cplx<R>& a, cplx<R>& b) {
+    cplx<R> s = cadd(a, b), d = csub(a, b);
+    a = s;
+    b = d;
+}
+
+// forward radix-4 butterfly on (u0,u1,u2,u3) in place, outputs in natural order
+template <typename R>
+__device__ __forceinline__ void dft4(cplx<R>* u) {
+    cplx<R> a = cadd(u[0], u[2]), b = csub(u[0], u[2]);
+    cplx<R> c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
+    u[0] = cadd(a, c);
+    u[2] = csub(a, c);
+    u[1] = {b.x + d.y, b.y - d.x};   // b - i d
+    u[3] = {b.x - d.y, b.y + d.x};   // b + i d
+}
+
+template <typename R, int N, int NB, int NT, int LD, int RAD>
+__device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw,
+                                          int tws, int p) {
+    constexpr int Q = N / RAD;              // butterflies per transform
+    constexpr int BF = NB * Q;              // butterflies in the batch
+    constexpr int IT = (BF + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    cplx<R> v[IT][RAD];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NT;
+        if (BF % NT == 0 || idx < BF) {
+            const int b = idx / Q, j = idx - b * Q;
+            const int k = j & (p - 1);
+            const int tstep = k * (N / (p * RAD)) * tws;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                cplx<R> val = buf[b * LD + j + t * Q];
+                if (t > 0) val = cmul(val, tw[t * tstep]);
+                v[it][t] = val;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NT;
+        if (BF % NT == 0 || idx < BF) {
+            const int b = idx / Q, j = idx - b * Q;
+            const int k = j & (p - 1);
+            if (RAD == 4) dft4(v[it]);
+            else dft2(v[it][0], v[it][1]);
+            const int base = b * LD + (j - k) * RAD + k;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) buf[base + q * p] = v[it][q];
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// NB forward FFTs of length N (power of two, >= 2) in LDS.  Caller must have
+// synchronised after writing buf; returns synchronised.
+template <typename R, int N, int NB, int NT, int LD>
+__device__ __forceinline__ void fft_lds(cplx<R>* buf, const cplx<R>* __restrict__ tw, int tws) {
+    constexpr int LOG = ilog2c(N);
+    int p = 1;
+    if (LOG & 1) {
+        fft_stage<R, N, NB, NT, LD, 2>(buf, tw, tws, p);
+        p = 2;
+    }
+#pragma unroll 1
+    for (int s = 0; s < LOG / 2; ++s) {
+        fft_stage<R, N, NB, NT, LD, 4>(buf, tw, tws, p);
+        p *= 4;
+    }
+}
+
+}  // namespace m2n

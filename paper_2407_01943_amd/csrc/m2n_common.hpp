@@ -1,0 +1,123 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/m2n.h"
+
+namespace m2n {
+
+// ---------------------------------------------------------------- complex
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R x, y;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) {
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) {
+    return {a.x - b.x, a.y - b.y};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cscale(cplx<R> a, R s) {
+    return {a.x * s, a.y * s};
+}
+
+// ------------------------------------------------------------- error state
+void set_error(const char* fmt, ...);
+
+#define M2N_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) {                                              \
+            ::m2n::set_error("%s failed: %s (%s:%d)", #call,                 \
+                             hipGetErrorString(e_), __FILE__, __LINE__);     \
+            return M2N_ERR_HIP;                                              \
+        }                                                                    \
+    } while (0)
+
+#define M2N_TRY(expr)                 \
+    do {                              \
+        int s_ = (expr);              \
+        if (s_ != M2N_OK) return s_;  \
+    } while (0)
+
+// Device-side sticky error bits (OR-ed by kernels, read by m2n_check).
+enum : unsigned {
+    DEVERR_NONFINITE = 1u,     // a non-finite t or x reached a kernel
+    DEVERR_E_UNSUPPORTED = 2u, // Ehat asked for a non-diagonal R(B)
+};
+
+// ---------------------------------------------------------- device buffers
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// --------------------------------------------------------------- NuFFT plan
+struct NufftPlan {
+    int64_t I = 0;     // number of bands
+    int64_t h = 0;     // mode offset: band i <-> mode i - h
+    int prec = 0;      // M2N_FP32 / M2N_FP64
+    int w = 0;         // kernel width (cells)
+    double beta = 0;   // ES kernel shape
+    int nf = 0;        // fine grid size (power of two, >= 2 I)
+    int log_nf = 0;
+    bool single = false;   // whole grid in one workgroup's LDS
+    int N1 = 0, N2 = 0;    // nf = N1 * N2 (two-pass)
+    int B = 0, M = 0;      // pass-1 column block, pass-2 row block
+    int lookback = 0;      // extra column blocks a point may reach into
+    int lo_bits = 0;       // 4-step twiddle split
+    DevBuf tw_fft;         // e^{-2 pi i j / Nt}, j < Nt (Nt = max FFT length)
+    int tw_len = 0;
+    DevBuf tw_lo, tw_hi;   // 4-step twiddle tables
+    DevBuf inv_phihat;     // 1 / phihat(|k|), |k| <= kmax
+    int64_t kmax = 0;
+};
+
+struct Ctx;
+
+// NuFFT entry used by the C-ABI (defined in nufft.hip)
+int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
+              int64_t N, const double* w, int K, double f_lo, double df,
+              int64_t I, int prec, double tol, const double* weights,
+              const double* lambda, double fmax, double fw, void* P, void* E,
+              void* J);
+
+// GEP entry (defined in gep.hip)
+int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N,
+            double fmax, double fw, int K, double* w, double* lambda);
+
+// ----------------------------------------------------------------- context
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;         // 0 = unlimited
+    size_t held = 0;           // bytes currently allocated
+    std::map<std::tuple<int64_t, int, int>, std::unique_ptr<NufftPlan>> plans;
+    std::map<std::string, DevBuf> ws;   // named grow-only workspaces
+    unsigned* dev_err = nullptr;        // sticky device error word
+    int cu_count = 256;
+
+    // grow-only named workspace; returns M2N_OK / M2N_ERR_OOM / M2N_ERR_HIP
+    int workspace(const char* name, size_t bytes, void** out);
+    int alloc(DevBuf& b, size_t bytes);
+    void release(DevBuf& b);
+};
+
+}  // namespace m2n

@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU FP64 oracle.
+
+Tolerances (normwise, after per-taper sign alignment):
+  FP64 mode: J and P within 1e-10, lambda within 1e-12 absolute, Ehat 1e-10 abs.
+  FP32 mode: J and P within 1e-5 (NuFFT tolerance 1e-6, kernel width 7).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.metrics import align_signs, normwise_rows, psd_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m2n():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_01943_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(m2n):
+    c = m2n.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------- NuFFT alone
+def _nufft_case(m2n, ctx, orc, s, w, prec, tol_J, tol_P):
+    _say(f"case {s.name} N={s.N} K={w.shape[0]} I={s.I} prec={prec}")
+    ref_J = orc.nudft(s.t, s.x, w, s.f_lo, s.df, I=s.I)
+    ref_P = orc.psd(ref_J)
+    out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), None, s.fmax, s.fw, s.f_lo,
+                          s.df, s.I, prec=prec, want_E=False, want_J=True)
+    J = out["J"].cpu().numpy().astype(np.complex128)
+    P = out["P"].cpu().numpy().astype(np.float64)
+    eJ, eP = normwise_rows(J, ref_J), psd_err(P, ref_P)
+    _say(f"  J normwise {eJ:.3e}  P {eP:.3e}")
+    assert eJ < tol_J and eP < tol_P
+    J2 = m2n.m2nufft_eigcoeffs(ctx, _dev(s.t), _dev(s.x), _dev(w), s.f_lo, s.df, s.I, prec=prec)
+    assert normwise_rows(J2.cpu().numpy().astype(np.complex128), ref_J) < tol_J
+
+
+@pytest.mark.parametrize("prec,tol", [(2, 1e-10), (1, 1e-5)])
+def test_nufft_single_workgroup(m2n, ctx, orc, prec, tol):
+    s = W.small_gapped()
+    w = np.random.default_rng(100).standard_normal((s.K, s.N)) * 0.1
+    _nufft_case(m2n, ctx, orc, s, w, prec, tol, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(2, 1e-10), (1, 1e-5)])
+def test_nufft_two_pass(m2n, ctx, orc, prec, tol):
+    # I = 2^14 -> nf = 2^15: two passes; a ragged N and a wrap of the points
+    s = W.gapped_scaled(3000, 5, 2 ** 14, seed=31)
+    w = np.random.default_rng(101).standard_normal((5, s.N)) * 0.05
+    _nufft_case(m2n, ctx, orc, s, w, prec, tol, tol)
+
+
+@pytest.mark.parametrize("name", ["jitter", "arithmetic", "missing"])
+def test_nufft_nonlattice_times(m2n, ctx, orc, name):
+    s = W.by_name(name)
+    s.I = 4096
+    s.df = 1.0 / 4096
+    w = np.random.default_rng(102).standard_normal((s.K, s.N))
+    _nufft_case(m2n, ctx, orc, s, w, 2, 1e-10, 1e-10)
+
+
+def test_nufft_wrapped_grid(m2n, ctx, orc):
+    # df * span > 1: the points wrap around the periodic grid several times
+    s = W.gapped_scaled(3000, 3, 2 ** 14, seed=33)
+    s.I = 8192            # two-pass grid (nf = 16384)
+    s.df = 1.0 / 1777.0
+    s.f_lo = -0.31
+    w = np.random.default_rng(103).standard_normal((3, s.N))
+    _nufft_case(m2n, ctx, orc, s, w, 2, 1e-10, 1e-10)
+
+
+# ---------------------------------------------------------------- the GEP
+def _gep_case(m2n, ctx, orc, t, fmax, fw, K, tol_w=1e-9):
+    _say(f"gep N={len(t)} fw={fw} K={K}")
+    w_ref, lam_ref = orc.gpss_tapers(t, fmax, fw, K)
+    w, lam = m2n.gpss_tapers(ctx, _dev(t), fmax, fw, K)
+    w, lam = w.cpu().numpy(), lam.cpu().numpy()
+    el = np.abs(lam - lam_ref).max()
+    wa, _ = align_signs(w, w_ref)
+    ew = normwise_rows(wa, w_ref)
+    _say(f"  lambda {el:.3e}  w {ew:.3e}")
+    assert el < 1e-12
+    assert ew < tol_w
+    return w, lam
+
+
+def test_gep_lattice_small(m2n, ctx, orc):
+    s = W.small_gapped()
+    _gep_case(m2n, ctx, orc, s.t, s.fmax, s.fw, s.K)
+
+
+@pytest.mark.parametrize("name", ["jitter", "missing", "arithmetic", "uniform"])
+def test_gep_dense_small(m2n, ctx, orc, name):
+    s = W.by_name(name)
+    _gep_case(m2n, ctx, orc, s.t, s.fmax, 0.0125 if name != "uniform" else s.fw, s.K)
+
+
+def test_gep_lattice_medium(m2n, ctx, orc):
+    s = W.gapped_scaled(2048, 6, 4096, seed=41)
+    _gep_case(m2n, ctx, orc, s.t, s.fmax, s.fw, 6)
+
+
+def test_gep_dense_medium(m2n, ctx, orc):
+    s = W.jitter_stress(n=300, seed=42, K=5)
+    _gep_case(m2n, ctx, orc, s.t, s.fmax, 2.5 / 300, 5)
+
+
+# ------------------------------------------------------------ end to end
+@pytest.mark.parametrize("prec,tol", [(2, 1e-10), (1, 1e-5)])
+def test_end_to_end_small(m2n, ctx, orc, prec, tol):
+    s = W.small_gapped()
+    ref = orc.m2nufft(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I)
+    t, x = _dev(s.t), _dev(s.x)
+    w, lam = m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K)
+    out = m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=prec,
+                          want_E=True, want_J=True)
+    P = out["P"].cpu().numpy().astype(np.float64)
+    E = out["E"].cpu().numpy().astype(np.float64)
+    assert psd_err(P, ref["P"]) < tol
+    assert np.abs(E - ref["E"]).max() < tol
+
+
+def test_errors(m2n, ctx):
+    t = _dev(np.array([0.0, 2.0, 1.0, 3.0]))
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.gpss_tapers(ctx, t, 0.5, 0.1, 2)
+    assert ei.value.code == m2n.M2N_ERR_T_ORDER
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.gpss_tapers(ctx, _dev(np.arange(4.0)), 0.5, 0.6, 2)
+    assert ei.value.code == m2n.M2N_ERR_ARG
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.gpss_tapers(ctx, _dev(np.arange(4.0)), 0.5, 0.1, 2, fc0=0.1)
+    assert ei.value.code == m2n.M2N_ERR_UNSUPPORTED
+    x = _dev(np.array([1.0, np.nan, 2.0, 3.0]))
+    w = _dev(np.ones((1, 4)))
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.m2nufft_psd(ctx, _dev(np.arange(4.0)), x, w, None, 0.5, 0.1, -0.5, 1 / 64, 64,
+                        want_E=False)
+    assert ei.value.code == m2n.M2N_ERR_ARG
