@@ -139,6 +139,18 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                 int prec, double nufft_tol, const double *weights, void *P,
                 void *E, void *J);
 
+/* Kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by a pair of HIP events recorded on the launch stream;
+ * m2n_profile_read waits for them and returns, per kernel name, the total
+ * milliseconds and the number of launches since the last reset.  `names`
+ * receives the names separated by '\n' (at most max_entries of them, as
+ * fit into names_len bytes); the return value is the number of entries or
+ * a negative m2n_status. */
+int m2n_profile_enable(m2n_ctx *ctx, int on);
+int m2n_profile_reset(m2n_ctx *ctx);
+int m2n_profile_read(m2n_ctx *ctx, char *names, size_t names_len, double *total_ms,
+                     int64_t *launches, int max_entries);
+
 /* Wait for `stream` and report the first device-side data error flagged by
  * the library's kernels since the last check (M2N_ERR_ARG for non-finite t). */
 int m2n_check(m2n_ctx *ctx, void *stream);

@@ -45,6 +45,8 @@ def lib():
             from . import build as _b
             _b.build()
         L = ctypes.CDLL(_LIB_PATH)
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_num_threads.argtypes = []
         L.or_validate.restype = ctypes.c_int
         L.or_validate.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.or_sinpi.restype = ctypes.c_double
@@ -85,6 +87,10 @@ def _p(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
 
 
 def validate(t, fmax, fw, K):

@@ -38,6 +38,7 @@
  * -3 R(B) not positive definite, -4 no convergence.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 #include <stdint.h>
@@ -49,6 +50,9 @@
 #define OR_ERR_NO_CONVERGE (-4)
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* number of OpenMP threads the parallel loops use */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* argument checks (Table 3 step 1: t_n strictly increasing, 0<fw<fmax) */

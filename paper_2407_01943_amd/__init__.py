@@ -35,7 +35,8 @@ M2N_FP32 = 1
 M2N_FP64 = 2
 
 EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes",
-            "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check"]
+            "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
+            "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read"]
 
 
 class M2NError(RuntimeError):
@@ -57,6 +58,14 @@ def _load():
     L.m2n_last_error.restype = ctypes.c_char_p
     L.m2n_workspace_bytes.argtypes = [vp]
     L.m2n_workspace_bytes.restype = ctypes.c_size_t
+    L.m2n_profile_enable.argtypes = [vp, i]
+    L.m2n_profile_enable.restype = i
+    L.m2n_profile_reset.argtypes = [vp]
+    L.m2n_profile_reset.restype = i
+    L.m2n_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64), i]
+    L.m2n_profile_read.restype = i
     L.m2n_check.argtypes = [vp, vp]
     L.m2n_check.restype = i
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
@@ -113,6 +122,25 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return lib.m2n_workspace_bytes(self.handle)
+
+    def profile(self, on: bool):
+        """Bracket every library kernel launch with HIP events (on the launch stream)."""
+        _err(lib.m2n_profile_enable(self.handle, 1 if on else 0), "m2n_profile_enable")
+
+    def profile_reset(self):
+        _err(lib.m2n_profile_reset(self.handle), "m2n_profile_reset")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last reset."""
+        cap = 128
+        buf = ctypes.create_string_buffer(16384)
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        n = lib.m2n_profile_read(self.handle, buf, len(buf), ms, cnt, cap)
+        if n < 0:
+            _err(n, "m2n_profile_read")
+        names = buf.value.decode().split("\n")[:n]
+        return {nm: (ms[i], int(cnt[i])) for i, nm in enumerate(names)}
 
     def check(self, stream=None):
         _err(lib.m2n_check(self.handle, _stream(stream)), "m2n_check")

@@ -59,6 +59,32 @@ int Ctx::workspace(const char* name, size_t bytes, void** out) {
     return M2N_OK;
 }
 
+hipEvent_t Ctx::take_event() {
+    if (!ev_pool.empty()) {
+        hipEvent_t e = ev_pool.back();
+        ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int Ctx::prof_flush() {
+    for (auto& r : pending) {
+        M2N_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        M2N_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        auto& st = prof_stats[r.name];
+        st.first += ms;
+        st.second += 1;
+        ev_pool.push_back(r.a);
+        ev_pool.push_back(r.b);
+    }
+    pending.clear();
+    return M2N_OK;
+}
+
 }  // namespace m2n
 
 using namespace m2n;
@@ -114,11 +140,61 @@ void m2n_destroy(m2n_ctx* ctx) {
         ctx->release(kv.second->inv_phihat);
     }
     for (auto& kv : ctx->ws) ctx->release(kv.second);
+    for (auto& r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
 }
 
 size_t m2n_workspace_bytes(const m2n_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+int m2n_profile_enable(m2n_ctx* ctx, int on) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return M2N_ERR_ARG;
+    }
+    if (!on) M2N_TRY(ctx->prof_flush());
+    ctx->prof = on != 0;
+    return M2N_OK;
+}
+
+int m2n_profile_reset(m2n_ctx* ctx) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return M2N_ERR_ARG;
+    }
+    M2N_TRY(ctx->prof_flush());
+    ctx->prof_stats.clear();
+    return M2N_OK;
+}
+
+int m2n_profile_read(m2n_ctx* ctx, char* names, size_t names_len, double* total_ms,
+                     int64_t* launches, int max_entries) {
+    if (!ctx || !names || names_len == 0) {
+        set_error("bad argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_TRY(ctx->prof_flush());
+    size_t used = 0;
+    int n = 0;
+    names[0] = 0;
+    for (auto& kv : ctx->prof_stats) {
+        if (n >= max_entries) break;
+        const size_t L = kv.first.size();
+        if (used + L + 2 > names_len) break;
+        memcpy(names + used, kv.first.c_str(), L);
+        used += L;
+        names[used++] = '\n';
+        names[used] = 0;
+        if (total_ms) total_ms[n] = kv.second.first;
+        if (launches) launches[n] = kv.second.second;
+        ++n;
+    }
+    return n;
+}
 
 int m2n_check(m2n_ctx* ctx, void* stream) {
     if (!ctx) {

@@ -906,6 +906,7 @@ struct Solver {
             a.p = p;
             a.Hhat = Hhat;
             a.Y = W;
+            M2N_PROF(ctx, st, "toeplitz_fft_conv");
             if (fft.single) {
                 // whole convolution in two single-workgroup transforms
                 a.dst = cbuf1;
@@ -923,7 +924,10 @@ struct Solver {
         // dense: tmp = L^{-T} V; W = R(A0) tmp; W = L^{-1} W
         M2N_HIP(hipMemcpyAsync(tmp, V, sizeof(double) * (size_t)p * Np, hipMemcpyDeviceToDevice, st));
         M2N_TRY(trsv(tmp, 1));
-        hipLaunchKernelGGL(k_gemm_rect, dim3((unsigned)nblk), dim3(GNT), 0, st, RA, Np, tmp, p, W);
+        {
+            M2N_PROF(ctx, st, "k_gemm_rect");
+            hipLaunchKernelGGL(k_gemm_rect, dim3((unsigned)nblk), dim3(GNT), 0, st, RA, Np, tmp, p, W);
+        }
         M2N_HIP(hipGetLastError());
         M2N_TRY(trsv(W, 0));
         return M2N_OK;
@@ -933,11 +937,17 @@ struct Solver {
     int trsv(double* Bm, int trans) {
         for (int s = 0; s < nblk; ++s) {
             const int kb = trans ? nblk - 1 - s : s;
-            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(GNT), 0, st, RB, Np, kb, trans, Bm, p);
+            {
+                M2N_PROF(ctx, st, "k_trsv_diag");
+                hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(GNT), 0, st, RB, Np, kb, trans, Bm, p);
+            }
             const int nupd = trans ? kb : nblk - kb - 1;
             if (nupd > 0)
-                hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)nupd), dim3(GNT), 0, st, RB, Np, kb,
-                                   trans, Bm, p);
+                {
+                    M2N_PROF(ctx, st, "k_trsv_update");
+                    hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)nupd), dim3(GNT), 0, st, RB, Np, kb,
+                                       trans, Bm, p);
+                }
         }
         M2N_HIP(hipGetLastError());
         return M2N_OK;
@@ -1036,12 +1046,21 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         S.Hhat = (double*)vH;
         S.cbuf1 = (cplx<double>*)vc1;
         S.cbuf2 = (cplx<double>*)vc2;
-        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S.map, M, -1);
-        hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                           (const int*)voff, N, S.map);
+        {
+            M2N_PROF(ctx, st, "k_fill_int");
+            hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S.map, M, -1);
+        }
+        {
+            M2N_PROF(ctx, st, "k_lattice_map");
+            hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                               (const int*)voff, N, S.map);
+        }
         // Hhat = FFT(h) / (M cB)
-        hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                           S.cbuf2, M, Sspan, fw);
+        {
+            M2N_PROF(ctx, st, "k_toep_kernel");
+            hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                               S.cbuf2, M, Sspan, fw);
+        }
         M2N_HIP(hipGetLastError());
         {
             ConvArgs a{};
@@ -1052,8 +1071,11 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
             cplx<double>* scratch = (cplx<double>*)vs;
             M2N_TRY(run_fft64(S.fft, st, a, 1, SRC_DIRECT, DST_DIRECT, scratch));
         }
-        hipLaunchKernelGGL(k_real_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                           (const cplx<double>*)S.cbuf1, M, 1.0 / ((double)M * cB), S.Hhat);
+        {
+            M2N_PROF(ctx, st, "k_real_scale");
+            hipLaunchKernelGGL(k_real_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                               (const cplx<double>*)S.cbuf1, M, 1.0 / ((double)M * cB), S.Hhat);
+        }
         M2N_HIP(hipGetLastError());
         M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
         scale = std::sqrt(2.0 * fw / cB);
@@ -1062,13 +1084,25 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         {
             // ---- subspace iteration
             dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
-            hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
+            {
+                M2N_PROF(ctx, st, "k_randinit");
+                hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
+            }
             M2N_HIP(hipGetLastError());
             auto cholqr = [&](double* src, double* dst) -> int {
-                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
-                                   nchunks, part);
-                hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
-                hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
+                {
+                    M2N_PROF(ctx, st, "k_gram");
+                    hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
+                                       nchunks, part);
+                }
+                {
+                    M2N_PROF(ctx, st, "k_chol_small");
+                    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
+                }
+                {
+                    M2N_PROF(ctx, st, "k_trsm_rows");
+                    hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
+                }
                 M2N_HIP(hipGetLastError());
                 return M2N_OK;
             };
@@ -1079,11 +1113,20 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
             bool ok = false;
             for (int it = 0; it < 40; ++it) {
                 M2N_TRY(S.apply(V, W));
-                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw,
-                                   nchunks, part);
-                hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
-                hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K,
-                                   Y, U, res);
+                {
+                    M2N_PROF(ctx, st, "k_gram");
+                    hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw,
+                                       nchunks, part);
+                }
+                {
+                    M2N_PROF(ctx, st, "k_rr");
+                    hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
+                }
+                {
+                    M2N_PROF(ctx, st, "k_rotate");
+                    hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K,
+                                       Y, U, res);
+                }
                 M2N_HIP(hipGetLastError());
                 M2N_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(),
                                        hipMemcpyDeviceToHost, st));
@@ -1127,16 +1170,31 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         S.nz = (int*)vnz;
         M2N_HIP(hipMemsetAsync(vst, 0, 64, st));
         dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
-        hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
-        hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fw, 0.0, S.RA);
+        {
+            M2N_PROF(ctx, st, "k_gen_sinc");
+            hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
+        }
+        {
+            M2N_PROF(ctx, st, "k_gen_sinc");
+            hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fw, 0.0, S.RA);
+        }
         M2N_HIP(hipGetLastError());
         for (int kb = 0; kb < S.nblk; ++kb) {
-            hipLaunchKernelGGL(k_potrf, dim3(1), dim3(GNT), 0, st, S.RB, Np, kb, N, (int*)vst);
+            {
+                M2N_PROF(ctx, st, "k_potrf");
+                hipLaunchKernelGGL(k_potrf, dim3(1), dim3(GNT), 0, st, S.RB, Np, kb, N, (int*)vst);
+            }
             const int rem = S.nblk - kb - 1;
             if (rem > 0) {
-                hipLaunchKernelGGL(k_trsm_panel, dim3(rem), dim3(GNT), 0, st, S.RB, Np, kb, S.nz);
+                {
+                    M2N_PROF(ctx, st, "k_trsm_panel");
+                    hipLaunchKernelGGL(k_trsm_panel, dim3(rem), dim3(GNT), 0, st, S.RB, Np, kb, S.nz);
+                }
                 const int ntiles = rem * (rem + 1) / 2;
-                hipLaunchKernelGGL(k_syrk, dim3(ntiles), dim3(GNT), 0, st, S.RB, Np, kb, S.nblk, S.nz);
+                {
+                    M2N_PROF(ctx, st, "k_syrk");
+                    hipLaunchKernelGGL(k_syrk, dim3(ntiles), dim3(GNT), 0, st, S.RB, Np, kb, S.nblk, S.nz);
+                }
             }
         }
         M2N_HIP(hipGetLastError());
@@ -1149,13 +1207,25 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         }
         scale = std::sqrt(2.0 * fw);
         dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
-        hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
+        {
+            M2N_PROF(ctx, st, "k_randinit");
+            hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
+        }
         M2N_HIP(hipGetLastError());
         auto cholqr = [&](double* src, double* dst) -> int {
-            hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
-                               nchunks, part);
-            hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
-            hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
+            {
+                M2N_PROF(ctx, st, "k_gram");
+                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
+                                   nchunks, part);
+            }
+            {
+                M2N_PROF(ctx, st, "k_chol_small");
+                hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
+            }
+            {
+                M2N_PROF(ctx, st, "k_trsm_rows");
+                hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
+            }
             M2N_HIP(hipGetLastError());
             return M2N_OK;
         };
@@ -1166,11 +1236,20 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         bool ok = false;
         for (int it = 0; it < 40; ++it) {
             M2N_TRY(S.apply(V, W));
-            hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw, nchunks,
-                               part);
-            hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
-            hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K, Y, U,
-                               res);
+            {
+                M2N_PROF(ctx, st, "k_gram");
+                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw, nchunks,
+                                   part);
+            }
+            {
+                M2N_PROF(ctx, st, "k_rr");
+                hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
+            }
+            {
+                M2N_PROF(ctx, st, "k_rotate");
+                hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K, Y, U,
+                                   res);
+            }
             M2N_HIP(hipGetLastError());
             M2N_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(),
                                    hipMemcpyDeviceToHost, st));
@@ -1199,10 +1278,16 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         S.p = psave;
     }
     // ---- sign convention, scale, output
-    hipLaunchKernelGGL(k_sign_sums, dim3(row_wg), dim3(GNT), 0, st, Y, Np, N, K, td, part);
+    {
+        M2N_PROF(ctx, st, "k_sign_sums");
+        hipLaunchKernelGGL(k_sign_sums, dim3(row_wg), dim3(GNT), 0, st, Y, Np, N, K, td, part);
+    }
     const int fin_wg = (int)((N + GNT - 1) / GNT);
-    hipLaunchKernelGGL(k_finalize, dim3(fin_wg), dim3(GNT), 0, st, Y, Np, N, K, scale, part,
-                       row_wg, th, w_out, lambda_out);
+    {
+        M2N_PROF(ctx, st, "k_finalize");
+        hipLaunchKernelGGL(k_finalize, dim3(fin_wg), dim3(GNT), 0, st, Y, Np, N, K, scale, part,
+                           row_wg, th, w_out, lambda_out);
+    }
     M2N_HIP(hipGetLastError());
     M2N_HIP(hipStreamSynchronize(st));
     return M2N_OK;

@@ -93,6 +93,12 @@ struct NufftPlan {
 
 struct Ctx;
 
+// Per-kernel timing with HIP events on the launch stream (off by default).
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
 // NuFFT entry used by the C-ABI (defined in nufft.hip)
 int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
               int64_t N, const double* w, int K, double f_lo, double df,
@@ -114,10 +120,45 @@ struct Ctx {
     unsigned* dev_err = nullptr;        // sticky device error word
     int cu_count = 256;
 
+    // kernel timing (m2n_profile_*)
+    bool prof = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> ev_pool;
+    std::map<std::string, std::pair<double, int64_t>> prof_stats;   // name -> (ms, launches)
+    hipEvent_t take_event();
+    int prof_flush();
+
     // grow-only named workspace; returns M2N_OK / M2N_ERR_OOM / M2N_ERR_HIP
     int workspace(const char* name, size_t bytes, void** out);
     int alloc(DevBuf& b, size_t bytes);
     void release(DevBuf& b);
 };
+
+// RAII: records an event pair around the launches in its scope when timing is on
+struct ProfScope {
+    Ctx* c;
+    hipStream_t s;
+    const char* n;
+    hipEvent_t a = nullptr;
+    ProfScope(Ctx* c_, hipStream_t s_, const char* n_) : c(c_), s(s_), n(n_) {
+        if (c && c->prof) {
+            a = c->take_event();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = c->take_event();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                c->pending.push_back({n, a, b});
+            }
+        }
+    }
+};
+
+#define M2N_PROF_CAT2(a, b) a##b
+#define M2N_PROF_CAT(a, b) M2N_PROF_CAT2(a, b)
+#define M2N_PROF(ctx, st, name) ::m2n::ProfScope M2N_PROF_CAT(prof_scope_, __LINE__)(ctx, st, name)
 
 }  // namespace m2n

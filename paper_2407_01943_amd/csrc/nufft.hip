@@ -618,9 +618,11 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
     M2N_TRY(upload(ctx, dgw, gw));
     M2N_TRY(ctx->alloc(p.inv_phihat, (size_t)(kmax + 1) * sizeof(R)));
     const int64_t nthr = kmax + 1;
-    hipLaunchKernelGGL(k_phihat<R>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, 0, kmax,
-                       p.nf, p.w, p.beta, (const double*)dgx.p, (const double*)dgw.p, ng,
-                       (R*)p.inv_phihat.p);
+    {
+        hipLaunchKernelGGL(k_phihat<R>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, 0, kmax,
+                           p.nf, p.w, p.beta, (const double*)dgx.p, (const double*)dgw.p, ng,
+                           (R*)p.inv_phihat.p);
+    }
     M2N_HIP(hipGetLastError());
     M2N_HIP(hipDeviceSynchronize());
     ctx->release(dgx);
@@ -749,6 +751,7 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const double* t, con
     R* E = (R*)Ev;
     cplx<R>* J = (cplx<R>*)Jv;
     if (p.single) {
+        M2N_PROF(ctx, st, "k_small");
         launch_small<R>(p, st, t, x, N, w, K, f_lo, df, dk, lambda, fmax, fw, ctx->dev_err, P, E,
                         J);
         M2N_HIP(hipGetLastError());
@@ -774,21 +777,36 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const double* t, con
     M2N_TRY(ctx->workspace("nu_idx", sizeof(int) * (size_t)N, &idxs));
     M2N_TRY(ctx->workspace("nu_inter", sizeof(cplx<R>) * (size_t)K * p.nf, &inter));
     M2N_TRY(ctx->workspace("nu_eval", 64, &eval));
-    hipLaunchKernelGGL(k_hist, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf, p.w,
-                       p.N2, p.B, nbins, (int*)hist, (int*)flags, w, K, needE ? 1 : 0,
-                       (double*)part);
-    hipLaunchKernelGGL(k_scan<R>, dim3(1), dim3(1024), 0, st, (const int*)hist, nwg, nbins,
-                       (int*)off, (int*)binoff, (const int*)flags, ctx->dev_err, needE ? 1 : 0,
-                       (const double*)part, lambda, K, fmax, fw, (R*)eval);
-    hipLaunchKernelGGL(k_scatter<R>, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf,
-                       p.w, p.N2, p.B, nbins, (const int*)off, (int*)l0s, (R*)dels,
-                       (cplx<R>*)c0s, (int*)idxs);
+    {
+        M2N_PROF(ctx, st, "k_hist");
+        hipLaunchKernelGGL(k_hist, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf, p.w,
+                           p.N2, p.B, nbins, (int*)hist, (int*)flags, w, K, needE ? 1 : 0,
+                           (double*)part);
+    }
+    {
+        M2N_PROF(ctx, st, "k_scan");
+        hipLaunchKernelGGL(k_scan<R>, dim3(1), dim3(1024), 0, st, (const int*)hist, nwg, nbins,
+                           (int*)off, (int*)binoff, (const int*)flags, ctx->dev_err, needE ? 1 : 0,
+                           (const double*)part, lambda, K, fmax, fw, (R*)eval);
+    }
+    {
+        M2N_PROF(ctx, st, "k_scatter");
+        hipLaunchKernelGGL(k_scatter<R>, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf,
+                           p.w, p.N2, p.B, nbins, (const int*)off, (int*)l0s, (R*)dels,
+                           (cplx<R>*)c0s, (int*)idxs);
+    }
     M2N_HIP(hipGetLastError());
-    M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(K * nbins)), (const int*)l0s, (const R*)dels,
+    {
+        M2N_PROF(ctx, st, "k_pass1");
+        M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(K * nbins)), (const int*)l0s, (const R*)dels,
                             (const cplx<R>*)c0s, (const int*)idxs, (const int*)binoff, w, N,
                             (cplx<R>*)inter));
+    }
     M2N_HIP(hipGetLastError());
-    M2N_TRY(launch_pass2<R>(p, st, (const cplx<R>*)inter, K, dk, P, E, (const R*)eval, J));
+    {
+        M2N_PROF(ctx, st, "k_pass2");
+        M2N_TRY(launch_pass2<R>(p, st, (const cplx<R>*)inter, K, dk, P, E, (const R*)eval, J));
+    }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
 }

@@ -118,6 +118,18 @@ def test_gep_lattice_medium(m2n, ctx, orc):
     _gep_case(m2n, ctx, orc, s.t, s.fmax, s.fw, 6)
 
 
+def test_gep_lattice_two_pass_fft(m2n, ctx, orc):
+    # span ~ 6000 -> convolution grid M = 16384 > 4096: two-pass FP64 FFT
+    s = W.gapped_scaled(6000, 7, 8192, seed=43)
+    _say(f"gep lattice two-pass N={s.N}")
+    w_ref, lam_ref = orc.gpss_tapers(s.t, s.fmax, s.fw, 7, method="lanczos")
+    w, lam = m2n.gpss_tapers(ctx, _dev(s.t), s.fmax, s.fw, 7)
+    w, lam = w.cpu().numpy(), lam.cpu().numpy()
+    assert np.abs(lam - lam_ref).max() < 1e-12
+    wa, _ = align_signs(w, w_ref)
+    assert normwise_rows(wa, w_ref) < 1e-8
+
+
 def test_gep_dense_medium(m2n, ctx, orc):
     s = W.jitter_stress(n=300, seed=42, K=5)
     _gep_case(m2n, ctx, orc, s.t, s.fmax, 2.5 / 300, 5)
