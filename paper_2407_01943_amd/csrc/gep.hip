@@ -68,36 +68,38 @@ __global__ void k_randinit(double* __restrict__ V, int64_t Np, int64_t N, int p,
 }
 
 // ------------------------------------------------------ Gram partials
-// part[wg][i * pb + j] = sum over this workgroup's rows of A[i][n] * B[j][n]
-__global__ __launch_bounds__(GNT) void k_gram(const double* __restrict__ A, const double* __restrict__ B,
-                                              int64_t Np, int64_t nrows, int pa, int pb, int nchunks_per_wg,
-                                              int64_t nchunks, double* __restrict__ part) {
-    __shared__ double As[MAXP][GRAM_ROWS + 1];
-    __shared__ double Bs[MAXP][GRAM_ROWS + 1];
-    const int np = pa * pb;
-    double acc[MAXP * MAXP / GNT];
-    constexpr int PER = MAXP * MAXP / GNT;
+// One pass over the rows of this workgroup's chunks:
+//   part[wg][0 .. p*p)      = V^T V   (entry i * p + j)
+//   part[wg][p*p .. 2 p*p)  = V^T W
+__global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, const double* __restrict__ W,
+                                               int64_t Np, int64_t nrows, int p, int nchunks_per_wg,
+                                               int64_t nchunks, double* __restrict__ part) {
+    __shared__ double Vs[MAXP][GRAM_ROWS + 1];
+    __shared__ double Ws[MAXP][GRAM_ROWS + 1];
+    constexpr int PER = 2 * MAXP * MAXP / GNT;
+    const int np = p * p;
+    double acc[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) acc[e] = 0.0;
     const int64_t c0 = (int64_t)blockIdx.x * nchunks_per_wg;
     for (int64_t c = c0; c < c0 + nchunks_per_wg && c < nchunks; ++c) {
         const int64_t r0 = c * GRAM_ROWS;
-        for (int e = threadIdx.x; e < pa * GRAM_ROWS; e += GNT) {
+        for (int e = threadIdx.x; e < p * GRAM_ROWS; e += GNT) {
             const int i = e / GRAM_ROWS, r = e % GRAM_ROWS;
-            As[i][r] = (r0 + r < nrows) ? A[(int64_t)i * Np + r0 + r] : 0.0;
-        }
-        for (int e = threadIdx.x; e < pb * GRAM_ROWS; e += GNT) {
-            const int i = e / GRAM_ROWS, r = e % GRAM_ROWS;
-            Bs[i][r] = (r0 + r < nrows) ? B[(int64_t)i * Np + r0 + r] : 0.0;
+            const bool in = r0 + r < nrows;
+            Vs[i][r] = in ? V[(int64_t)i * Np + r0 + r] : 0.0;
+            Ws[i][r] = in ? W[(int64_t)i * Np + r0 + r] : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = threadIdx.x + e * GNT;
-            if (idx < np) {
-                const int i = idx / pb, j = idx % pb;
+            if (idx < 2 * np) {
+                const int which = idx >= np, q = idx - which * np;
+                const int i = q / p, j = q % p;
+                const double* b = which ? Ws[j] : Vs[j];
                 double s = 0.0;
-                for (int r = 0; r < GRAM_ROWS; ++r) s += As[i][r] * Bs[j][r];
+                for (int r = 0; r < GRAM_ROWS; ++r) s += Vs[i][r] * b[r];
                 acc[e] += s;
             }
         }
@@ -106,225 +108,265 @@ __global__ __launch_bounds__(GNT) void k_gram(const double* __restrict__ A, cons
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int idx = threadIdx.x + e * GNT;
-        if (idx < np) part[(int64_t)blockIdx.x * np + idx] = acc[e];
+        if (idx < 2 * np) part[(int64_t)blockIdx.x * 2 * np + idx] = acc[e];
     }
 }
 
-// ------------------------------------------- Rayleigh-Ritz: sum + Jacobi
-// H = sum of the Gram partials (p x p, symmetrised), then cyclic Jacobi in
-// LDS; Q (column-major, Q[i + j p] = component i of eigenvector j) and theta
-// sorted in descending order.
-__global__ __launch_bounds__(64) void k_rr(const double* __restrict__ part, int nwg, int p,
-                                           double* __restrict__ Q, double* __restrict__ theta) {
-    __shared__ double A[MAXP][MAXP + 1];
-    __shared__ double Vv[MAXP][MAXP + 1];
-    __shared__ double rot[4];
-    __shared__ double sred[64];
+// ------------------------------------- Rayleigh-Ritz on a general basis
+// With G = V^T V = R^T R (Cholesky) and H = V^T W (W = C V), the Ritz pairs
+// of C in span(V) are (theta, V Q) with Q = R^{-1} Q', where
+// R^{-T} H R^{-1} = Q' diag(theta) Q'^T.  Y = V Q has orthonormal columns.
+// The small symmetric eigenproblem is solved by parallel cyclic Jacobi:
+// each round rotates n/2 disjoint index pairs (round-robin schedule).
+// Output: Q (column-major, Q[i + j p] = component i of Ritz vector j) and
+// theta, both in descending order of theta.
+__global__ __launch_bounds__(GNT) void k_small_rr(const double* __restrict__ part, int nwg, int p,
+                                                  double* __restrict__ Qout,
+                                                  double* __restrict__ theta) {
+    constexpr int LDA = MAXP + 1;
+    __shared__ double G[MAXP * LDA];    // V^T V, then R (upper)
+    __shared__ double H[MAXP * LDA];    // V^T W, then R^{-T} H R^{-1}, then Jacobi
+    __shared__ double Qv[MAXP * LDA];   // Jacobi vectors
+    __shared__ double cs[MAXP / 2][2];
+    __shared__ int pr[MAXP / 2][2];
     __shared__ int order[MAXP];
-    const int lane = threadIdx.x;
-    for (int e = lane; e < p * p; e += 64) {
-        double s = 0.0;
-        for (int g = 0; g < nwg; ++g) s += part[(int64_t)g * p * p + e];
-        A[e / p][e % p] = s;
+    __shared__ double red[GNT / 64];
+    __shared__ int s_any;
+    const int tid = threadIdx.x;
+    const int np = p * p;
+    const int n = p + (p & 1);          // even size; a dummy index is decoupled
+    // 1. sum the partials
+    for (int e = tid; e < 2 * np; e += GNT) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int g = 0;
+        for (; g + 3 < nwg; g += 4) {
+            s0 += part[(int64_t)(g + 0) * 2 * np + e];
+            s1 += part[(int64_t)(g + 1) * 2 * np + e];
+            s2 += part[(int64_t)(g + 2) * 2 * np + e];
+            s3 += part[(int64_t)(g + 3) * 2 * np + e];
+        }
+        for (; g < nwg; ++g) s0 += part[(int64_t)g * 2 * np + e];
+        const double s = (s0 + s1) + (s2 + s3);
+        const int q = e % np, i = q / p, j = q % p;
+        if (e < np) G[i * LDA + j] = s;
+        else H[i * LDA + j] = s;
     }
     __syncthreads();
-    for (int e = lane; e < p * p; e += 64) {
+    // symmetrise H
+    for (int e = tid; e < np; e += GNT) {
         const int i = e / p, j = e % p;
         if (i < j) {
-            const double m = 0.5 * (A[i][j] + A[j][i]);
-            A[i][j] = m;
-            A[j][i] = m;
+            const double m = 0.5 * (H[i * LDA + j] + H[j * LDA + i]);
+            H[i * LDA + j] = m;
+            H[j * LDA + i] = m;
         }
-        Vv[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    // 2. Cholesky G = R^T R (R upper, in place), pivots floored
+    double dmax = 0.0;
+    for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i * LDA + i]);
+    const double pfloor = dmax * 1e-24 + 1e-300;
+    for (int j = 0; j < p; ++j) {
+        if (tid == 0) {
+            const double d = G[j * LDA + j];
+            G[j * LDA + j] = sqrt(d > pfloor ? d : pfloor);
+        }
+        __syncthreads();
+        const double rjj = G[j * LDA + j];
+        for (int c = j + 1 + tid; c < p; c += GNT) G[j * LDA + c] /= rjj;
+        __syncthreads();
+        const int rem = p - j - 1;
+        for (int e = tid; e < rem * rem; e += GNT) {
+            const int a = j + 1 + e / rem, b = j + 1 + e % rem;
+            if (b >= a) G[a * LDA + b] -= G[j * LDA + a] * G[j * LDA + b];
+        }
+        __syncthreads();
+    }
+    // 3. H <- R^{-T} H  (forward substitution down each column)
+    for (int c = tid; c < p; c += GNT) {
+        for (int i = 0; i < p; ++i) {
+            double s = H[i * LDA + c];
+            for (int k = 0; k < i; ++k) s -= G[k * LDA + i] * H[k * LDA + c];
+            H[i * LDA + c] = s / G[i * LDA + i];
+        }
     }
     __syncthreads();
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, fro = 0.0;
-        for (int e = lane; e < p * p; e += 64) {
-            const int i = e / p, j = e % p;
-            const double v = A[i][j] * A[i][j];
-            fro += v;
-            if (i != j) off += v;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_xor(off, o, 64);
-            fro += __shfl_xor(fro, o, 64);
-        }
-        if (off <= 1e-30 * fro || off == 0.0) break;
-        for (int i = 0; i < p - 1; ++i) {
-            for (int j = i + 1; j < p; ++j) {
-                if (lane == 0) {
-                    const double aij = A[i][j];
-                    double c = 1.0, s = 0.0, t = 0.0, tau = 0.0;
-                    if (aij != 0.0 && fabs(aij) > 1e-300) {
-                        const double th = (A[j][j] - A[i][i]) / (2.0 * aij);
-                        t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
-                        if (th < 0.0) t = -t;
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                        tau = s / (1.0 + c);
-                    }
-                    rot[0] = s;
-                    rot[1] = tau;
-                    rot[2] = t;
-                    rot[3] = aij;
-                }
-                __syncthreads();
-                const double s = rot[0], tau = rot[1], t = rot[2], aij = rot[3];
-                if (s != 0.0) {
-                    for (int m = lane; m < p; m += 64) {
-                        if (m != i && m != j) {
-                            const double ami = A[m][i], amj = A[m][j];
-                            const double ni = ami - s * (amj + tau * ami);
-                            const double nj = amj + s * (ami - tau * amj);
-                            A[m][i] = ni;
-                            A[i][m] = ni;
-                            A[m][j] = nj;
-                            A[j][m] = nj;
-                        }
-                        const double vmi = Vv[m][i], vmj = Vv[m][j];
-                        Vv[m][i] = vmi - s * (vmj + tau * vmi);
-                        Vv[m][j] = vmj + s * (vmi - tau * vmj);
-                    }
-                    __syncthreads();
-                    if (lane == 0) {
-                        A[i][i] -= t * aij;
-                        A[j][j] += t * aij;
-                        A[i][j] = 0.0;
-                        A[j][i] = 0.0;
-                    }
-                }
-                __syncthreads();
-            }
+    //    H <- H R^{-1}  (forward substitution along each row)
+    for (int r = tid; r < p; r += GNT) {
+        for (int j = 0; j < p; ++j) {
+            double s = H[r * LDA + j];
+            for (int k = 0; k < j; ++k) s -= H[r * LDA + k] * G[k * LDA + j];
+            H[r * LDA + j] = s / G[j * LDA + j];
         }
     }
-    // sort descending (lane 0, p <= 64)
-    if (lane == 0) {
-        for (int i = 0; i < p; ++i) order[i] = i;
-        for (int i = 0; i < p; ++i) {
+    __syncthreads();
+    for (int e = tid; e < n * n; e += GNT) {
+        const int i = e / n, j = e % n;
+        if (i < p && j < p) {
+            if (i < j) {
+                const double m = 0.5 * (H[i * LDA + j] + H[j * LDA + i]);
+                H[i * LDA + j] = m;
+                H[j * LDA + i] = m;
+            }
+        } else {
+            H[i * LDA + j] = (i == j) ? -1.0 : 0.0;   // dummy: decoupled, sorts last
+        }
+        Qv[i * LDA + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // 4. parallel cyclic Jacobi
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) s_any = 0;
+        __syncthreads();
+        for (int r = 0; r < n - 1; ++r) {
+            if (tid < n / 2) {
+                int i, j;
+                if (tid == 0) {
+                    i = r;
+                    j = n - 1;
+                } else {
+                    i = (r + tid) % (n - 1);
+                    j = (r - tid + n - 1) % (n - 1);
+                }
+                if (i > j) {
+                    const int tmp = i;
+                    i = j;
+                    j = tmp;
+                }
+                const double aij = H[i * LDA + j], aii = H[i * LDA + i], ajj = H[j * LDA + j];
+                double c = 1.0, s = 0.0;
+                if (fabs(aij) > 1e-18 * sqrt(fabs(aii * ajj)) && fabs(aij) > 1e-300) {
+                    const double th = (ajj - aii) / (2.0 * aij);
+                    double t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
+                    if (th < 0.0) t = -t;
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    s = t * c;
+                    s_any = 1;
+                }
+                pr[tid][0] = i;
+                pr[tid][1] = j;
+                cs[tid][0] = c;
+                cs[tid][1] = s;
+            }
+            __syncthreads();
+            // rows i, j of H  <- J^T H
+            for (int e = tid; e < (n / 2) * n; e += GNT) {
+                const int k = e / n, m = e % n;
+                const double s = cs[k][1];
+                if (s != 0.0) {
+                    const int i = pr[k][0], j = pr[k][1];
+                    const double c = cs[k][0];
+                    const double hi = H[i * LDA + m], hj = H[j * LDA + m];
+                    H[i * LDA + m] = c * hi - s * hj;
+                    H[j * LDA + m] = s * hi + c * hj;
+                }
+            }
+            __syncthreads();
+            // columns i, j of H and of Q  <- H J, Q J
+            for (int e = tid; e < (n / 2) * n; e += GNT) {
+                const int k = e / n, m = e % n;
+                const double s = cs[k][1];
+                if (s != 0.0) {
+                    const int i = pr[k][0], j = pr[k][1];
+                    const double c = cs[k][0];
+                    const double hi = H[m * LDA + i], hj = H[m * LDA + j];
+                    H[m * LDA + i] = c * hi - s * hj;
+                    H[m * LDA + j] = s * hi + c * hj;
+                    const double qi = Qv[m * LDA + i], qj = Qv[m * LDA + j];
+                    Qv[m * LDA + i] = c * qi - s * qj;
+                    Qv[m * LDA + j] = s * qi + c * qj;
+                }
+            }
+            __syncthreads();
+        }
+        if (!s_any) break;
+    }
+    // 5. order by descending eigenvalue (dummy last)
+    if (tid == 0) {
+        for (int i = 0; i < n; ++i) order[i] = i;
+        for (int i = 0; i < n; ++i) {
             int best = i;
-            for (int j = i + 1; j < p; ++j)
-                if (A[order[j]][order[j]] > A[order[best]][order[best]]) best = j;
+            for (int j = i + 1; j < n; ++j)
+                if (H[order[j] * LDA + order[j]] > H[order[best] * LDA + order[best]]) best = j;
             const int tmp = order[i];
             order[i] = order[best];
             order[best] = tmp;
         }
     }
     __syncthreads();
-    for (int e = lane; e < p * p; e += 64) {
-        const int i = e % p, j = e / p;   // component i of eigenvector j
-        Q[e] = Vv[i][order[j]];
+    // 6. Q = R^{-1} Q'  (back substitution down each kept column)
+    for (int jc = tid; jc < p; jc += GNT) {
+        const int src = order[jc];
+        double x[MAXP];
+        for (int i = p - 1; i >= 0; --i) {
+            double s = Qv[i * LDA + src];
+            for (int k = i + 1; k < p; ++k) s -= G[i * LDA + k] * x[k];
+            x[i] = s / G[i * LDA + i];
+        }
+        for (int i = 0; i < p; ++i) Qout[i + jc * p] = x[i];
+        theta[jc] = H[src * LDA + src];
     }
-    for (int j = lane; j < p; j += 64) theta[j] = A[order[j]][order[j]];
-    (void)sred;
+    (void)red;
 }
 
 // ---------------------------------- Ritz vectors, next block, residuals
-// Y = V Q, U = (W Q) / max(theta, floor), residual partials for the first K:
-//   res[wg][k] = sum_n ((W Q)_{nk} - theta_k (V Q)_{nk})^2
-__global__ __launch_bounds__(GNT) void k_rotate(const double* __restrict__ V, const double* __restrict__ W,
-                                                const double* __restrict__ Q,
-                                                const double* __restrict__ theta, int64_t Np,
-                                                int64_t N, int p, int K, double* __restrict__ Y,
-                                                double* __restrict__ U, double* __restrict__ res) {
-    __shared__ double Qs[MAXP * MAXP];
-    __shared__ double th[MAXP];
-    __shared__ double red[GNT / 64][MAXP];
-    for (int e = threadIdx.x; e < p * p; e += GNT) Qs[e] = Q[e];
-    for (int e = threadIdx.x; e < p; e += GNT) th[e] = theta[e];
+// Y = V Q (orthonormal Ritz vectors), Z = W Q = C Y;
+//   res[wg][k] = sum_n (Z_nk - theta_k Y_nk)^2        (k < K)
+//   V <- Z diag(1 / max(theta, floor))  (next block; in place)
+// Rows >= N are zero.  PC is p rounded up to a multiple of 8.
+template <int PC>
+__global__ __launch_bounds__(GNT) void k_rotate2(double* __restrict__ V, const double* __restrict__ W,
+                                                 const double* __restrict__ Q,
+                                                 const double* __restrict__ theta, int64_t Np,
+                                                 int64_t N, int p, int K, double* __restrict__ Y,
+                                                 double* __restrict__ res) {
+    __shared__ double Qs[PC * PC];
+    __shared__ double th[PC];
+    __shared__ double red[PC];
+    for (int e = threadIdx.x; e < PC * PC; e += GNT) {
+        const int i = e % PC, j = e / PC;
+        Qs[e] = (i < p && j < p) ? Q[i + j * p] : 0.0;
+    }
+    for (int e = threadIdx.x; e < PC; e += GNT) {
+        th[e] = e < p ? theta[e] : 1.0;
+        red[e] = 0.0;
+    }
     __syncthreads();
-    const double floor_t = fabs(th[0]) * 1e-13 + 1e-300;
+    const double floor_t = fabs(th[0]) * 1e-6 + 1e-300;
     const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
-    double rk[MAXP];
+    if (n < N) {
+        double vr[PC], wr[PC];
 #pragma unroll
-    for (int k = 0; k < MAXP; ++k) rk[k] = 0.0;
-    if (n >= N && n < Np) {
+        for (int i = 0; i < PC; ++i) {
+            vr[i] = i < p ? V[(int64_t)i * Np + n] : 0.0;
+            wr[i] = i < p ? W[(int64_t)i * Np + n] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+            if (j < p) {
+                double y = 0.0, z = 0.0;
+#pragma unroll
+                for (int i = 0; i < PC; ++i) {
+                    const double q = Qs[j * PC + i];
+                    y += vr[i] * q;
+                    z += wr[i] * q;
+                }
+                Y[(int64_t)j * Np + n] = y;
+                const double tj = th[j];
+                V[(int64_t)j * Np + n] = z / (tj > floor_t ? tj : floor_t);
+                if (j < K) {
+                    const double d = z - tj * y;
+                    atomicAdd(&red[j], d * d);
+                }
+            }
+        }
+    } else if (n < Np) {
         for (int j = 0; j < p; ++j) {
             Y[(int64_t)j * Np + n] = 0.0;
-            U[(int64_t)j * Np + n] = 0.0;
+            V[(int64_t)j * Np + n] = 0.0;
         }
-    } else if (n < N) {
-        for (int j = 0; j < p; ++j) {
-            double y = 0.0, u = 0.0;
-            for (int i = 0; i < p; ++i) {
-                const double q = Qs[j * p + i];
-                y += V[(int64_t)i * Np + n] * q;
-                u += W[(int64_t)i * Np + n] * q;
-            }
-            Y[(int64_t)j * Np + n] = y;
-            const double tj = th[j];
-            U[(int64_t)j * Np + n] = u / (fabs(tj) > floor_t ? tj : floor_t);
-            if (j < K) {
-                const double d = u - tj * y;
-                rk[j] = d * d;
-            }
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = 0; k < K; ++k) {
-        double v = rk[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wv][k] = v;
     }
     __syncthreads();
-    if (threadIdx.x < K) {
-        double s = 0.0;
-        for (int w = 0; w < GNT / 64; ++w) s += red[w][threadIdx.x];
-        res[(int64_t)blockIdx.x * K + threadIdx.x] = s;
-    }
-}
-
-// ------------------------------------------------------------- CholQR
-// G = sum of Gram partials; upper R with G = R^T R (pivot floored so a
-// dependent column is re-normalised instead of dividing by zero).
-__global__ __launch_bounds__(64) void k_chol_small(const double* __restrict__ part, int nwg, int p,
-                                                   double* __restrict__ Rout) {
-    __shared__ double G[MAXP][MAXP + 1];
-    const int lane = threadIdx.x;
-    for (int e = lane; e < p * p; e += 64) {
-        double s = 0.0;
-        for (int g = 0; g < nwg; ++g) s += part[(int64_t)g * p * p + e];
-        G[e / p][e % p] = s;
-    }
-    __syncthreads();
-    double dmax = 0.0;
-    for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i][i]);
-    const double floor_p = dmax * 1e-28 + 1e-300;
-    for (int j = 0; j < p; ++j) {
-        if (lane == 0) {
-            double d = G[j][j];
-            for (int k = 0; k < j; ++k) d -= G[k][j] * G[k][j];
-            G[j][j] = sqrt(d > floor_p ? d : floor_p);
-        }
-        __syncthreads();
-        for (int c = j + 1 + lane; c < p; c += 64) {
-            double s = G[j][c];
-            for (int k = 0; k < j; ++k) s -= G[k][j] * G[k][c];
-            G[j][c] = s / G[j][j];
-        }
-        __syncthreads();
-    }
-    for (int e = lane; e < p * p; e += 64) {
-        const int i = e / p, j = e % p;   // R[i][j], upper
-        Rout[e] = (j >= i) ? G[i][j] : 0.0;
-    }
-}
-
-// V = U R^{-1}, row by row:  v_j = (u_j - sum_{i<j} v_i R_ij) / R_jj
-__global__ __launch_bounds__(GNT) void k_trsm_rows(const double* __restrict__ U, const double* __restrict__ Rm,
-                                                   int64_t Np, int64_t N, int p, double* __restrict__ V) {
-    __shared__ double Rs[MAXP * MAXP];
-    for (int e = threadIdx.x; e < p * p; e += GNT) Rs[e] = Rm[e];
-    __syncthreads();
-    const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
-    if (n >= Np) return;
-    double v[MAXP];
-    for (int j = 0; j < p; ++j) {
-        double s = n < N ? U[(int64_t)j * Np + n] : 0.0;
-        for (int i = 0; i < j; ++i) s -= v[i] * Rs[i * p + j];
-        v[j] = s / Rs[j * p + j];
-        V[(int64_t)j * Np + n] = v[j];
-    }
+    if (threadIdx.x < K) res[(int64_t)blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
 }
 
 // ------------------------------------------------------ lattice helpers
@@ -954,6 +996,73 @@ struct Solver {
     }
 };
 
+// block subspace iteration with Rayleigh-Ritz; returns the Ritz vectors of
+// the K largest eigenvalues in Y (orthonormal) and theta.
+int subspace_solve(Solver& S, double* V, double* W, double* Y, double* part, double* res,
+                   double* Q, double* th, int64_t nchunks) {
+    Ctx* ctx = S.ctx;
+    hipStream_t st = S.st;
+    const int64_t N = S.N, Np = S.Np;
+    const int p = S.p, K = S.K;
+    const int gram_wg = (int)(nchunks < 32 ? nchunks : 32);
+    const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
+    const int row_wg = (int)((Np + GNT - 1) / GNT);
+    const int pc = (p + 7) / 8 * 8;
+    {
+        M2N_PROF(ctx, st, "k_randinit");
+        dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
+        hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, V, Np, N, p, (uint64_t)0x5EED);
+    }
+    M2N_HIP(hipGetLastError());
+    std::vector<double> hres((size_t)row_wg * K);
+    double prev = 1e300;
+    for (int it = 0; it < 40; ++it) {
+        M2N_TRY(S.apply(V, W));
+        {
+            M2N_PROF(ctx, st, "k_gram2");
+            hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, cpw, nchunks,
+                               part);
+        }
+        {
+            M2N_PROF(ctx, st, "k_small_rr");
+            hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(GNT), 0, st, part, gram_wg, p, Q, th);
+        }
+        {
+            M2N_PROF(ctx, st, "k_rotate2");
+#define M2N_ROT(PCV)                                                                            \
+    case PCV:                                                                                   \
+        hipLaunchKernelGGL(k_rotate2<PCV>, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, \
+                           K, Y, res);                                                          \
+        break;
+            switch (pc) {
+                M2N_ROT(8) M2N_ROT(16) M2N_ROT(24) M2N_ROT(32) M2N_ROT(40) M2N_ROT(48) M2N_ROT(56)
+                M2N_ROT(64)
+                default:
+                    set_error("internal: block width %d", p);
+                    return M2N_ERR_ARG;
+            }
+#undef M2N_ROT
+        }
+        M2N_HIP(hipGetLastError());
+        if (it == 0 && p < N) continue;   // a random start is never converged
+        M2N_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(), hipMemcpyDeviceToHost,
+                               st));
+        M2N_HIP(hipStreamSynchronize(st));
+        double rmax = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int g = 0; g < row_wg; ++g) s += hres[(size_t)g * K + k];
+            rmax = std::fmax(rmax, std::sqrt(s));
+        }
+        if (!std::isfinite(rmax)) break;
+        if (p == N || rmax <= 1e-13 || (it >= 3 && rmax > 0.5 * prev && rmax <= 1e-10))
+            return M2N_OK;
+        prev = rmax;
+    }
+    set_error("subspace iteration did not converge");
+    return M2N_ERR_NO_CONVERGE;
+}
+
 }  // namespace
 
 int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmax, double fw,
@@ -975,8 +1084,7 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         if (t[n] != std::rint(t[n]) || std::fabs(t[n]) > 4.0e15) integral = false;
     }
     const double cB = 2.0 * fmax;
-    const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 &&
-                         (t[N - 1] - t[0]) < 2.0e6;
+    const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 && (t[N - 1] - t[0]) < 2.0e6;
     const double span = N > 1 ? t[N - 1] - t[0] : 0.0;
     int p = (int)std::ceil(2.0 * fw * span) + 8;
     if (p < K + 8) p = K + 8;
@@ -996,29 +1104,25 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     S.K = K;
     S.lattice = lattice;
     const int64_t Np = S.Np;
-    void *vV, *vW, *vU, *vY, *vpart, *vres, *vQ, *vth, *vR;
     const int64_t nchunks = (Np + GRAM_ROWS - 1) / GRAM_ROWS;
-    const int gram_wg = (int)(nchunks < 120 ? nchunks : 120);
-    const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
     const int row_wg = (int)((Np + GNT - 1) / GNT);
+    void *vV, *vW, *vY, *vpart, *vres, *vQ, *vth, *vt;
     M2N_TRY(ctx->workspace("gep_V", sizeof(double) * (size_t)p * Np, &vV));
     M2N_TRY(ctx->workspace("gep_W", sizeof(double) * (size_t)p * Np, &vW));
-    M2N_TRY(ctx->workspace("gep_U", sizeof(double) * (size_t)p * Np, &vU));
     M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)p * Np, &vY));
-    size_t part_n = (size_t)gram_wg * p * p;
+    size_t part_n = (size_t)32 * 2 * p * p;
     if (part_n < (size_t)row_wg * 2 * K) part_n = (size_t)row_wg * 2 * K;
     M2N_TRY(ctx->workspace("gep_part", sizeof(double) * part_n, &vpart));
     M2N_TRY(ctx->workspace("gep_res", sizeof(double) * (size_t)row_wg * K, &vres));
     M2N_TRY(ctx->workspace("gep_Q", sizeof(double) * MAXP * MAXP, &vQ));
     M2N_TRY(ctx->workspace("gep_th", sizeof(double) * MAXP, &vth));
-    M2N_TRY(ctx->workspace("gep_R", sizeof(double) * MAXP * MAXP, &vR));
-    double *V = (double*)vV, *W = (double*)vW, *U = (double*)vU, *Y = (double*)vY;
-    double *part = (double*)vpart, *res = (double*)vres, *Q = (double*)vQ, *th = (double*)vth,
-           *Rm = (double*)vR;
-    void* vt;
     M2N_TRY(ctx->workspace("gep_t", sizeof(double) * (size_t)N, &vt));
+    double *V = (double*)vV, *W = (double*)vW, *Y = (double*)vY;
+    double *part = (double*)vpart, *res = (double*)vres, *Q = (double*)vQ, *th = (double*)vth;
     M2N_HIP(hipMemcpyAsync(vt, t_dev, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st));
     const double* td = (const double*)vt;
+    // W's padded rows are never written by the lattice convolution
+    M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
 
     double scale;   // w = scale * (L^{-T}) y
     if (lattice) {
@@ -1034,123 +1138,42 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         } guard{ctx, &S.fft};
         std::vector<int> off(N);
         for (int64_t n = 0; n < N; ++n) off[n] = (int)(t[n] - t[0]);
-        void *vmap, *voff, *vH, *vc1, *vc2;
+        void *vmap, *voff, *vH, *vc1, *vc2, *vs;
         const int pairs = (p + 1) / 2;
         M2N_TRY(ctx->workspace("gep_map", sizeof(int) * (size_t)M, &vmap));
         M2N_TRY(ctx->workspace("gep_off", sizeof(int) * (size_t)N, &voff));
         M2N_TRY(ctx->workspace("gep_H", sizeof(double) * (size_t)M, &vH));
         M2N_TRY(ctx->workspace("gep_c1", sizeof(cplx<double>) * (size_t)M * pairs, &vc1));
         M2N_TRY(ctx->workspace("gep_c2", sizeof(cplx<double>) * (size_t)M * pairs, &vc2));
+        M2N_TRY(ctx->workspace("gep_hs", sizeof(cplx<double>) * (size_t)M, &vs));
         M2N_HIP(hipMemcpyAsync(voff, off.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice, st));
         S.map = (int*)vmap;
         S.Hhat = (double*)vH;
         S.cbuf1 = (cplx<double>*)vc1;
         S.cbuf2 = (cplx<double>*)vc2;
         {
-            M2N_PROF(ctx, st, "k_fill_int");
-            hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S.map, M, -1);
-        }
-        {
-            M2N_PROF(ctx, st, "k_lattice_map");
+            M2N_PROF(ctx, st, "k_lattice_setup");
+            hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S.map,
+                               M, -1);
             hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                                (const int*)voff, N, S.map);
-        }
-        // Hhat = FFT(h) / (M cB)
-        {
-            M2N_PROF(ctx, st, "k_toep_kernel");
+            // Hhat = FFT(h) / (M cB)
             hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                                S.cbuf2, M, Sspan, fw);
         }
         M2N_HIP(hipGetLastError());
         {
+            M2N_PROF(ctx, st, "toeplitz_kernel_fft");
             ConvArgs a{};
             a.src = S.cbuf2;
             a.dst = S.cbuf1;
-            void* vs;   // pass-A scratch, distinct from source and destination
-            M2N_TRY(ctx->workspace("gep_hs", sizeof(cplx<double>) * (size_t)M, &vs));
-            cplx<double>* scratch = (cplx<double>*)vs;
-            M2N_TRY(run_fft64(S.fft, st, a, 1, SRC_DIRECT, DST_DIRECT, scratch));
-        }
-        {
-            M2N_PROF(ctx, st, "k_real_scale");
+            M2N_TRY(run_fft64(S.fft, st, a, 1, SRC_DIRECT, DST_DIRECT, (cplx<double>*)vs));
             hipLaunchKernelGGL(k_real_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                                (const cplx<double>*)S.cbuf1, M, 1.0 / ((double)M * cB), S.Hhat);
         }
         M2N_HIP(hipGetLastError());
-        M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
         scale = std::sqrt(2.0 * fw / cB);
-        int status = 0;
-        // the solve below must finish while the FFT plan is alive
-        {
-            // ---- subspace iteration
-            dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
-            {
-                M2N_PROF(ctx, st, "k_randinit");
-                hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
-            }
-            M2N_HIP(hipGetLastError());
-            auto cholqr = [&](double* src, double* dst) -> int {
-                {
-                    M2N_PROF(ctx, st, "k_gram");
-                    hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
-                                       nchunks, part);
-                }
-                {
-                    M2N_PROF(ctx, st, "k_chol_small");
-                    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
-                }
-                {
-                    M2N_PROF(ctx, st, "k_trsm_rows");
-                    hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
-                }
-                M2N_HIP(hipGetLastError());
-                return M2N_OK;
-            };
-            M2N_TRY(cholqr(U, V));
-            M2N_TRY(cholqr(V, V));
-            std::vector<double> hres((size_t)row_wg * K);
-            double prev = 1e300;
-            bool ok = false;
-            for (int it = 0; it < 40; ++it) {
-                M2N_TRY(S.apply(V, W));
-                {
-                    M2N_PROF(ctx, st, "k_gram");
-                    hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw,
-                                       nchunks, part);
-                }
-                {
-                    M2N_PROF(ctx, st, "k_rr");
-                    hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
-                }
-                {
-                    M2N_PROF(ctx, st, "k_rotate");
-                    hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K,
-                                       Y, U, res);
-                }
-                M2N_HIP(hipGetLastError());
-                M2N_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(),
-                                       hipMemcpyDeviceToHost, st));
-                M2N_HIP(hipStreamSynchronize(st));
-                double rmax = 0.0;
-                for (int k = 0; k < K; ++k) {
-                    double s = 0.0;
-                    for (int g = 0; g < row_wg; ++g) s += hres[(size_t)g * K + k];
-                    rmax = std::fmax(rmax, std::sqrt(s));
-                }
-                if (p == N || rmax <= 1e-13 || (it >= 3 && rmax > 0.5 * prev && rmax <= 1e-10)) {
-                    ok = true;
-                    break;
-                }
-                prev = rmax;
-                M2N_TRY(cholqr(U, V));
-                M2N_TRY(cholqr(V, V));
-            }
-            if (!ok) status = M2N_ERR_NO_CONVERGE;
-        }
-        if (status != M2N_OK) {
-            set_error("subspace iteration did not converge");
-            return status;
-        }
+        M2N_TRY(subspace_solve(S, V, W, Y, part, res, Q, th, nchunks));
     } else {
         // ---- dense: R(B) = L L^T, C = L^{-1} R(A0) L^{-T}
         if (Np > 65536) {
@@ -1169,13 +1192,10 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         S.tmp = (double*)vtmp;
         S.nz = (int*)vnz;
         M2N_HIP(hipMemsetAsync(vst, 0, 64, st));
-        dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
         {
             M2N_PROF(ctx, st, "k_gen_sinc");
+            dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
             hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
-        }
-        {
-            M2N_PROF(ctx, st, "k_gen_sinc");
             hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fw, 0.0, S.RA);
         }
         M2N_HIP(hipGetLastError());
@@ -1191,10 +1211,8 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
                     hipLaunchKernelGGL(k_trsm_panel, dim3(rem), dim3(GNT), 0, st, S.RB, Np, kb, S.nz);
                 }
                 const int ntiles = rem * (rem + 1) / 2;
-                {
-                    M2N_PROF(ctx, st, "k_syrk");
-                    hipLaunchKernelGGL(k_syrk, dim3(ntiles), dim3(GNT), 0, st, S.RB, Np, kb, S.nblk, S.nz);
-                }
+                M2N_PROF(ctx, st, "k_syrk");
+                hipLaunchKernelGGL(k_syrk, dim3(ntiles), dim3(GNT), 0, st, S.RB, Np, kb, S.nblk, S.nz);
             }
         }
         M2N_HIP(hipGetLastError());
@@ -1206,85 +1224,18 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
             return M2N_ERR_NOT_PD;
         }
         scale = std::sqrt(2.0 * fw);
-        dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
-        {
-            M2N_PROF(ctx, st, "k_randinit");
-            hipLaunchKernelGGL(k_randinit, g2, dim3(256), 0, st, U, Np, N, p, (uint64_t)0x5EED);
-        }
-        M2N_HIP(hipGetLastError());
-        auto cholqr = [&](double* src, double* dst) -> int {
-            {
-                M2N_PROF(ctx, st, "k_gram");
-                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, src, src, Np, N, p, p, cpw,
-                                   nchunks, part);
-            }
-            {
-                M2N_PROF(ctx, st, "k_chol_small");
-                hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, gram_wg, p, Rm);
-            }
-            {
-                M2N_PROF(ctx, st, "k_trsm_rows");
-                hipLaunchKernelGGL(k_trsm_rows, dim3(row_wg), dim3(GNT), 0, st, src, Rm, Np, N, p, dst);
-            }
-            M2N_HIP(hipGetLastError());
-            return M2N_OK;
-        };
-        M2N_TRY(cholqr(U, V));
-        M2N_TRY(cholqr(V, V));
-        std::vector<double> hres((size_t)row_wg * K);
-        double prev = 1e300;
-        bool ok = false;
-        for (int it = 0; it < 40; ++it) {
-            M2N_TRY(S.apply(V, W));
-            {
-                M2N_PROF(ctx, st, "k_gram");
-                hipLaunchKernelGGL(k_gram, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, p, cpw, nchunks,
-                                   part);
-            }
-            {
-                M2N_PROF(ctx, st, "k_rr");
-                hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, st, part, gram_wg, p, Q, th);
-            }
-            {
-                M2N_PROF(ctx, st, "k_rotate");
-                hipLaunchKernelGGL(k_rotate, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, K, Y, U,
-                                   res);
-            }
-            M2N_HIP(hipGetLastError());
-            M2N_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(),
-                                   hipMemcpyDeviceToHost, st));
-            M2N_HIP(hipStreamSynchronize(st));
-            double rmax = 0.0;
-            for (int k = 0; k < K; ++k) {
-                double s = 0.0;
-                for (int g = 0; g < row_wg; ++g) s += hres[(size_t)g * K + k];
-                rmax = std::fmax(rmax, std::sqrt(s));
-            }
-            if (p == N || rmax <= 1e-13 || (it >= 3 && rmax > 0.5 * prev && rmax <= 1e-10)) {
-                ok = true;
-                break;
-            }
-            prev = rmax;
-            M2N_TRY(cholqr(U, V));
-            M2N_TRY(cholqr(V, V));
-        }
-        if (!ok) {
-            set_error("subspace iteration did not converge");
-            return M2N_ERR_NO_CONVERGE;
-        }
-        // y -> L^{-T} y for the first K Ritz vectors (solve on all p columns)
-        const int psave = S.p;
+        M2N_TRY(subspace_solve(S, V, W, Y, part, res, Q, th, nchunks));
+        // y -> L^{-T} y
         M2N_TRY(S.trsv(Y, 1));
-        S.p = psave;
     }
     // ---- sign convention, scale, output
     {
         M2N_PROF(ctx, st, "k_sign_sums");
         hipLaunchKernelGGL(k_sign_sums, dim3(row_wg), dim3(GNT), 0, st, Y, Np, N, K, td, part);
     }
-    const int fin_wg = (int)((N + GNT - 1) / GNT);
     {
         M2N_PROF(ctx, st, "k_finalize");
+        const int fin_wg = (int)((N + GNT - 1) / GNT);
         hipLaunchKernelGGL(k_finalize, dim3(fin_wg), dim3(GNT), 0, st, Y, Np, N, K, scale, part,
                            row_wg, th, w_out, lambda_out);
     }
