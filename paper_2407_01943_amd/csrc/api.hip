@@ -139,6 +139,11 @@ void m2n_destroy(m2n_ctx* ctx) {
         ctx->release(kv.second->tw_hi);
         ctx->release(kv.second->inv_phihat);
     }
+    for (auto& kv : ctx->fft64) {
+        ctx->release(kv.second->tw);
+        ctx->release(kv.second->tw_lo);
+        ctx->release(kv.second->tw_hi);
+    }
     for (auto& kv : ctx->ws) ctx->release(kv.second);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);

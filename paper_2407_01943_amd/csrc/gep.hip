@@ -67,13 +67,16 @@ __global__ void k_randinit(double* __restrict__ V, int64_t Np, int64_t N, int p,
     V[(int64_t)j * Np + n] = n < N ? hash_uniform(seed * 0x100000001B3ull + (uint64_t)j * (uint64_t)Np + (uint64_t)n) : 0.0;
 }
 
-// ------------------------------------------------------ Gram partials
-// One pass over the rows of this workgroup's chunks:
-//   part[wg][0 .. p*p)      = V^T V   (entry i * p + j)
-//   part[wg][p*p .. 2 p*p)  = V^T W
+// ------------------------------------------------------ Gram matrices
+// One pass over this workgroup's rows; the workgroup's contribution to
+//   acc[0 .. p*p)     += V^T V   (entry i * p + j)
+//   acc[p*p .. 2p*p)  += V^T W
+// is added with device-scope FP64 atomics (acc is zero on entry; the
+// consumer clears it).
 __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, const double* __restrict__ W,
                                                int64_t Np, int64_t nrows, int p, int nchunks_per_wg,
-                                               int64_t nchunks, double* __restrict__ part) {
+                                               int64_t nchunks, int nmat,
+                                               double* __restrict__ acc_out) {
     __shared__ double Vs[MAXP][GRAM_ROWS + 1];
     __shared__ double Ws[MAXP][GRAM_ROWS + 1];
     constexpr int PER = 2 * MAXP * MAXP / GNT;
@@ -88,13 +91,13 @@ __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, con
             const int i = e / GRAM_ROWS, r = e % GRAM_ROWS;
             const bool in = r0 + r < nrows;
             Vs[i][r] = in ? V[(int64_t)i * Np + r0 + r] : 0.0;
-            Ws[i][r] = in ? W[(int64_t)i * Np + r0 + r] : 0.0;
+            if (nmat > 1) Ws[i][r] = in ? W[(int64_t)i * Np + r0 + r] : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = threadIdx.x + e * GNT;
-            if (idx < 2 * np) {
+            if (idx < nmat * np) {
                 const int which = idx >= np, q = idx - which * np;
                 const int i = q / p, j = q % p;
                 const double* b = which ? Ws[j] : Vs[j];
@@ -108,231 +111,505 @@ __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, con
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int idx = threadIdx.x + e * GNT;
-        if (idx < 2 * np) part[(int64_t)blockIdx.x * 2 * np + idx] = acc[e];
+        if (idx < nmat * np) atomicAdd(&acc_out[idx], acc[e]);
     }
+}
+
+// ------------------------------------ top eigenpairs of a small symmetric
+// One wavefront (64 lanes, n <= 64).  On entry A (LDS, row stride LDA)
+// holds the symmetric matrix; on exit lam[0..K) are its K largest
+// eigenvalues in descending order and X[k][0..n) (stride LDA) the unit
+// eigenvectors.  Steps: Householder reduction to tridiagonal form (lane =
+// row), bisection on a division-free Sturm sequence (lane = eigenvalue),
+// inverse iteration with partial-pivoting tridiagonal solves (lane =
+// eigenvector) followed by modified Gram-Schmidt inside clusters of close
+// eigenvalues, and back-transformation by the stored reflectors.
+// move a double across lanes with a DPP pattern (both halves); lanes whose
+// source is out of range or whose row is masked off receive 0
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 64 lanes, returned to every lane: quad permutes, row shifts
+// and row broadcasts accumulate the total in lane 63, read back with
+// readlane (cheaper than a ds_bpermute butterfly)
+__device__ __forceinline__ double wsum(double v) {
+    v += dpp_d<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_d<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_d<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// reference butterfly sum (used to check the DPP pattern)
+__device__ __forceinline__ double wsum_shfl(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wmin(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// number of eigenvalues of the tridiagonal (d, e^2) below sigma: sign
+// changes of p_i = (d_i - sigma) p_{i-1} - e_{i-1}^2 p_{i-2}, kept in range
+// by exact power-of-two rescaling
+__device__ __forceinline__ int sturm_below(const double* dr, const double* e2r, int n, double sigma) {
+    double pp = 1.0, pc = dr[0] - sigma;
+    if (pc == 0.0) pc = -1e-300;
+    int cnt = pc < 0.0 ? 1 : 0;
+#pragma unroll
+    for (int i = 1; i < MAXP; ++i) {
+        if (i < n) {
+            double pn = (dr[i] - sigma) * pc - e2r[i - 1] * pp;
+            if (pn == 0.0) pn = pc > 0.0 ? -1e-300 : 1e-300;
+            cnt += ((pn < 0.0) != (pc < 0.0)) ? 1 : 0;
+            if ((i & 3) == 0) {
+                const double m = fmax(fabs(pn), fabs(pc));
+                if (m > 0x1p+400) {
+                    pn *= 0x1p-400;
+                    pc *= 0x1p-400;
+                } else if (m < 0x1p-400) {
+                    pn *= 0x1p+400;
+                    pc *= 0x1p+400;
+                }
+            }
+            pp = pc;
+            pc = pn;
+        }
+    }
+    return cnt;
+}
+
+template <int LDA>
+__device__ void sym_topk_wave(double (*A)[LDA], int n, int K, double (*Vh)[LDA], double* Bh,
+                              double* d, double* e, double* e2, double* lam,
+                              double (*X)[LDA], double* tmp, long long* stamp = nullptr) {
+    const int lane = threadIdx.x;
+    const double eps = 2.220446049250313e-16;
+    if (stamp && lane == 0) stamp[0] = clock64();
+    // 1. tridiagonalise: A <- H_k A H_k, H_k = I - beta_k v_k v_k^T (lane = row)
+    for (int k = 0; k + 2 < n; ++k) {
+        const double xi = (lane > k && lane < n) ? A[lane][k] : 0.0;
+        const double nx2 = wsum(xi * xi);
+        double beta = 0.0, vi = 0.0;
+        if (nx2 > 0.0) {
+            const double x0 = A[k + 1][k];
+            const double alpha = x0 >= 0.0 ? -sqrt(nx2) : sqrt(nx2);
+            vi = xi - (lane == k + 1 ? alpha : 0.0);
+            // |v|^2 = |x|^2 - x0^2 + (x0 - alpha)^2 = 2 |x|^2 - 2 x0 alpha
+            beta = 1.0 / (nx2 - x0 * alpha);
+            if (lane == 0) e[k] = alpha;
+        } else if (lane == 0) {
+            e[k] = 0.0;
+        }
+        if (lane < n) {
+            Vh[k][lane] = vi;
+            tmp[lane] = vi;
+        }
+        if (lane == 0) Bh[k] = beta;
+        __syncthreads();
+        if (beta != 0.0) {
+            double pi = 0.0;
+            if (lane > k && lane < n) {
+                const double* __restrict__ Ai = A[lane];
+                const double* __restrict__ vt = tmp;
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+                int j = k + 1;
+                for (; j + 3 < n; j += 4) {
+                    p0 += Ai[j] * vt[j];
+                    p1 += Ai[j + 1] * vt[j + 1];
+                    p2 += Ai[j + 2] * vt[j + 2];
+                    p3 += Ai[j + 3] * vt[j + 3];
+                }
+                for (; j < n; ++j) p0 += Ai[j] * vt[j];
+                pi = beta * ((p0 + p1) + (p2 + p3));
+            }
+            const double kc = 0.5 * beta * wsum(vi * pi);
+            const double wi = pi - kc * vi;
+            if (lane < n) tmp[MAXP + lane] = wi;
+            __syncthreads();
+            if (lane > k && lane < n) {
+                double* __restrict__ Ai = A[lane];
+                const double* __restrict__ vt = tmp;
+                const double* __restrict__ wt = tmp + MAXP;
+                int j = k + 1;
+                for (; j + 3 < n; j += 4) {
+                    const double a0 = Ai[j], a1 = Ai[j + 1], a2 = Ai[j + 2], a3 = Ai[j + 3];
+                    Ai[j] = a0 - (vi * wt[j] + wi * vt[j]);
+                    Ai[j + 1] = a1 - (vi * wt[j + 1] + wi * vt[j + 1]);
+                    Ai[j + 2] = a2 - (vi * wt[j + 2] + wi * vt[j + 2]);
+                    Ai[j + 3] = a3 - (vi * wt[j + 3] + wi * vt[j + 3]);
+                }
+                for (; j < n; ++j) Ai[j] -= vi * wt[j] + wi * vt[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (lane < n) d[lane] = A[lane][lane];
+    if (lane == 0 && n >= 2) e[n - 2] = A[n - 1][n - 2];
+    __syncthreads();
+    if (lane + 1 < n) e2[lane] = e[lane] * e[lane];
+    double glo = 1e300, ghi = -1e300;
+    if (lane < n) {
+        const double r = (lane > 0 ? fabs(e[lane - 1]) : 0.0) + (lane + 1 < n ? fabs(e[lane]) : 0.0);
+        glo = d[lane] - r;
+        ghi = d[lane] + r;
+    }
+    glo = wmin(glo);
+    ghi = wmax(ghi);
+    const double tnorm = fmax(fmax(fabs(glo), fabs(ghi)), 1e-300);
+    double* lo = tmp;              // [K]
+    double* hi = tmp + MAXP;       // [K]
+    double* sig = X[0];            // [64] samples
+    double* cntd = X[1];           // [64] counts (as doubles)
+    if (lane < K) {
+        lo[lane] = glo;
+        hi[lane] = ghi;
+    }
+    __syncthreads();
+    if (stamp && lane == 0) stamp[1] = clock64();
+    // 2. multisection: g lanes per wanted eigenvalue sample its interval
+    double dr[MAXP], e2r[MAXP];
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+        dr[i] = i < n ? d[i] : 0.0;
+        e2r[i] = i + 1 < n ? e2[i] : 0.0;
+    }
+    const int g = K < 64 ? 64 / K : 1;
+    const int grp = lane / g, sub = lane % g;
+    for (int round = 0; round < 80; ++round) {
+        int done = 1;
+        if (grp < K) {
+            const double l = lo[grp], h = hi[grp];
+            done = (h - l) <= 1e-14 * tnorm ? 1 : 0;
+            const double s = l + (double)(sub + 1) * (h - l) / (double)(g + 1);
+            sig[lane] = s;
+            cntd[lane] = (double)sturm_below(dr, e2r, n, s);
+        }
+        if (__all(done)) break;
+        __syncthreads();
+        if (grp < K && sub == 0) {
+            const int idx = n - 1 - grp;
+            double nl = lo[grp], nh = hi[grp];
+            for (int s2 = 0; s2 < g; ++s2) {
+                const double sv = sig[grp * g + s2];
+                if ((int)cntd[grp * g + s2] > idx) nh = fmin(nh, sv);
+                else nl = fmax(nl, sv);
+            }
+            lo[grp] = nl;
+            hi[grp] = nh;
+        }
+        __syncthreads();
+    }
+    if (lane < K) lam[lane] = 0.5 * (lo[lane] + hi[lane]);
+    __syncthreads();
+    if (stamp && lane == 0) stamp[2] = clock64();
+    // 3. inverse iteration in batches of 16 eigenvectors (lane = eigenvector);
+    //    the LU rows of T - lam I live in A's storage, [i][lane]
+    double* U1 = &A[0][0];
+    double* U2 = U1 + 16 * MAXP;
+    double* U3 = U2 + 16 * MAXP;
+    double* Bv = U3 + 16 * MAXP;
+    for (int kb = 0; kb < K; kb += 16) {
+        const int kk = kb + lane;
+        const bool mine = lane < 16 && kk < K;
+        for (int it = 0; it < 3; ++it) {
+            if (mine) {
+                double sh = lam[kk];
+                for (int j = 0; j < kk; ++j)
+                    if (fabs(sh - lam[j]) < 10.0 * eps * tnorm) sh = lam[j] - 10.0 * eps * tnorm * (kk - j);
+                // forward elimination with partial pivoting; the current row
+                // (c1, c2, c3) and right-hand side cb are carried in registers
+                double c1 = d[0] - sh, c2 = n > 1 ? e[0] : 0.0, c3 = 0.0;
+                double cb = it == 0 ? 1.0 + 0.3 * sin(0.9 * kk) : X[kk][0];
+                for (int i = 0; i + 1 < n; ++i) {
+                    const double sub = e[i];
+                    const double nd = d[i + 1] - sh, ne = (i + 2 < n) ? e[i + 1] : 0.0;
+                    const double nb = it == 0 ? 1.0 + 0.3 * sin(1.7 * (i + 1) + 0.9 * kk) : X[kk][i + 1];
+                    double r1, r2, r3, rb, m1, m2, mb;
+                    if (fabs(sub) > fabs(c1)) {
+                        const double mult = c1 / sub;
+                        r1 = sub; r2 = nd; r3 = ne; rb = nb;
+                        m1 = c2 - mult * nd; m2 = c3 - mult * ne; mb = cb - mult * nb;
+                    } else {
+                        const double piv = c1 != 0.0 ? c1 : eps * tnorm;
+                        const double mult = sub / piv;
+                        r1 = piv; r2 = c2; r3 = c3; rb = cb;
+                        m1 = nd - mult * c2; m2 = ne - mult * c3; mb = nb - mult * cb;
+                    }
+                    U1[i * 16 + lane] = r1;
+                    U2[i * 16 + lane] = r2;
+                    U3[i * 16 + lane] = r3;
+                    Bv[i * 16 + lane] = rb;
+                    c1 = m1; c2 = m2; c3 = 0.0; cb = mb;
+                    (void)m2;
+                    c2 = m2;
+                }
+                U1[(n - 1) * 16 + lane] = c1 != 0.0 ? c1 : eps * tnorm;
+                U2[(n - 1) * 16 + lane] = 0.0;
+                U3[(n - 1) * 16 + lane] = 0.0;
+                Bv[(n - 1) * 16 + lane] = cb;
+                double x1 = 0.0, x2 = 0.0;
+                for (int i = n - 1; i >= 0; --i) {
+                    const double piv = U1[i * 16 + lane];
+                    const double v = (Bv[i * 16 + lane] - U2[i * 16 + lane] * x1 - U3[i * 16 + lane] * x2) /
+                                     (piv != 0.0 ? piv : eps * tnorm);
+                    X[kk][i] = v;
+                    x2 = x1;
+                    x1 = v;
+                }
+            }
+            __syncthreads();
+            // normalise and orthogonalise this batch against earlier close vectors
+            for (int k = kb; k < kb + 16 && k < K; ++k) {
+                double xk = lane < n ? X[k][lane] : 0.0;
+                for (int j = 0; j < k; ++j)
+                    if (fabs(lam[j] - lam[k]) < 1e-3 * tnorm) {
+                        const double xj = lane < n ? X[j][lane] : 0.0;
+                        xk -= wsum(xj * xk) * xj;
+                    }
+                const double nrm = sqrt(wsum(xk * xk));
+                xk = nrm > 0.0 ? xk / nrm : 0.0;
+                if (lane < n) X[k][lane] = xk;
+                __syncthreads();
+            }
+        }
+    }
+    // eigenvalue = Rayleigh quotient of the tridiagonal on the final vector
+    for (int k = 0; k < K; ++k) {
+        double tx = 0.0, xi = 0.0;
+        if (lane < n) {
+            xi = X[k][lane];
+            tx = d[lane] * xi;
+            if (lane > 0) tx += e[lane - 1] * X[k][lane - 1];
+            if (lane + 1 < n) tx += e[lane] * X[k][lane + 1];
+        }
+        const double rq = wsum(xi * tx);
+        if (lane == 0) lam[k] = rq;
+    }
+    __syncthreads();
+    if (stamp && lane == 0) stamp[3] = clock64();
+    // 4. back-transform by the reflectors, last to first (lane = component)
+    for (int k = n - 3; k >= 0; --k) {
+        const double beta = Bh[k];
+        if (beta == 0.0) continue;
+        const double vi = lane < n ? Vh[k][lane] : 0.0;
+        for (int j0 = 0; j0 < K; j0 += 8) {
+            double xs[8], ps[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                xs[u] = (j0 + u < K && lane < n) ? X[j0 + u][lane] : 0.0;
+                ps[u] = vi * xs[u];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) ps[u] += __shfl_xor(ps[u], o, 64);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < K && lane < n) X[j0 + u][lane] = xs[u] - beta * ps[u] * vi;
+        }
+        __syncthreads();
+    }
+    if (stamp && lane == 0) stamp[4] = clock64();
+}
+
+// K largest eigenpairs of the symmetric q x q matrix scale * acc (row-major):
+// Z (column-major q x K, Z[i + k q] = component i of eigenvector k) and
+// theta, descending.  Clears acc.  One wavefront.
+__global__ __launch_bounds__(64) void k_sym_topk(double* __restrict__ acc, int q, double scale,
+                                                 int K, double* __restrict__ Zout,
+                                                 double* __restrict__ theta,
+                                                 long long* __restrict__ stamp) {
+    constexpr int LDA = MAXP + 1;
+    __shared__ double A[MAXP][LDA];
+    __shared__ double Vh[MAXP][LDA];
+    __shared__ double X[MAXP][LDA];
+    __shared__ double Bh[MAXP], d[MAXP], e[MAXP], e2[MAXP], lam[MAXP], tmp[2 * MAXP];
+    const int lane = threadIdx.x;
+    for (int e_ = lane; e_ < q * q; e_ += 64) {
+        const int i = e_ / q, j = e_ % q;
+        A[i][j] = 0.5 * scale * (acc[i * q + j] + acc[j * q + i]);
+    }
+    __syncthreads();
+    for (int e_ = lane; e_ < q * q; e_ += 64) acc[e_] = 0.0;
+    sym_topk_wave<LDA>(A, q, K, Vh, Bh, d, e, e2, lam, X, tmp, stamp);
+    for (int e_ = lane; e_ < q * K; e_ += 64) {
+        const int i = e_ % q, k = e_ / q;
+        Zout[e_] = X[k][i];
+    }
+    if (lane < K) theta[lane] = lam[lane];
 }
 
 // ------------------------------------- Rayleigh-Ritz on a general basis
 // With G = V^T V = R^T R (Cholesky) and H = V^T W (W = C V), the Ritz pairs
 // of C in span(V) are (theta, V Q) with Q = R^{-1} Q', where
 // R^{-T} H R^{-1} = Q' diag(theta) Q'^T.  Y = V Q has orthonormal columns.
-// The small symmetric eigenproblem is solved by parallel cyclic Jacobi:
-// each round rotates n/2 disjoint index pairs (round-robin schedule).
 // Output: Q (column-major, Q[i + j p] = component i of Ritz vector j) and
-// theta, both in descending order of theta.
-__global__ __launch_bounds__(GNT) void k_small_rr(const double* __restrict__ part, int nwg, int p,
-                                                  double* __restrict__ Qout,
-                                                  double* __restrict__ theta) {
+// theta, in descending order of theta.  Clears acc.  One wavefront.
+__global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p,
+                                                 double* __restrict__ Qout,
+                                                 double* __restrict__ theta) {
     constexpr int LDA = MAXP + 1;
-    __shared__ double G[MAXP * LDA];    // V^T V, then R (upper)
-    __shared__ double H[MAXP * LDA];    // V^T W, then R^{-T} H R^{-1}, then Jacobi
-    __shared__ double Qv[MAXP * LDA];   // Jacobi vectors
-    __shared__ double cs[MAXP / 2][2];
-    __shared__ int pr[MAXP / 2][2];
-    __shared__ int order[MAXP];
-    __shared__ double red[GNT / 64];
-    __shared__ int s_any;
+    __shared__ double G[MAXP][LDA];     // V^T V, then R (upper)
+    __shared__ double H[MAXP][LDA];     // V^T W, then R^{-T} H R^{-1}
+    __shared__ double Vh[MAXP][LDA];
+    __shared__ double X[MAXP][LDA];
+    __shared__ double Bh[MAXP], d[MAXP], e[MAXP], e2[MAXP], lam[MAXP], tmp[2 * MAXP];
     const int tid = threadIdx.x;
     const int np = p * p;
-    const int n = p + (p & 1);          // even size; a dummy index is decoupled
-    // 1. sum the partials
-    for (int e = tid; e < 2 * np; e += GNT) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int g = 0;
-        for (; g + 3 < nwg; g += 4) {
-            s0 += part[(int64_t)(g + 0) * 2 * np + e];
-            s1 += part[(int64_t)(g + 1) * 2 * np + e];
-            s2 += part[(int64_t)(g + 2) * 2 * np + e];
-            s3 += part[(int64_t)(g + 3) * 2 * np + e];
-        }
-        for (; g < nwg; ++g) s0 += part[(int64_t)g * 2 * np + e];
-        const double s = (s0 + s1) + (s2 + s3);
-        const int q = e % np, i = q / p, j = q % p;
-        if (e < np) G[i * LDA + j] = s;
-        else H[i * LDA + j] = s;
+    for (int e_ = tid; e_ < 2 * np; e_ += 64) {
+        const double s = acc[e_];
+        const int q = e_ % np, i = q / p, j = q % p;
+        if (e_ < np) G[i][j] = s;
+        else H[i][j] = s;
     }
     __syncthreads();
-    // symmetrise H
-    for (int e = tid; e < np; e += GNT) {
-        const int i = e / p, j = e % p;
-        if (i < j) {
-            const double m = 0.5 * (H[i * LDA + j] + H[j * LDA + i]);
-            H[i * LDA + j] = m;
-            H[j * LDA + i] = m;
-        }
-    }
-    // 2. Cholesky G = R^T R (R upper, in place), pivots floored
+    for (int e_ = tid; e_ < 2 * np; e_ += 64) acc[e_] = 0.0;
     double dmax = 0.0;
-    for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i * LDA + i]);
+    for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i][i]);
     const double pfloor = dmax * 1e-24 + 1e-300;
     for (int j = 0; j < p; ++j) {
         if (tid == 0) {
-            const double d = G[j * LDA + j];
-            G[j * LDA + j] = sqrt(d > pfloor ? d : pfloor);
+            const double dd = G[j][j];
+            G[j][j] = sqrt(dd > pfloor ? dd : pfloor);
         }
         __syncthreads();
-        const double rjj = G[j * LDA + j];
-        for (int c = j + 1 + tid; c < p; c += GNT) G[j * LDA + c] /= rjj;
+        const double rjj = G[j][j];
+        for (int c = j + 1 + tid; c < p; c += 64) G[j][c] /= rjj;
         __syncthreads();
         const int rem = p - j - 1;
-        for (int e = tid; e < rem * rem; e += GNT) {
-            const int a = j + 1 + e / rem, b = j + 1 + e % rem;
-            if (b >= a) G[a * LDA + b] -= G[j * LDA + a] * G[j * LDA + b];
+        for (int e_ = tid; e_ < rem * rem; e_ += 64) {
+            const int a = j + 1 + e_ / rem, b = j + 1 + e_ % rem;
+            if (b >= a) G[a][b] -= G[j][a] * G[j][b];
         }
         __syncthreads();
     }
-    // 3. H <- R^{-T} H  (forward substitution down each column)
-    for (int c = tid; c < p; c += GNT) {
+    for (int c = tid; c < p; c += 64) {   // H <- R^{-T} H
         for (int i = 0; i < p; ++i) {
-            double s = H[i * LDA + c];
-            for (int k = 0; k < i; ++k) s -= G[k * LDA + i] * H[k * LDA + c];
-            H[i * LDA + c] = s / G[i * LDA + i];
+            double s = H[i][c];
+            for (int k = 0; k < i; ++k) s -= G[k][i] * H[k][c];
+            H[i][c] = s / G[i][i];
         }
     }
     __syncthreads();
-    //    H <- H R^{-1}  (forward substitution along each row)
-    for (int r = tid; r < p; r += GNT) {
+    for (int r = tid; r < p; r += 64) {   // H <- H R^{-1}
         for (int j = 0; j < p; ++j) {
-            double s = H[r * LDA + j];
-            for (int k = 0; k < j; ++k) s -= H[r * LDA + k] * G[k * LDA + j];
-            H[r * LDA + j] = s / G[j * LDA + j];
+            double s = H[r][j];
+            for (int k = 0; k < j; ++k) s -= H[r][k] * G[k][j];
+            H[r][j] = s / G[j][j];
         }
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += GNT) {
-        const int i = e / n, j = e % n;
-        if (i < p && j < p) {
-            if (i < j) {
-                const double m = 0.5 * (H[i * LDA + j] + H[j * LDA + i]);
-                H[i * LDA + j] = m;
-                H[j * LDA + i] = m;
-            }
-        } else {
-            H[i * LDA + j] = (i == j) ? -1.0 : 0.0;   // dummy: decoupled, sorts last
-        }
-        Qv[i * LDA + j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // 4. parallel cyclic Jacobi
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) s_any = 0;
-        __syncthreads();
-        for (int r = 0; r < n - 1; ++r) {
-            if (tid < n / 2) {
-                int i, j;
-                if (tid == 0) {
-                    i = r;
-                    j = n - 1;
-                } else {
-                    i = (r + tid) % (n - 1);
-                    j = (r - tid + n - 1) % (n - 1);
-                }
-                if (i > j) {
-                    const int tmp = i;
-                    i = j;
-                    j = tmp;
-                }
-                const double aij = H[i * LDA + j], aii = H[i * LDA + i], ajj = H[j * LDA + j];
-                double c = 1.0, s = 0.0;
-                if (fabs(aij) > 1e-18 * sqrt(fabs(aii * ajj)) && fabs(aij) > 1e-300) {
-                    const double th = (ajj - aii) / (2.0 * aij);
-                    double t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
-                    if (th < 0.0) t = -t;
-                    c = 1.0 / sqrt(t * t + 1.0);
-                    s = t * c;
-                    s_any = 1;
-                }
-                pr[tid][0] = i;
-                pr[tid][1] = j;
-                cs[tid][0] = c;
-                cs[tid][1] = s;
-            }
-            __syncthreads();
-            // rows i, j of H  <- J^T H
-            for (int e = tid; e < (n / 2) * n; e += GNT) {
-                const int k = e / n, m = e % n;
-                const double s = cs[k][1];
-                if (s != 0.0) {
-                    const int i = pr[k][0], j = pr[k][1];
-                    const double c = cs[k][0];
-                    const double hi = H[i * LDA + m], hj = H[j * LDA + m];
-                    H[i * LDA + m] = c * hi - s * hj;
-                    H[j * LDA + m] = s * hi + c * hj;
-                }
-            }
-            __syncthreads();
-            // columns i, j of H and of Q  <- H J, Q J
-            for (int e = tid; e < (n / 2) * n; e += GNT) {
-                const int k = e / n, m = e % n;
-                const double s = cs[k][1];
-                if (s != 0.0) {
-                    const int i = pr[k][0], j = pr[k][1];
-                    const double c = cs[k][0];
-                    const double hi = H[m * LDA + i], hj = H[m * LDA + j];
-                    H[m * LDA + i] = c * hi - s * hj;
-                    H[m * LDA + j] = s * hi + c * hj;
-                    const double qi = Qv[m * LDA + i], qj = Qv[m * LDA + j];
-                    Qv[m * LDA + i] = c * qi - s * qj;
-                    Qv[m * LDA + j] = s * qi + c * qj;
-                }
-            }
-            __syncthreads();
-        }
-        if (!s_any) break;
-    }
-    // 5. order by descending eigenvalue (dummy last)
-    if (tid == 0) {
-        for (int i = 0; i < n; ++i) order[i] = i;
-        for (int i = 0; i < n; ++i) {
-            int best = i;
-            for (int j = i + 1; j < n; ++j)
-                if (H[order[j] * LDA + order[j]] > H[order[best] * LDA + order[best]]) best = j;
-            const int tmp = order[i];
-            order[i] = order[best];
-            order[best] = tmp;
+    for (int e_ = tid; e_ < np; e_ += 64) {
+        const int i = e_ / p, j = e_ % p;
+        if (i < j) {
+            const double m = 0.5 * (H[i][j] + H[j][i]);
+            H[i][j] = m;
+            H[j][i] = m;
         }
     }
     __syncthreads();
-    // 6. Q = R^{-1} Q'  (back substitution down each kept column)
-    for (int jc = tid; jc < p; jc += GNT) {
-        const int src = order[jc];
-        double x[MAXP];
+    sym_topk_wave<LDA>(H, p, p, Vh, Bh, d, e, e2, lam, X, tmp);
+    for (int jc = tid; jc < p; jc += 64) {   // Q = R^{-1} Q'
         for (int i = p - 1; i >= 0; --i) {
-            double s = Qv[i * LDA + src];
-            for (int k = i + 1; k < p; ++k) s -= G[i * LDA + k] * x[k];
-            x[i] = s / G[i * LDA + i];
+            double s = X[jc][i];
+            for (int k = i + 1; k < p; ++k) s -= G[i][k] * Qout[k + jc * p];
+            Qout[i + jc * p] = s / G[i][i];
         }
-        for (int i = 0; i < p; ++i) Qout[i + jc * p] = x[i];
-        theta[jc] = H[src * LDA + src];
+        theta[jc] = lam[jc];
     }
-    (void)red;
+}
+
+// ------------------------------------------- quadrature basis of R(A0)
+// R(A0)_{nm} = int_{-fw}^{fw} e^{j 2 pi f (t_n - t_m)} df.  With Gauss-Legendre
+// nodes +-f_q and weights w_q on [-fw, fw] (symmetric pairs), the imaginary
+// parts cancel and R(A0) = F F^T with the 2 columns per positive node
+//   F[2q][n] = sqrt(2 w_q) cos(2 pi f_q tau_n),
+//   F[2q+1][n] = sqrt(2 w_q) sin(2 pi f_q tau_n),   tau_n = t_n - t_c.
+// Rows n >= N are zero.  Column-major with leading dimension Np.
+__global__ void k_lr_basis(const double* __restrict__ t, int64_t N, int64_t Np, double tc,
+                           const double* __restrict__ fq, const double* __restrict__ sq, int nq,
+                           double* __restrict__ F) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (n >= Np || q >= nq) return;
+    double c = 0.0, s = 0.0;
+    if (n < N) {
+        sincospi(2.0 * fq[q] * (t[n] - tc), &s, &c);
+        c *= sq[q];
+        s *= sq[q];
+    }
+    F[(int64_t)(2 * q) * Np + n] = c;
+    F[(int64_t)(2 * q + 1) * Np + n] = s;
+}
+
+// Y[k][n] = s_k * sum_j A[j][n] Z[j + k q] for k < K, s_k = 1 / sqrt(c theta_k)
+template <int QC>
+__global__ __launch_bounds__(64) void k_lr_expand(const double* __restrict__ A, int64_t Np,
+                                                  int64_t N, int q, const double* __restrict__ Z,
+                                                  const double* __restrict__ theta, double c,
+                                                  int K, double* __restrict__ Y) {
+    __shared__ double Zs[QC * MAXP];
+    __shared__ double sk[MAXP];
+    for (int e = threadIdx.x; e < QC * K; e += 64) {
+        const int j = e % QC, k = e / QC;
+        Zs[e] = j < q ? Z[j + k * q] : 0.0;
+    }
+    for (int k = threadIdx.x; k < K; k += 64) sk[k] = 1.0 / sqrt(c * theta[k]);
+    __syncthreads();
+    const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (n >= Np) return;
+    double a[QC];
+#pragma unroll
+    for (int j = 0; j < QC; ++j) a[j] = (j < q && n < N) ? A[(int64_t)j * Np + n] : 0.0;
+    for (int k = 0; k < K; ++k) {
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < QC; ++j) y += a[j] * Zs[k * QC + j];
+        Y[(int64_t)k * Np + n] = y * sk[k];
+    }
 }
 
 // ---------------------------------- Ritz vectors, next block, residuals
 // Y = V Q (orthonormal Ritz vectors), Z = W Q = C Y;
 //   res[wg][k] = sum_n (Z_nk - theta_k Y_nk)^2        (k < K)
 //   V <- Z diag(1 / max(theta, floor))  (next block; in place)
-// Rows >= N are zero.  PC is p rounded up to a multiple of 8.
+// Rows >= N are zero.  PC is p rounded up to a multiple of 8; one row per
+// thread, 64 threads per workgroup.
 template <int PC>
-__global__ __launch_bounds__(GNT) void k_rotate2(double* __restrict__ V, const double* __restrict__ W,
-                                                 const double* __restrict__ Q,
-                                                 const double* __restrict__ theta, int64_t Np,
-                                                 int64_t N, int p, int K, double* __restrict__ Y,
-                                                 double* __restrict__ res) {
+__global__ __launch_bounds__(64) void k_rotate2(double* __restrict__ V, const double* __restrict__ W,
+                                                const double* __restrict__ Q,
+                                                const double* __restrict__ theta, int64_t Np,
+                                                int64_t N, int p, int K, double* __restrict__ Y,
+                                                double* __restrict__ res) {
     __shared__ double Qs[PC * PC];
     __shared__ double th[PC];
-    __shared__ double red[PC];
-    for (int e = threadIdx.x; e < PC * PC; e += GNT) {
+    for (int e = threadIdx.x; e < PC * PC; e += 64) {
         const int i = e % PC, j = e / PC;
         Qs[e] = (i < p && j < p) ? Q[i + j * p] : 0.0;
     }
-    for (int e = threadIdx.x; e < PC; e += GNT) {
-        th[e] = e < p ? theta[e] : 1.0;
-        red[e] = 0.0;
-    }
+    for (int e = threadIdx.x; e < PC; e += 64) th[e] = e < p ? theta[e] : 1.0;
     __syncthreads();
     const double floor_t = fabs(th[0]) * 1e-6 + 1e-300;
-    const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    double rk[PC];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) rk[j] = 0.0;
     if (n < N) {
         double vr[PC], wr[PC];
 #pragma unroll
@@ -353,10 +630,8 @@ __global__ __launch_bounds__(GNT) void k_rotate2(double* __restrict__ V, const d
                 Y[(int64_t)j * Np + n] = y;
                 const double tj = th[j];
                 V[(int64_t)j * Np + n] = z / (tj > floor_t ? tj : floor_t);
-                if (j < K) {
-                    const double d = z - tj * y;
-                    atomicAdd(&red[j], d * d);
-                }
+                const double d = z - tj * y;
+                rk[j] = d * d;
             }
         }
     } else if (n < Np) {
@@ -365,8 +640,15 @@ __global__ __launch_bounds__(GNT) void k_rotate2(double* __restrict__ V, const d
             V[(int64_t)j * Np + n] = 0.0;
         }
     }
-    __syncthreads();
-    if (threadIdx.x < K) res[(int64_t)blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
+    // all 64 lanes are active here
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+        if (j < K) {
+            double v = rk[j];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (threadIdx.x == 0) res[(int64_t)blockIdx.x * K + j] = v;
+        }
+    }
 }
 
 // ------------------------------------------------------ lattice helpers
@@ -801,13 +1083,6 @@ __global__ __launch_bounds__(GNT) void k_finalize(const double* __restrict__ Y, 
 }
 
 // ------------------------------------------------------------ host side
-struct FftPlan64 {
-    int64_t M = 0;
-    int log_M = 0;
-    bool single = false;
-    int N1 = 0, N2 = 0, BB = 0, MM = 0, lo_bits = 0, tw_len = 0;
-    DevBuf tw, tw_lo, tw_hi;
-};
 
 int ilog2i(int64_t v) {
     int l = 0;
@@ -926,7 +1201,7 @@ struct Solver {
     int p, K;
     // lattice
     bool lattice = false;
-    FftPlan64 fft;
+    const FftPlan64* fft = nullptr;
     int* map = nullptr;
     double* Hhat = nullptr;
     cplx<double>* cbuf1 = nullptr;   // pass-A output / natural-order temp
@@ -949,17 +1224,17 @@ struct Solver {
             a.Hhat = Hhat;
             a.Y = W;
             M2N_PROF(ctx, st, "toeplitz_fft_conv");
-            if (fft.single) {
+            if (fft->single) {
                 // whole convolution in two single-workgroup transforms
                 a.dst = cbuf1;
-                M2N_TRY(run_fft64(fft, st, a, pairs, SRC_PAIR, DST_MULCONJ, nullptr));
+                M2N_TRY(run_fft64(*fft, st, a, pairs, SRC_PAIR, DST_MULCONJ, nullptr));
                 a.src = cbuf1;
-                M2N_TRY(run_fft64(fft, st, a, pairs, SRC_DIRECT, DST_PAIR, nullptr));
+                M2N_TRY(run_fft64(*fft, st, a, pairs, SRC_DIRECT, DST_PAIR, nullptr));
             } else {
                 a.dst = cbuf1;
-                M2N_TRY(run_fft64(fft, st, a, pairs, SRC_PAIR, DST_MULCONJ, cbuf2));
+                M2N_TRY(run_fft64(*fft, st, a, pairs, SRC_PAIR, DST_MULCONJ, cbuf2));
                 a.src = cbuf1;
-                M2N_TRY(run_fft64(fft, st, a, pairs, SRC_DIRECT, DST_PAIR, cbuf2));
+                M2N_TRY(run_fft64(*fft, st, a, pairs, SRC_DIRECT, DST_PAIR, cbuf2));
             }
             return M2N_OK;
         }
@@ -998,16 +1273,17 @@ struct Solver {
 
 // block subspace iteration with Rayleigh-Ritz; returns the Ritz vectors of
 // the K largest eigenvalues in Y (orthonormal) and theta.
-int subspace_solve(Solver& S, double* V, double* W, double* Y, double* part, double* res,
+int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, double* res,
                    double* Q, double* th, int64_t nchunks) {
     Ctx* ctx = S.ctx;
     hipStream_t st = S.st;
     const int64_t N = S.N, Np = S.Np;
     const int p = S.p, K = S.K;
-    const int gram_wg = (int)(nchunks < 32 ? nchunks : 32);
+    const int gram_wg = (int)(nchunks < 256 ? nchunks : 256);
     const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
-    const int row_wg = (int)((Np + GNT - 1) / GNT);
+    const int row_wg = (int)((Np + 63) / 64);
     const int pc = (p + 7) / 8 * 8;
+    M2N_HIP(hipMemsetAsync(gacc, 0, sizeof(double) * 2 * (size_t)p * p, st));
     {
         M2N_PROF(ctx, st, "k_randinit");
         dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
@@ -1021,17 +1297,17 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* part, dou
         {
             M2N_PROF(ctx, st, "k_gram2");
             hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, cpw, nchunks,
-                               part);
+                               2, gacc);
         }
         {
             M2N_PROF(ctx, st, "k_small_rr");
-            hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(GNT), 0, st, part, gram_wg, p, Q, th);
+            hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
         }
         {
             M2N_PROF(ctx, st, "k_rotate2");
 #define M2N_ROT(PCV)                                                                            \
     case PCV:                                                                                   \
-        hipLaunchKernelGGL(k_rotate2<PCV>, dim3(row_wg), dim3(GNT), 0, st, V, W, Q, th, Np, N, p, \
+        hipLaunchKernelGGL(k_rotate2<PCV>, dim3(row_wg), dim3(64), 0, st, V, W, Q, th, Np, N, p, \
                            K, Y, res);                                                          \
         break;
             switch (pc) {
@@ -1086,117 +1362,57 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     const double cB = 2.0 * fmax;
     const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 && (t[N - 1] - t[0]) < 2.0e6;
     const double span = N > 1 ? t[N - 1] - t[0] : 0.0;
-    int p = (int)std::ceil(2.0 * fw * span) + 8;
-    if (p < K + 8) p = K + 8;
-    p = (p + 15) / 16 * 16;
-    if (p > MAXP) p = MAXP;
-    if (p > N) p = (int)N;
-    if (p < K) {
-        set_error("internal: block width %d < K %d", p, K);
-        return M2N_ERR_ARG;
-    }
+    // quadrature rank of R(A0): Gauss-Legendre in f over [-fw, fw]; the
+    // integrand e^{j 2 pi f tau} has at most beta = 2 pi fw span radians
+    const double beta = 2.0 * M_PI * fw * span;
+    int Qn = (int)std::ceil(0.8 * beta) + 16;
+    if (Qn < K + 2) Qn = K + 2;
+    Qn += Qn & 1;
+    const bool lowrank = Qn <= MAXP;
     Solver S;
     S.ctx = ctx;
     S.st = st;
     S.N = N;
     S.Np = (N + TB - 1) / TB * TB;
-    S.p = p;
     S.K = K;
     S.lattice = lattice;
     const int64_t Np = S.Np;
     const int64_t nchunks = (Np + GRAM_ROWS - 1) / GRAM_ROWS;
+    const int gram_wg = (int)(nchunks < 256 ? nchunks : 256);
+    const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
     const int row_wg = (int)((Np + GNT - 1) / GNT);
-    void *vV, *vW, *vY, *vpart, *vres, *vQ, *vth, *vt;
-    M2N_TRY(ctx->workspace("gep_V", sizeof(double) * (size_t)p * Np, &vV));
-    M2N_TRY(ctx->workspace("gep_W", sizeof(double) * (size_t)p * Np, &vW));
-    M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)p * Np, &vY));
-    size_t part_n = (size_t)32 * 2 * p * p;
-    if (part_n < (size_t)row_wg * 2 * K) part_n = (size_t)row_wg * 2 * K;
-    M2N_TRY(ctx->workspace("gep_part", sizeof(double) * part_n, &vpart));
-    M2N_TRY(ctx->workspace("gep_res", sizeof(double) * (size_t)row_wg * K, &vres));
+    const int rot_wg = (int)((Np + 63) / 64);
+    void *vt, *vY, *vpart, *vQ, *vth, *vgacc;
+    M2N_TRY(ctx->workspace("gep_t", sizeof(double) * (size_t)N, &vt));
+    M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)MAXP * Np, &vY));
+    M2N_TRY(ctx->workspace("gep_part", sizeof(double) * (size_t)row_wg * 2 * K + 64, &vpart));
     M2N_TRY(ctx->workspace("gep_Q", sizeof(double) * MAXP * MAXP, &vQ));
     M2N_TRY(ctx->workspace("gep_th", sizeof(double) * MAXP, &vth));
-    M2N_TRY(ctx->workspace("gep_t", sizeof(double) * (size_t)N, &vt));
-    double *V = (double*)vV, *W = (double*)vW, *Y = (double*)vY;
-    double *part = (double*)vpart, *res = (double*)vres, *Q = (double*)vQ, *th = (double*)vth;
+    M2N_TRY(ctx->workspace("gep_gacc", sizeof(double) * 2 * MAXP * MAXP, &vgacc));
+    double *Y = (double*)vY, *part = (double*)vpart, *Qm = (double*)vQ, *th = (double*)vth;
+    double* gacc = (double*)vgacc;
     M2N_HIP(hipMemcpyAsync(vt, t_dev, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st));
     const double* td = (const double*)vt;
-    // W's padded rows are never written by the lattice convolution
-    M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
+    M2N_HIP(hipMemsetAsync(gacc, 0, sizeof(double) * 2 * MAXP * MAXP, st));
 
-    double scale;   // w = scale * (L^{-T}) y
-    if (lattice) {
-        // ---- lattice: R(B) = cB I, C = R(A0) / cB
-        const int64_t Sspan = (int64_t)(t[N - 1] - t[0]);
-        int64_t M = 64;
-        while (M < 2 * Sspan + 1) M *= 2;
-        M2N_TRY(make_fft64(ctx, M, S.fft));
-        struct Guard {
-            Ctx* c;
-            FftPlan64* f;
-            ~Guard() { release_fft(c, *f); }
-        } guard{ctx, &S.fft};
-        std::vector<int> off(N);
-        for (int64_t n = 0; n < N; ++n) off[n] = (int)(t[n] - t[0]);
-        void *vmap, *voff, *vH, *vc1, *vc2, *vs;
-        const int pairs = (p + 1) / 2;
-        M2N_TRY(ctx->workspace("gep_map", sizeof(int) * (size_t)M, &vmap));
-        M2N_TRY(ctx->workspace("gep_off", sizeof(int) * (size_t)N, &voff));
-        M2N_TRY(ctx->workspace("gep_H", sizeof(double) * (size_t)M, &vH));
-        M2N_TRY(ctx->workspace("gep_c1", sizeof(cplx<double>) * (size_t)M * pairs, &vc1));
-        M2N_TRY(ctx->workspace("gep_c2", sizeof(cplx<double>) * (size_t)M * pairs, &vc2));
-        M2N_TRY(ctx->workspace("gep_hs", sizeof(cplx<double>) * (size_t)M, &vs));
-        M2N_HIP(hipMemcpyAsync(voff, off.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice, st));
-        S.map = (int*)vmap;
-        S.Hhat = (double*)vH;
-        S.cbuf1 = (cplx<double>*)vc1;
-        S.cbuf2 = (cplx<double>*)vc2;
-        {
-            M2N_PROF(ctx, st, "k_lattice_setup");
-            hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S.map,
-                               M, -1);
-            hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                               (const int*)voff, N, S.map);
-            // Hhat = FFT(h) / (M cB)
-            hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                               S.cbuf2, M, Sspan, fw);
-        }
-        M2N_HIP(hipGetLastError());
-        {
-            M2N_PROF(ctx, st, "toeplitz_kernel_fft");
-            ConvArgs a{};
-            a.src = S.cbuf2;
-            a.dst = S.cbuf1;
-            M2N_TRY(run_fft64(S.fft, st, a, 1, SRC_DIRECT, DST_DIRECT, (cplx<double>*)vs));
-            hipLaunchKernelGGL(k_real_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                               (const cplx<double>*)S.cbuf1, M, 1.0 / ((double)M * cB), S.Hhat);
-        }
-        M2N_HIP(hipGetLastError());
-        scale = std::sqrt(2.0 * fw / cB);
-        M2N_TRY(subspace_solve(S, V, W, Y, part, res, Q, th, nchunks));
-    } else {
-        // ---- dense: R(B) = L L^T, C = L^{-1} R(A0) L^{-T}
+    // dense path: R(B) = L L^T by the tiled Cholesky (zero tiles skipped)
+    auto factor_RB = [&]() -> int {
         if (Np > 65536) {
             set_error("dense GEP limited to N <= 65536 in this build");
             return M2N_ERR_UNSUPPORTED;
         }
         S.nblk = (int)(Np / TB);
-        void *vRB, *vRA, *vtmp, *vnz, *vst;
+        void *vRB, *vnz, *vst;
         M2N_TRY(ctx->workspace("gep_RB", sizeof(double) * (size_t)Np * Np, &vRB));
-        M2N_TRY(ctx->workspace("gep_RA", sizeof(double) * (size_t)Np * Np, &vRA));
-        M2N_TRY(ctx->workspace("gep_tmp", sizeof(double) * (size_t)p * Np, &vtmp));
         M2N_TRY(ctx->workspace("gep_nz", sizeof(int) * (size_t)S.nblk, &vnz));
         M2N_TRY(ctx->workspace("gep_status", 64, &vst));
         S.RB = (double*)vRB;
-        S.RA = (double*)vRA;
-        S.tmp = (double*)vtmp;
         S.nz = (int*)vnz;
         M2N_HIP(hipMemsetAsync(vst, 0, 64, st));
         {
             M2N_PROF(ctx, st, "k_gen_sinc");
             dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
             hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
-            hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fw, 0.0, S.RA);
         }
         M2N_HIP(hipGetLastError());
         for (int kb = 0; kb < S.nblk; ++kb) {
@@ -1223,10 +1439,163 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
             set_error("R(B) is not numerically positive definite (Cholesky pivot %d)", -hstatus - 1);
             return M2N_ERR_NOT_PD;
         }
-        scale = std::sqrt(2.0 * fw);
-        M2N_TRY(subspace_solve(S, V, W, Y, part, res, Q, th, nchunks));
-        // y -> L^{-T} y
-        M2N_TRY(S.trsv(Y, 1));
+        return M2N_OK;
+    };
+
+    double scale;   // w = scale * (L^{-T}) y
+    std::vector<double> fq, sq;
+    if (lowrank) {
+        // ---- R(A0) = F F^T from the quadrature of its defining integral
+        std::vector<double> gx, gw;
+        gauss_legendre(Qn, gx, gw);
+        for (int i = 0; i < Qn; ++i)
+            if (gx[i] > 0.0) {
+                fq.push_back(fw * gx[i]);
+                sq.push_back(std::sqrt(2.0 * fw * gw[i]));
+            }
+        const int nq = (int)fq.size();   // Qn / 2
+        void *vF, *vfq;
+        M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)Qn * Np, &vF));
+        M2N_TRY(ctx->workspace("gep_fq", sizeof(double) * 2 * MAXP, &vfq));
+        double* F = (double*)vF;
+        double* dfq = (double*)vfq;
+        M2N_HIP(hipMemcpyAsync(dfq, fq.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
+        M2N_HIP(hipMemcpyAsync(dfq + MAXP, sq.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
+        {
+            M2N_PROF(ctx, st, "k_lr_basis");
+            dim3 g((unsigned)((Np + 255) / 256), (unsigned)nq);
+            hipLaunchKernelGGL(k_lr_basis, g, dim3(256), 0, st, td, N, Np, 0.5 * (t[0] + t[N - 1]),
+                               (const double*)dfq, (const double*)(dfq + MAXP), nq, F);
+        }
+        M2N_HIP(hipGetLastError());
+        double cdiv = cB;
+        if (!lattice) {
+            // X = L^{-1} F, then the reduced matrix X^T X
+            M2N_TRY(factor_RB());
+            S.p = Qn;
+            M2N_TRY(S.trsv(F, 0));
+            cdiv = 1.0;
+        }
+        {
+            M2N_PROF(ctx, st, "k_gram2");
+            hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, F, F, Np, N, Qn, cpw,
+                               nchunks, 1, gacc);
+        }
+        {
+            M2N_PROF(ctx, st, "k_sym_topk");
+            hipLaunchKernelGGL(k_sym_topk, dim3(1), dim3(64), 0, st, gacc, Qn, 1.0 / cdiv, K, Qm, th,
+                               (long long*)nullptr);
+        }
+        {
+            M2N_PROF(ctx, st, "k_lr_expand");
+            const int qc = (Qn + 7) / 8 * 8;
+#define M2N_EXP(QCV)                                                                              \
+    case QCV:                                                                                     \
+        hipLaunchKernelGGL(k_lr_expand<QCV>, dim3(rot_wg), dim3(64), 0, st, F, Np, N, Qn, Qm, th, \
+                           cdiv, K, Y);                                                           \
+        break;
+            switch (qc) {
+                M2N_EXP(8) M2N_EXP(16) M2N_EXP(24) M2N_EXP(32) M2N_EXP(40) M2N_EXP(48) M2N_EXP(56)
+                M2N_EXP(64)
+                default:
+                    set_error("internal: quadrature rank %d", Qn);
+                    return M2N_ERR_ARG;
+            }
+#undef M2N_EXP
+        }
+        M2N_HIP(hipGetLastError());
+        if (lattice) {
+            scale = std::sqrt(2.0 * fw / cB);
+        } else {
+            S.p = K;
+            M2N_TRY(S.trsv(Y, 1));   // w = L^{-T} y
+            scale = std::sqrt(2.0 * fw);
+        }
+    } else {
+        // ---- wide band: block subspace iteration
+        int p = (int)std::ceil(2.0 * fw * span) + 8;
+        if (p < K + 8) p = K + 8;
+        p = (p + 15) / 16 * 16;
+        if (p > MAXP) p = MAXP;
+        if (p > N) p = (int)N;
+        S.p = p;
+        void *vV, *vW, *vres;
+        M2N_TRY(ctx->workspace("gep_V", sizeof(double) * (size_t)p * Np, &vV));
+        M2N_TRY(ctx->workspace("gep_W", sizeof(double) * (size_t)p * Np, &vW));
+        M2N_TRY(ctx->workspace("gep_res", sizeof(double) * (size_t)rot_wg * K, &vres));
+        double *V = (double*)vV, *W = (double*)vW, *res = (double*)vres;
+        // W's padded rows are never written by the lattice convolution
+        M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
+        if (lattice) {
+            const int64_t Sspan = (int64_t)(t[N - 1] - t[0]);
+            int64_t M = 64;
+            while (M < 2 * Sspan + 1) M *= 2;
+            auto itp = ctx->fft64.find(M);
+            if (itp == ctx->fft64.end()) {
+                auto plan = std::make_unique<FftPlan64>();
+                const int stp = make_fft64(ctx, M, *plan);
+                if (stp != M2N_OK) {
+                    release_fft(ctx, *plan);
+                    return stp;
+                }
+                itp = ctx->fft64.emplace(M, std::move(plan)).first;
+            }
+            S.fft = itp->second.get();
+            std::vector<int> off(N);
+            for (int64_t n = 0; n < N; ++n) off[n] = (int)(t[n] - t[0]);
+            void *vmap, *voff, *vH, *vc1, *vc2, *vs;
+            const int pairs = (p + 1) / 2;
+            M2N_TRY(ctx->workspace("gep_map", sizeof(int) * (size_t)M, &vmap));
+            M2N_TRY(ctx->workspace("gep_off", sizeof(int) * (size_t)N, &voff));
+            M2N_TRY(ctx->workspace("gep_H", sizeof(double) * (size_t)M, &vH));
+            M2N_TRY(ctx->workspace("gep_c1", sizeof(cplx<double>) * (size_t)M * pairs, &vc1));
+            M2N_TRY(ctx->workspace("gep_c2", sizeof(cplx<double>) * (size_t)M * pairs, &vc2));
+            M2N_TRY(ctx->workspace("gep_hs", sizeof(cplx<double>) * (size_t)M, &vs));
+            M2N_HIP(hipMemcpyAsync(voff, off.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice,
+                                   st));
+            S.map = (int*)vmap;
+            S.Hhat = (double*)vH;
+            S.cbuf1 = (cplx<double>*)vc1;
+            S.cbuf2 = (cplx<double>*)vc2;
+            {
+                M2N_PROF(ctx, st, "k_lattice_setup");
+                hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                                   S.map, M, -1);
+                hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                                   (const int*)voff, N, S.map);
+                hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                                   S.cbuf2, M, Sspan, fw);
+            }
+            M2N_HIP(hipGetLastError());
+            {
+                M2N_PROF(ctx, st, "toeplitz_kernel_fft");
+                ConvArgs a{};
+                a.src = S.cbuf2;
+                a.dst = S.cbuf1;
+                M2N_TRY(run_fft64(*S.fft, st, a, 1, SRC_DIRECT, DST_DIRECT, (cplx<double>*)vs));
+                hipLaunchKernelGGL(k_real_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                                   (const cplx<double>*)S.cbuf1, M, 1.0 / ((double)M * cB), S.Hhat);
+            }
+            M2N_HIP(hipGetLastError());
+            scale = std::sqrt(2.0 * fw / cB);
+            M2N_TRY(subspace_solve(S, V, W, Y, gacc, res, Qm, th, nchunks));
+        } else {
+            M2N_TRY(factor_RB());
+            void *vRA, *vtmp;
+            M2N_TRY(ctx->workspace("gep_RA", sizeof(double) * (size_t)Np * Np, &vRA));
+            M2N_TRY(ctx->workspace("gep_tmp", sizeof(double) * (size_t)p * Np, &vtmp));
+            S.RA = (double*)vRA;
+            S.tmp = (double*)vtmp;
+            {
+                M2N_PROF(ctx, st, "k_gen_sinc");
+                dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
+                hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fw, 0.0, S.RA);
+            }
+            M2N_HIP(hipGetLastError());
+            scale = std::sqrt(2.0 * fw);
+            M2N_TRY(subspace_solve(S, V, W, Y, gacc, res, Qm, th, nchunks));
+            M2N_TRY(S.trsv(Y, 1));   // w = L^{-T} y
+        }
     }
     // ---- sign convention, scale, output
     {

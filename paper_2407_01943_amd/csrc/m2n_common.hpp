@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -81,7 +82,8 @@ struct NufftPlan {
     int log_nf = 0;
     bool single = false;   // whole grid in one workgroup's LDS
     int N1 = 0, N2 = 0;    // nf = N1 * N2 (two-pass)
-    int B = 0, M = 0;      // pass-1 column block, pass-2 row block
+    int B = 0, M = 0;      // pass-1 column block, pass-2 rows per workgroup (max)
+    int KC = 0;            // pass-2 tapers transformed together
     int lookback = 0;      // extra column blocks a point may reach into
     int lo_bits = 0;       // 4-step twiddle split
     DevBuf tw_fft;         // e^{-2 pi i j / Nt}, j < Nt (Nt = max FFT length)
@@ -89,6 +91,15 @@ struct NufftPlan {
     DevBuf tw_lo, tw_hi;   // 4-step twiddle tables
     DevBuf inv_phihat;     // 1 / phihat(|k|), |k| <= kmax
     int64_t kmax = 0;
+};
+
+// FP64 complex FFT plan of length M (lattice convolution in the GEP)
+struct FftPlan64 {
+    int64_t M = 0;
+    int log_M = 0;
+    bool single = false;
+    int N1 = 0, N2 = 0, BB = 0, MM = 0, lo_bits = 0, tw_len = 0;
+    DevBuf tw, tw_lo, tw_hi;
 };
 
 struct Ctx;
@@ -116,6 +127,7 @@ struct Ctx {
     size_t budget = 0;         // 0 = unlimited
     size_t held = 0;           // bytes currently allocated
     std::map<std::tuple<int64_t, int, int>, std::unique_ptr<NufftPlan>> plans;
+    std::map<int64_t, std::unique_ptr<FftPlan64>> fft64;   // by length
     std::map<std::string, DevBuf> ws;   // named grow-only workspaces
     unsigned* dev_err = nullptr;        // sticky device error word
     int cu_count = 256;
@@ -133,6 +145,41 @@ struct Ctx {
     int alloc(DevBuf& b, size_t bytes);
     void release(DevBuf& b);
 };
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n)
+inline void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt) {
+    x.assign(n, 0.0);
+    wt.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int itr = 0; itr < 100; ++itr) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            // p1 = P_n(z), p0 = P_{n-1}(z)
+            double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                // recompute the derivative at the converged node
+                p0 = 1.0;
+                p1 = z;
+                for (int j = 2; j <= n; ++j) {
+                    double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (z * p1 - p0) / (z * z - 1.0);
+                x[i] = z;
+                wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+        }
+    }
+}
 
 // RAII: records an event pair around the launches in its scope when timing is on
 struct ProfScope {

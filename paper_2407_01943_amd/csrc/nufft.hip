@@ -132,18 +132,14 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* >= NT/6
 }
 
 // ------------------------------------------------- binning (counting sort)
-// K1a: per-workgroup bin histograms, lattice / finiteness flags and the
-// partial squared norms of the tapers (for Ehat).
+// K1a: per-workgroup bin histograms and lattice / finiteness flags.
 __global__ __launch_bounds__(NT) void k_hist(const double* __restrict__ t,
                                              const double* __restrict__ x, int64_t N,
                                              double f_lo, double df, int64_t h, int nf,
-                                             int w, int N2, int B, int nbins,
-                                             int* __restrict__ hist, int* __restrict__ flags,
-                                             const double* __restrict__ wt, int K, int needE,
-                                             double* __restrict__ part) {
+                                             int w, int N2, int B, int nbins, int ppw,
+                                             int* __restrict__ hist, int* __restrict__ flags) {
     __shared__ int sh[MAX_BINS];
     __shared__ int s_int, s_bad;
-    __shared__ double red[NT / 64];
     const int wg = blockIdx.x;
     for (int b = threadIdx.x; b < nbins; b += NT) sh[b] = 0;
     if (threadIdx.x == 0) {
@@ -151,9 +147,9 @@ __global__ __launch_bounds__(NT) void k_hist(const double* __restrict__ t,
         s_bad = 0;
     }
     __syncthreads();
-    const int64_t n0 = (int64_t)wg * PTS_PER_WG;
+    const int64_t n0 = (int64_t)wg * ppw;
     int my_int = 1, my_bad = 0;
-    for (int j = threadIdx.x; j < PTS_PER_WG; j += NT) {
+    for (int j = threadIdx.x; j < ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= N) break;
         Geo g = point_geo(t[n], x[n], f_lo, df, h, nf, w);
@@ -167,43 +163,35 @@ __global__ __launch_bounds__(NT) void k_hist(const double* __restrict__ t,
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += NT) hist[(int64_t)wg * nbins + b] = sh[b];
     if (threadIdx.x == 0) flags[wg] = (s_int ? 1 : 0) | (s_bad ? 2 : 0);
-    if (needE) {
-        for (int k = 0; k < K; ++k) {
-            double acc = 0.0;
-            for (int j = threadIdx.x; j < PTS_PER_WG; j += NT) {
-                const int64_t n = n0 + j;
-                if (n >= N) break;
-                const double v = wt[(int64_t)k * N + n];
-                acc += v * v;
-            }
-            acc = block_sum(acc, red);
-            if (threadIdx.x == 0) part[(int64_t)wg * K + k] = acc;
-        }
-    }
 }
 
 // K1b: one workgroup.  off[wg][b] = start of (wg, b) in bin-major order,
-// bin_off[b] = start of bin b; reduces the flags; forms Ehat when R(B) is
-// 2 f_max I (integer t and integer 2 f_max):  D_k = 2 f_max |w_k|^2.
-template <typename R>
+// bin_off[b] = start of bin b.  Reduces the flags: diag[0] = 1 when R(B) is
+// 2 f_max I (every t integer and 2 f_max a positive integer).  Clears the
+// taper norms that pass 1 accumulates for Ehat.
+constexpr int SCAN_LDS = 12288;   // (workgroup, bin) counts staged in LDS
 __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ hist, int nwg, int nbins,
                                                int* __restrict__ off, int* __restrict__ bin_off,
                                                const int* __restrict__ flags,
                                                unsigned* __restrict__ dev_err, int needE,
-                                               const double* __restrict__ part,
-                                               const double* __restrict__ lambda, int K,
-                                               double fmax, double fw, R* __restrict__ Eval) {
+                                               double fmax, int* __restrict__ diag,
+                                               double* __restrict__ norms, int K) {
+    __shared__ int cnt[SCAN_LDS];
     __shared__ int tot[MAX_BINS + 1];
     __shared__ int s_int, s_bad;
     const int tid = threadIdx.x;
+    const bool staged = (int64_t)nwg * nbins <= SCAN_LDS;
     if (tid == 0) {
         s_int = 1;
         s_bad = 0;
     }
+    if (staged)
+        for (int e = tid; e < nwg * nbins; e += blockDim.x) cnt[e] = hist[e];
+    for (int k = tid; k < K; k += blockDim.x) norms[k] = 0.0;
     __syncthreads();
     for (int b = tid; b < nbins; b += blockDim.x) {
         int s = 0;
-        for (int g = 0; g < nwg; ++g) s += hist[(int64_t)g * nbins + b];
+        for (int g = 0; g < nwg; ++g) s += staged ? cnt[g * nbins + b] : hist[(int64_t)g * nbins + b];
         tot[b] = s;
     }
     int li = 1, lb = 0;
@@ -214,43 +202,42 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ hist, int
     if (!li) atomicAnd(&s_int, 0);
     if (lb) atomicOr(&s_bad, 1);
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int b = 0; b < nbins; ++b) {
-            int v = tot[b];
-            tot[b] = run;
-            run += v;
+    // exclusive scan over the bins (one wavefront, 64-wide chunks)
+    if (tid < 64) {
+        int carry = 0;
+        for (int c0 = 0; c0 < nbins; c0 += 64) {
+            const int b = c0 + tid;
+            int v = b < nbins ? tot[b] : 0;
+            int incl = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (tid >= o) incl += u;
+            }
+            if (b < nbins) tot[b] = carry + incl - v;
+            carry += __shfl(incl, 63, 64);
         }
-        tot[nbins] = run;
+        if (tid == 0) tot[nbins] = carry;
     }
     __syncthreads();
     for (int b = tid; b <= nbins; b += blockDim.x) bin_off[b] = tot[b];
     for (int b = tid; b < nbins; b += blockDim.x) {
         int run = tot[b];
         for (int g = 0; g < nwg; ++g) {
-            off[(int64_t)g * nbins + b] = run;
-            run += hist[(int64_t)g * nbins + b];
+            const int c = staged ? cnt[g * nbins + b] : hist[(int64_t)g * nbins + b];
+            if (staged) cnt[g * nbins + b] = run;
+            else off[(int64_t)g * nbins + b] = run;
+            run += c;
         }
     }
+    __syncthreads();
+    if (staged)
+        for (int e = tid; e < nwg * nbins; e += blockDim.x) off[e] = cnt[e];
     if (tid == 0) {
+        const double c = 2.0 * fmax;
+        const int d = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
+        diag[0] = d;
         if (s_bad) atomicOr(dev_err, (unsigned)DEVERR_NONFINITE);
-        if (needE) {
-            const double c = 2.0 * fmax;
-            const bool diag = s_int && c == rint(c) && c >= 1.0;
-            if (diag) {
-                double e = 0.0;
-                for (int k = 0; k < K; ++k) {
-                    double nrm = 0.0;
-                    for (int g = 0; g < nwg; ++g) nrm += part[(int64_t)g * K + k];
-                    const double lh = 2.0 * fw * lambda[k] / (c * nrm);
-                    e += fabs(lambda[k] - lh);
-                }
-                *Eval = (R)(e / (double)K);
-            } else {
-                *Eval = (R)NAN;
-                atomicOr(dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
-            }
-        }
+        if (needE && !d) atomicOr(dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
     }
 }
 
@@ -259,7 +246,7 @@ template <typename R>
 __global__ __launch_bounds__(NT) void k_scatter(const double* __restrict__ t,
                                                 const double* __restrict__ x, int64_t N,
                                                 double f_lo, double df, int64_t h, int nf, int w,
-                                                int N2, int B, int nbins,
+                                                int N2, int B, int nbins, int ppw,
                                                 const int* __restrict__ off,
                                                 int* __restrict__ l0s, R* __restrict__ dels,
                                                 cplx<R>* __restrict__ c0s,
@@ -268,8 +255,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const double* __restrict__ t,
     const int wg = blockIdx.x;
     for (int b = threadIdx.x; b < nbins; b += NT) cur[b] = 0;
     __syncthreads();
-    const int64_t n0 = (int64_t)wg * PTS_PER_WG;
-    for (int j = threadIdx.x; j < PTS_PER_WG; j += NT) {
+    const int64_t n0 = (int64_t)wg * ppw;
+    for (int j = threadIdx.x; j < ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= N) break;
         Geo g = point_geo(t[n], x[n], f_lo, df, h, nf, w);
@@ -283,36 +270,47 @@ __global__ __launch_bounds__(NT) void k_scatter(const double* __restrict__ t,
 }
 
 // -------------------------------------------------------------- pass 1
+constexpr int NT1 = 512;   // threads per pass-1 workgroup
+constexpr int NT2 = 512;   // threads per pass-2 workgroup
+
 template <typename R, int N1, int B>
-__global__ __launch_bounds__(NT) void k_pass1(const int* __restrict__ l0s, const R* __restrict__ dels,
-                                              const cplx<R>* __restrict__ c0s,
-                                              const int* __restrict__ idxs,
-                                              const int* __restrict__ bin_off,
-                                              const double* __restrict__ wt, int64_t N,
-                                              int log_N2, int nf, int w, R beta, int lookback,
-                                              const cplx<R>* __restrict__ tw, int tws,
-                                              const cplx<R>* __restrict__ tw_lo,
-                                              const cplx<R>* __restrict__ tw_hi, int lo_bits,
-                                              cplx<R>* __restrict__ inter) {
+__global__ __launch_bounds__(NT1) void k_pass1(const int* __restrict__ l0s, const R* __restrict__ dels,
+                                               const cplx<R>* __restrict__ c0s,
+                                               const int* __restrict__ idxs,
+                                               const int* __restrict__ bin_off,
+                                               const double* __restrict__ wt, int64_t N,
+                                               int log_N2, int nf, int w, R beta, int lookback,
+                                               const cplx<R>* __restrict__ tw_g, int tws,
+                                               const cplx<R>* __restrict__ tw_lo,
+                                               const cplx<R>* __restrict__ tw_hi, int lo_bits,
+                                               cplx<R>* __restrict__ inter, int needE,
+                                               double* __restrict__ norms) {
     constexpr int LD = N1 + 1;
     __shared__ cplx<R> tile[B * LD];
+    __shared__ cplx<R> tw[N1];
+    __shared__ double nred;
     const int N2 = 1 << log_N2;
     const int nblk = N2 / B;
     const int blk = blockIdx.x % nblk;
     const int k = blockIdx.x / nblk;
     const int a = blk * B;
-    for (int e = threadIdx.x; e < B * LD; e += NT) tile[e] = {(R)0, (R)0};
+    for (int e = threadIdx.x; e < B * LD; e += NT1) tile[e] = {(R)0, (R)0};
+    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * tws];
+    if (threadIdx.x == 0) nred = 0.0;
     __syncthreads();
     const R two_over_w = (R)2 / (R)w;
     const double* wk = wt + (int64_t)k * N;
+    double nrm = 0.0;   // sum of w_k^2 over this block's own points (for Ehat)
     for (int q = 0; q <= lookback; ++q) {
         int bb = blk - q;
         if (bb < 0) bb += nblk;
         const int s = bin_off[bb], e = bin_off[bb + 1];
-        for (int j = s + threadIdx.x; j < e; j += NT) {
+        for (int j = s + threadIdx.x; j < e; j += NT1) {
             const int l0 = l0s[j];
             const R del = dels[j];
-            const R wv = (R)wk[idxs[j]];
+            const double wd = wk[idxs[j]];
+            if (q == 0) nrm += wd * wd;
+            const R wv = (R)wd;
             const cplx<R> c = cscale(c0s[j], wv);
             for (int r = 0; r < w; ++r) {
                 int cell = l0 + r;
@@ -327,11 +325,16 @@ __global__ __launch_bounds__(NT) void k_pass1(const int* __restrict__ l0s, const
             }
         }
     }
+    if (needE) {
+        for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&nred, nrm);
+    }
     __syncthreads();
-    fft_lds<R, N1, B, NT, LD>(tile, tw, tws);
+    if (needE && threadIdx.x == 0) atomicAdd(&norms[k], nred);
+    fft_lds<R, N1, B, NT1, LD>(tile, tw, 1);
     const int lo_mask = (1 << lo_bits) - 1;
     cplx<R>* out = inter + (int64_t)k * nf;
-    for (int e = threadIdx.x; e < B * N1; e += NT) {
+    for (int e = threadIdx.x; e < B * N1; e += NT1) {
         const int cb = e % B, m1 = e / B;
         const int q = (a + cb) * m1;    // < nf
         const cplx<R> twv = cmul(tw_lo[q & lo_mask], tw_hi[q >> lo_bits]);
@@ -340,41 +343,61 @@ __global__ __launch_bounds__(NT) void k_pass1(const int* __restrict__ l0s, const
 }
 
 // -------------------------------------------------------------- pass 2
-template <typename R, int N2, int M>
-__global__ __launch_bounds__(NT) void k_pass2(const cplx<R>* __restrict__ inter, int K, int N1,
-                                              int nf, int64_t I, int64_t h,
-                                              const cplx<R>* __restrict__ tw, int tws,
-                                              const R* __restrict__ inv_phihat,
-                                              const double* __restrict__ dk,
-                                              R* __restrict__ P, R* __restrict__ E,
-                                              const R* __restrict__ Eval,
-                                              cplx<R>* __restrict__ J) {
+// A workgroup owns M consecutive rows m1 and transforms KC tapers at a time
+// (KC * M rows in LDS); every output mode is owned by one thread, which
+// accumulates sum_k d_k |J_k|^2 across the tapers in a register.
+template <typename R, int N2, int M, int KC>
+__global__ __launch_bounds__(NT2) void k_pass2(const cplx<R>* __restrict__ inter, int K, int N1,
+                                               int nf, int64_t I, int64_t h,
+                                               const cplx<R>* __restrict__ tw_g, int tws,
+                                               const R* __restrict__ inv_phihat,
+                                               const double* __restrict__ dk,
+                                               R* __restrict__ P, R* __restrict__ E,
+                                               const double* __restrict__ norms,
+                                               const int* __restrict__ diag,
+                                               const double* __restrict__ lambda, double fmax,
+                                               double fw, cplx<R>* __restrict__ J) {
     constexpr int LD = N2 + 1;
-    constexpr int OUT_IT = (M * N2 + NT - 1) / NT;
-    __shared__ cplx<R> rows[M * LD];
+    constexpr int ROWS = KC * M;
+    constexpr int OUT_IT = (M * (N2 / 2 + 2) + NT2 - 1) / NT2;
+    __shared__ cplx<R> rows[ROWS * LD];
+    __shared__ cplx<R> tw[N2];
+    __shared__ R s_eval;
     const int m1_0 = blockIdx.x * M;
-    // modes kept: m2 in [0, npos) (i' >= 0) and [N2 - nneg, N2) (i' < 0)
+    for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * tws];
+    if (E && threadIdx.x == 0) {
+        // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I
+        double e = 0.0;
+        const double c = 2.0 * fmax;
+        for (int k = 0; k < K; ++k) e += fabs(lambda[k] - 2.0 * fw * lambda[k] / (c * norms[k]));
+        s_eval = diag[0] ? (R)(e / (double)K) : (R)NAN;
+    }
+    // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
     if (npos > N2) npos = N2;
     int m2neg0 = (int)((nf - h) / N1);
     if (m2neg0 < npos) m2neg0 = npos;
     const int nneg = N2 - m2neg0;
-    const int nout = M * (npos + nneg);
+    int nout = M * (npos + nneg);
+    if (nout > OUT_IT * NT2) nout = OUT_IT * NT2;   // cannot happen for nf >= 2 I
     R acc[OUT_IT];
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) acc[it] = (R)0;
-    for (int k = 0; k < K; ++k) {
-        const cplx<R>* src = inter + (int64_t)k * nf + (int64_t)m1_0 * N2;
-        for (int e = threadIdx.x; e < M * N2; e += NT) {
-            const int mm = e / N2, l2 = e - mm * N2;
-            rows[mm * LD + l2] = src[(int64_t)mm * N2 + l2];
+    for (int kc0 = 0; kc0 < K; kc0 += KC) {
+        const int nk = K - kc0 < KC ? K - kc0 : KC;
+        for (int e = threadIdx.x; e < ROWS * N2; e += NT2) {
+            const int r = e / N2, l2 = e - r * N2;
+            const int kq = r / M, mm = r - kq * M;
+            cplx<R> v = {(R)0, (R)0};
+            if (kq < nk)
+                v = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
+            rows[r * LD + l2] = v;
         }
         __syncthreads();
-        fft_lds<R, N2, M, NT, LD>(rows, tw, tws);
-        const R d = dk ? (R)dk[k] : (R)1 / (R)K;
+        fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1);
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
-            const int e = threadIdx.x + it * NT;
+            const int e = threadIdx.x + it * NT2;
             if (e < nout) {
                 const int mm = e % M, c = e / M;
                 const int m2 = c < npos ? c : m2neg0 + (c - npos);
@@ -383,9 +406,12 @@ __global__ __launch_bounds__(NT) void k_pass2(const cplx<R>* __restrict__ inter,
                 const int64_t i = kk + h;
                 if (i >= 0 && i < I) {
                     const R s = inv_phihat[kk < 0 ? -kk : kk];
-                    const cplx<R> v = cscale(rows[mm * LD + m2], s);
-                    acc[it] += d * (v.x * v.x + v.y * v.y);
-                    if (J) J[(int64_t)k * I + i] = v;
+                    for (int kq = 0; kq < nk; ++kq) {
+                        const cplx<R> v = cscale(rows[(kq * M + mm) * LD + m2], s);
+                        const R d = dk ? (R)dk[kc0 + kq] : (R)1 / (R)K;
+                        acc[it] += d * (v.x * v.x + v.y * v.y);
+                        if (J) J[(int64_t)(kc0 + kq) * I + i] = v;
+                    }
                 }
             }
         }
@@ -393,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_pass2(const cplx<R>* __restrict__ inter,
     }
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = threadIdx.x + it * NT2;
         if (e < nout) {
             const int mm = e % M, c = e / M;
             const int m2 = c < npos ? c : m2neg0 + (c - npos);
@@ -402,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_pass2(const cplx<R>* __restrict__ inter,
             const int64_t i = kk + h;
             if (i >= 0 && i < I) {
                 if (P) P[i] = acc[it];
-                if (E) E[i] = *Eval;
+                if (E) E[i] = s_eval;
             }
         }
     }
@@ -513,40 +539,6 @@ __global__ void k_phihat(int64_t kmax, int nf, int w, double beta, const double*
 }
 
 // ------------------------------------------------------------ host helpers
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt) {
-    x.assign(n, 0.0);
-    wt.assign(n, 0.0);
-    for (int i = 0; i < n; ++i) {
-        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
-        for (int itr = 0; itr < 100; ++itr) {
-            double p0 = 1.0, p1 = z;
-            for (int j = 2; j <= n; ++j) {
-                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
-                p0 = p1;
-                p1 = p2;
-            }
-            // p1 = P_n(z), p0 = P_{n-1}(z)
-            double dp = n * (z * p1 - p0) / (z * z - 1.0);
-            double dz = p1 / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16) {
-                // recompute the derivative at the converged node
-                p0 = 1.0;
-                p1 = z;
-                for (int j = 2; j <= n; ++j) {
-                    double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
-                    p0 = p1;
-                    p1 = p2;
-                }
-                dp = n * (z * p1 - p0) / (z * z - 1.0);
-                x[i] = z;
-                wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
-                break;
-            }
-        }
-    }
-}
-
 template <typename R>
 std::vector<cplx<R>> twiddles(int64_t n, int64_t count, int64_t stride) {
     // exp(-2 pi i j stride / n) for j < count
@@ -597,9 +589,13 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
             set_error("unsupported grid split (N2 = %d, B = %d, w = %d)", p.N2, p.B, p.w);
             return M2N_ERR_UNSUPPORTED;
         }
-        p.M = 65536 / (p.N2 * cs);
-        if (p.M > 16) p.M = 16;
-        if (p.M > p.N1) p.M = p.N1;
+        // pass 2: KC tapers x M rows of N2 (+1 pad) values plus the N2-entry
+        // twiddle table must fit the 160 KB LDS of a compute unit
+        int rows_max = 1;
+        while (2 * rows_max * (p.N2 + 1) * cs + p.N2 * cs <= 160000) rows_max *= 2;
+        p.KC = rows_max < 8 ? rows_max : 8;
+        p.M = rows_max / p.KC;
+        if (p.M > 4) p.M = 4;
         p.lo_bits = (p.log_nf + 1) / 2;
         Nt = p.N1 > p.N2 ? p.N1 : p.N2;
         M2N_TRY(upload(ctx, p.tw_lo, twiddles<R>(p.nf, int64_t(1) << p.lo_bits, 1)));
@@ -698,16 +694,16 @@ void launch_small(const NufftPlan& p, hipStream_t st, const double* t, const dou
 template <typename R>
 int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const int* l0s, const R* dels,
                  const cplx<R>* c0s, const int* idxs, const int* bin_off, const double* w,
-                 int64_t N, cplx<R>* inter) {
+                 int64_t N, cplx<R>* inter, int needE, double* norms) {
     const int tws = p.tw_len / p.N1;
     const int logN2 = ilog2i(p.N2);
-#define M2N_P1(N1V, BV)                                                                         \
-    if (p.N1 == N1V && p.B == BV) {                                                             \
-        hipLaunchKernelGGL((k_pass1<R, N1V, BV>), grid, dim3(NT), 0, st, l0s, dels, c0s, idxs,  \
-                           bin_off, w, N, logN2, p.nf, p.w, (R)p.beta, p.lookback,              \
-                           (const cplx<R>*)p.tw_fft.p, tws, (const cplx<R>*)p.tw_lo.p,          \
-                           (const cplx<R>*)p.tw_hi.p, p.lo_bits, inter);                        \
-        return M2N_OK;                                                                          \
+#define M2N_P1(N1V, BV)                                                                          \
+    if (p.N1 == N1V && p.B == BV) {                                                              \
+        hipLaunchKernelGGL((k_pass1<R, N1V, BV>), grid, dim3(NT1), 0, st, l0s, dels, c0s, idxs,  \
+                           bin_off, w, N, logN2, p.nf, p.w, (R)p.beta, p.lookback,               \
+                           (const cplx<R>*)p.tw_fft.p, tws, (const cplx<R>*)p.tw_lo.p,           \
+                           (const cplx<R>*)p.tw_hi.p, p.lo_bits, inter, needE, norms);           \
+        return M2N_OK;                                                                           \
     }
     if constexpr (sizeof(R) == 4) {
         M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 32) M2N_P1(512, 16) M2N_P1(1024, 8)
@@ -719,27 +715,42 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const int* l0s, 
     return M2N_ERR_UNSUPPORTED;
 }
 
+// rows-per-workgroup choice for pass 2: largest M the LDS budget allows that
+// still gives at least two workgroups per compute unit
+inline int pass2_rows(const NufftPlan& p, int cu_count) {
+    int M = p.M;
+    while (M > 1 && (p.N1 / M) < 2 * cu_count) M /= 2;
+    return M;
+}
+
 template <typename R>
-int launch_pass2(const NufftPlan& p, hipStream_t st, const cplx<R>* inter, int K,
-                 const double* dk, R* P, R* E, const R* Eval, cplx<R>* J) {
+int launch_pass2(const NufftPlan& p, hipStream_t st, int M, const cplx<R>* inter, int K,
+                 const double* dk, R* P, R* E, const double* norms, const int* diag,
+                 const double* lambda, double fmax, double fw, cplx<R>* J) {
     const int tws = p.tw_len / p.N2;
-    dim3 grid(p.N1 / p.M);
-#define M2N_P2(N2V, MV)                                                                        \
-    if (p.N2 == N2V && p.M == MV) {                                                            \
-        hipLaunchKernelGGL((k_pass2<R, N2V, MV>), grid, dim3(NT), 0, st, inter, K, p.N1, p.nf,  \
-                           p.I, p.h, (const cplx<R>*)p.tw_fft.p, tws,                          \
-                           (const R*)p.inv_phihat.p, dk, P, E, Eval, J);                      \
-        return M2N_OK;                                                                         \
+    dim3 grid(p.N1 / M);
+#define M2N_P2(N2V, MV, KCV)                                                                     \
+    if (p.N2 == N2V && M == MV && p.KC == KCV) {                                                 \
+        hipLaunchKernelGGL((k_pass2<R, N2V, MV, KCV>), grid, dim3(NT2), 0, st, inter, K, p.N1,   \
+                           p.nf, p.I, p.h, (const cplx<R>*)p.tw_fft.p, tws,                      \
+                           (const R*)p.inv_phihat.p, dk, P, E, norms, diag, lambda, fmax, fw,    \
+                           J);                                                                   \
+        return M2N_OK;                                                                           \
     }
     if constexpr (sizeof(R) == 4) {
-        M2N_P2(128, 16) M2N_P2(256, 16) M2N_P2(512, 16) M2N_P2(1024, 8) M2N_P2(2048, 4)
-        M2N_P2(4096, 2)
+        M2N_P2(128, 1, 8) M2N_P2(128, 2, 8) M2N_P2(128, 4, 8)
+        M2N_P2(256, 1, 8) M2N_P2(256, 2, 8) M2N_P2(256, 4, 8)
+        M2N_P2(512, 1, 8) M2N_P2(512, 2, 8) M2N_P2(512, 4, 8)
+        M2N_P2(1024, 1, 8) M2N_P2(1024, 2, 8)
+        M2N_P2(2048, 1, 8) M2N_P2(4096, 1, 2)
     } else {
-        M2N_P2(128, 16) M2N_P2(256, 16) M2N_P2(512, 8) M2N_P2(1024, 4) M2N_P2(2048, 2)
-        M2N_P2(4096, 1)
+        M2N_P2(128, 1, 8) M2N_P2(128, 2, 8) M2N_P2(128, 4, 8)
+        M2N_P2(256, 1, 8) M2N_P2(256, 2, 8) M2N_P2(256, 4, 8)
+        M2N_P2(512, 1, 8) M2N_P2(512, 2, 8)
+        M2N_P2(1024, 1, 8) M2N_P2(2048, 1, 2) M2N_P2(4096, 1, 1)
     }
 #undef M2N_P2
-    set_error("no pass-2 kernel for N2 = %d, M = %d", p.N2, p.M);
+    set_error("no pass-2 kernel for N2 = %d, M = %d, KC = %d", p.N2, M, p.KC);
     return M2N_ERR_UNSUPPORTED;
 }
 
@@ -758,54 +769,58 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const double* t, con
         return M2N_OK;
     }
     const int nbins = p.N2 / p.B;
-    const int64_t nwg64 = (N + PTS_PER_WG - 1) / PTS_PER_WG;
+    // points per binning workgroup: at least PTS_PER_WG, and few enough
+    // workgroups that the scan can stage every (workgroup, bin) count in LDS
+    int64_t ppw = PTS_PER_WG;
+    while ((N + ppw - 1) / ppw * nbins > SCAN_LDS && ppw < (int64_t(1) << 20)) ppw *= 2;
+    const int64_t nwg64 = (N + ppw - 1) / ppw;
     if (nwg64 > (1 << 20)) {
         set_error("N too large");
         return M2N_ERR_ARG;
     }
     const int nwg = (int)nwg64;
     const bool needE = E != nullptr;
-    void *hist, *off, *binoff, *flags, *part, *l0s, *dels, *c0s, *idxs, *inter, *eval;
+    void *hist, *off, *binoff, *flags, *l0s, *dels, *c0s, *idxs, *inter, *norms, *diag;
     M2N_TRY(ctx->workspace("nu_hist", sizeof(int) * (size_t)nwg * nbins, &hist));
     M2N_TRY(ctx->workspace("nu_off", sizeof(int) * (size_t)nwg * nbins, &off));
     M2N_TRY(ctx->workspace("nu_binoff", sizeof(int) * (size_t)(nbins + 1), &binoff));
     M2N_TRY(ctx->workspace("nu_flags", sizeof(int) * (size_t)nwg, &flags));
-    M2N_TRY(ctx->workspace("nu_part", sizeof(double) * (size_t)nwg * K, &part));
     M2N_TRY(ctx->workspace("nu_l0", sizeof(int) * (size_t)N, &l0s));
     M2N_TRY(ctx->workspace("nu_del", sizeof(R) * (size_t)N, &dels));
     M2N_TRY(ctx->workspace("nu_c0", sizeof(cplx<R>) * (size_t)N, &c0s));
     M2N_TRY(ctx->workspace("nu_idx", sizeof(int) * (size_t)N, &idxs));
     M2N_TRY(ctx->workspace("nu_inter", sizeof(cplx<R>) * (size_t)K * p.nf, &inter));
-    M2N_TRY(ctx->workspace("nu_eval", 64, &eval));
+    M2N_TRY(ctx->workspace("nu_norms", sizeof(double) * 64, &norms));
+    M2N_TRY(ctx->workspace("nu_diag", 64, &diag));
     {
         M2N_PROF(ctx, st, "k_hist");
         hipLaunchKernelGGL(k_hist, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf, p.w,
-                           p.N2, p.B, nbins, (int*)hist, (int*)flags, w, K, needE ? 1 : 0,
-                           (double*)part);
+                           p.N2, p.B, nbins, (int)ppw, (int*)hist, (int*)flags);
     }
     {
         M2N_PROF(ctx, st, "k_scan");
-        hipLaunchKernelGGL(k_scan<R>, dim3(1), dim3(1024), 0, st, (const int*)hist, nwg, nbins,
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const int*)hist, nwg, nbins,
                            (int*)off, (int*)binoff, (const int*)flags, ctx->dev_err, needE ? 1 : 0,
-                           (const double*)part, lambda, K, fmax, fw, (R*)eval);
+                           fmax, (int*)diag, (double*)norms, K);
     }
     {
         M2N_PROF(ctx, st, "k_scatter");
         hipLaunchKernelGGL(k_scatter<R>, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf,
-                           p.w, p.N2, p.B, nbins, (const int*)off, (int*)l0s, (R*)dels,
+                           p.w, p.N2, p.B, nbins, (int)ppw, (const int*)off, (int*)l0s, (R*)dels,
                            (cplx<R>*)c0s, (int*)idxs);
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass1");
         M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(K * nbins)), (const int*)l0s, (const R*)dels,
-                            (const cplx<R>*)c0s, (const int*)idxs, (const int*)binoff, w, N,
-                            (cplx<R>*)inter));
+                                (const cplx<R>*)c0s, (const int*)idxs, (const int*)binoff, w, N,
+                                (cplx<R>*)inter, needE ? 1 : 0, (double*)norms));
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass2");
-        M2N_TRY(launch_pass2<R>(p, st, (const cplx<R>*)inter, K, dk, P, E, (const R*)eval, J));
+        M2N_TRY(launch_pass2<R>(p, st, pass2_rows(p, ctx->cu_count), (const cplx<R>*)inter, K, dk,
+                                P, E, (const double*)norms, (const int*)diag, lambda, fmax, fw, J));
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;

@@ -68,6 +68,47 @@ def test_nufft_two_pass(m2n, ctx, orc, prec, tol):
     _nufft_case(m2n, ctx, orc, s, w, prec, tol, tol)
 
 
+@pytest.mark.parametrize("prec,tol", [(2, 1e-10), (1, 1e-5)])
+def test_nufft_two_pass_k9(m2n, ctx, orc, prec, tol):
+    # K = 9 > 8 tapers per pass-2 chunk: the average spans two chunks
+    s = W.gapped_scaled(4000, 9, 2 ** 13, seed=34)
+    w = np.random.default_rng(104).standard_normal((9, s.N)) * 0.05
+    _nufft_case(m2n, ctx, orc, s, w, prec, tol, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(2, 1e-10), (1, 1e-5)])
+def test_nufft_large_grid_sampled(m2n, ctx, orc, prec, tol):
+    # I = 2^17 (nf = 2^18, 512 x 512 split); the oracle evaluates 512 bands
+    s = W.gapped_scaled(12000, 5, 2 ** 17, seed=35)
+    w = np.random.default_rng(105).standard_normal((5, s.N)) * 0.02
+    bands = np.unique(np.concatenate([np.arange(0, 64), np.arange(s.I - 64, s.I),
+                                      np.random.default_rng(7).integers(0, s.I, 384)]))
+    _say(f"case sampled N={s.N} I={s.I} prec={prec}")
+    ref_J = orc.nudft(s.t, s.x, w, s.f_lo, s.df, bands=bands)
+    out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), None, s.fmax, s.fw, s.f_lo,
+                          s.df, s.I, prec=prec, want_E=False, want_J=True)
+    J = out["J"].cpu().numpy().astype(np.complex128)[:, bands]
+    P = out["P"].cpu().numpy().astype(np.float64)[bands]
+    # normwise over the sampled bands; the tolerance scales with the full-band norm
+    eJ = normwise_rows(J, ref_J)
+    eP = psd_err(P, orc.psd(ref_J))
+    _say(f"  J sampled {eJ:.3e}  P {eP:.3e}")
+    assert eJ < 10 * tol and eP < 10 * tol
+
+
+def test_ehat_two_pass_lattice(m2n, ctx, orc):
+    # Ehat through the two-pass path on a lattice (R(B) = I): identically ~0
+    s = W.gapped_scaled(3000, 5, 2 ** 14, seed=36)
+    w, lam = orc.gpss_tapers(s.t, s.fmax, s.fw, 5, method="lanczos")
+    bands = np.array([0, 1, 777, 8192, 16383], dtype=np.int64)
+    E_ref, _ = orc.ehat(s.t, w, lam, s.fmax, s.fw, s.f_lo, s.df, bands=bands)
+    out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), _dev(lam), s.fmax, s.fw, s.f_lo,
+                          s.df, s.I, prec=2, want_E=True)
+    E = out["E"].cpu().numpy()
+    assert np.abs(E[bands] - E_ref).max() < 1e-10
+    assert np.abs(E).max() < 1e-10
+
+
 @pytest.mark.parametrize("name", ["jitter", "arithmetic", "missing"])
 def test_nufft_nonlattice_times(m2n, ctx, orc, name):
     s = W.by_name(name)
@@ -128,6 +169,35 @@ def test_gep_lattice_two_pass_fft(m2n, ctx, orc):
     assert np.abs(lam - lam_ref).max() < 1e-12
     wa, _ = align_signs(w, w_ref)
     assert normwise_rows(wa, w_ref) < 1e-8
+
+
+def _gep_subspace_case(m2n, ctx, orc, s, fw, K, I=4096):
+    """Wide band (quadrature rank > 64): block subspace iteration.  Top
+    eigenvalues cluster, so tapers are compared through what is unique: the
+    eigenvalues and the PSD of a series (invariant to rotations of the span)."""
+    _say(f"gep subspace N={s.N} fw={fw} K={K}")
+    w_ref, lam_ref = orc.gpss_tapers(s.t, s.fmax, fw, K, method="jacobi" if s.N <= 600 else "lanczos")
+    t, x = _dev(s.t), _dev(s.x)
+    w, lam = m2n.gpss_tapers(ctx, t, s.fmax, fw, K)
+    el = np.abs(lam.cpu().numpy() - lam_ref).max()
+    P = m2n.m2nufft_psd(ctx, t, x, w, None, s.fmax, fw, -0.5, 1.0 / I, I, prec=2,
+                        want_E=False)["P"].cpu().numpy()
+    P_ref = orc.psd(orc.nudft(s.t, s.x, w_ref, -0.5, 1.0 / I, I=I))
+    eP = psd_err(P, P_ref)
+    G = w.cpu().numpy() @ orc.gpss_matrix(s.t, s.fmax) @ w.cpu().numpy().T
+    eG = np.abs(G - 2 * fw * np.eye(K)).max()
+    _say(f"  lambda {el:.3e}  P {eP:.3e}  R(B)-orthonormality {eG:.3e}")
+    assert el < 1e-12 and eP < 1e-10 and eG < 1e-12
+
+
+def test_gep_lattice_subspace_fallback(m2n, ctx, orc):
+    s = W.gapped_scaled(3000, 14, 4096, seed=44)
+    _gep_subspace_case(m2n, ctx, orc, s, 12 / 3000, 14)
+
+
+def test_gep_dense_subspace_fallback(m2n, ctx, orc):
+    s = W.jitter_stress(n=300, seed=45, K=35)
+    _gep_subspace_case(m2n, ctx, orc, s, 0.06, 35)
 
 
 def test_gep_dense_medium(m2n, ctx, orc):
