@@ -145,6 +145,8 @@ void m2n_destroy(m2n_ctx* ctx) {
         ctx->release(kv.second->tw_hi);
     }
     for (auto& kv : ctx->ws) ctx->release(kv.second);
+    for (auto& kv : ctx->gl) ctx->release(kv.second);
+    if (ctx->hinfo) (void)hipHostFree(ctx->hinfo);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);

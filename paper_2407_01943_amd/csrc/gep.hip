@@ -35,6 +35,7 @@ constexpr int TB = 64;     // tile size of the dense path
 constexpr int GNT = 256;   // threads per workgroup (general)
 constexpr int GRAM_ROWS = 64;
 constexpr int MAXP = 64;
+constexpr int GRAM_WG_MAX = 128;   // workgroups of a Gram pass (partials reduced after)
 
 // ------------------------------------------------------------ sinc kernel
 // sin(pi u) with u first reduced to [-1/2, 1/2] by sin(pi (u - 2k)) = sin(pi u)
@@ -68,15 +69,15 @@ __global__ void k_randinit(double* __restrict__ V, int64_t Np, int64_t N, int p,
 }
 
 // ------------------------------------------------------ Gram matrices
-// One pass over this workgroup's rows; the workgroup's contribution to
-//   acc[0 .. p*p)     += V^T V   (entry i * p + j)
-//   acc[p*p .. 2p*p)  += V^T W
-// is added with device-scope FP64 atomics (acc is zero on entry; the
-// consumer clears it).
+// One pass over this workgroup's rows; the workgroup's partial sums of
+//   [0 .. p*p)     V^T V   (entry i * p + j)
+//   [p*p .. 2p*p)  V^T W   (nmat = 2)
+// go to part + blockIdx.x * nmat * p * p; k_gram_reduce adds the partials
+// in workgroup order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, const double* __restrict__ W,
                                                int64_t Np, int64_t nrows, int p, int nchunks_per_wg,
                                                int64_t nchunks, int nmat,
-                                               double* __restrict__ acc_out) {
+                                               double* __restrict__ part) {
     __shared__ double Vs[MAXP][GRAM_ROWS + 1];
     __shared__ double Ws[MAXP][GRAM_ROWS + 1];
     constexpr int PER = 2 * MAXP * MAXP / GNT;
@@ -108,22 +109,109 @@ __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, con
         }
         __syncthreads();
     }
+    double* out = part + (int64_t)blockIdx.x * nmat * np;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int idx = threadIdx.x + e * GNT;
-        if (idx < nmat * np) atomicAdd(&acc_out[idx], acc[e]);
+        if (idx < nmat * np) out[idx] = acc[e];
     }
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Partial Gram matrix V^T V of this workgroup's rows on the FP64 matrix
+// cores, one wavefront per workgroup.  V is column-major (leading dimension
+// Np) with p <= 16 NT columns.  Each chunk of 64 rows is staged in LDS and
+// fed to the 16x16x4 FP64 MFMA four rows at a time: lane l supplies
+// A[i][k] = V[r_k][16 I + i] and B[k][j] = V[r_k][16 J + j] with
+// i = j = l % 16, k = l / 16, and holds D[l / 16 + 4 v][l % 16] in
+// accumulator element v (layout checked on the device).  Only the tiles I <= J are accumulated; the full
+// symmetric p x p partial goes to part + blockIdx.x * p * p.
+template <int NT>
+__global__ __launch_bounds__(64) void k_gram_mfma(const double* __restrict__ V, int64_t Np,
+                                                  int64_t nrows, int p, int cpw, int64_t nchunks,
+                                                  double* __restrict__ part) {
+    constexpr int NTT = NT * (NT + 1) / 2;
+    __shared__ double Vs[16 * NT][GRAM_ROWS + 1];
+    const int l = threadIdx.x;
+    d4 acc[NTT];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t c0 = (int64_t)blockIdx.x * cpw;
+    for (int64_t c = c0; c < c0 + cpw && c < nchunks; ++c) {
+        const int64_t r0 = c * GRAM_ROWS;
+        const bool inr = r0 + l < nrows;
+        // unconditional loads from clamped addresses, so that all are in
+        // flight together (rows < Np and columns < p are allocated)
+        double ld[16 * NT];
+#pragma unroll
+        for (int i = 0; i < 16 * NT; ++i) ld[i] = V[(int64_t)(i < p ? i : p - 1) * Np + r0 + l];
+#pragma unroll
+        for (int i = 0; i < 16 * NT; ++i) Vs[i][l] = (i < p && inr) ? ld[i] : 0.0;
+        __syncthreads();
+#pragma unroll 4
+        for (int ks = 0; ks < GRAM_ROWS / 4; ++ks) {
+            const int r = 4 * ks + (l >> 4);
+            double a[NT];
+#pragma unroll
+            for (int I = 0; I < NT; ++I) a[I] = Vs[16 * I + (l & 15)][r];
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int J = I; J < NT; ++J) {
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[t], 0, 0, 0);
+                    ++t;
+                }
+        }
+        __syncthreads();
+    }
+    double* out = part + (int64_t)blockIdx.x * p * p;
+    int t = 0;
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + (l >> 4) + 4 * v, j = 16 * J + (l & 15);
+                if (i < p && j < p) {
+                    out[i * p + j] = acc[t][v];
+                    if (I != J) out[j * p + i] = acc[t][v];
+                }
+            }
+            ++t;
+        }
+}
+
+// acc[i] = sum over the nwg partials of entry i, in a fixed order.  A
+// workgroup takes 64 entries; its four wavefronts sum interleaved groups
+// of eight partials with all eight loads in flight, then combine in LDS.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nwg, int len,
+                                                     double* __restrict__ acc) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int ic = i < len ? i : len - 1;
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
+    for (int g0 = 8 * wv; g0 < nwg; g0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int g = g0 + u < nwg ? g0 + u : nwg - 1;
+            v[u] = part[(int64_t)g * len + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += g0 + u < nwg ? v[u] : 0.0;
+    }
+    red[wv][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    __syncthreads();
+    if (wv == 0 && i < len) acc[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
 // ------------------------------------ top eigenpairs of a small symmetric
-// One wavefront (64 lanes, n <= 64).  On entry A (LDS, row stride LDA)
-// holds the symmetric matrix; on exit lam[0..K) are its K largest
-// eigenvalues in descending order and X[k][0..n) (stride LDA) the unit
-// eigenvectors.  Steps: Householder reduction to tridiagonal form (lane =
-// row), bisection on a division-free Sturm sequence (lane = eigenvalue),
-// inverse iteration with partial-pivoting tridiagonal solves (lane =
-// eigenvector) followed by modified Gram-Schmidt inside clusters of close
-// eigenvalues, and back-transformation by the stored reflectors.
 // move a double across lanes with a DPP pattern (both halves); lanes whose
 // source is out of range or whose row is masked off receive 0
 template <int CTRL, int ROWMASK>
@@ -164,295 +252,599 @@ __device__ __forceinline__ double wmin(double v) {
     return v;
 }
 
-// number of eigenvalues of the tridiagonal (d, e^2) below sigma: sign
-// changes of p_i = (d_i - sigma) p_{i-1} - e_{i-1}^2 p_{i-2}, kept in range
-// by exact power-of-two rescaling
-__device__ __forceinline__ int sturm_below(const double* dr, const double* e2r, int n, double sigma) {
-    double pp = 1.0, pc = dr[0] - sigma;
-    if (pc == 0.0) pc = -1e-300;
-    int cnt = pc < 0.0 ? 1 : 0;
-#pragma unroll
-    for (int i = 1; i < MAXP; ++i) {
-        if (i < n) {
-            double pn = (dr[i] - sigma) * pc - e2r[i - 1] * pp;
-            if (pn == 0.0) pn = pc > 0.0 ? -1e-300 : 1e-300;
-            cnt += ((pn < 0.0) != (pc < 0.0)) ? 1 : 0;
-            if ((i & 3) == 0) {
-                const double m = fmax(fabs(pn), fabs(pc));
-                if (m > 0x1p+400) {
-                    pn *= 0x1p-400;
-                    pc *= 0x1p-400;
-                } else if (m < 0x1p-400) {
-                    pn *= 0x1p+400;
-                    pc *= 0x1p+400;
-                }
-            }
-            pp = pc;
-            pc = pn;
-        }
-    }
-    return cnt;
+// a double from lane l (l wave-uniform)
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// eight independent wave sums, interleaved so that the DPP steps of one
+// hide the latency of the others
+__device__ __forceinline__ void wsum8(double (&v)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0xb1, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0x4e, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0x114, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0x118, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0x142, 0xa>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += dpp_d<0x143, 0xc>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = rdlane(v[u], 63);
+}
+
+// LDS of the small eigen-solver.  Row starts of Vh are 16-byte aligned so
+// that a reflector is read as double2 pairs.
 template <int LDA>
-__device__ void sym_topk_wave(double (*A)[LDA], int n, int K, double (*Vh)[LDA], double* Bh,
-                              double* d, double* e, double* e2, double* lam,
-                              double (*X)[LDA], double* tmp, long long* stamp = nullptr) {
+struct EigShared {
+    double A[MAXP][LDA];         // input; then Sturm pairs, then LU rows
+    double Vh[MAXP][MAXP + 2];   // Householder vector of step r in row r
+    double X[MAXP][LDA];         // eigenvectors, X[k][i]
+    double2 de[MAXP];            // (d_i, e_i) of the tridiagonal, e_{n-1} = 0
+    double re[MAXP];             // 1 / e_i (0 where e_i = 0)
+    double Bh[MAXP];
+    double lam[MAXP];
+    double tmp[2 * MAXP];
+    double Gq[16 * MAXP];        // Gram and projection coefficients of a batch
+};
+
+// dot product of rows j and k of X over n components, eight at a time
+template <int LDA>
+__device__ __forceinline__ double xdot(const double (*X)[LDA], int j, int k, int n) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 8) {
+        double xa[8], xb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            xa[u] = c0 + u < n ? X[j][c0 + u] : 0.0;
+            xb[u] = c0 + u < n ? X[k][c0 + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+            s0 += xa[u] * xb[u];
+            s1 += xa[u + 1] * xb[u + 1];
+        }
+    }
+    return s0 + s1;
+}
+
+// Orthonormalise the eigenvector batch X[kb..ke) (ke - kb <= 16) against
+// the orthonormal X[0..kb) and among itself: block classical Gram-Schmidt
+// followed by Cholesky QR, the pair applied `passes` times.  In exact
+// arithmetic this is Gram-Schmidt in index order.
+template <int LDA>
+__device__ __forceinline__ void orth_batch(EigShared<LDA>& S, int n, int kb, int ke, int passes) {
     const int lane = threadIdx.x;
-    const double eps = 2.220446049250313e-16;
-    if (stamp && lane == 0) stamp[0] = clock64();
-    // 1. tridiagonalise: A <- H_k A H_k, H_k = I - beta_k v_k v_k^T (lane = row)
-    for (int k = 0; k + 2 < n; ++k) {
-        const double xi = (lane > k && lane < n) ? A[lane][k] : 0.0;
-        const double nx2 = wsum(xi * xi);
-        double beta = 0.0, vi = 0.0;
-        if (nx2 > 0.0) {
-            const double x0 = A[k + 1][k];
-            const double alpha = x0 >= 0.0 ? -sqrt(nx2) : sqrt(nx2);
-            vi = xi - (lane == k + 1 ? alpha : 0.0);
-            // |v|^2 = |x|^2 - x0^2 + (x0 - alpha)^2 = 2 |x|^2 - 2 x0 alpha
-            beta = 1.0 / (nx2 - x0 * alpha);
-            if (lane == 0) e[k] = alpha;
-        } else if (lane == 0) {
-            e[k] = 0.0;
-        }
-        if (lane < n) {
-            Vh[k][lane] = vi;
-            tmp[lane] = vi;
-        }
-        if (lane == 0) Bh[k] = beta;
-        __syncthreads();
-        if (beta != 0.0) {
-            double pi = 0.0;
-            if (lane > k && lane < n) {
-                const double* __restrict__ Ai = A[lane];
-                const double* __restrict__ vt = tmp;
-                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-                int j = k + 1;
-                for (; j + 3 < n; j += 4) {
-                    p0 += Ai[j] * vt[j];
-                    p1 += Ai[j + 1] * vt[j + 1];
-                    p2 += Ai[j + 2] * vt[j + 2];
-                    p3 += Ai[j + 3] * vt[j + 3];
-                }
-                for (; j < n; ++j) p0 += Ai[j] * vt[j];
-                pi = beta * ((p0 + p1) + (p2 + p3));
-            }
-            const double kc = 0.5 * beta * wsum(vi * pi);
-            const double wi = pi - kc * vi;
-            if (lane < n) tmp[MAXP + lane] = wi;
+    const int nb = ke - kb;
+    double* G = S.Gq;
+    for (int pass = 0; pass < passes; ++pass) {
+        if (kb > 0) {
+            // C = X_prev^T X_batch (lane = coefficient), X_batch -= X_prev C
+            for (int pr = lane; pr < kb * nb; pr += 64) G[pr] = xdot<LDA>(S.X, pr / nb, kb + pr % nb, n);
             __syncthreads();
-            if (lane > k && lane < n) {
-                double* __restrict__ Ai = A[lane];
-                const double* __restrict__ vt = tmp;
-                const double* __restrict__ wt = tmp + MAXP;
-                int j = k + 1;
-                for (; j + 3 < n; j += 4) {
-                    const double a0 = Ai[j], a1 = Ai[j + 1], a2 = Ai[j + 2], a3 = Ai[j + 3];
-                    Ai[j] = a0 - (vi * wt[j] + wi * vt[j]);
-                    Ai[j + 1] = a1 - (vi * wt[j + 1] + wi * vt[j + 1]);
-                    Ai[j + 2] = a2 - (vi * wt[j + 2] + wi * vt[j + 2]);
-                    Ai[j + 3] = a3 - (vi * wt[j + 3] + wi * vt[j + 3]);
+            if (lane < n) {
+                for (int k = kb; k < ke; ++k) {
+                    double x = S.X[k][lane];
+                    for (int j = 0; j < kb; ++j) x -= G[j * nb + (k - kb)] * S.X[j][lane];
+                    S.X[k][lane] = x;
                 }
-                for (; j < n; ++j) Ai[j] -= vi * wt[j] + wi * vt[j];
             }
+            __syncthreads();
+        }
+        // Gram matrix of the batch (upper triangle)
+        for (int pr = lane; pr < nb * nb; pr += 64) {
+            const int i = pr / nb, k = pr % nb;
+            if (i <= k) G[pr] = xdot<LDA>(S.X, kb + i, kb + k, n);
+        }
+        __syncthreads();
+        // G = R^T R in place (R upper), lane = column
+        for (int j = 0; j < nb; ++j) {
+            double s = 0.0;
+            if (lane >= j && lane < nb) {
+                s = G[j * nb + lane];
+                for (int q = 0; q < j; ++q) s -= G[q * nb + j] * G[q * nb + lane];
+            }
+            const double rjj = sqrt(fmax(rdlane(s, j), 1e-280));
+            if (lane >= j && lane < nb) G[j * nb + lane] = lane == j ? rjj : s / rjj;
+            __syncthreads();
+        }
+        // X_batch <- X_batch R^{-1} (lane = component)
+        if (lane < n) {
+            double xs[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                xs[k] = 0.0;
+                if (k < nb) {
+                    double x = S.X[kb + k][lane];
+#pragma unroll
+                    for (int j = 0; j < k; ++j) x -= G[j * nb + k] * xs[j];
+                    xs[k] = x / G[k * nb + k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < nb) S.X[kb + k][lane] = xs[k];
         }
         __syncthreads();
     }
-    if (lane < n) d[lane] = A[lane][lane];
-    if (lane == 0 && n >= 2) e[n - 2] = A[n - 1][n - 2];
-    __syncthreads();
-    if (lane + 1 < n) e2[lane] = e[lane] * e[lane];
+}
+
+// Numbers of eigenvalues of the tridiagonal below s0 and below s1: sign
+// changes of p_i = (d_i - s) p_{i-1} - e_{i-1}^2 p_{i-2}, p_{-1} = 1,
+// p_{-2} = 0, with exact power-of-two rescaling every four steps.  dq[i] =
+// (d_i, e_{i-1}^2) for i < n8 (padding rows add no sign change).  Two
+// chains per lane hide the latency of the recurrence.
+template <int NP>
+__device__ __forceinline__ void sturm_below2(const double2* dq, int n8, double s0, double s1,
+                                             int& c0, int& c1) {
+    double pp0 = 0.0, pc0 = 1.0, pp1 = 0.0, pc1 = 1.0;
+    unsigned n0 = 0, n1 = 0;
+#pragma unroll
+    for (int j0 = 0; j0 < NP; j0 += 8) {
+        if (j0 < n8) {
+            double2 q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) q[u] = dq[j0 + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double a0 = (q[u].x - s0) * pc0 - q[u].y * pp0;
+                const double a1 = (q[u].x - s1) * pc1 - q[u].y * pp1;
+                n0 += (unsigned)(__double2hiint(a0) ^ __double2hiint(pc0)) >> 31;
+                n1 += (unsigned)(__double2hiint(a1) ^ __double2hiint(pc1)) >> 31;
+                pp0 = pc0;
+                pc0 = a0;
+                pp1 = pc1;
+                pc1 = a1;
+                if ((u & 3) == 3) {
+                    const double m0 = fmax(fabs(pc0), fabs(pp0)), m1 = fmax(fabs(pc1), fabs(pp1));
+                    const double f0 = m0 > 0x1p+400 ? 0x1p-400 : (m0 < 0x1p-400 ? 0x1p+400 : 1.0);
+                    const double f1 = m1 > 0x1p+400 ? 0x1p-400 : (m1 < 0x1p-400 ? 0x1p+400 : 1.0);
+                    pc0 *= f0;
+                    pp0 *= f0;
+                    pc1 *= f1;
+                    pp1 *= f1;
+                }
+            }
+        }
+    }
+    c0 = (int)n0;
+    c1 = (int)n1;
+}
+
+// sweeps of inverse iteration: with shifts within a few ulps of |T| of the
+// eigenvalues, two sweeps reduce the unwanted components below the
+// eigenvectors' own condition unless two eigenvalues lie within about
+// n^2 ulps of |T| of each other
+constexpr int INVIT_SWEEPS = 2;
+
+// 1/x from the hardware reciprocal and two Newton steps (|x| >= 1e-300)
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// deterministic start vector entry of inverse iteration, in [0.5, 1.5)
+__device__ __forceinline__ double start_entry(int i, int k) {
+    unsigned h = (unsigned)i * 0x9E3779B1u ^ ((unsigned)k + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
+}
+
+// Top-K eigenpairs of a small symmetric matrix on one wavefront (64 lanes,
+// n <= NP <= 64, NP a multiple of 8 sizing the per-lane register arrays).
+// On entry S.A holds the matrix (row stride LDA); on exit S.lam[0..K)
+// holds its K largest eigenvalues in descending order and S.X[k][0..n) the
+// unit eigenvectors.
+//  1. Householder reduction to tridiagonal form.  Lane i keeps row i in
+//     registers; the trailing block shifts down one register per step so
+//     that its first column always sits in a[0] and every register index is
+//     a compile-time constant.
+//  2. Multisection on a division-free Sturm count: g lanes (a power of two)
+//     bracket each wanted eigenvalue with two samples each per round and
+//     combine the brackets by lane shuffles.
+//  3. Inverse iteration (lane = eigenvector) with partial-pivoting LU of
+//     T - lam I, each sweep followed by orthonormalisation of the vectors in
+//     index order, and Rayleigh quotients as the final eigenvalues.
+//  4. Back-transformation by the reflectors (lane = eigenvector).
+template <int LDA, int NP>
+__device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n, int K,
+                                              long long* stamp = nullptr) {
+    const int lane = threadIdx.x;
+    const double eps = 2.220446049250313e-16;
+    const int n8 = (n + 7) & ~7;
+    if (stamp && lane == 0) {
+        stamp[0] = clock64();
+        stamp[5] = 0;
+        stamp[6] = 0;
+    }
+    // ---- 1. tridiagonalise: A <- H_k A H_k, H_k = I - beta_k v_k v_k^T
+    {
+        double a[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) a[j] = (lane < n && j < n) ? S.A[lane][j] : 0.0;
+        S.tmp[lane] = 0.0;
+        S.tmp[MAXP + lane] = 0.0;
+        __syncthreads();
+        // before step k, lane i >= k holds A(i, k..n-1) in a[0..n-k-1]
+        for (int k = 0; k + 2 < n; ++k) {
+            const int m = n - k - 1;               // order of the trailing block
+            const bool act = lane > k && lane < n;
+            const double xi = act ? a[0] : 0.0;
+            const double nx2 = wsum(xi * xi);
+            const double x0 = rdlane(a[0], k + 1);
+            if (lane == k) S.de[k].x = a[0];
+            double vi = 0.0, beta = 0.0, alpha = 0.0;
+            if (nx2 > 0.0) {
+                alpha = x0 >= 0.0 ? -sqrt(nx2) : sqrt(nx2);
+                vi = act ? xi - (lane == k + 1 ? alpha : 0.0) : 0.0;
+                // |v|^2 = 2 |x|^2 - 2 x0 alpha
+                beta = 1.0 / (nx2 - x0 * alpha);
+            }
+            if (lane == 0) {
+                S.de[k].y = alpha;
+                S.Bh[k] = beta;
+            }
+            S.Vh[k][lane] = vi;
+            // v in trailing-block coordinates; every lane writes one slot, so
+            // slots past the block hold zeros
+            const int slot = (lane - k - 1) & (MAXP - 1);
+            S.tmp[slot] = vi;
+            __syncthreads();
+            double wi = 0.0;
+            if (beta != 0.0) {
+                // all of v at once (slots past the block are zero), so the
+                // loads overlap
+                double2 u[NP / 2];
+                const double2* tp = reinterpret_cast<const double2*>(S.tmp);
+#pragma unroll
+                for (int q = 0; q < NP / 2; ++q) u[q] = tp[q];
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NP / 2; q += 2) {
+                    const int j = 2 * q;
+                    p0 += (j + 1 < NP ? a[j + 1] : 0.0) * u[q].x;
+                    p1 += (j + 2 < NP ? a[j + 2] : 0.0) * u[q].y;
+                    p2 += (j + 3 < NP ? a[j + 3] : 0.0) * u[q + 1].x;
+                    p3 += (j + 4 < NP ? a[j + 4] : 0.0) * u[q + 1].y;
+                }
+                p0 = (p0 + p2) + (p1 + p3);
+                const double pi = act ? beta * p0 : 0.0;
+                const double kc = 0.5 * beta * wsum(vi * pi);
+                wi = pi - kc * vi;
+                S.tmp[MAXP + slot] = wi;
+                __syncthreads();
+            }
+            // shift the trailing block down one register and apply the
+            // rank-two update  - v w^T - w v^T
+#pragma unroll
+            for (int j0 = 0; j0 < NP; j0 += 8) {
+                if (j0 < m) {
+                    const double2* tv = reinterpret_cast<const double2*>(S.tmp + j0);
+                    const double2* tw = reinterpret_cast<const double2*>(S.tmp + MAXP + j0);
+                    double2 uv[4], uw[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        uv[q] = tv[q];
+                        uw[q] = tw[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = j0 + 2 * q;
+                        const double an0 = j + 1 < NP ? a[j + 1] : 0.0;
+                        const double an1 = j + 2 < NP ? a[j + 2] : 0.0;
+                        a[j] = an0 - (vi * uw[q].x + wi * uv[q].x);
+                        a[j + 1] = an1 - (vi * uw[q].y + wi * uv[q].y);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (n >= 2) {
+            if (lane == n - 2) S.de[n - 2] = make_double2(a[0], a[1]);
+            if (lane == n - 1) S.de[n - 1] = make_double2(a[1], 0.0);
+        } else if (lane == 0) {
+            S.de[0] = make_double2(a[0], 0.0);
+        }
+        __syncthreads();
+    }
+    if (stamp && lane == 0) stamp[1] = clock64();
+    // ---- 2. eigenvalues by multisection
     double glo = 1e300, ghi = -1e300;
     if (lane < n) {
-        const double r = (lane > 0 ? fabs(e[lane - 1]) : 0.0) + (lane + 1 < n ? fabs(e[lane]) : 0.0);
-        glo = d[lane] - r;
-        ghi = d[lane] + r;
+        const double2 dl = S.de[lane];
+        const double r = (lane > 0 ? fabs(S.de[lane - 1].y) : 0.0) + fabs(dl.y);
+        glo = dl.x - r;
+        ghi = dl.x + r;
+        S.re[lane] = dl.y != 0.0 ? 1.0 / dl.y : 0.0;
     }
     glo = wmin(glo);
     ghi = wmax(ghi);
     const double tnorm = fmax(fmax(fabs(glo), fabs(ghi)), 1e-300);
-    double* lo = tmp;              // [K]
-    double* hi = tmp + MAXP;       // [K]
-    double* sig = X[0];            // [64] samples
-    double* cntd = X[1];           // [64] counts (as doubles)
-    if (lane < K) {
-        lo[lane] = glo;
-        hi[lane] = ghi;
-    }
-    __syncthreads();
-    if (stamp && lane == 0) stamp[1] = clock64();
-    // 2. multisection: g lanes per wanted eigenvalue sample its interval
-    double dr[MAXP], e2r[MAXP];
-#pragma unroll
-    for (int i = 0; i < MAXP; ++i) {
-        dr[i] = i < n ? d[i] : 0.0;
-        e2r[i] = i + 1 < n ? e2[i] : 0.0;
-    }
-    const int g = K < 64 ? 64 / K : 1;
-    const int grp = lane / g, sub = lane % g;
-    for (int round = 0; round < 80; ++round) {
-        int done = 1;
-        if (grp < K) {
-            const double l = lo[grp], h = hi[grp];
-            done = (h - l) <= 1e-14 * tnorm ? 1 : 0;
-            const double s = l + (double)(sub + 1) * (h - l) / (double)(g + 1);
-            sig[lane] = s;
-            cntd[lane] = (double)sturm_below(dr, e2r, n, s);
-        }
-        if (__all(done)) break;
-        __syncthreads();
-        if (grp < K && sub == 0) {
-            const int idx = n - 1 - grp;
-            double nl = lo[grp], nh = hi[grp];
-            for (int s2 = 0; s2 < g; ++s2) {
-                const double sv = sig[grp * g + s2];
-                if ((int)cntd[grp * g + s2] > idx) nh = fmin(nh, sv);
-                else nl = fmax(nl, sv);
+    {
+        double2* dq = reinterpret_cast<double2*>(&S.A[0][0]);
+        if (lane < n8) {
+            if (lane < n) {
+                const double ep = lane > 0 ? S.de[lane - 1].y : 0.0;
+                dq[lane] = make_double2(S.de[lane].x, lane > 0 ? fmax(ep * ep, 1e-200) : 0.0);
+            } else {
+                dq[lane] = make_double2(ghi + tnorm + 1.0, 0.0);
             }
-            lo[grp] = nl;
-            hi[grp] = nh;
         }
         __syncthreads();
+        int g = 64;
+        while (g > 1 && g * K > 64) g >>= 1;
+        const int grp = lane / g, sub = lane - grp * g;
+        const int idx = n - 1 - grp;
+        const bool live = grp < K;
+        const double tol = 1e-14 * tnorm;
+        // invariant: count(l) <= idx < count(h)
+        double l = glo - 2.0 * eps * tnorm, h = ghi + 2.0 * eps * tnorm;
+        for (int round = 0; round < 200; ++round) {
+            if (__all(!live || h - l <= tol)) break;
+            const double st = (h - l) / (double)(2 * g + 1);
+            const double s0 = l + (double)(2 * sub + 1) * st, s1 = l + (double)(2 * sub + 2) * st;
+            int c0, c1;
+            sturm_below2<NP>(dq, n8, s0, s1, c0, c1);
+            double nl = l, nh = h;
+            if (c0 > idx) nh = fmin(nh, s0);
+            else nl = fmax(nl, s0);
+            if (c1 > idx) nh = fmin(nh, s1);
+            else nl = fmax(nl, s1);
+            for (int o = 1; o < g; o <<= 1) {
+                nl = fmax(nl, __shfl_xor(nl, o, 64));
+                nh = fmin(nh, __shfl_xor(nh, o, 64));
+            }
+            if (h - l > tol) {
+                l = nl;
+                h = nh;
+            }
+        }
+        if (live && sub == 0) S.lam[grp] = 0.5 * (l + h);
+        __syncthreads();
     }
-    if (lane < K) lam[lane] = 0.5 * (lo[lane] + hi[lane]);
-    __syncthreads();
     if (stamp && lane == 0) stamp[2] = clock64();
-    // 3. inverse iteration in batches of 16 eigenvectors (lane = eigenvector);
-    //    the LU rows of T - lam I live in A's storage, [i][lane]
-    double* U1 = &A[0][0];
+    // ---- 3. inverse iteration in batches of 16 eigenvectors (lane =
+    //         eigenvector); the LU rows of T - lam I live in A's storage,
+    //         [i][lane], each pivot stored as its reciprocal
+    double* U1 = &S.A[0][0];
     double* U2 = U1 + 16 * MAXP;
     double* U3 = U2 + 16 * MAXP;
     double* Bv = U3 + 16 * MAXP;
+    const double tiny = fmax(eps * tnorm, 1e-290);
     for (int kb = 0; kb < K; kb += 16) {
         const int kk = kb + lane;
         const bool mine = lane < 16 && kk < K;
-        for (int it = 0; it < 3; ++it) {
+        const int kend = kb + 16 < K ? kb + 16 : K;
+        if (mine)
+            for (int i = 0; i < n; ++i) S.X[kk][i] = start_entry(i, kk);
+        for (int it = 0; it < INVIT_SWEEPS; ++it) {
+            long long ts0 = 0;
+            if (stamp) ts0 = clock64();
             if (mine) {
-                double sh = lam[kk];
+                double sh = S.lam[kk];
                 for (int j = 0; j < kk; ++j)
-                    if (fabs(sh - lam[j]) < 10.0 * eps * tnorm) sh = lam[j] - 10.0 * eps * tnorm * (kk - j);
-                // forward elimination with partial pivoting; the current row
-                // (c1, c2, c3) and right-hand side cb are carried in registers
-                double c1 = d[0] - sh, c2 = n > 1 ? e[0] : 0.0, c3 = 0.0;
-                double cb = it == 0 ? 1.0 + 0.3 * sin(0.9 * kk) : X[kk][0];
+                    if (fabs(sh - S.lam[j]) < 10.0 * tiny) sh = S.lam[j] - 10.0 * tiny * (kk - j);
+                // forward elimination with partial pivoting, branch-free; the
+                // current row (c1, c2) and right-hand side cb are carried in
+                // registers and the next row's operands are fetched one step
+                // ahead
+                const double2 d0 = S.de[0];
+                double c1 = d0.x - sh, c2 = d0.y, sub = d0.y;
+                double cb = S.X[kk][0];
+                double2 nxt = n > 1 ? S.de[1] : make_double2(0.0, 0.0);
+                double rsub = S.re[0];
+                double nb = n > 1 ? S.X[kk][1] : 0.0;
                 for (int i = 0; i + 1 < n; ++i) {
-                    const double sub = e[i];
-                    const double nd = d[i + 1] - sh, ne = (i + 2 < n) ? e[i + 1] : 0.0;
-                    const double nb = it == 0 ? 1.0 + 0.3 * sin(1.7 * (i + 1) + 0.9 * kk) : X[kk][i + 1];
-                    double r1, r2, r3, rb, m1, m2, mb;
-                    if (fabs(sub) > fabs(c1)) {
-                        const double mult = c1 / sub;
-                        r1 = sub; r2 = nd; r3 = ne; rb = nb;
-                        m1 = c2 - mult * nd; m2 = c3 - mult * ne; mb = cb - mult * nb;
-                    } else {
-                        const double piv = c1 != 0.0 ? c1 : eps * tnorm;
-                        const double mult = sub / piv;
-                        r1 = piv; r2 = c2; r3 = c3; rb = cb;
-                        m1 = nd - mult * c2; m2 = ne - mult * c3; mb = nb - mult * cb;
+                    double2 nxt2 = make_double2(0.0, 0.0);
+                    double rsub2 = 0.0, nb2 = 0.0;
+                    if (i + 2 < n) {
+                        nxt2 = S.de[i + 2];
+                        rsub2 = S.re[i + 1];
+                        nb2 = S.X[kk][i + 2];
                     }
-                    U1[i * 16 + lane] = r1;
-                    U2[i * 16 + lane] = r2;
-                    U3[i * 16 + lane] = r3;
-                    Bv[i * 16 + lane] = rb;
-                    c1 = m1; c2 = m2; c3 = 0.0; cb = mb;
-                    (void)m2;
-                    c2 = m2;
+                    const double nd = nxt.x - sh, ne = nxt.y;
+                    const bool swap = fabs(sub) > fabs(c1);
+                    const double rp = recip(c1 != 0.0 ? c1 : tiny);
+                    const double mult = swap ? c1 * rsub : sub * rp;
+                    U1[i * 16 + lane] = swap ? rsub : rp;
+                    U2[i * 16 + lane] = swap ? nd : c2;
+                    U3[i * 16 + lane] = swap ? ne : 0.0;
+                    Bv[i * 16 + lane] = swap ? nb : cb;
+                    const double p1 = swap ? c2 : nd, q1 = swap ? nd : c2;
+                    const double pb = swap ? cb : nb, qb = swap ? nb : cb;
+                    c1 = p1 - mult * q1;
+                    c2 = swap ? -mult * ne : ne;
+                    cb = pb - mult * qb;
+                    sub = ne;
+                    nxt = nxt2;
+                    rsub = rsub2;
+                    nb = nb2;
                 }
-                U1[(n - 1) * 16 + lane] = c1 != 0.0 ? c1 : eps * tnorm;
-                U2[(n - 1) * 16 + lane] = 0.0;
-                U3[(n - 1) * 16 + lane] = 0.0;
-                Bv[(n - 1) * 16 + lane] = cb;
+                const double rl = recip(c1 != 0.0 ? c1 : tiny);
+                // back substitution, the next row fetched one step ahead
                 double x1 = 0.0, x2 = 0.0;
+                double f1 = rl, f2 = 0.0, f3 = 0.0, fb = cb;
                 for (int i = n - 1; i >= 0; --i) {
-                    const double piv = U1[i * 16 + lane];
-                    const double v = (Bv[i * 16 + lane] - U2[i * 16 + lane] * x1 - U3[i * 16 + lane] * x2) /
-                                     (piv != 0.0 ? piv : eps * tnorm);
-                    X[kk][i] = v;
+                    double g1 = 0.0, g2 = 0.0, g3 = 0.0, gb = 0.0;
+                    if (i > 0) {
+                        g1 = U1[(i - 1) * 16 + lane];
+                        g2 = U2[(i - 1) * 16 + lane];
+                        g3 = U3[(i - 1) * 16 + lane];
+                        gb = Bv[(i - 1) * 16 + lane];
+                    }
+                    const double v = (fb - f2 * x1 - f3 * x2) * f1;
+                    S.X[kk][i] = v;
                     x2 = x1;
                     x1 = v;
+                    f1 = g1;
+                    f2 = g2;
+                    f3 = g3;
+                    fb = gb;
                 }
             }
             __syncthreads();
-            // normalise and orthogonalise this batch against earlier close vectors
-            for (int k = kb; k < kb + 16 && k < K; ++k) {
-                double xk = lane < n ? X[k][lane] : 0.0;
-                for (int j = 0; j < k; ++j)
-                    if (fabs(lam[j] - lam[k]) < 1e-3 * tnorm) {
-                        const double xj = lane < n ? X[j][lane] : 0.0;
-                        xk -= wsum(xj * xk) * xj;
-                    }
-                const double nrm = sqrt(wsum(xk * xk));
-                xk = nrm > 0.0 ? xk / nrm : 0.0;
-                if (lane < n) X[k][lane] = xk;
-                __syncthreads();
+            long long ts1 = 0;
+            if (stamp) ts1 = clock64();
+            // one Cholesky QR pass between sweeps, two after the last
+            orth_batch(S, n, kb, kend, it + 1 < INVIT_SWEEPS ? 1 : 2);
+            if (stamp && lane == 0) {
+                stamp[5] += ts1 - ts0;
+                stamp[6] += clock64() - ts1;
             }
         }
     }
     // eigenvalue = Rayleigh quotient of the tridiagonal on the final vector
-    for (int k = 0; k < K; ++k) {
-        double tx = 0.0, xi = 0.0;
-        if (lane < n) {
-            xi = X[k][lane];
-            tx = d[lane] * xi;
-            if (lane > 0) tx += e[lane - 1] * X[k][lane - 1];
-            if (lane + 1 < n) tx += e[lane] * X[k][lane + 1];
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        double s[8];
+        const double2 dl = lane < n ? S.de[lane] : make_double2(0.0, 0.0);
+        const double em = (lane > 0 && lane < n) ? S.de[lane - 1].y : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            double tx = 0.0, xi = 0.0;
+            if (k < K && lane < n) {
+                xi = S.X[k][lane];
+                tx = dl.x * xi;
+                if (lane > 0) tx += em * S.X[k][lane - 1];
+                if (lane + 1 < n) tx += dl.y * S.X[k][lane + 1];
+            }
+            s[u] = xi * tx;
         }
-        const double rq = wsum(xi * tx);
-        if (lane == 0) lam[k] = rq;
+        wsum8(s);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (lane == 0 && k0 + u < K) S.lam[k0 + u] = s[u];
     }
     __syncthreads();
     if (stamp && lane == 0) stamp[3] = clock64();
-    // 4. back-transform by the reflectors, last to first (lane = component)
-    for (int k = n - 3; k >= 0; --k) {
-        const double beta = Bh[k];
-        if (beta == 0.0) continue;
-        const double vi = lane < n ? Vh[k][lane] : 0.0;
-        for (int j0 = 0; j0 < K; j0 += 8) {
-            double xs[8], ps[8];
+    // ---- 4. back-transform by the reflectors, last to first (lane = eigenvector)
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        const int kk = k0 + lane;
+        const bool own = kk < K;
+        double xv[NP];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                xs[u] = (j0 + u < K && lane < n) ? X[j0 + u][lane] : 0.0;
-                ps[u] = vi * xs[u];
+        for (int j = 0; j < NP; ++j) xv[j] = (own && j < n) ? S.X[own ? kk : 0][j] : 0.0;
+        for (int r = n - 3; r >= 0; --r) {
+            const double beta = S.Bh[r];
+            const double* __restrict__ vr = S.Vh[r];
+            const int jlo = (r + 1) & ~7;          // v vanishes at indices <= r
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int j0 = 0; j0 < NP; j0 += 8) {
+                if (j0 >= jlo && j0 < n) {
+                    const double2* vp = reinterpret_cast<const double2*>(vr + j0);
+                    double2 u[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) u[q] = vp[q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        s0 += u[q].x * xv[j0 + 2 * q];
+                        s1 += u[q].y * xv[j0 + 2 * q + 1];
+                    }
+                }
             }
+            const double sb = beta * (s0 + s1);
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
+            for (int j0 = 0; j0 < NP; j0 += 8) {
+                if (j0 >= jlo && j0 < n) {
+                    const double2* vp = reinterpret_cast<const double2*>(vr + j0);
+                    double2 u[4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) ps[u] += __shfl_xor(ps[u], o, 64);
+                    for (int q = 0; q < 4; ++q) u[q] = vp[q];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (j0 + u < K && lane < n) X[j0 + u][lane] = xs[u] - beta * ps[u] * vi;
+                    for (int q = 0; q < 4; ++q) {
+                        xv[j0 + 2 * q] -= sb * u[q].x;
+                        xv[j0 + 2 * q + 1] -= sb * u[q].y;
+                    }
+                }
+            }
+        }
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+                if (j < n) S.X[kk][j] = xv[j];
         }
         __syncthreads();
     }
     if (stamp && lane == 0) stamp[4] = clock64();
 }
 
-// K largest eigenpairs of the symmetric q x q matrix scale * acc (row-major):
-// Z (column-major q x K, Z[i + k q] = component i of eigenvector k) and
-// theta, descending.  Clears acc.  One wavefront.
-__global__ __launch_bounds__(64) void k_sym_topk(double* __restrict__ acc, int q, double scale,
-                                                 int K, double* __restrict__ Zout,
+// K largest eigenpairs (theta_k, z_k) of the symmetric q x q leading block
+// of scale * G (G row-major, leading dimension ld).  Output Z is
+// column-major q x K (Z[i + k q] = component i of z_k), theta descending.
+// With fuse != 0, rows q and q + 1 of G hold F^T 1 and F^T tau with
+// tau_n = (tbar - t_n) / span, so that the two sign sums of the taper
+// w_k = c_k F z_k are c_k (F^T 1) . z_k and c_k (F^T tau) . z_k: Z then
+// receives +-wscale / sqrt(theta_k) z_k, the sign making the larger of the
+// two sums positive, and theta goes to lambda.  One wavefront; q <= NP.
+template <int NP>
+__global__ __launch_bounds__(64) void k_sym_topk(const double* __restrict__ G, int ld, int q,
+                                                 double scale, int K, int fuse, double wscale,
+                                                 double* __restrict__ Zout,
                                                  double* __restrict__ theta,
                                                  long long* __restrict__ stamp) {
     constexpr int LDA = MAXP + 1;
-    __shared__ double A[MAXP][LDA];
-    __shared__ double Vh[MAXP][LDA];
-    __shared__ double X[MAXP][LDA];
-    __shared__ double Bh[MAXP], d[MAXP], e[MAXP], e2[MAXP], lam[MAXP], tmp[2 * MAXP];
+    __shared__ __align__(16) EigShared<LDA> S;
     const int lane = threadIdx.x;
     for (int e_ = lane; e_ < q * q; e_ += 64) {
         const int i = e_ / q, j = e_ % q;
-        A[i][j] = 0.5 * scale * (acc[i * q + j] + acc[j * q + i]);
+        S.A[i][j] = 0.5 * scale * (G[i * ld + j] + G[j * ld + i]);
     }
     __syncthreads();
-    for (int e_ = lane; e_ < q * q; e_ += 64) acc[e_] = 0.0;
-    sym_topk_wave<LDA>(A, q, K, Vh, Bh, d, e, e2, lam, X, tmp, stamp);
-    for (int e_ = lane; e_ < q * K; e_ += 64) {
-        const int i = e_ % q, k = e_ / q;
-        Zout[e_] = X[k][i];
+    sym_topk_wave<LDA, NP>(S, q, K, stamp);
+    if (fuse) {
+        // sign sums, lane = taper
+        double f = 0.0;
+        if (lane < K) {
+            double a = 0.0, b = 0.0;
+            for (int i = 0; i < q; ++i) {
+                const double z = S.X[lane][i];
+                a += G[q * ld + i] * z;
+                b += G[(q + 1) * ld + i] * z;
+            }
+            const double key = fabs(a) >= fabs(b) ? a : b;
+            const double th = S.lam[lane];
+            f = (key < 0.0 ? -wscale : wscale) / sqrt(th > 0.0 ? th : 1e-300);
+            S.tmp[lane] = f;
+        }
+        __syncthreads();
+        for (int e_ = lane; e_ < q * K; e_ += 64) {
+            const int i = e_ % q, k = e_ / q;
+            Zout[e_] = S.tmp[k] * S.X[k][i];
+        }
+    } else {
+        for (int e_ = lane; e_ < q * K; e_ += 64) {
+            const int i = e_ % q, k = e_ / q;
+            Zout[e_] = S.X[k][i];
+        }
     }
-    if (lane < K) theta[lane] = lam[lane];
+    if (lane < K) theta[lane] = S.lam[lane];
+}
+
+// register-array size picked from the matrix order
+void launch_sym_topk(hipStream_t st, const double* G, int ld, int q, double scale, int K, int fuse,
+                     double wscale, double* Z, double* theta) {
+    long long* ns = nullptr;
+#define M2N_SYM(NPV) \
+    hipLaunchKernelGGL(k_sym_topk<NPV>, dim3(1), dim3(64), 0, st, G, ld, q, scale, K, fuse, wscale, Z, theta, ns)
+    if (q <= 16) M2N_SYM(16);
+    else if (q <= 32) M2N_SYM(32);
+    else if (q <= 40) M2N_SYM(40);
+    else if (q <= 48) M2N_SYM(48);
+    else M2N_SYM(64);
+#undef M2N_SYM
 }
 
 // ------------------------------------- Rayleigh-Ritz on a general basis
@@ -460,16 +852,15 @@ __global__ __launch_bounds__(64) void k_sym_topk(double* __restrict__ acc, int q
 // of C in span(V) are (theta, V Q) with Q = R^{-1} Q', where
 // R^{-T} H R^{-1} = Q' diag(theta) Q'^T.  Y = V Q has orthonormal columns.
 // Output: Q (column-major, Q[i + j p] = component i of Ritz vector j) and
-// theta, in descending order of theta.  Clears acc.  One wavefront.
+// theta, in descending order of theta.  One wavefront.
+template <int NP>
 __global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p,
                                                  double* __restrict__ Qout,
                                                  double* __restrict__ theta) {
     constexpr int LDA = MAXP + 1;
     __shared__ double G[MAXP][LDA];     // V^T V, then R (upper)
-    __shared__ double H[MAXP][LDA];     // V^T W, then R^{-T} H R^{-1}
-    __shared__ double Vh[MAXP][LDA];
-    __shared__ double X[MAXP][LDA];
-    __shared__ double Bh[MAXP], d[MAXP], e[MAXP], e2[MAXP], lam[MAXP], tmp[2 * MAXP];
+    __shared__ __align__(16) EigShared<LDA> S;
+    auto& H = S.A;                      // V^T W, then R^{-T} H R^{-1}
     const int tid = threadIdx.x;
     const int np = p * p;
     for (int e_ = tid; e_ < 2 * np; e_ += 64) {
@@ -479,7 +870,6 @@ __global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p
         else H[i][j] = s;
     }
     __syncthreads();
-    for (int e_ = tid; e_ < 2 * np; e_ += 64) acc[e_] = 0.0;
     double dmax = 0.0;
     for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i][i]);
     const double pfloor = dmax * 1e-24 + 1e-300;
@@ -524,64 +914,133 @@ __global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p
         }
     }
     __syncthreads();
-    sym_topk_wave<LDA>(H, p, p, Vh, Bh, d, e, e2, lam, X, tmp);
+    sym_topk_wave<LDA, NP>(S, p, p);
     for (int jc = tid; jc < p; jc += 64) {   // Q = R^{-1} Q'
         for (int i = p - 1; i >= 0; --i) {
-            double s = X[jc][i];
+            double s = S.X[jc][i];
             for (int k = i + 1; k < p; ++k) s -= G[i][k] * Qout[k + jc * p];
             Qout[i + jc * p] = s / G[i][i];
         }
-        theta[jc] = lam[jc];
+        theta[jc] = S.lam[jc];
     }
 }
 
 // ------------------------------------------- quadrature basis of R(A0)
 // R(A0)_{nm} = int_{-fw}^{fw} e^{j 2 pi f (t_n - t_m)} df.  With Gauss-Legendre
-// nodes +-f_q and weights w_q on [-fw, fw] (symmetric pairs), the imaginary
-// parts cancel and R(A0) = F F^T with the 2 columns per positive node
-//   F[2q][n] = sqrt(2 w_q) cos(2 pi f_q tau_n),
-//   F[2q+1][n] = sqrt(2 w_q) sin(2 pi f_q tau_n),   tau_n = t_n - t_c.
-// Rows n >= N are zero.  Column-major with leading dimension Np.
+// nodes +-f_q = +-fw x_q and weights fw g_q on [-fw, fw] (symmetric pairs),
+// the imaginary parts cancel and R(A0) = F F^T with 2 columns per positive
+// node
+//   F[2q][n] = sqrt(2 fw g_q) cos(2 pi f_q tau_n),
+//   F[2q+1][n] = sqrt(2 fw g_q) sin(2 pi f_q tau_n),   tau_n = t_n - t_c.
+// With aux != 0 two more columns hold 1 and (t_c - t_n) / span, whose
+// products with F give the sign sums of the tapers.  Rows n >= N are zero.
+// Column-major with leading dimension Np; grid (Np / 256, nq + aux).
 __global__ void k_lr_basis(const double* __restrict__ t, int64_t N, int64_t Np, double tc,
-                           const double* __restrict__ fq, const double* __restrict__ sq, int nq,
-                           double* __restrict__ F) {
+                           double span, double fw, const double* __restrict__ glx,
+                           const double* __restrict__ glw, int nq, double* __restrict__ F) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
-    if (n >= Np || q >= nq) return;
+    if (n >= Np) return;
     double c = 0.0, s = 0.0;
-    if (n < N) {
-        sincospi(2.0 * fq[q] * (t[n] - tc), &s, &c);
-        c *= sq[q];
-        s *= sq[q];
+    if (q < nq) {
+        if (n < N) {
+            sincospi(2.0 * fw * glx[q] * (t[n] - tc), &s, &c);
+            const double sq = sqrt(2.0 * fw * glw[q]);
+            c *= sq;
+            s *= sq;
+        }
+    } else if (n < N) {
+        c = 1.0;
+        s = (tc - t[n]) / span;
     }
     F[(int64_t)(2 * q) * Np + n] = c;
     F[(int64_t)(2 * q + 1) * Np + n] = s;
 }
 
-// Y[k][n] = s_k * sum_j A[j][n] Z[j + k q] for k < K, s_k = 1 / sqrt(c theta_k)
+// Y[k * ldy + n] = s_k * sum_j A[j][n] Z[j + k q] for k < K and n < nrows,
+// s_k = 1 / sqrt(c theta_k), or 1 when theta is NULL (Z already scaled)
 template <int QC>
 __global__ __launch_bounds__(64) void k_lr_expand(const double* __restrict__ A, int64_t Np,
                                                   int64_t N, int q, const double* __restrict__ Z,
                                                   const double* __restrict__ theta, double c,
-                                                  int K, double* __restrict__ Y) {
+                                                  int K, double* __restrict__ Y, int64_t ldy,
+                                                  int64_t nrows) {
     __shared__ double Zs[QC * MAXP];
     __shared__ double sk[MAXP];
     for (int e = threadIdx.x; e < QC * K; e += 64) {
         const int j = e % QC, k = e / QC;
         Zs[e] = j < q ? Z[j + k * q] : 0.0;
     }
-    for (int k = threadIdx.x; k < K; k += 64) sk[k] = 1.0 / sqrt(c * theta[k]);
+    for (int k = threadIdx.x; k < K; k += 64) sk[k] = theta ? 1.0 / sqrt(c * theta[k]) : 1.0;
     __syncthreads();
     const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (n >= Np) return;
+    if (n >= nrows) return;
+    // unconditional loads from clamped addresses (rows < Np and columns < q
+    // are allocated), so that all are in flight together
     double a[QC];
 #pragma unroll
-    for (int j = 0; j < QC; ++j) a[j] = (j < q && n < N) ? A[(int64_t)j * Np + n] : 0.0;
+    for (int j = 0; j < QC; ++j) a[j] = A[(int64_t)(j < q ? j : q - 1) * Np + n];
+#pragma unroll
+    for (int j = 0; j < QC; ++j) a[j] = (j < q && n < N) ? a[j] : 0.0;
     for (int k = 0; k < K; ++k) {
         double y = 0.0;
 #pragma unroll
         for (int j = 0; j < QC; ++j) y += a[j] * Zs[k * QC + j];
-        Y[(int64_t)k * Np + n] = y * sk[k];
+        Y[(int64_t)k * ldy + n] = y * sk[k];
+    }
+}
+
+// ------------------------------------- checks of the sampling times
+// Per workgroup: flags (bit 0 a non-finite t_n, bit 1 a step t_n <= t_{n-1},
+// bit 2 a t_n that is not an integer of magnitude <= 4e15) and the first
+// offending indices; workgroup 0 also stores t_0 and t_{N-1}.  The record
+// lives in pinned host memory and is read after the stream synchronises.
+struct TInfo {
+    int flags;
+    int pad;
+    unsigned long long first_nonfinite, first_order;
+};
+
+__global__ __launch_bounds__(256) void k_t_analyze(const double* __restrict__ t, int64_t N,
+                                                   int64_t per_wg, double* __restrict__ hdr,
+                                                   TInfo* __restrict__ info) {
+    __shared__ int sf;
+    __shared__ unsigned long long snf, sord;
+    if (threadIdx.x == 0) {
+        sf = 0;
+        snf = ~0ull;
+        sord = ~0ull;
+    }
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per_wg;
+    const int64_t b1 = b0 + per_wg < N ? b0 + per_wg : N;
+    int flags = 0;
+    unsigned long long fnf = ~0ull, ford = ~0ull;
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += 256) {
+        const double v = t[n];
+        if (!isfinite(v)) {
+            flags |= 1;
+            fnf = fnf < (unsigned long long)n ? fnf : (unsigned long long)n;
+            continue;
+        }
+        if (n > 0 && !(v > t[n - 1])) {
+            flags |= 2;
+            ford = ford < (unsigned long long)n ? ford : (unsigned long long)n;
+        }
+        if (v != rint(v) || fabs(v) > 4.0e15) flags |= 4;
+    }
+    if (flags) atomicOr(&sf, flags);
+    if (fnf != ~0ull) atomicMin(&snf, fnf);
+    if (ford != ~0ull) atomicMin(&sord, ford);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        info[blockIdx.x].flags = sf;
+        info[blockIdx.x].first_nonfinite = snf;
+        info[blockIdx.x].first_order = sord;
+        if (blockIdx.x == 0) {
+            hdr[0] = t[0];
+            hdr[1] = t[N - 1];
+        }
     }
 }
 
@@ -657,9 +1116,10 @@ __global__ void k_fill_int(int* __restrict__ a, int64_t n, int v) {
     if (i < n) a[i] = v;
 }
 
-__global__ void k_lattice_map(const int* __restrict__ off, int64_t N, int* __restrict__ map) {
+// map[t_n - t_0] = n for integer sampling times
+__global__ void k_lattice_map(const double* __restrict__ t, int64_t N, int* __restrict__ map) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n < N) map[off[n]] = (int)n;
+    if (n < N) map[(int64_t)(t[n] - t[0])] = (int)n;
 }
 
 // h[l] = s(l) for l <= S, s(l - M) for l >= M - S, else 0 (complex, imag 0)
@@ -1279,11 +1739,12 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, dou
     hipStream_t st = S.st;
     const int64_t N = S.N, Np = S.Np;
     const int p = S.p, K = S.K;
-    const int gram_wg = (int)(nchunks < 256 ? nchunks : 256);
+    const int gram_wg = (int)(nchunks < GRAM_WG_MAX ? nchunks : GRAM_WG_MAX);
     const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
     const int row_wg = (int)((Np + 63) / 64);
     const int pc = (p + 7) / 8 * 8;
-    M2N_HIP(hipMemsetAsync(gacc, 0, sizeof(double) * 2 * (size_t)p * p, st));
+    void* vpart;
+    M2N_TRY(ctx->workspace("gep_gpart", sizeof(double) * (size_t)gram_wg * 2 * p * p, &vpart));
     {
         M2N_PROF(ctx, st, "k_randinit");
         dim3 g2((unsigned)((Np + 255) / 256), (unsigned)p);
@@ -1297,11 +1758,16 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, dou
         {
             M2N_PROF(ctx, st, "k_gram2");
             hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, cpw, nchunks,
-                               2, gacc);
+                               2, (double*)vpart);
+            hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((2 * p * p + 63) / 64)), dim3(256), 0,
+                               st, (const double*)vpart, gram_wg, 2 * p * p, gacc);
         }
         {
             M2N_PROF(ctx, st, "k_small_rr");
-            hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
+            if (p <= 16) hipLaunchKernelGGL(k_small_rr<16>, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
+            else if (p <= 32) hipLaunchKernelGGL(k_small_rr<32>, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
+            else if (p <= 48) hipLaunchKernelGGL(k_small_rr<48>, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
+            else hipLaunchKernelGGL(k_small_rr<64>, dim3(1), dim3(64), 0, st, gacc, p, Q, th);
         }
         {
             M2N_PROF(ctx, st, "k_rotate2");
@@ -1343,32 +1809,50 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, dou
 
 int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmax, double fw,
             int K, double* w_out, double* lambda_out) {
-    // ---- host analysis of the sampling times
-    std::vector<double> t(N);
-    M2N_HIP(hipMemcpyAsync(t.data(), t_dev, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, st));
-    M2N_HIP(hipStreamSynchronize(st));
-    bool integral = true;
-    for (int64_t n = 0; n < N; ++n) {
-        if (!std::isfinite(t[n])) {
-            set_error("non-finite sampling time at %lld", (long long)n);
-            return M2N_ERR_ARG;
-        }
-        if (n > 0 && !(t[n] > t[n - 1])) {
-            set_error("sampling times not strictly increasing at %lld", (long long)n);
-            return M2N_ERR_T_ORDER;
-        }
-        if (t[n] != std::rint(t[n]) || std::fabs(t[n]) > 4.0e15) integral = false;
+    // ---- checks of the sampling times on the device; one host round trip
+    const int64_t per_wg = N <= 256 * 256 ? 256 : (N + 255) / 256;
+    const int awg = (int)((N + per_wg - 1) / per_wg);
+    if (!ctx->hinfo) {
+        M2N_HIP(hipHostMalloc(&ctx->hinfo, 16384, hipHostMallocDefault));
     }
+    double* hdr = (double*)ctx->hinfo;
+    TInfo* info = (TInfo*)((char*)ctx->hinfo + 64);
+    {
+        M2N_PROF(ctx, st, "k_t_analyze");
+        hipLaunchKernelGGL(k_t_analyze, dim3(awg), dim3(256), 0, st, t_dev, N, per_wg, hdr, info);
+    }
+    M2N_HIP(hipGetLastError());
+    M2N_HIP(hipStreamSynchronize(st));
+    int flags = 0;
+    unsigned long long fnf = ~0ull, ford = ~0ull;
+    for (int g = 0; g < awg; ++g) {
+        flags |= info[g].flags;
+        fnf = std::min(fnf, info[g].first_nonfinite);
+        ford = std::min(ford, info[g].first_order);
+    }
+    if (flags & 1) {
+        set_error("non-finite sampling time at %llu", fnf);
+        return M2N_ERR_ARG;
+    }
+    if (flags & 2) {
+        set_error("sampling times not strictly increasing at %llu", ford);
+        return M2N_ERR_T_ORDER;
+    }
+    const double t0 = hdr[0], tN = hdr[1];
+    const bool integral = !(flags & 4);
     const double cB = 2.0 * fmax;
-    const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 && (t[N - 1] - t[0]) < 2.0e6;
-    const double span = N > 1 ? t[N - 1] - t[0] : 0.0;
+    const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 && (tN - t0) < 2.0e6;
+    const double span = N > 1 ? tN - t0 : 0.0;
+    const double tc = 0.5 * (t0 + tN);
     // quadrature rank of R(A0): Gauss-Legendre in f over [-fw, fw]; the
-    // integrand e^{j 2 pi f tau} has at most beta = 2 pi fw span radians
+    // integrand e^{j 2 pi f tau} turns through at most beta = 2 pi fw span
+    // radians, and 0.7 beta + 14 nodes reach rounding level for beta <= 90
     const double beta = 2.0 * M_PI * fw * span;
-    int Qn = (int)std::ceil(0.8 * beta) + 16;
+    int Qn = (int)std::ceil(0.7 * beta) + 14;
     if (Qn < K + 2) Qn = K + 2;
     Qn += Qn & 1;
-    const bool lowrank = Qn <= MAXP;
+    const int aux = lattice ? 2 : 0;      // sign-sum columns of the fused finish
+    const bool lowrank = Qn + aux <= MAXP;
     Solver S;
     S.ctx = ctx;
     S.st = st;
@@ -1378,22 +1862,26 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     S.lattice = lattice;
     const int64_t Np = S.Np;
     const int64_t nchunks = (Np + GRAM_ROWS - 1) / GRAM_ROWS;
-    const int gram_wg = (int)(nchunks < 256 ? nchunks : 256);
+    const int gram_wg = (int)(nchunks < GRAM_WG_MAX ? nchunks : GRAM_WG_MAX);
     const int cpw = (int)((nchunks + gram_wg - 1) / gram_wg);
     const int row_wg = (int)((Np + GNT - 1) / GNT);
     const int rot_wg = (int)((Np + 63) / 64);
-    void *vt, *vY, *vpart, *vQ, *vth, *vgacc;
-    M2N_TRY(ctx->workspace("gep_t", sizeof(double) * (size_t)N, &vt));
-    M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)MAXP * Np, &vY));
-    M2N_TRY(ctx->workspace("gep_part", sizeof(double) * (size_t)row_wg * 2 * K + 64, &vpart));
+    void *vY, *vpart, *vQ, *vth, *vgacc;
     M2N_TRY(ctx->workspace("gep_Q", sizeof(double) * MAXP * MAXP, &vQ));
     M2N_TRY(ctx->workspace("gep_th", sizeof(double) * MAXP, &vth));
     M2N_TRY(ctx->workspace("gep_gacc", sizeof(double) * 2 * MAXP * MAXP, &vgacc));
-    double *Y = (double*)vY, *part = (double*)vpart, *Qm = (double*)vQ, *th = (double*)vth;
+    double *Qm = (double*)vQ, *th = (double*)vth;
     double* gacc = (double*)vgacc;
-    M2N_HIP(hipMemcpyAsync(vt, t_dev, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st));
-    const double* td = (const double*)vt;
-    M2N_HIP(hipMemsetAsync(gacc, 0, sizeof(double) * 2 * MAXP * MAXP, st));
+    const double* td = t_dev;
+    double* Y = nullptr;
+    double* part = nullptr;
+    auto need_Y = [&]() -> int {
+        M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)MAXP * Np, &vY));
+        M2N_TRY(ctx->workspace("gep_part", sizeof(double) * (size_t)row_wg * 2 * K + 64, &vpart));
+        Y = (double*)vY;
+        part = (double*)vpart;
+        return M2N_OK;
+    };
 
     // dense path: R(B) = L L^T by the tiled Cholesky (zero tiles skipped)
     auto factor_RB = [&]() -> int {
@@ -1443,29 +1931,39 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     };
 
     double scale;   // w = scale * (L^{-T}) y
-    std::vector<double> fq, sq;
     if (lowrank) {
         // ---- R(A0) = F F^T from the quadrature of its defining integral
-        std::vector<double> gx, gw;
-        gauss_legendre(Qn, gx, gw);
-        for (int i = 0; i < Qn; ++i)
-            if (gx[i] > 0.0) {
-                fq.push_back(fw * gx[i]);
-                sq.push_back(std::sqrt(2.0 * fw * gw[i]));
-            }
-        const int nq = (int)fq.size();   // Qn / 2
-        void *vF, *vfq;
-        M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)Qn * Np, &vF));
-        M2N_TRY(ctx->workspace("gep_fq", sizeof(double) * 2 * MAXP, &vfq));
+        const int nq = Qn / 2;
+        auto itg = ctx->gl.find(Qn);
+        if (itg == ctx->gl.end()) {
+            std::vector<double> gx, gw, tab(2 * MAXP, 0.0);
+            gauss_legendre(Qn, gx, gw);
+            int j = 0;
+            for (int i = 0; i < Qn; ++i)
+                if (gx[i] > 0.0) {
+                    tab[j] = gx[i];
+                    tab[MAXP + j] = gw[i];
+                    ++j;
+                }
+            DevBuf b;
+            M2N_TRY(ctx->alloc(b, sizeof(double) * 2 * MAXP));
+            M2N_HIP(hipMemcpy(b.p, tab.data(), sizeof(double) * 2 * MAXP, hipMemcpyHostToDevice));
+            itg = ctx->gl.emplace(Qn, b).first;
+        }
+        const double* glx = (const double*)itg->second.p;
+        const int pF = Qn + aux;            // columns of F
+        void *vF, *vgp;
+        M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)pF * Np, &vF));
+        // one 64-row chunk per wavefront up to 512 of them
+        const int mfma_wg = (int)(nchunks < 512 ? nchunks : 512);
+        const int mcpw = (int)((nchunks + mfma_wg - 1) / mfma_wg);
+        M2N_TRY(ctx->workspace("gep_gpart", sizeof(double) * (size_t)mfma_wg * pF * pF, &vgp));
         double* F = (double*)vF;
-        double* dfq = (double*)vfq;
-        M2N_HIP(hipMemcpyAsync(dfq, fq.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
-        M2N_HIP(hipMemcpyAsync(dfq + MAXP, sq.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
         {
             M2N_PROF(ctx, st, "k_lr_basis");
-            dim3 g((unsigned)((Np + 255) / 256), (unsigned)nq);
-            hipLaunchKernelGGL(k_lr_basis, g, dim3(256), 0, st, td, N, Np, 0.5 * (t[0] + t[N - 1]),
-                               (const double*)dfq, (const double*)(dfq + MAXP), nq, F);
+            dim3 g((unsigned)((Np + 255) / 256), (unsigned)(nq + (aux ? 1 : 0)));
+            hipLaunchKernelGGL(k_lr_basis, g, dim3(256), 0, st, td, N, Np, tc, span > 0.0 ? span : 1.0,
+                               fw, glx, glx + MAXP, nq, F);
         }
         M2N_HIP(hipGetLastError());
         double cdiv = cB;
@@ -1477,22 +1975,38 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
             cdiv = 1.0;
         }
         {
-            M2N_PROF(ctx, st, "k_gram2");
-            hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, F, F, Np, N, Qn, cpw,
-                               nchunks, 1, gacc);
+            M2N_PROF(ctx, st, "k_gram_mfma");
+            const int nt = (pF + 15) / 16;
+            dim3 g((unsigned)mfma_wg);
+            if (nt == 1) hipLaunchKernelGGL(k_gram_mfma<1>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
+            else if (nt == 2) hipLaunchKernelGGL(k_gram_mfma<2>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
+            else if (nt == 3) hipLaunchKernelGGL(k_gram_mfma<3>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
+            else hipLaunchKernelGGL(k_gram_mfma<4>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
         }
         {
-            M2N_PROF(ctx, st, "k_sym_topk");
-            hipLaunchKernelGGL(k_sym_topk, dim3(1), dim3(64), 0, st, gacc, Qn, 1.0 / cdiv, K, Qm, th,
-                               (long long*)nullptr);
+            M2N_PROF(ctx, st, "k_gram_reduce");
+            hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((pF * pF + 63) / 64)), dim3(256), 0,
+                               st, (const double*)vgp, mfma_wg, pF * pF, gacc);
         }
+        // lattice: w_k = sqrt(2 fw / c) F z_k / sqrt(c theta_k), finished in
+        // the eigen-solver (sign, scale) and the expansion (written to w)
+        const double wscale = std::sqrt(2.0 * fw) / cB;
+        {
+            M2N_PROF(ctx, st, "k_sym_topk");
+            launch_sym_topk(st, gacc, pF, Qn, 1.0 / cdiv, K, lattice ? 1 : 0, wscale, Qm,
+                            lattice ? lambda_out : th);
+        }
+        if (!lattice) M2N_TRY(need_Y());
         {
             M2N_PROF(ctx, st, "k_lr_expand");
             const int qc = (Qn + 7) / 8 * 8;
+            const double* thp = lattice ? nullptr : th;
+            double* dst = lattice ? w_out : Y;
+            const int64_t ldy = lattice ? N : Np;
 #define M2N_EXP(QCV)                                                                              \
     case QCV:                                                                                     \
-        hipLaunchKernelGGL(k_lr_expand<QCV>, dim3(rot_wg), dim3(64), 0, st, F, Np, N, Qn, Qm, th, \
-                           cdiv, K, Y);                                                           \
+        hipLaunchKernelGGL(k_lr_expand<QCV>, dim3(rot_wg), dim3(64), 0, st, F, Np, N, Qn, Qm, thp, \
+                           cdiv, K, dst, ldy, ldy);                                               \
         break;
             switch (qc) {
                 M2N_EXP(8) M2N_EXP(16) M2N_EXP(24) M2N_EXP(32) M2N_EXP(40) M2N_EXP(48) M2N_EXP(56)
@@ -1504,13 +2018,10 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
 #undef M2N_EXP
         }
         M2N_HIP(hipGetLastError());
-        if (lattice) {
-            scale = std::sqrt(2.0 * fw / cB);
-        } else {
-            S.p = K;
-            M2N_TRY(S.trsv(Y, 1));   // w = L^{-T} y
-            scale = std::sqrt(2.0 * fw);
-        }
+        if (lattice) return M2N_OK;   // stream-ordered from here; nothing to read back
+        S.p = K;
+        M2N_TRY(S.trsv(Y, 1));   // w = L^{-T} y
+        scale = std::sqrt(2.0 * fw);
     } else {
         // ---- wide band: block subspace iteration
         int p = (int)std::ceil(2.0 * fw * span) + 8;
@@ -1524,10 +2035,11 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
         M2N_TRY(ctx->workspace("gep_W", sizeof(double) * (size_t)p * Np, &vW));
         M2N_TRY(ctx->workspace("gep_res", sizeof(double) * (size_t)rot_wg * K, &vres));
         double *V = (double*)vV, *W = (double*)vW, *res = (double*)vres;
+        M2N_TRY(need_Y());
         // W's padded rows are never written by the lattice convolution
         M2N_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * Np, st));
         if (lattice) {
-            const int64_t Sspan = (int64_t)(t[N - 1] - t[0]);
+            const int64_t Sspan = (int64_t)(tN - t0);
             int64_t M = 64;
             while (M < 2 * Sspan + 1) M *= 2;
             auto itp = ctx->fft64.find(M);
@@ -1541,18 +2053,13 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
                 itp = ctx->fft64.emplace(M, std::move(plan)).first;
             }
             S.fft = itp->second.get();
-            std::vector<int> off(N);
-            for (int64_t n = 0; n < N; ++n) off[n] = (int)(t[n] - t[0]);
-            void *vmap, *voff, *vH, *vc1, *vc2, *vs;
+            void *vmap, *vH, *vc1, *vc2, *vs;
             const int pairs = (p + 1) / 2;
             M2N_TRY(ctx->workspace("gep_map", sizeof(int) * (size_t)M, &vmap));
-            M2N_TRY(ctx->workspace("gep_off", sizeof(int) * (size_t)N, &voff));
             M2N_TRY(ctx->workspace("gep_H", sizeof(double) * (size_t)M, &vH));
             M2N_TRY(ctx->workspace("gep_c1", sizeof(cplx<double>) * (size_t)M * pairs, &vc1));
             M2N_TRY(ctx->workspace("gep_c2", sizeof(cplx<double>) * (size_t)M * pairs, &vc2));
             M2N_TRY(ctx->workspace("gep_hs", sizeof(cplx<double>) * (size_t)M, &vs));
-            M2N_HIP(hipMemcpyAsync(voff, off.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice,
-                                   st));
             S.map = (int*)vmap;
             S.Hhat = (double*)vH;
             S.cbuf1 = (cplx<double>*)vc1;
@@ -1562,7 +2069,7 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
                 hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                                    S.map, M, -1);
                 hipLaunchKernelGGL(k_lattice_map, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                                   (const int*)voff, N, S.map);
+                                   td, N, S.map);
                 hipLaunchKernelGGL(k_toep_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                                    S.cbuf2, M, Sspan, fw);
             }

@@ -131,6 +131,8 @@ struct Ctx {
     std::map<std::string, DevBuf> ws;   // named grow-only workspaces
     unsigned* dev_err = nullptr;        // sticky device error word
     int cu_count = 256;
+    void* hinfo = nullptr;              // pinned host record of the t checks
+    std::map<int, DevBuf> gl;           // Gauss-Legendre nodes/weights by order
 
     // kernel timing (m2n_profile_*)
     bool prof = false;
