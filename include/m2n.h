@@ -27,11 +27,13 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *  - Layouts are row-major: tapers w are K x N (taper k at w + k*N), the
  *    eigencoefficients J are K x I complex (interleaved re, im).
- *  - Sizes are int64_t; N >= 1, 1 <= K <= min(N, 64), 1 <= I <= 2^23.
+ *  - Sizes are int64_t; N >= 1, 1 <= K <= min(N, 64), 1 <= I <= 2^21.
  *  - Errors are returned as m2n_status codes; nothing aborts and no C++
  *    exception crosses the ABI.  m2n_last_error() gives a text for the last
  *    failure on the calling thread.
  *  - A context is not thread-safe: one host thread at a time per context.
+ *    Its workspace is reused from call to call, so calls on one context
+ *    must be ordered: one stream, or the caller synchronises between them.
  */
 #ifndef M2N_H
 #define M2N_H
@@ -88,9 +90,15 @@ size_t m2n_workspace_bytes(const m2n_ctx *ctx);
  *                   sum_n (tbar - t_n) w_k(t_n) is positive, tbar = (t_1+t_N)/2
  *   lambda  [K]     device, FP64 out, descending, in [0, 1]
  *
- * Blocks the calling thread until the tapers are on the device (the solver
- * reads back its convergence test).  Errors: M2N_ERR_T_ORDER, M2N_ERR_NOT_PD
- * (Cholesky pivot <= 0; no silent regularisation), M2N_ERR_NO_CONVERGE.
+ * The call first checks t on the device and waits for that check (one short
+ * round trip; t is never copied to the host).  When R(B) is a multiple of
+ * the identity (t on an integer lattice, 2 f_max a positive integer) the rest
+ * is stream-ordered and the call returns before the tapers are complete;
+ * otherwise (dense R(B), or the subspace-iteration fallback for wide bands)
+ * it blocks until they are, since it reads back the Cholesky or convergence
+ * status.  Errors: M2N_ERR_ARG (non-finite t), M2N_ERR_T_ORDER,
+ * M2N_ERR_NOT_PD (Cholesky pivot <= 0; no silent regularisation),
+ * M2N_ERR_NO_CONVERGE, M2N_ERR_UNSUPPORTED (dense N > 65536).
  */
 int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                 double fmax, double fw, double fc0, int K,
