@@ -147,6 +147,39 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                 int prec, double nufft_tol, const double *weights, void *P,
                 void *E, void *J);
 
+/*
+ * m2n_batch_psd -- gpss_tapers followed by m2nufft_psd for many series, in
+ * batched launches: one check of all sampling times (one host round trip),
+ * the tapers of every series whose R(B) is a multiple of the identity in
+ * one set of launches (the others one by one), then one NuFFT launch set per
+ * distinct band count I.  Results equal the per-series calls within the
+ * NuFFT tolerance (the tapers are bitwise equal).
+ *
+ *   series  [nseries] HOST array of descriptors; every pointer inside is a
+ *           device pointer with the layout of the per-series calls:
+ *             t, x [N]; w [K*N] out; lambda [K] out; weights [K] or NULL;
+ *             P [I] out; E [I] out or NULL; J [K*I] out or NULL
+ *   prec, nufft_tol as in m2nufft_psd (one value for the whole batch)
+ *
+ * Errors name the offending series in m2n_last_error().  Stream-ordered
+ * after the t check, except for series that take the dense or wide-band
+ * taper path (see gpss_tapers), which block.
+ */
+typedef struct {
+    const double *t, *x;
+    int64_t N;
+    int K;
+    double fmax, fw;
+    double f_lo, df;
+    int64_t I;
+    const double *weights;
+    double *w, *lambda;
+    void *P, *E, *J;
+} m2n_series;
+
+int m2n_batch_psd(m2n_ctx *ctx, void *stream, const m2n_series *series, int nseries,
+                  int prec, double nufft_tol);
+
 /* Kernel timing.  While enabled, every kernel launch of the library is
  * bracketed by a pair of HIP events recorded on the launch stream;
  * m2n_profile_read waits for them and returns, per kernel name, the total

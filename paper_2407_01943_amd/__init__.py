@@ -7,6 +7,7 @@ The functions keep the C-ABI names:
     gpss_tapers(ctx, t, fmax, fw, K, fc0=0.0)            -> (w [K, N], lam [K])
     m2nufft_eigcoeffs(ctx, t, x, w, f_lo, df, I, prec)   -> J [K, I] complex
     m2nufft_psd(ctx, t, x, w, lam, fmax, fw, f_lo, df, I, prec, ...) -> dict
+    m2n_batch_psd(ctx, series, prec, ...)                -> list of dicts
 
 If libm2n.so is missing or cannot be loaded the import fails: there is no
 CPU fallback.
@@ -36,7 +37,18 @@ M2N_FP64 = 2
 
 EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes",
             "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
-            "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read"]
+            "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
+            "m2n_batch_psd"]
+
+
+class M2NSeries(ctypes.Structure):
+    """m2n_series of include/m2n.h (device pointers, host array)."""
+    _fields_ = [("t", ctypes.c_void_p), ("x", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int), ("fmax", ctypes.c_double), ("fw", ctypes.c_double),
+                ("f_lo", ctypes.c_double), ("df", ctypes.c_double), ("I", ctypes.c_int64),
+                ("weights", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("P", ctypes.c_void_p), ("E", ctypes.c_void_p),
+                ("J", ctypes.c_void_p)]
 
 
 class M2NError(RuntimeError):
@@ -75,6 +87,8 @@ def _load():
     L.m2nufft_psd.argtypes = [vp, vp, vp, vp, i64, vp, vp, i, d, d, d, d, i64, i, d,
                               vp, vp, vp, vp]
     L.m2nufft_psd.restype = i
+    L.m2n_batch_psd.argtypes = [vp, vp, ctypes.POINTER(M2NSeries), i, i, d]
+    L.m2n_batch_psd.restype = i
     return L
 
 
@@ -201,3 +215,38 @@ def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64
     if check:
         ctx.check(stream)
     return {"P": P, "E": E, "J": J}
+
+
+def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=True,
+                  want_J=False, stream=None, check=True):
+    """Tapers and PSD of many series in batched launches.  `series` is a list of
+    dicts with device tensors t, x and the numbers fmax, fw, K, f_lo, df, I
+    (optional "weights", "want_E", and "w", "lam", "P", "E", "J" output
+    tensors).
+    Returns a list of {"w", "lam", "P", "E", "J"}."""
+    rdt = torch.float32 if prec == M2N_FP32 else torch.float64
+    cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
+    arr = (M2NSeries * len(series))()
+    outs = []
+    for j, s in enumerate(series):
+        t, x = _dev(s["t"]), _dev(s["x"])
+        N, K, I = t.shape[0], int(s["K"]), int(s["I"])
+        dev = t.device
+        w = s.get("w") if s.get("w") is not None else torch.empty((K, N), dtype=torch.float64, device=dev)
+        lam = s.get("lam") if s.get("lam") is not None else torch.empty((K,), dtype=torch.float64, device=dev)
+        P = s.get("P") if s.get("P") is not None else torch.empty((I,), dtype=rdt, device=dev)
+        wE = s.get("want_E", want_E)
+        E = s.get("E") if s.get("E") is not None else (torch.empty((I,), dtype=rdt, device=dev) if wE else None)
+        J = s.get("J") if s.get("J") is not None else (torch.empty((K, I), dtype=cdt, device=dev) if want_J else None)
+        wt = s.get("weights")
+        arr[j] = M2NSeries(t.data_ptr(), x.data_ptr(), N, K, float(s["fmax"]), float(s["fw"]),
+                           float(s["f_lo"]), float(s["df"]), I,
+                           None if wt is None else _dev(wt).data_ptr(), w.data_ptr(),
+                           lam.data_ptr(), P.data_ptr(), None if E is None else E.data_ptr(),
+                           None if J is None else J.data_ptr())
+        outs.append({"w": w, "lam": lam, "P": P, "E": E, "J": J})
+    _err(lib.m2n_batch_psd(ctx.handle, _stream(stream), arr, len(series), int(prec),
+                           float(nufft_tol)), "m2n_batch_psd")
+    if check:
+        ctx.check(stream)
+    return outs

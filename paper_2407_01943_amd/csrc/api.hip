@@ -59,6 +59,34 @@ int Ctx::workspace(const char* name, size_t bytes, void** out) {
     return M2N_OK;
 }
 
+int Ctx::pinned_info(size_t bytes) {
+    if (hinfo_bytes >= bytes) return M2N_OK;
+    // every earlier use of the record was followed by a stream synchronise
+    if (hinfo) (void)hipHostFree(hinfo);
+    hinfo = nullptr;
+    hinfo_bytes = 0;
+    M2N_HIP(hipHostMalloc(&hinfo, bytes, hipHostMallocDefault));
+    hinfo_bytes = bytes;
+    return M2N_OK;
+}
+
+int Ctx::stage(hipStream_t st, const void* src, size_t bytes, void* dst_dev) {
+    if (hstage_used) M2N_HIP(hipEventSynchronize(hstage_ev));
+    if (hstage_bytes < bytes) {
+        if (hstage) (void)hipHostFree(hstage);
+        hstage = nullptr;
+        hstage_bytes = 0;
+        M2N_HIP(hipHostMalloc(&hstage, bytes + bytes / 2, hipHostMallocDefault));
+        hstage_bytes = bytes + bytes / 2;
+    }
+    if (!hstage_ev) M2N_HIP(hipEventCreateWithFlags(&hstage_ev, hipEventDisableTiming));
+    std::memcpy(hstage, src, bytes);
+    M2N_HIP(hipMemcpyAsync(dst_dev, hstage, bytes, hipMemcpyHostToDevice, st));
+    M2N_HIP(hipEventRecord(hstage_ev, st));
+    hstage_used = true;
+    return M2N_OK;
+}
+
 hipEvent_t Ctx::take_event() {
     if (!ev_pool.empty()) {
         hipEvent_t e = ev_pool.back();
@@ -135,8 +163,6 @@ void m2n_destroy(m2n_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->plans) {
         ctx->release(kv.second->tw_fft);
-        ctx->release(kv.second->tw_lo);
-        ctx->release(kv.second->tw_hi);
         ctx->release(kv.second->inv_phihat);
     }
     for (auto& kv : ctx->fft64) {
@@ -147,6 +173,8 @@ void m2n_destroy(m2n_ctx* ctx) {
     for (auto& kv : ctx->ws) ctx->release(kv.second);
     for (auto& kv : ctx->gl) ctx->release(kv.second);
     if (ctx->hinfo) (void)hipHostFree(ctx->hinfo);
+    if (ctx->hstage) (void)hipHostFree(ctx->hstage);
+    if (ctx->hstage_ev) (void)hipEventDestroy(ctx->hstage_ev);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -273,6 +301,64 @@ int m2nufft_psd(m2n_ctx* ctx, void* stream, const double* t, const double* x, in
     M2N_HIP(hipSetDevice(ctx->device));
     return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
                      weights, lambda, fmax, fw, P, E, J);
+}
+
+int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nseries, int prec,
+                  double nufft_tol) {
+    if (!ctx || !series || nseries < 1) {
+        set_error("NULL argument or empty batch");
+        return M2N_ERR_ARG;
+    }
+    std::vector<GepIn> g((size_t)nseries);
+    for (int i = 0; i < nseries; ++i) {
+        const m2n_series& s = series[i];
+        if (!s.t || !s.x || !s.w || !s.lambda || !s.P) {
+            set_error("series %d: NULL argument", i);
+            return M2N_ERR_ARG;
+        }
+        if (s.N < 1 || s.K < 1 || s.K > 64 || s.K > s.N) {
+            set_error("series %d: need 1 <= K <= min(N, 64) (N = %lld, K = %d)", i, (long long)s.N, s.K);
+            return M2N_ERR_ARG;
+        }
+        if (!std::isfinite(s.fmax) || !std::isfinite(s.fw) || !(s.fw > 0.0) || !(s.fw < s.fmax)) {
+            set_error("series %d: need 0 < fw < fmax (fw = %g, fmax = %g)", i, s.fw, s.fmax);
+            return M2N_ERR_ARG;
+        }
+        g[i].t = s.t;
+        g[i].N = s.N;
+        g[i].fmax = s.fmax;
+        g[i].fw = s.fw;
+        g[i].K = s.K;
+        g[i].w = s.w;
+        g[i].lambda = s.lambda;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    M2N_TRY(gep_run_batch(ctx, st, g.data(), nseries));
+    // one NuFFT batch per distinct band count
+    std::map<int64_t, std::vector<NuSeriesIn>> groups;
+    for (int i = 0; i < nseries; ++i) {
+        const m2n_series& s = series[i];
+        NuSeriesIn n;
+        n.t = s.t;
+        n.x = s.x;
+        n.w = s.w;
+        n.lambda = s.lambda;
+        n.dk = s.weights;
+        n.N = s.N;
+        n.K = s.K;
+        n.f_lo = s.f_lo;
+        n.df = s.df;
+        n.fmax = s.fmax;
+        n.fw = s.fw;
+        n.P = s.P;
+        n.E = s.E;
+        n.J = s.J;
+        groups[s.I].push_back(n);
+    }
+    for (auto& kv : groups)
+        M2N_TRY(nufft_run_batch(ctx, st, kv.first, prec, nufft_tol, kv.second.data(), (int)kv.second.size()));
+    return M2N_OK;
 }
 
 }  // extern "C"

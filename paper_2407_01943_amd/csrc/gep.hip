@@ -117,6 +117,30 @@ __global__ __launch_bounds__(GNT) void k_gram2(const double* __restrict__ V, con
     }
 }
 
+// One series of the low-rank GEP path.  Every low-rank kernel takes the
+// descriptor by value for one series, or a device array indexed by
+// blockIdx.y (blockIdx.x for the eigen-solver) for a batch.
+struct LrSeries {
+    const double* t;       // [N] sampling times
+    const double* glx;     // Gauss-Legendre nodes [nq]; weights at glx + MAXP
+    double* F;             // basis, column-major Np x pF
+    double* gpart;         // Gram partials [nred][pF * pF]
+    double* G;             // reduced Gram [pF * pF]
+    double* Z;             // eigenvectors, Qn x K column-major
+    double* theta;         // [K] eigenvalues (the lambda output on lattices)
+    double* Y;             // expansion output (the tapers on lattices)
+    int64_t N, Np, ldy;
+    double tc, span, fw;
+    double scale;          // eigen-solver input scale (1 / c)
+    double wscale;         // fused taper scale sqrt(2 fw) / c
+    double c;              // expansion scale without fusion
+    int K, Qn, pF, nq, fuse, nchunks, cpw, nred;
+};
+
+__device__ __forceinline__ LrSeries lr_of(const LrSeries& d0, const LrSeries* D, int s) {
+    return D ? D[s] : d0;
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Partial Gram matrix V^T V of this workgroup's rows on the FP64 matrix
@@ -128,19 +152,22 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // accumulator element v (layout checked on the device).  Only the tiles I <= J are accumulated; the full
 // symmetric p x p partial goes to part + blockIdx.x * p * p.
 template <int NT>
-__global__ __launch_bounds__(64) void k_gram_mfma(const double* __restrict__ V, int64_t Np,
-                                                  int64_t nrows, int p, int cpw, int64_t nchunks,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(64) void k_gram_mfma(LrSeries d0, const LrSeries* D) {
+    const LrSeries d = lr_of(d0, D, blockIdx.y);
+    if ((int64_t)blockIdx.x * d.cpw >= d.nchunks) return;
     constexpr int NTT = NT * (NT + 1) / 2;
     __shared__ double Vs[16 * NT][GRAM_ROWS + 1];
     const int l = threadIdx.x;
+    const int p = d.pF;
+    const int64_t Np = d.Np;
+    const double* __restrict__ V = d.F;
     d4 acc[NTT];
 #pragma unroll
     for (int t = 0; t < NTT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t c0 = (int64_t)blockIdx.x * cpw;
-    for (int64_t c = c0; c < c0 + cpw && c < nchunks; ++c) {
+    const int64_t c0 = (int64_t)blockIdx.x * d.cpw;
+    for (int64_t c = c0; c < c0 + d.cpw && c < d.nchunks; ++c) {
         const int64_t r0 = c * GRAM_ROWS;
-        const bool inr = r0 + l < nrows;
+        const bool inr = r0 + l < d.N;
         // unconditional loads from clamped addresses, so that all are in
         // flight together (rows < Np and columns < p are allocated)
         double ld[16 * NT];
@@ -152,21 +179,21 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const double* __restrict__ V, 
 #pragma unroll 4
         for (int ks = 0; ks < GRAM_ROWS / 4; ++ks) {
             const int r = 4 * ks + (l >> 4);
-            double a[NT];
+            double av[NT];
 #pragma unroll
-            for (int I = 0; I < NT; ++I) a[I] = Vs[16 * I + (l & 15)][r];
+            for (int I = 0; I < NT; ++I) av[I] = Vs[16 * I + (l & 15)][r];
             int t = 0;
 #pragma unroll
             for (int I = 0; I < NT; ++I)
 #pragma unroll
                 for (int J = I; J < NT; ++J) {
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[I], av[J], acc[t], 0, 0, 0);
                     ++t;
                 }
         }
         __syncthreads();
     }
-    double* out = part + (int64_t)blockIdx.x * p * p;
+    double* out = d.gpart + (int64_t)blockIdx.x * p * p;
     int t = 0;
 #pragma unroll
     for (int I = 0; I < NT; ++I)
@@ -187,11 +214,11 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const double* __restrict__ V, 
 // acc[i] = sum over the nwg partials of entry i, in a fixed order.  A
 // workgroup takes 64 entries; its four wavefronts sum interleaved groups
 // of eight partials with all eight loads in flight, then combine in LDS.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nwg, int len,
-                                                     double* __restrict__ acc) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nwg, int len,
+                                             double* __restrict__ acc, int blk) {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
+    const int i = blk * 64 + lane;
     const int ic = i < len ? i : len - 1;
     double s[8];
 #pragma unroll
@@ -209,6 +236,19 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
     red[wv][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     if (wv == 0 && i < len) acc[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nwg, int len,
+                                                      double* __restrict__ acc) {
+    sum_partials(part, nwg, len, acc, blockIdx.x);
+}
+
+// the Gram matrix of each low-rank series from its partials
+__global__ __launch_bounds__(256) void k_gram_reduce(LrSeries d0, const LrSeries* D) {
+    const LrSeries d = lr_of(d0, D, blockIdx.y);
+    const int len = d.pF * d.pF;
+    if ((int)blockIdx.x * 64 >= len) return;
+    sum_partials(d.gpart, d.nred, len, d.G, blockIdx.x);
 }
 
 // ------------------------------------ top eigenpairs of a small symmetric
@@ -781,32 +821,30 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n, int K,
     if (stamp && lane == 0) stamp[4] = clock64();
 }
 
-// K largest eigenpairs (theta_k, z_k) of the symmetric q x q leading block
-// of scale * G (G row-major, leading dimension ld).  Output Z is
-// column-major q x K (Z[i + k q] = component i of z_k), theta descending.
-// With fuse != 0, rows q and q + 1 of G hold F^T 1 and F^T tau with
+// K largest eigenpairs (theta_k, z_k) of the symmetric Qn x Qn leading
+// block of scale * G (G row-major, leading dimension pF).  Output Z is
+// column-major Qn x K (Z[i + k Qn] = component i of z_k), theta descending.
+// With fuse != 0, rows Qn and Qn + 1 of G hold F^T 1 and F^T tau with
 // tau_n = (tbar - t_n) / span, so that the two sign sums of the taper
 // w_k = c_k F z_k are c_k (F^T 1) . z_k and c_k (F^T tau) . z_k: Z then
 // receives +-wscale / sqrt(theta_k) z_k, the sign making the larger of the
-// two sums positive, and theta goes to lambda.  One wavefront; q <= NP.
+// two sums positive.  One wavefront per series (blockIdx.x); Qn <= NP.
 template <int NP>
-__global__ __launch_bounds__(64) void k_sym_topk(const double* __restrict__ G, int ld, int q,
-                                                 double scale, int K, int fuse, double wscale,
-                                                 double* __restrict__ Zout,
-                                                 double* __restrict__ theta,
-                                                 long long* __restrict__ stamp) {
+__global__ __launch_bounds__(64) void k_sym_topk(LrSeries d0, const LrSeries* D, long long* stamp) {
+    const LrSeries d = lr_of(d0, D, blockIdx.x);
     constexpr int LDA = MAXP + 1;
     __shared__ __align__(16) EigShared<LDA> S;
     const int lane = threadIdx.x;
+    const int q = d.Qn, ld = d.pF, K = d.K;
+    const double* __restrict__ G = d.G;
     for (int e_ = lane; e_ < q * q; e_ += 64) {
         const int i = e_ / q, j = e_ % q;
-        S.A[i][j] = 0.5 * scale * (G[i * ld + j] + G[j * ld + i]);
+        S.A[i][j] = 0.5 * d.scale * (G[i * ld + j] + G[j * ld + i]);
     }
     __syncthreads();
     sym_topk_wave<LDA, NP>(S, q, K, stamp);
-    if (fuse) {
+    if (d.fuse) {
         // sign sums, lane = taper
-        double f = 0.0;
         if (lane < K) {
             double a = 0.0, b = 0.0;
             for (int i = 0; i < q; ++i) {
@@ -816,33 +854,31 @@ __global__ __launch_bounds__(64) void k_sym_topk(const double* __restrict__ G, i
             }
             const double key = fabs(a) >= fabs(b) ? a : b;
             const double th = S.lam[lane];
-            f = (key < 0.0 ? -wscale : wscale) / sqrt(th > 0.0 ? th : 1e-300);
-            S.tmp[lane] = f;
+            S.tmp[lane] = (key < 0.0 ? -d.wscale : d.wscale) / sqrt(th > 0.0 ? th : 1e-300);
         }
         __syncthreads();
         for (int e_ = lane; e_ < q * K; e_ += 64) {
             const int i = e_ % q, k = e_ / q;
-            Zout[e_] = S.tmp[k] * S.X[k][i];
+            d.Z[e_] = S.tmp[k] * S.X[k][i];
         }
     } else {
         for (int e_ = lane; e_ < q * K; e_ += 64) {
             const int i = e_ % q, k = e_ / q;
-            Zout[e_] = S.X[k][i];
+            d.Z[e_] = S.X[k][i];
         }
     }
-    if (lane < K) theta[lane] = S.lam[lane];
+    if (lane < K) d.theta[lane] = S.lam[lane];
 }
 
-// register-array size picked from the matrix order
-void launch_sym_topk(hipStream_t st, const double* G, int ld, int q, double scale, int K, int fuse,
-                     double wscale, double* Z, double* theta) {
+// register-array size picked from the largest matrix order of the launch
+void launch_sym_topk(hipStream_t st, int maxq, int nseries, const LrSeries& d0, const LrSeries* D) {
     long long* ns = nullptr;
-#define M2N_SYM(NPV) \
-    hipLaunchKernelGGL(k_sym_topk<NPV>, dim3(1), dim3(64), 0, st, G, ld, q, scale, K, fuse, wscale, Z, theta, ns)
-    if (q <= 16) M2N_SYM(16);
-    else if (q <= 32) M2N_SYM(32);
-    else if (q <= 40) M2N_SYM(40);
-    else if (q <= 48) M2N_SYM(48);
+    const dim3 g((unsigned)nseries);
+#define M2N_SYM(NPV) hipLaunchKernelGGL(k_sym_topk<NPV>, g, dim3(64), 0, st, d0, D, ns)
+    if (maxq <= 16) M2N_SYM(16);
+    else if (maxq <= 32) M2N_SYM(32);
+    else if (maxq <= 40) M2N_SYM(40);
+    else if (maxq <= 48) M2N_SYM(48);
     else M2N_SYM(64);
 #undef M2N_SYM
 }
@@ -935,58 +971,57 @@ __global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p
 // With aux != 0 two more columns hold 1 and (t_c - t_n) / span, whose
 // products with F give the sign sums of the tapers.  Rows n >= N are zero.
 // Column-major with leading dimension Np; grid (Np / 256, nq + aux).
-__global__ void k_lr_basis(const double* __restrict__ t, int64_t N, int64_t Np, double tc,
-                           double span, double fw, const double* __restrict__ glx,
-                           const double* __restrict__ glw, int nq, double* __restrict__ F) {
+__global__ void k_lr_basis(LrSeries d0, const LrSeries* D) {
+    const LrSeries d = lr_of(d0, D, blockIdx.z);
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
-    if (n >= Np) return;
+    const int aux = d.pF > d.Qn ? 1 : 0;
+    if (n >= d.Np || q >= d.nq + aux) return;
     double c = 0.0, s = 0.0;
-    if (q < nq) {
-        if (n < N) {
-            sincospi(2.0 * fw * glx[q] * (t[n] - tc), &s, &c);
-            const double sq = sqrt(2.0 * fw * glw[q]);
+    if (q < d.nq) {
+        if (n < d.N) {
+            sincospi(2.0 * d.fw * d.glx[q] * (d.t[n] - d.tc), &s, &c);
+            const double sq = sqrt(2.0 * d.fw * d.glx[MAXP + q]);
             c *= sq;
             s *= sq;
         }
-    } else if (n < N) {
+    } else if (n < d.N) {
         c = 1.0;
-        s = (tc - t[n]) / span;
+        s = (d.tc - d.t[n]) / d.span;
     }
-    F[(int64_t)(2 * q) * Np + n] = c;
-    F[(int64_t)(2 * q + 1) * Np + n] = s;
+    d.F[(int64_t)(2 * q) * d.Np + n] = c;
+    d.F[(int64_t)(2 * q + 1) * d.Np + n] = s;
 }
 
-// Y[k * ldy + n] = s_k * sum_j A[j][n] Z[j + k q] for k < K and n < nrows,
-// s_k = 1 / sqrt(c theta_k), or 1 when theta is NULL (Z already scaled)
+// Y[k * ldy + n] = s_k * sum_j F[j][n] Z[j + k Qn] for k < K, n < ldy, with
+// s_k = 1 / sqrt(c theta_k), or 1 when the eigen-solver already scaled Z
 template <int QC>
-__global__ __launch_bounds__(64) void k_lr_expand(const double* __restrict__ A, int64_t Np,
-                                                  int64_t N, int q, const double* __restrict__ Z,
-                                                  const double* __restrict__ theta, double c,
-                                                  int K, double* __restrict__ Y, int64_t ldy,
-                                                  int64_t nrows) {
+__global__ __launch_bounds__(64) void k_lr_expand(LrSeries d0, const LrSeries* D) {
+    const LrSeries d = lr_of(d0, D, blockIdx.y);
+    const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if ((int64_t)blockIdx.x * 64 >= d.ldy) return;
     __shared__ double Zs[QC * MAXP];
     __shared__ double sk[MAXP];
+    const int q = d.Qn, K = d.K;
     for (int e = threadIdx.x; e < QC * K; e += 64) {
         const int j = e % QC, k = e / QC;
-        Zs[e] = j < q ? Z[j + k * q] : 0.0;
+        Zs[e] = j < q ? d.Z[j + k * q] : 0.0;
     }
-    for (int k = threadIdx.x; k < K; k += 64) sk[k] = theta ? 1.0 / sqrt(c * theta[k]) : 1.0;
+    for (int k = threadIdx.x; k < K; k += 64) sk[k] = d.fuse ? 1.0 : 1.0 / sqrt(d.c * d.theta[k]);
     __syncthreads();
-    const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (n >= nrows) return;
+    if (n >= d.ldy) return;
     // unconditional loads from clamped addresses (rows < Np and columns < q
     // are allocated), so that all are in flight together
     double a[QC];
 #pragma unroll
-    for (int j = 0; j < QC; ++j) a[j] = A[(int64_t)(j < q ? j : q - 1) * Np + n];
+    for (int j = 0; j < QC; ++j) a[j] = d.F[(int64_t)(j < q ? j : q - 1) * d.Np + n];
 #pragma unroll
-    for (int j = 0; j < QC; ++j) a[j] = (j < q && n < N) ? a[j] : 0.0;
+    for (int j = 0; j < QC; ++j) a[j] = (j < q && n < d.N) ? a[j] : 0.0;
     for (int k = 0; k < K; ++k) {
         double y = 0.0;
 #pragma unroll
         for (int j = 0; j < QC; ++j) y += a[j] * Zs[k * QC + j];
-        Y[(int64_t)k * ldy + n] = y * sk[k];
+        d.Y[(int64_t)k * d.ldy + n] = y * sk[k];
     }
 }
 
@@ -1001,9 +1036,18 @@ struct TInfo {
     unsigned long long first_nonfinite, first_order;
 };
 
-__global__ __launch_bounds__(256) void k_t_analyze(const double* __restrict__ t, int64_t N,
-                                                   int64_t per_wg, double* __restrict__ hdr,
-                                                   TInfo* __restrict__ info) {
+// one series of a t check: ranges of per_wg samples, records at info / hdr
+struct TaSeries {
+    const double* t;
+    int64_t N, per_wg;
+    int nblk, pad;
+    TInfo* info;      // [nblk]
+    double* hdr;      // [2]
+};
+
+__global__ __launch_bounds__(256) void k_t_analyze(TaSeries d0, const TaSeries* D) {
+    const TaSeries d = D ? D[blockIdx.y] : d0;
+    if ((int)blockIdx.x >= d.nblk) return;
     __shared__ int sf;
     __shared__ unsigned long long snf, sord;
     if (threadIdx.x == 0) {
@@ -1012,8 +1056,10 @@ __global__ __launch_bounds__(256) void k_t_analyze(const double* __restrict__ t,
         sord = ~0ull;
     }
     __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * per_wg;
-    const int64_t b1 = b0 + per_wg < N ? b0 + per_wg : N;
+    const double* __restrict__ t = d.t;
+    const int64_t N = d.N;
+    const int64_t b0 = (int64_t)blockIdx.x * d.per_wg;
+    const int64_t b1 = b0 + d.per_wg < N ? b0 + d.per_wg : N;
     int flags = 0;
     unsigned long long fnf = ~0ull, ford = ~0ull;
     for (int64_t n = b0 + threadIdx.x; n < b1; n += 256) {
@@ -1034,12 +1080,12 @@ __global__ __launch_bounds__(256) void k_t_analyze(const double* __restrict__ t,
     if (ford != ~0ull) atomicMin(&sord, ford);
     __syncthreads();
     if (threadIdx.x == 0) {
-        info[blockIdx.x].flags = sf;
-        info[blockIdx.x].first_nonfinite = snf;
-        info[blockIdx.x].first_order = sord;
+        d.info[blockIdx.x].flags = sf;
+        d.info[blockIdx.x].first_nonfinite = snf;
+        d.info[blockIdx.x].first_order = sord;
         if (blockIdx.x == 0) {
-            hdr[0] = t[0];
-            hdr[1] = t[N - 1];
+            d.hdr[0] = t[0];
+            d.hdr[1] = t[N - 1];
         }
     }
 }
@@ -1759,7 +1805,7 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, dou
             M2N_PROF(ctx, st, "k_gram2");
             hipLaunchKernelGGL(k_gram2, dim3(gram_wg), dim3(GNT), 0, st, V, W, Np, N, p, cpw, nchunks,
                                2, (double*)vpart);
-            hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((2 * p * p + 63) / 64)), dim3(256), 0,
+            hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((2 * p * p + 63) / 64)), dim3(256), 0,
                                st, (const double*)vpart, gram_wg, 2 * p * p, gacc);
         }
         {
@@ -1807,52 +1853,273 @@ int subspace_solve(Solver& S, double* V, double* W, double* Y, double* gacc, dou
 
 }  // namespace
 
-int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmax, double fw,
-            int K, double* w_out, double* lambda_out) {
-    // ---- checks of the sampling times on the device; one host round trip
-    const int64_t per_wg = N <= 256 * 256 ? 256 : (N + 255) / 256;
-    const int awg = (int)((N + per_wg - 1) / per_wg);
-    if (!ctx->hinfo) {
-        M2N_HIP(hipHostMalloc(&ctx->hinfo, 16384, hipHostMallocDefault));
-    }
-    double* hdr = (double*)ctx->hinfo;
-    TInfo* info = (TInfo*)((char*)ctx->hinfo + 64);
+// Gram partials on the matrix cores and their fixed-order reduction
+int launch_gram_mfma(Ctx* ctx, hipStream_t st, int maxpF, int maxred, int ns, const LrSeries& d0,
+                     const LrSeries* D) {
     {
-        M2N_PROF(ctx, st, "k_t_analyze");
-        hipLaunchKernelGGL(k_t_analyze, dim3(awg), dim3(256), 0, st, t_dev, N, per_wg, hdr, info);
+        M2N_PROF(ctx, st, "k_gram_mfma");
+        const int nt = (maxpF + 15) / 16;
+        const dim3 g((unsigned)maxred, (unsigned)ns);
+        if (nt == 1) hipLaunchKernelGGL(k_gram_mfma<1>, g, dim3(64), 0, st, d0, D);
+        else if (nt == 2) hipLaunchKernelGGL(k_gram_mfma<2>, g, dim3(64), 0, st, d0, D);
+        else if (nt == 3) hipLaunchKernelGGL(k_gram_mfma<3>, g, dim3(64), 0, st, d0, D);
+        else hipLaunchKernelGGL(k_gram_mfma<4>, g, dim3(64), 0, st, d0, D);
+    }
+    {
+        M2N_PROF(ctx, st, "k_gram_reduce");
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((maxpF * maxpF + 63) / 64), (unsigned)ns),
+                           dim3(256), 0, st, d0, D);
     }
     M2N_HIP(hipGetLastError());
-    M2N_HIP(hipStreamSynchronize(st));
-    int flags = 0;
-    unsigned long long fnf = ~0ull, ford = ~0ull;
-    for (int g = 0; g < awg; ++g) {
-        flags |= info[g].flags;
-        fnf = std::min(fnf, info[g].first_nonfinite);
-        ford = std::min(ford, info[g].first_order);
+    return M2N_OK;
+}
+
+int launch_lr_expand(Ctx* ctx, hipStream_t st, int maxq, int64_t blocks, int ns, const LrSeries& d0,
+                     const LrSeries* D) {
+    M2N_PROF(ctx, st, "k_lr_expand");
+    const dim3 g((unsigned)blocks, (unsigned)ns);
+    switch ((maxq + 7) / 8 * 8) {
+        case 8: hipLaunchKernelGGL(k_lr_expand<8>, g, dim3(64), 0, st, d0, D); break;
+        case 16: hipLaunchKernelGGL(k_lr_expand<16>, g, dim3(64), 0, st, d0, D); break;
+        case 24: hipLaunchKernelGGL(k_lr_expand<24>, g, dim3(64), 0, st, d0, D); break;
+        case 32: hipLaunchKernelGGL(k_lr_expand<32>, g, dim3(64), 0, st, d0, D); break;
+        case 40: hipLaunchKernelGGL(k_lr_expand<40>, g, dim3(64), 0, st, d0, D); break;
+        case 48: hipLaunchKernelGGL(k_lr_expand<48>, g, dim3(64), 0, st, d0, D); break;
+        case 56: hipLaunchKernelGGL(k_lr_expand<56>, g, dim3(64), 0, st, d0, D); break;
+        case 64: hipLaunchKernelGGL(k_lr_expand<64>, g, dim3(64), 0, st, d0, D); break;
+        default:
+            set_error("internal: quadrature rank %d", maxq);
+            return M2N_ERR_ARG;
     }
-    if (flags & 1) {
-        set_error("non-finite sampling time at %llu", fnf);
-        return M2N_ERR_ARG;
+    M2N_HIP(hipGetLastError());
+    return M2N_OK;
+}
+
+// Gauss-Legendre table (positive nodes, then weights at + MAXP) of order Q,
+// uploaded once per context
+int gl_table(Ctx* ctx, int Q, const double** out) {
+    auto itg = ctx->gl.find(Q);
+    if (itg == ctx->gl.end()) {
+        std::vector<double> gx, gw, tab(2 * MAXP, 0.0);
+        gauss_legendre(Q, gx, gw);
+        int j = 0;
+        for (int i = 0; i < Q; ++i)
+            if (gx[i] > 0.0) {
+                tab[j] = gx[i];
+                tab[MAXP + j] = gw[i];
+                ++j;
+            }
+        DevBuf b;
+        M2N_TRY(ctx->alloc(b, sizeof(double) * 2 * MAXP));
+        M2N_HIP(hipMemcpy(b.p, tab.data(), sizeof(double) * 2 * MAXP, hipMemcpyHostToDevice));
+        itg = ctx->gl.emplace(Q, b).first;
     }
-    if (flags & 2) {
-        set_error("sampling times not strictly increasing at %llu", ford);
-        return M2N_ERR_T_ORDER;
-    }
-    const double t0 = hdr[0], tN = hdr[1];
-    const bool integral = !(flags & 4);
-    const double cB = 2.0 * fmax;
-    const bool lattice = integral && cB == std::rint(cB) && cB >= 1.0 && (tN - t0) < 2.0e6;
-    const double span = N > 1 ? tN - t0 : 0.0;
-    const double tc = 0.5 * (t0 + tN);
-    // quadrature rank of R(A0): Gauss-Legendre in f over [-fw, fw]; the
-    // integrand e^{j 2 pi f tau} turns through at most beta = 2 pi fw span
-    // radians, and 0.7 beta + 14 nodes reach rounding level for beta <= 90
+    *out = (const double*)itg->second.p;
+    return M2N_OK;
+}
+
+// quadrature rank of R(A0): Gauss-Legendre in f over [-fw, fw]; the
+// integrand e^{j 2 pi f tau} turns through at most beta = 2 pi fw span
+// radians, and 0.7 beta + 14 nodes reach rounding level for beta <= 90
+int quad_rank(double fw, double span, int K) {
     const double beta = 2.0 * M_PI * fw * span;
     int Qn = (int)std::ceil(0.7 * beta) + 14;
     if (Qn < K + 2) Qn = K + 2;
-    Qn += Qn & 1;
-    const int aux = lattice ? 2 : 0;      // sign-sum columns of the fused finish
-    const bool lowrank = Qn + aux <= MAXP;
+    return Qn + (Qn & 1);
+}
+
+// what the t check found for one series
+struct TStat {
+    int flags = 0;
+    unsigned long long first_nonfinite = ~0ull, first_order = ~0ull;
+    double t0 = 0, tN = 0;
+};
+
+// Check the sampling times of every series on the device (one launch) and
+// wait for the records: one host round trip for the whole set.
+int t_check(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TStat>& out) {
+    std::vector<TaSeries> ds(ns);
+    size_t ninfo = 0;
+    int maxblk = 1;
+    for (int i = 0; i < ns; ++i) {
+        const int64_t N = in[i].N;
+        TaSeries& d = ds[i];
+        d.t = in[i].t;
+        d.N = N;
+        d.per_wg = N <= 256 * 256 ? 256 : (N + 255) / 256;
+        d.nblk = (int)((N + d.per_wg - 1) / d.per_wg);
+        d.pad = 0;
+        ninfo += (size_t)d.nblk;
+        maxblk = std::max(maxblk, d.nblk);
+    }
+    const size_t hdr_bytes = ((size_t)ns * 2 * sizeof(double) + 255) & ~size_t(255);
+    M2N_TRY(ctx->pinned_info(hdr_bytes + ninfo * sizeof(TInfo)));
+    double* hdr = (double*)ctx->hinfo;
+    TInfo* info = (TInfo*)((char*)ctx->hinfo + hdr_bytes);
+    size_t o = 0;
+    for (int i = 0; i < ns; ++i) {
+        ds[i].hdr = hdr + 2 * i;
+        ds[i].info = info + o;
+        o += (size_t)ds[i].nblk;
+    }
+    const TaSeries* D = nullptr;
+    if (ns > 1) {
+        void* vd;
+        M2N_TRY(ctx->workspace("gep_tdesc", sizeof(TaSeries) * (size_t)ns, &vd));
+        M2N_TRY(ctx->stage(st, ds.data(), sizeof(TaSeries) * (size_t)ns, vd));
+        D = (const TaSeries*)vd;
+    }
+    {
+        M2N_PROF(ctx, st, "k_t_analyze");
+        hipLaunchKernelGGL(k_t_analyze, dim3((unsigned)maxblk, (unsigned)ns), dim3(256), 0, st, ds[0], D);
+    }
+    M2N_HIP(hipGetLastError());
+    M2N_HIP(hipStreamSynchronize(st));
+    out.assign(ns, TStat());
+    for (int i = 0; i < ns; ++i) {
+        TStat& r = out[i];
+        for (int g = 0; g < ds[i].nblk; ++g) {
+            const TInfo& f = ds[i].info[g];
+            r.flags |= f.flags;
+            r.first_nonfinite = std::min(r.first_nonfinite, f.first_nonfinite);
+            r.first_order = std::min(r.first_order, f.first_order);
+        }
+        r.t0 = ds[i].hdr[0];
+        r.tN = ds[i].hdr[1];
+    }
+    return M2N_OK;
+}
+
+int t_status(const TStat& r, int series) {
+    if (r.flags & 1) {
+        set_error("series %d: non-finite sampling time at %llu", series, r.first_nonfinite);
+        return M2N_ERR_ARG;
+    }
+    if (r.flags & 2) {
+        set_error("series %d: sampling times not strictly increasing at %llu", series, r.first_order);
+        return M2N_ERR_T_ORDER;
+    }
+    return M2N_OK;
+}
+
+bool on_lattice(const GepIn& s, const TStat& r) {
+    const double cB = 2.0 * s.fmax;
+    return !(r.flags & 4) && cB == std::rint(cB) && cB >= 1.0 && (r.tN - r.t0) < 2.0e6;
+}
+
+// R(B) = c I and Q + 2 <= 64: the batched low-rank path
+bool lattice_lowrank(const GepIn& s, const TStat& r) {
+    if (!on_lattice(s, r)) return false;
+    const double span = s.N > 1 ? r.tN - r.t0 : 0.0;
+    return quad_rank(s.fw, span, s.K) + 2 <= MAXP;
+}
+
+// The K largest generalized eigenpairs for series whose R(B) is c I, all in
+// one set of launches: quadrature basis F = [cos | sin | 1 | tau], its Gram
+// matrix on the matrix cores, the Q x Q eigenproblem with the sign and the
+// scale folded in, and the expansion straight into the caller's tapers.
+int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* stat,
+                      const std::vector<int>& idx) {
+    const int ns = (int)idx.size();
+    if (ns == 0) return M2N_OK;
+    std::vector<LrSeries> ds(ns);
+    int maxq = 0, maxpF = 0, maxcol = 0, maxred = 0;
+    int64_t maxNp = 0, maxN = 0;
+    for (int j = 0; j < ns; ++j) {
+        const GepIn& g = in[idx[j]];
+        const TStat& r = stat[idx[j]];
+        LrSeries& d = ds[j];
+        std::memset(&d, 0, sizeof(d));
+        const double cB = 2.0 * g.fmax;
+        const double span = g.N > 1 ? r.tN - r.t0 : 0.0;
+        d.t = g.t;
+        d.N = g.N;
+        d.Np = (g.N + TB - 1) / TB * TB;
+        d.ldy = g.N;
+        d.tc = 0.5 * (r.t0 + r.tN);
+        d.span = span > 0.0 ? span : 1.0;
+        d.fw = g.fw;
+        d.scale = 1.0 / cB;
+        d.wscale = std::sqrt(2.0 * g.fw) / cB;
+        d.c = cB;
+        d.K = g.K;
+        d.Qn = quad_rank(g.fw, span, g.K);
+        d.pF = d.Qn + 2;
+        d.nq = d.Qn / 2;
+        d.fuse = 1;
+        d.nchunks = (int)((d.Np + GRAM_ROWS - 1) / GRAM_ROWS);
+        d.nred = d.nchunks < 512 ? d.nchunks : 512;   // one chunk per wavefront up to 512
+        d.cpw = (d.nchunks + d.nred - 1) / d.nred;
+        d.nred = (d.nchunks + d.cpw - 1) / d.cpw;
+        d.theta = g.lambda;
+        d.Y = g.w;
+        M2N_TRY(gl_table(ctx, d.Qn, &d.glx));
+        maxq = std::max(maxq, d.Qn);
+        maxpF = std::max(maxpF, d.pF);
+        maxcol = std::max(maxcol, d.nq + 1);
+        maxred = std::max(maxred, d.nred);
+        maxNp = std::max(maxNp, d.Np);
+        maxN = std::max(maxN, d.N);
+    }
+    // workspace: F, Gram partials, Gram, Z per series (256-byte aligned)
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    size_t tot = 0;
+    for (auto& d : ds)
+        tot += al(sizeof(double) * (size_t)d.pF * d.Np) + al(sizeof(double) * (size_t)d.nred * d.pF * d.pF) +
+               al(sizeof(double) * (size_t)d.pF * d.pF) + al(sizeof(double) * (size_t)d.Qn * d.K);
+    void* vw;
+    M2N_TRY(ctx->workspace("gep_lr", tot, &vw));
+    char* cur = (char*)vw;
+    for (auto& d : ds) {
+        d.F = (double*)cur;
+        cur += al(sizeof(double) * (size_t)d.pF * d.Np);
+        d.gpart = (double*)cur;
+        cur += al(sizeof(double) * (size_t)d.nred * d.pF * d.pF);
+        d.G = (double*)cur;
+        cur += al(sizeof(double) * (size_t)d.pF * d.pF);
+        d.Z = (double*)cur;
+        cur += al(sizeof(double) * (size_t)d.Qn * d.K);
+    }
+    const LrSeries* D = nullptr;
+    if (ns > 1) {
+        void* vd;
+        M2N_TRY(ctx->workspace("gep_lrdesc", sizeof(LrSeries) * (size_t)ns, &vd));
+        M2N_TRY(ctx->stage(st, ds.data(), sizeof(LrSeries) * (size_t)ns, vd));
+        D = (const LrSeries*)vd;
+    }
+    const LrSeries& d0 = ds[0];
+    const unsigned ys = (unsigned)ns;
+    {
+        M2N_PROF(ctx, st, "k_lr_basis");
+        hipLaunchKernelGGL(k_lr_basis, dim3((unsigned)((maxNp + 255) / 256), (unsigned)maxcol, ys),
+                           dim3(256), 0, st, d0, D);
+    }
+    M2N_HIP(hipGetLastError());
+    M2N_TRY(launch_gram_mfma(ctx, st, maxpF, maxred, ns, d0, D));
+    {
+        M2N_PROF(ctx, st, "k_sym_topk");
+        launch_sym_topk(st, maxq, ns, d0, D);
+    }
+    M2N_TRY(launch_lr_expand(ctx, st, maxq, (maxN + 63) / 64, ns, d0, D));
+    M2N_HIP(hipGetLastError());
+    return M2N_OK;
+}
+
+// One series by the dense (R(B) not c I) or wide-band (Q + 2 > 64) paths.
+int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
+    const double* t_dev = g.t;
+    const int64_t N = g.N;
+    const double fmax = g.fmax, fw = g.fw;
+    const int K = g.K;
+    double* w_out = g.w;
+    double* lambda_out = g.lambda;
+    const double t0 = r.t0, tN = r.tN;
+    const double cB = 2.0 * fmax;
+    const bool lattice = on_lattice(g, r);
+    const double span = N > 1 ? tN - t0 : 0.0;
+    const double tc = 0.5 * (t0 + tN);
+    const int Qn = quad_rank(fw, span, K);
+    const bool lowrank = !lattice && Qn <= MAXP;
     Solver S;
     S.ctx = ctx;
     S.st = st;
@@ -1932,93 +2199,54 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
 
     double scale;   // w = scale * (L^{-T}) y
     if (lowrank) {
-        // ---- R(A0) = F F^T from the quadrature of its defining integral
-        const int nq = Qn / 2;
-        auto itg = ctx->gl.find(Qn);
-        if (itg == ctx->gl.end()) {
-            std::vector<double> gx, gw, tab(2 * MAXP, 0.0);
-            gauss_legendre(Qn, gx, gw);
-            int j = 0;
-            for (int i = 0; i < Qn; ++i)
-                if (gx[i] > 0.0) {
-                    tab[j] = gx[i];
-                    tab[MAXP + j] = gw[i];
-                    ++j;
-                }
-            DevBuf b;
-            M2N_TRY(ctx->alloc(b, sizeof(double) * 2 * MAXP));
-            M2N_HIP(hipMemcpy(b.p, tab.data(), sizeof(double) * 2 * MAXP, hipMemcpyHostToDevice));
-            itg = ctx->gl.emplace(Qn, b).first;
-        }
-        const double* glx = (const double*)itg->second.p;
-        const int pF = Qn + aux;            // columns of F
+        // ---- dense R(B): X = L^{-1} F with R(A0) = F F^T from the quadrature
+        LrSeries d;
+        std::memset(&d, 0, sizeof(d));
+        d.t = t_dev;
+        d.N = N;
+        d.Np = Np;
+        d.ldy = Np;
+        d.tc = tc;
+        d.span = span > 0.0 ? span : 1.0;
+        d.fw = fw;
+        d.scale = 1.0;
+        d.c = 1.0;
+        d.K = K;
+        d.Qn = Qn;
+        d.pF = Qn;
+        d.nq = Qn / 2;
+        d.fuse = 0;
+        d.nchunks = (int)nchunks;
+        d.nred = d.nchunks < 512 ? d.nchunks : 512;
+        d.cpw = (d.nchunks + d.nred - 1) / d.nred;
+        d.nred = (d.nchunks + d.cpw - 1) / d.cpw;
+        M2N_TRY(gl_table(ctx, Qn, &d.glx));
         void *vF, *vgp;
-        M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)pF * Np, &vF));
-        // one 64-row chunk per wavefront up to 512 of them
-        const int mfma_wg = (int)(nchunks < 512 ? nchunks : 512);
-        const int mcpw = (int)((nchunks + mfma_wg - 1) / mfma_wg);
-        M2N_TRY(ctx->workspace("gep_gpart", sizeof(double) * (size_t)mfma_wg * pF * pF, &vgp));
-        double* F = (double*)vF;
+        M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)Qn * Np, &vF));
+        M2N_TRY(ctx->workspace("gep_gpart", sizeof(double) * (size_t)d.nred * Qn * Qn, &vgp));
+        d.F = (double*)vF;
+        d.gpart = (double*)vgp;
+        d.G = gacc;
+        d.Z = Qm;
+        d.theta = th;
+        M2N_TRY(need_Y());
+        d.Y = Y;
         {
             M2N_PROF(ctx, st, "k_lr_basis");
-            dim3 g((unsigned)((Np + 255) / 256), (unsigned)(nq + (aux ? 1 : 0)));
-            hipLaunchKernelGGL(k_lr_basis, g, dim3(256), 0, st, td, N, Np, tc, span > 0.0 ? span : 1.0,
-                               fw, glx, glx + MAXP, nq, F);
+            dim3 gq((unsigned)((Np + 255) / 256), (unsigned)d.nq, 1);
+            hipLaunchKernelGGL(k_lr_basis, gq, dim3(256), 0, st, d, (const LrSeries*)nullptr);
         }
         M2N_HIP(hipGetLastError());
-        double cdiv = cB;
-        if (!lattice) {
-            // X = L^{-1} F, then the reduced matrix X^T X
-            M2N_TRY(factor_RB());
-            S.p = Qn;
-            M2N_TRY(S.trsv(F, 0));
-            cdiv = 1.0;
-        }
-        {
-            M2N_PROF(ctx, st, "k_gram_mfma");
-            const int nt = (pF + 15) / 16;
-            dim3 g((unsigned)mfma_wg);
-            if (nt == 1) hipLaunchKernelGGL(k_gram_mfma<1>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
-            else if (nt == 2) hipLaunchKernelGGL(k_gram_mfma<2>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
-            else if (nt == 3) hipLaunchKernelGGL(k_gram_mfma<3>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
-            else hipLaunchKernelGGL(k_gram_mfma<4>, g, dim3(64), 0, st, F, Np, N, pF, mcpw, nchunks, (double*)vgp);
-        }
-        {
-            M2N_PROF(ctx, st, "k_gram_reduce");
-            hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((pF * pF + 63) / 64)), dim3(256), 0,
-                               st, (const double*)vgp, mfma_wg, pF * pF, gacc);
-        }
-        // lattice: w_k = sqrt(2 fw / c) F z_k / sqrt(c theta_k), finished in
-        // the eigen-solver (sign, scale) and the expansion (written to w)
-        const double wscale = std::sqrt(2.0 * fw) / cB;
+        M2N_TRY(factor_RB());
+        S.p = Qn;
+        M2N_TRY(S.trsv(d.F, 0));
+        M2N_TRY(launch_gram_mfma(ctx, st, Qn, d.nred, 1, d, nullptr));
         {
             M2N_PROF(ctx, st, "k_sym_topk");
-            launch_sym_topk(st, gacc, pF, Qn, 1.0 / cdiv, K, lattice ? 1 : 0, wscale, Qm,
-                            lattice ? lambda_out : th);
+            launch_sym_topk(st, Qn, 1, d, nullptr);
         }
-        if (!lattice) M2N_TRY(need_Y());
-        {
-            M2N_PROF(ctx, st, "k_lr_expand");
-            const int qc = (Qn + 7) / 8 * 8;
-            const double* thp = lattice ? nullptr : th;
-            double* dst = lattice ? w_out : Y;
-            const int64_t ldy = lattice ? N : Np;
-#define M2N_EXP(QCV)                                                                              \
-    case QCV:                                                                                     \
-        hipLaunchKernelGGL(k_lr_expand<QCV>, dim3(rot_wg), dim3(64), 0, st, F, Np, N, Qn, Qm, thp, \
-                           cdiv, K, dst, ldy, ldy);                                               \
-        break;
-            switch (qc) {
-                M2N_EXP(8) M2N_EXP(16) M2N_EXP(24) M2N_EXP(32) M2N_EXP(40) M2N_EXP(48) M2N_EXP(56)
-                M2N_EXP(64)
-                default:
-                    set_error("internal: quadrature rank %d", Qn);
-                    return M2N_ERR_ARG;
-            }
-#undef M2N_EXP
-        }
+        M2N_TRY(launch_lr_expand(ctx, st, Qn, (Np + 63) / 64, 1, d, nullptr));
         M2N_HIP(hipGetLastError());
-        if (lattice) return M2N_OK;   // stream-ordered from here; nothing to read back
         S.p = K;
         M2N_TRY(S.trsv(Y, 1));   // w = L^{-T} y
         scale = std::sqrt(2.0 * fw);
@@ -2118,6 +2346,34 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     M2N_HIP(hipGetLastError());
     M2N_HIP(hipStreamSynchronize(st));
     return M2N_OK;
+}
+
+int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int ns) {
+    if (ns < 1 || !in) {
+        set_error("empty batch");
+        return M2N_ERR_ARG;
+    }
+    std::vector<TStat> stat;
+    M2N_TRY(t_check(ctx, st, in, ns, stat));
+    for (int i = 0; i < ns; ++i) M2N_TRY(t_status(stat[i], i));
+    std::vector<int> lat, other;
+    for (int i = 0; i < ns; ++i) (lattice_lowrank(in[i], stat[i]) ? lat : other).push_back(i);
+    M2N_TRY(gep_lattice_batch(ctx, st, in, stat.data(), lat));
+    for (int i : other) M2N_TRY(gep_general(ctx, st, in[i], stat[i]));
+    return M2N_OK;
+}
+
+int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmax, double fw,
+            int K, double* w_out, double* lambda_out) {
+    GepIn g;
+    g.t = t_dev;
+    g.N = N;
+    g.fmax = fmax;
+    g.fw = fw;
+    g.K = K;
+    g.w = w_out;
+    g.lambda = lambda_out;
+    return gep_run_batch(ctx, st, &g, 1);
 }
 
 }  // namespace m2n

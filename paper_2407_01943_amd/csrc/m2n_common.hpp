@@ -85,12 +85,26 @@ struct NufftPlan {
     int B = 0, M = 0;      // pass-1 column block, pass-2 rows per workgroup (max)
     int KC = 0;            // pass-2 tapers transformed together
     int lookback = 0;      // extra column blocks a point may reach into
-    int lo_bits = 0;       // 4-step twiddle split
     DevBuf tw_fft;         // e^{-2 pi i j / Nt}, j < Nt (Nt = max FFT length)
     int tw_len = 0;
-    DevBuf tw_lo, tw_hi;   // 4-step twiddle tables
     DevBuf inv_phihat;     // 1 / phihat(|k|), |k| <= kmax
     int64_t kmax = 0;
+};
+
+// One series of a NuFFT launch, as the host describes it (all pointers are
+// device pointers; P, E, J may be NULL as in m2nufft_psd).
+struct NuSeriesIn {
+    const double* t = nullptr;
+    const double* x = nullptr;
+    const double* w = nullptr;        // K x N tapers
+    const double* lambda = nullptr;   // needed for E
+    const double* dk = nullptr;       // weights or NULL (1/K)
+    int64_t N = 0;
+    int K = 0;
+    double f_lo = 0, df = 0, fmax = 0, fw = 0;
+    void* P = nullptr;
+    void* E = nullptr;
+    void* J = nullptr;
 };
 
 // FP64 complex FFT plan of length M (lattice convolution in the GEP)
@@ -110,16 +124,31 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
-// NuFFT entry used by the C-ABI (defined in nufft.hip)
+// NuFFT entries used by the C-ABI (defined in nufft.hip)
 int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
               int64_t N, const double* w, int K, double f_lo, double df,
               int64_t I, int prec, double tol, const double* weights,
               const double* lambda, double fmax, double fw, void* P, void* E,
               void* J);
+// many series with one band count I and precision in one set of launches
+int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
+                    const NuSeriesIn* series, int nseries);
 
-// GEP entry (defined in gep.hip)
+// GEP entries (defined in gep.hip)
 int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N,
             double fmax, double fw, int K, double* w, double* lambda);
+// one series of a taper solve (device pointers; w is K x N, lambda K)
+struct GepIn {
+    const double* t = nullptr;
+    int64_t N = 0;
+    double fmax = 0, fw = 0;
+    int K = 0;
+    double* w = nullptr;
+    double* lambda = nullptr;
+};
+// many series: one t check for all, the lattice low-rank ones in one set of
+// launches, the rest one by one
+int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
 
 // ----------------------------------------------------------------- context
 struct Ctx {
@@ -132,7 +161,16 @@ struct Ctx {
     unsigned* dev_err = nullptr;        // sticky device error word
     int cu_count = 256;
     void* hinfo = nullptr;              // pinned host record of the t checks
+    size_t hinfo_bytes = 0;
     std::map<int, DevBuf> gl;           // Gauss-Legendre nodes/weights by order
+    // pinned staging of launch descriptors; hstage_ev marks the last copy
+    // out of it, so it is rewritten only after that copy has run
+    void* hstage = nullptr;
+    size_t hstage_bytes = 0;
+    hipEvent_t hstage_ev = nullptr;
+    bool hstage_used = false;
+    int stage(hipStream_t st, const void* src, size_t bytes, void* dst_dev);
+    int pinned_info(size_t bytes);
 
     // kernel timing (m2n_profile_*)
     bool prof = false;

@@ -24,6 +24,11 @@
 // per-workgroup histograms, one scan, scatter) so pass 1 reads contiguous runs.
 // Small grids (nf <= 8192 FP32 / 4096 FP64) run the whole transform in one
 // workgroup's LDS.
+//
+// Every kernel serves one series or a batch: the per-series inputs, outputs
+// and workspace are a NuSeries descriptor, passed by value for one series or
+// as a device array indexed by blockIdx.y for a batch; NuArgs holds what the
+// plan fixes (band count, grid split, tables).
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -131,73 +136,108 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* >= NT/6
     return s;
 }
 
+// ------------------------------------------------------ launch descriptors
+struct NuSeries {
+    const double* t;
+    const double* x;
+    const double* w;        // K x N tapers
+    const double* lambda;   // for E
+    const double* dk;       // weights or NULL
+    void* P;
+    void* E;
+    void* J;
+    int* hist;     // [nwg][nbins] counts
+    int* off;      // [nwg][nbins] scatter offsets
+    int* binoff;   // [nbins + 1]
+    int* flags;    // [nwg]
+    int* l0s;      // [N] binned first cells
+    void* dels;    // [N] R offsets
+    void* c0s;     // [N] cplx<R> pre-phased samples
+    int* idxs;     // [N] sample index
+    void* inter;   // [K][nf] cplx<R> after pass 1
+    double* norms; // [K] sum of w_k^2 (for E)
+    int* diag;     // [1] R(B) = 2 f_max I
+    int64_t N;
+    double f_lo, df, fmax, fw;
+    int K, nwg, ppw, pad;
+};
+
+struct NuArgs {
+    int64_t I, h;
+    double beta;
+    int nf, w, N1, N2, B, nbins, log_N2, lookback, tws1, tws2;
+    const void* tw;          // FFT twiddles
+    const void* inv_phihat;  // deconvolution table
+    unsigned* dev_err;
+};
+
+// this workgroup's series
+__device__ __forceinline__ NuSeries series_of(const NuSeries& d0, const NuSeries* D) {
+    return D ? D[blockIdx.y] : d0;
+}
+
 // ------------------------------------------------- binning (counting sort)
 // K1a: per-workgroup bin histograms and lattice / finiteness flags.
-__global__ __launch_bounds__(NT) void k_hist(const double* __restrict__ t,
-                                             const double* __restrict__ x, int64_t N,
-                                             double f_lo, double df, int64_t h, int nf,
-                                             int w, int N2, int B, int nbins, int ppw,
-                                             int* __restrict__ hist, int* __restrict__ flags) {
+__global__ __launch_bounds__(NT) void k_hist(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
+    const int wg = blockIdx.x;
+    if (wg >= d.nwg) return;
     __shared__ int sh[MAX_BINS];
     __shared__ int s_int, s_bad;
-    const int wg = blockIdx.x;
-    for (int b = threadIdx.x; b < nbins; b += NT) sh[b] = 0;
+    for (int b = threadIdx.x; b < a.nbins; b += NT) sh[b] = 0;
     if (threadIdx.x == 0) {
         s_int = 1;
         s_bad = 0;
     }
     __syncthreads();
-    const int64_t n0 = (int64_t)wg * ppw;
+    const int64_t n0 = (int64_t)wg * d.ppw;
     int my_int = 1, my_bad = 0;
-    for (int j = threadIdx.x; j < ppw; j += NT) {
+    for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
-        if (n >= N) break;
-        Geo g = point_geo(t[n], x[n], f_lo, df, h, nf, w);
+        if (n >= d.N) break;
+        Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, a.h, a.nf, a.w);
         my_int &= g.integral ? 1 : 0;
         my_bad |= g.ok ? 0 : 1;
-        const int bin = (g.l0 & (N2 - 1)) / B;
+        const int bin = (g.l0 & (a.N2 - 1)) / a.B;
         atomicAdd(&sh[bin], 1);
     }
     if (!my_int) atomicAnd(&s_int, 0);
     if (my_bad) atomicOr(&s_bad, 1);
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += NT) hist[(int64_t)wg * nbins + b] = sh[b];
-    if (threadIdx.x == 0) flags[wg] = (s_int ? 1 : 0) | (s_bad ? 2 : 0);
+    for (int b = threadIdx.x; b < a.nbins; b += NT) d.hist[(int64_t)wg * a.nbins + b] = sh[b];
+    if (threadIdx.x == 0) d.flags[wg] = (s_int ? 1 : 0) | (s_bad ? 2 : 0);
 }
 
-// K1b: one workgroup.  off[wg][b] = start of (wg, b) in bin-major order,
-// bin_off[b] = start of bin b.  Reduces the flags: diag[0] = 1 when R(B) is
-// 2 f_max I (every t integer and 2 f_max a positive integer).  Clears the
-// taper norms that pass 1 accumulates for Ehat.
+// K1b: one workgroup per series.  off[wg][b] = start of (wg, b) in bin-major
+// order, binoff[b] = start of bin b.  Reduces the flags: diag[0] = 1 when
+// R(B) is 2 f_max I (every t integer and 2 f_max a positive integer).
+// Clears the taper norms that pass 1 accumulates for Ehat.
 constexpr int SCAN_LDS = 12288;   // (workgroup, bin) counts staged in LDS
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ hist, int nwg, int nbins,
-                                               int* __restrict__ off, int* __restrict__ bin_off,
-                                               const int* __restrict__ flags,
-                                               unsigned* __restrict__ dev_err, int needE,
-                                               double fmax, int* __restrict__ diag,
-                                               double* __restrict__ norms, int K) {
+__global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
     __shared__ int cnt[SCAN_LDS];
     __shared__ int tot[MAX_BINS + 1];
     __shared__ int s_int, s_bad;
     const int tid = threadIdx.x;
+    const int nwg = d.nwg, nbins = a.nbins;
     const bool staged = (int64_t)nwg * nbins <= SCAN_LDS;
     if (tid == 0) {
         s_int = 1;
         s_bad = 0;
     }
     if (staged)
-        for (int e = tid; e < nwg * nbins; e += blockDim.x) cnt[e] = hist[e];
-    for (int k = tid; k < K; k += blockDim.x) norms[k] = 0.0;
+        for (int e = tid; e < nwg * nbins; e += blockDim.x) cnt[e] = d.hist[e];
+    for (int k = tid; k < d.K; k += blockDim.x) d.norms[k] = 0.0;
     __syncthreads();
     for (int b = tid; b < nbins; b += blockDim.x) {
         int s = 0;
-        for (int g = 0; g < nwg; ++g) s += staged ? cnt[g * nbins + b] : hist[(int64_t)g * nbins + b];
+        for (int g = 0; g < nwg; ++g) s += staged ? cnt[g * nbins + b] : d.hist[(int64_t)g * nbins + b];
         tot[b] = s;
     }
     int li = 1, lb = 0;
     for (int g = tid; g < nwg; g += blockDim.x) {
-        li &= flags[g] & 1;
-        lb |= (flags[g] >> 1) & 1;
+        li &= d.flags[g] & 1;
+        lb |= (d.flags[g] >> 1) & 1;
     }
     if (!li) atomicAnd(&s_int, 0);
     if (lb) atomicOr(&s_bad, 1);
@@ -219,53 +259,50 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ hist, int
         if (tid == 0) tot[nbins] = carry;
     }
     __syncthreads();
-    for (int b = tid; b <= nbins; b += blockDim.x) bin_off[b] = tot[b];
+    for (int b = tid; b <= nbins; b += blockDim.x) d.binoff[b] = tot[b];
     for (int b = tid; b < nbins; b += blockDim.x) {
         int run = tot[b];
         for (int g = 0; g < nwg; ++g) {
-            const int c = staged ? cnt[g * nbins + b] : hist[(int64_t)g * nbins + b];
+            const int c = staged ? cnt[g * nbins + b] : d.hist[(int64_t)g * nbins + b];
             if (staged) cnt[g * nbins + b] = run;
-            else off[(int64_t)g * nbins + b] = run;
+            else d.off[(int64_t)g * nbins + b] = run;
             run += c;
         }
     }
     __syncthreads();
     if (staged)
-        for (int e = tid; e < nwg * nbins; e += blockDim.x) off[e] = cnt[e];
+        for (int e = tid; e < nwg * nbins; e += blockDim.x) d.off[e] = cnt[e];
     if (tid == 0) {
-        const double c = 2.0 * fmax;
-        const int d = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
-        diag[0] = d;
-        if (s_bad) atomicOr(dev_err, (unsigned)DEVERR_NONFINITE);
-        if (needE && !d) atomicOr(dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
+        const double c = 2.0 * d.fmax;
+        const int dg = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
+        d.diag[0] = dg;
+        if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
+        if (d.E && !dg) atomicOr(a.dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
     }
 }
 
 // K1c: scatter the points into bin order.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_scatter(const double* __restrict__ t,
-                                                const double* __restrict__ x, int64_t N,
-                                                double f_lo, double df, int64_t h, int nf, int w,
-                                                int N2, int B, int nbins, int ppw,
-                                                const int* __restrict__ off,
-                                                int* __restrict__ l0s, R* __restrict__ dels,
-                                                cplx<R>* __restrict__ c0s,
-                                                int* __restrict__ idxs) {
-    __shared__ int cur[MAX_BINS];
+__global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
     const int wg = blockIdx.x;
-    for (int b = threadIdx.x; b < nbins; b += NT) cur[b] = 0;
+    if (wg >= d.nwg) return;
+    __shared__ int cur[MAX_BINS];
+    for (int b = threadIdx.x; b < a.nbins; b += NT) cur[b] = 0;
     __syncthreads();
-    const int64_t n0 = (int64_t)wg * ppw;
-    for (int j = threadIdx.x; j < ppw; j += NT) {
+    R* dels = (R*)d.dels;
+    cplx<R>* c0s = (cplx<R>*)d.c0s;
+    const int64_t n0 = (int64_t)wg * d.ppw;
+    for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
-        if (n >= N) break;
-        Geo g = point_geo(t[n], x[n], f_lo, df, h, nf, w);
-        const int bin = (g.l0 & (N2 - 1)) / B;
-        const int pos = off[(int64_t)wg * nbins + bin] + atomicAdd(&cur[bin], 1);
-        l0s[pos] = g.l0;
+        if (n >= d.N) break;
+        Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, a.h, a.nf, a.w);
+        const int bin = (g.l0 & (a.N2 - 1)) / a.B;
+        const int pos = d.off[(int64_t)wg * a.nbins + bin] + atomicAdd(&cur[bin], 1);
+        d.l0s[pos] = g.l0;
         dels[pos] = (R)g.del;
         c0s[pos] = {(R)g.cre, (R)g.cim};
-        idxs[pos] = (int)n;
+        d.idxs[pos] = (int)n;
     }
 }
 
@@ -273,49 +310,62 @@ __global__ __launch_bounds__(NT) void k_scatter(const double* __restrict__ t,
 constexpr int NT1 = 512;   // threads per pass-1 workgroup
 constexpr int NT2 = 512;   // threads per pass-2 workgroup
 
+// exp(-2 pi i q / nf) for 0 <= q < nf (nf a power of two: 2 q / nf is exact)
+template <typename R>
+__device__ __forceinline__ cplx<R> twiddle_nf(int q, R two_over_nf);
+template <>
+__device__ __forceinline__ cplx<float> twiddle_nf<float>(int q, float two_over_nf) {
+    float sn, cs;
+    sincospif((float)q * two_over_nf, &sn, &cs);
+    return {cs, -sn};
+}
+template <>
+__device__ __forceinline__ cplx<double> twiddle_nf<double>(int q, double two_over_nf) {
+    double sn, cs;
+    sincospi((double)q * two_over_nf, &sn, &cs);
+    return {cs, -sn};
+}
+
 template <typename R, int N1, int B>
-__global__ __launch_bounds__(NT1) void k_pass1(const int* __restrict__ l0s, const R* __restrict__ dels,
-                                               const cplx<R>* __restrict__ c0s,
-                                               const int* __restrict__ idxs,
-                                               const int* __restrict__ bin_off,
-                                               const double* __restrict__ wt, int64_t N,
-                                               int log_N2, int nf, int w, R beta, int lookback,
-                                               const cplx<R>* __restrict__ tw_g, int tws,
-                                               const cplx<R>* __restrict__ tw_lo,
-                                               const cplx<R>* __restrict__ tw_hi, int lo_bits,
-                                               cplx<R>* __restrict__ inter, int needE,
-                                               double* __restrict__ norms) {
+__global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
+    const int nblk = a.N2 / B;
+    const int blk = blockIdx.x % nblk;
+    const int k = blockIdx.x / nblk;
+    if (k >= d.K) return;
     constexpr int LD = N1 + 1;
     __shared__ cplx<R> tile[B * LD];
     __shared__ cplx<R> tw[N1];
     __shared__ double nred;
-    const int N2 = 1 << log_N2;
-    const int nblk = N2 / B;
-    const int blk = blockIdx.x % nblk;
-    const int k = blockIdx.x / nblk;
-    const int a = blk * B;
+    const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
+    const int c0 = blk * B;
+    const cplx<R>* tw_g = (const cplx<R>*)a.tw;
     for (int e = threadIdx.x; e < B * LD; e += NT1) tile[e] = {(R)0, (R)0};
-    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * tws];
+    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     if (threadIdx.x == 0) nred = 0.0;
     __syncthreads();
     const R two_over_w = (R)2 / (R)w;
-    const double* wk = wt + (int64_t)k * N;
+    const R beta = (R)a.beta;
+    const double* wk = d.w + (int64_t)k * d.N;
+    const R* dels = (const R*)d.dels;
+    const cplx<R>* c0s = (const cplx<R>*)d.c0s;
+    const bool needE = d.E != nullptr;
     double nrm = 0.0;   // sum of w_k^2 over this block's own points (for Ehat)
-    for (int q = 0; q <= lookback; ++q) {
+    for (int q = 0; q <= a.lookback; ++q) {
         int bb = blk - q;
         if (bb < 0) bb += nblk;
-        const int s = bin_off[bb], e = bin_off[bb + 1];
+        const int s = d.binoff[bb], e = d.binoff[bb + 1];
         for (int j = s + threadIdx.x; j < e; j += NT1) {
-            const int l0 = l0s[j];
+            const int l0 = d.l0s[j];
             const R del = dels[j];
-            const double wd = wk[idxs[j]];
+            const cplx<R> cin = c0s[j];
+            const double wd = wk[d.idxs[j]];
             if (q == 0) nrm += wd * wd;
-            const R wv = (R)wd;
-            const cplx<R> c = cscale(c0s[j], wv);
+            const cplx<R> c = cscale(cin, (R)wd);
             for (int r = 0; r < w; ++r) {
                 int cell = l0 + r;
                 if (cell >= nf) cell -= nf;
-                const int cb = (cell & (N2 - 1)) - a;
+                const int cb = (cell & (N2 - 1)) - c0;
                 if (cb >= 0 && cb < B) {
                     const int row = cell >> log_N2;
                     const R phi = es_kernel<R>(((R)r + del) * two_over_w, beta);
@@ -330,15 +380,15 @@ __global__ __launch_bounds__(NT1) void k_pass1(const int* __restrict__ l0s, cons
         if ((threadIdx.x & 63) == 0) atomicAdd(&nred, nrm);
     }
     __syncthreads();
-    if (needE && threadIdx.x == 0) atomicAdd(&norms[k], nred);
+    if (needE && threadIdx.x == 0) atomicAdd(&d.norms[k], nred);
     fft_lds<R, N1, B, NT1, LD>(tile, tw, 1);
-    const int lo_mask = (1 << lo_bits) - 1;
-    cplx<R>* out = inter + (int64_t)k * nf;
+    // four-step twiddle exp(-2 pi i (c0 + cb) m1 / nf), then G[k][m1][l2]
+    const R two_nf = (R)2 / (R)nf;
+    cplx<R>* out = (cplx<R>*)d.inter + (int64_t)k * nf;
     for (int e = threadIdx.x; e < B * N1; e += NT1) {
         const int cb = e % B, m1 = e / B;
-        const int q = (a + cb) * m1;    // < nf
-        const cplx<R> twv = cmul(tw_lo[q & lo_mask], tw_hi[q >> lo_bits]);
-        out[(int64_t)m1 * N2 + a + cb] = cmul(tile[cb * LD + m1], twv);
+        const cplx<R> twv = twiddle_nf<R>((c0 + cb) * m1, two_nf);
+        out[(int64_t)m1 * N2 + c0 + cb] = cmul(tile[cb * LD + m1], twv);
     }
 }
 
@@ -347,30 +397,36 @@ __global__ __launch_bounds__(NT1) void k_pass1(const int* __restrict__ l0s, cons
 // (KC * M rows in LDS); every output mode is owned by one thread, which
 // accumulates sum_k d_k |J_k|^2 across the tapers in a register.
 template <typename R, int N2, int M, int KC>
-__global__ __launch_bounds__(NT2) void k_pass2(const cplx<R>* __restrict__ inter, int K, int N1,
-                                               int nf, int64_t I, int64_t h,
-                                               const cplx<R>* __restrict__ tw_g, int tws,
-                                               const R* __restrict__ inv_phihat,
-                                               const double* __restrict__ dk,
-                                               R* __restrict__ P, R* __restrict__ E,
-                                               const double* __restrict__ norms,
-                                               const int* __restrict__ diag,
-                                               const double* __restrict__ lambda, double fmax,
-                                               double fw, cplx<R>* __restrict__ J) {
+__global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
     constexpr int LD = N2 + 1;
     constexpr int ROWS = KC * M;
     constexpr int OUT_IT = (M * (N2 / 2 + 2) + NT2 - 1) / NT2;
     __shared__ cplx<R> rows[ROWS * LD];
     __shared__ cplx<R> tw[N2];
     __shared__ R s_eval;
-    const int m1_0 = blockIdx.x * M;
-    for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * tws];
+    const int K = d.K, N1 = a.N1, nf = a.nf;
+    const int64_t I = a.I, h = a.h;
+    // workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous
+    // range of rows so that the P / E lines it writes merge in its own L2
+    int bid = blockIdx.x;
+    const int nwg = gridDim.x;
+    if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    const int m1_0 = bid * M;
+    const cplx<R>* tw_g = (const cplx<R>*)a.tw;
+    const cplx<R>* inter = (const cplx<R>*)d.inter;
+    const R* inv_phihat = (const R*)a.inv_phihat;
+    R* P = (R*)d.P;
+    R* E = (R*)d.E;
+    cplx<R>* J = (cplx<R>*)d.J;
+    for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
     if (E && threadIdx.x == 0) {
         // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I
         double e = 0.0;
-        const double c = 2.0 * fmax;
-        for (int k = 0; k < K; ++k) e += fabs(lambda[k] - 2.0 * fw * lambda[k] / (c * norms[k]));
-        s_eval = diag[0] ? (R)(e / (double)K) : (R)NAN;
+        const double c = 2.0 * d.fmax;
+        for (int k = 0; k < K; ++k)
+            e += fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * d.norms[k]));
+        s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
     }
     // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
@@ -389,8 +445,7 @@ __global__ __launch_bounds__(NT2) void k_pass2(const cplx<R>* __restrict__ inter
             const int r = e / N2, l2 = e - r * N2;
             const int kq = r / M, mm = r - kq * M;
             cplx<R> v = {(R)0, (R)0};
-            if (kq < nk)
-                v = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
+            if (kq < nk) v = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
             rows[r * LD + l2] = v;
         }
         __syncthreads();
@@ -405,11 +460,11 @@ __global__ __launch_bounds__(NT2) void k_pass2(const cplx<R>* __restrict__ inter
                 const int64_t kk = m < nf / 2 ? m : m - nf;
                 const int64_t i = kk + h;
                 if (i >= 0 && i < I) {
-                    const R s = inv_phihat[kk < 0 ? -kk : kk];
+                    const R sc = inv_phihat[kk < 0 ? -kk : kk];
                     for (int kq = 0; kq < nk; ++kq) {
-                        const cplx<R> v = cscale(rows[(kq * M + mm) * LD + m2], s);
-                        const R d = dk ? (R)dk[kc0 + kq] : (R)1 / (R)K;
-                        acc[it] += d * (v.x * v.x + v.y * v.y);
+                        const cplx<R> v = cscale(rows[(kq * M + mm) * LD + m2], sc);
+                        const R dd = d.dk ? (R)d.dk[kc0 + kq] : (R)1 / (R)K;
+                        acc[it] += dd * (v.x * v.x + v.y * v.y);
                         if (J) J[(int64_t)(kc0 + kq) * I + i] = v;
                     }
                 }
@@ -436,17 +491,8 @@ __global__ __launch_bounds__(NT2) void k_pass2(const cplx<R>* __restrict__ inter
 
 // ------------------------------------------------- single-workgroup path
 template <typename R, int NF>
-__global__ __launch_bounds__(NT) void k_small(const double* __restrict__ t,
-                                              const double* __restrict__ x, int64_t N,
-                                              const double* __restrict__ wt, int K, double f_lo,
-                                              double df, int64_t I, int64_t h, int w, R beta,
-                                              const cplx<R>* __restrict__ tw, int tws,
-                                              const R* __restrict__ inv_phihat,
-                                              const double* __restrict__ dk,
-                                              const double* __restrict__ lambda, double fmax,
-                                              double fw, unsigned* __restrict__ dev_err,
-                                              R* __restrict__ P, R* __restrict__ E,
-                                              cplx<R>* __restrict__ J) {
+__global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
     constexpr int OUT_IT = (NF / 2 + NT - 1) / NT;
     __shared__ cplx<R> grid[NF];
     __shared__ double red[NT / 64];
@@ -455,19 +501,27 @@ __global__ __launch_bounds__(NT) void k_small(const double* __restrict__ t,
         s_int = 1;
         s_bad = 0;
     }
+    const int K = d.K, w = a.w;
+    const int64_t I = a.I, h = a.h, N = d.N;
+    const cplx<R>* tw = (const cplx<R>*)a.tw;
+    const R* inv_phihat = (const R*)a.inv_phihat;
+    R* P = (R*)d.P;
+    R* E = (R*)d.E;
+    cplx<R>* J = (cplx<R>*)d.J;
     R acc[OUT_IT];
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) acc[it] = (R)0;
     const R two_over_w = (R)2 / (R)w;
+    const R beta = (R)a.beta;
     double esum = 0.0;
     for (int k = 0; k < K; ++k) {
         for (int e = threadIdx.x; e < NF; e += NT) grid[e] = {(R)0, (R)0};
         __syncthreads();
-        const double* wk = wt + (int64_t)k * N;
+        const double* wk = d.w + (int64_t)k * N;
         double nrm = 0.0;
         int my_int = 1, my_bad = 0;
         for (int64_t n = threadIdx.x; n < N; n += NT) {
-            const Geo g = point_geo(t[n], x[n], f_lo, df, h, NF, w);
+            const Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, h, NF, w);
             my_int &= g.integral ? 1 : 0;
             my_bad |= g.ok ? 0 : 1;
             const double wv = wk[n];
@@ -485,32 +539,32 @@ __global__ __launch_bounds__(NT) void k_small(const double* __restrict__ t,
         if (!my_int) atomicAnd(&s_int, 0);
         if (my_bad) atomicOr(&s_bad, 1);
         nrm = block_sum(nrm, red);   // contains barriers
-        if (E && lambda) {
-            const double c = 2.0 * fmax;
-            esum += fabs(lambda[k] - 2.0 * fw * lambda[k] / (c * nrm));
+        if (E && d.lambda) {
+            const double c = 2.0 * d.fmax;
+            esum += fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * nrm));
         }
-        fft_lds<R, NF, 1, NT, NF>(grid, tw, tws);
-        const R d = dk ? (R)dk[k] : (R)1 / (R)K;
+        fft_lds<R, NF, 1, NT, NF>(grid, tw, a.tws1);
+        const R dd = d.dk ? (R)d.dk[k] : (R)1 / (R)K;
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
             const int64_t i = threadIdx.x + (int64_t)it * NT;
             if (i < I) {
                 const int64_t kk = i - h;
                 const int64_t m = kk < 0 ? kk + NF : kk;
-                const R s = inv_phihat[kk < 0 ? -kk : kk];
-                const cplx<R> v = cscale(grid[m], s);
-                acc[it] += d * (v.x * v.x + v.y * v.y);
+                const R sc = inv_phihat[kk < 0 ? -kk : kk];
+                const cplx<R> v = cscale(grid[m], sc);
+                acc[it] += dd * (v.x * v.x + v.y * v.y);
                 if (J) J[(int64_t)k * I + i] = v;
             }
         }
         __syncthreads();
     }
-    const double c = 2.0 * fmax;
+    const double c = 2.0 * d.fmax;
     const bool diag = s_int && c == rint(c) && c >= 1.0;
     const R ev = diag ? (R)(esum / (double)K) : (R)NAN;
     if (threadIdx.x == 0) {
-        if (s_bad) atomicOr(dev_err, (unsigned)DEVERR_NONFINITE);
-        if (E && !diag) atomicOr(dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
+        if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
+        if (E && !diag) atomicOr(a.dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
     }
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) {
@@ -596,10 +650,7 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
         p.KC = rows_max < 8 ? rows_max : 8;
         p.M = rows_max / p.KC;
         if (p.M > 4) p.M = 4;
-        p.lo_bits = (p.log_nf + 1) / 2;
         Nt = p.N1 > p.N2 ? p.N1 : p.N2;
-        M2N_TRY(upload(ctx, p.tw_lo, twiddles<R>(p.nf, int64_t(1) << p.lo_bits, 1)));
-        M2N_TRY(upload(ctx, p.tw_hi, twiddles<R>(p.nf, p.nf >> p.lo_bits, int64_t(1) << p.lo_bits)));
     }
     p.tw_len = Nt;
     M2N_TRY(upload(ctx, p.tw_fft, twiddles<R>(Nt, Nt, 1)));
@@ -652,8 +703,6 @@ int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
     int st = prec == M2N_FP32 ? build_plan<float>(ctx, *p) : build_plan<double>(ctx, *p);
     if (st != M2N_OK) {
         ctx->release(p->tw_fft);
-        ctx->release(p->tw_lo);
-        ctx->release(p->tw_hi);
         ctx->release(p->inv_phihat);
         return st;
     }
@@ -663,17 +712,34 @@ int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
 }
 
 // ---------------------------------------------------------- dispatchers
+NuArgs make_args(Ctx* ctx, const NufftPlan& p) {
+    NuArgs a{};
+    a.I = p.I;
+    a.h = p.h;
+    a.beta = p.beta;
+    a.nf = p.nf;
+    a.w = p.w;
+    a.N1 = p.N1;
+    a.N2 = p.N2;
+    a.B = p.B;
+    a.nbins = p.single ? 0 : p.N2 / p.B;
+    a.log_N2 = p.single ? 0 : ilog2i(p.N2);
+    a.lookback = p.lookback;
+    a.tws1 = p.single ? 1 : p.tw_len / p.N1;
+    a.tws2 = p.single ? 1 : p.tw_len / p.N2;
+    a.tw = p.tw_fft.p;
+    a.inv_phihat = p.inv_phihat.p;
+    a.dev_err = ctx->dev_err;
+    return a;
+}
+
 template <typename R>
-void launch_small(const NufftPlan& p, hipStream_t st, const double* t, const double* x,
-                  int64_t N, const double* w, int K, double f_lo, double df,
-                  const double* dk, const double* lambda, double fmax, double fw,
-                  unsigned* dev_err, R* P, R* E, cplx<R>* J) {
-#define M2N_SMALL(NFV)                                                                         \
-    case NFV:                                                                                  \
-        hipLaunchKernelGGL((k_small<R, NFV>), dim3(1), dim3(NT), 0, st, t, x, N, w, K, f_lo,    \
-                           df, p.I, p.h, p.w, (R)p.beta, (const cplx<R>*)p.tw_fft.p, 1,        \
-                           (const R*)p.inv_phihat.p, dk, lambda, fmax, fw, dev_err, P, E, J); \
-        break;
+int launch_small(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a, const NuSeries& d0,
+                 const NuSeries* D) {
+#define M2N_SMALL(NFV)                                                                       \
+    case NFV:                                                                                \
+        hipLaunchKernelGGL((k_small<R, NFV>), grid, dim3(NT), 0, st, a, d0, D);            \
+        return M2N_OK;
     switch (p.nf) {
         M2N_SMALL(64)
         M2N_SMALL(128)
@@ -689,21 +755,17 @@ void launch_small(const NufftPlan& p, hipStream_t st, const double* t, const dou
             break;
     }
 #undef M2N_SMALL
+    set_error("no single-workgroup kernel for nf = %d", p.nf);
+    return M2N_ERR_UNSUPPORTED;
 }
 
 template <typename R>
-int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const int* l0s, const R* dels,
-                 const cplx<R>* c0s, const int* idxs, const int* bin_off, const double* w,
-                 int64_t N, cplx<R>* inter, int needE, double* norms) {
-    const int tws = p.tw_len / p.N1;
-    const int logN2 = ilog2i(p.N2);
-#define M2N_P1(N1V, BV)                                                                          \
-    if (p.N1 == N1V && p.B == BV) {                                                              \
-        hipLaunchKernelGGL((k_pass1<R, N1V, BV>), grid, dim3(NT1), 0, st, l0s, dels, c0s, idxs,  \
-                           bin_off, w, N, logN2, p.nf, p.w, (R)p.beta, p.lookback,               \
-                           (const cplx<R>*)p.tw_fft.p, tws, (const cplx<R>*)p.tw_lo.p,           \
-                           (const cplx<R>*)p.tw_hi.p, p.lo_bits, inter, needE, norms);           \
-        return M2N_OK;                                                                           \
+int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a, const NuSeries& d0,
+                 const NuSeries* D) {
+#define M2N_P1(N1V, BV)                                                                    \
+    if (p.N1 == N1V && p.B == BV) {                                                        \
+        hipLaunchKernelGGL((k_pass1<R, N1V, BV>), grid, dim3(NT1), 0, st, a, d0, D);       \
+        return M2N_OK;                                                                     \
     }
     if constexpr (sizeof(R) == 4) {
         M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 32) M2N_P1(512, 16) M2N_P1(1024, 8)
@@ -716,26 +778,20 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const int* l0s, 
 }
 
 // rows-per-workgroup choice for pass 2: largest M the LDS budget allows that
-// still gives at least two workgroups per compute unit
-inline int pass2_rows(const NufftPlan& p, int cu_count) {
+// still gives at least two workgroups per compute unit (counting a batch)
+inline int pass2_rows(const NufftPlan& p, int cu_count, int nseries) {
     int M = p.M;
-    while (M > 1 && (p.N1 / M) < 2 * cu_count) M /= 2;
+    while (M > 1 && (int64_t)(p.N1 / M) * nseries < 2 * cu_count) M /= 2;
     return M;
 }
 
 template <typename R>
-int launch_pass2(const NufftPlan& p, hipStream_t st, int M, const cplx<R>* inter, int K,
-                 const double* dk, R* P, R* E, const double* norms, const int* diag,
-                 const double* lambda, double fmax, double fw, cplx<R>* J) {
-    const int tws = p.tw_len / p.N2;
-    dim3 grid(p.N1 / M);
-#define M2N_P2(N2V, MV, KCV)                                                                     \
-    if (p.N2 == N2V && M == MV && p.KC == KCV) {                                                 \
-        hipLaunchKernelGGL((k_pass2<R, N2V, MV, KCV>), grid, dim3(NT2), 0, st, inter, K, p.N1,   \
-                           p.nf, p.I, p.h, (const cplx<R>*)p.tw_fft.p, tws,                      \
-                           (const R*)p.inv_phihat.p, dk, P, E, norms, diag, lambda, fmax, fw,    \
-                           J);                                                                   \
-        return M2N_OK;                                                                           \
+int launch_pass2(const NufftPlan& p, hipStream_t st, int M, dim3 grid, const NuArgs& a,
+                 const NuSeries& d0, const NuSeries* D) {
+#define M2N_P2(N2V, MV, KCV)                                                               \
+    if (p.N2 == N2V && M == MV && p.KC == KCV) {                                           \
+        hipLaunchKernelGGL((k_pass2<R, N2V, MV, KCV>), grid, dim3(NT2), 0, st, a, d0, D);  \
+        return M2N_OK;                                                                     \
     }
     if constexpr (sizeof(R) == 4) {
         M2N_P2(128, 1, 8) M2N_P2(128, 2, 8) M2N_P2(128, 4, 8)
@@ -754,111 +810,187 @@ int launch_pass2(const NufftPlan& p, hipStream_t st, int M, const cplx<R>* inter
     return M2N_ERR_UNSUPPORTED;
 }
 
+// 256-byte aligned carving of one workspace
+struct Carver {
+    char* base = nullptr;
+    size_t used = 0;
+    void* take(size_t bytes) {
+        void* p = base ? base + used : nullptr;
+        used += (bytes + 255) & ~size_t(255);
+        return p;
+    }
+};
+
 template <typename R>
-int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const double* t, const double* x,
-              int64_t N, const double* w, int K, double f_lo, double df, const double* dk,
-              const double* lambda, double fmax, double fw, void* Pv, void* Ev, void* Jv) {
-    R* P = (R*)Pv;
-    R* E = (R*)Ev;
-    cplx<R>* J = (cplx<R>*)Jv;
+int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns) {
+    const NuArgs a = make_args(ctx, p);
+    std::vector<NuSeries> ds(ns);
+    int maxK = 0, maxwg = 0;
+    // per-series binning geometry, then the workspace layout (two passes:
+    // measure with a null base, then carve)
+    const int nbins = p.single ? 0 : p.N2 / p.B;
+    for (int i = 0; i < ns; ++i) {
+        NuSeries& d = ds[i];
+        std::memset(&d, 0, sizeof(d));
+        const NuSeriesIn& s = in[i];
+        d.t = s.t;
+        d.x = s.x;
+        d.w = s.w;
+        d.lambda = s.lambda;
+        d.dk = s.dk;
+        d.P = s.P;
+        d.E = s.E;
+        d.J = s.J;
+        d.N = s.N;
+        d.f_lo = s.f_lo;
+        d.df = s.df;
+        d.fmax = s.fmax;
+        d.fw = s.fw;
+        d.K = s.K;
+        if (!p.single) {
+            // points per binning workgroup: at least PTS_PER_WG, and few enough
+            // workgroups that the scan can stage every (workgroup, bin) count
+            int64_t ppw = PTS_PER_WG;
+            while ((s.N + ppw - 1) / ppw * nbins > SCAN_LDS && ppw < (int64_t(1) << 20)) ppw *= 2;
+            const int64_t nwg64 = (s.N + ppw - 1) / ppw;
+            if (nwg64 > (1 << 20)) {
+                set_error("N too large");
+                return M2N_ERR_ARG;
+            }
+            d.ppw = (int)ppw;
+            d.nwg = (int)nwg64;
+        }
+        maxK = std::max(maxK, s.K);
+        maxwg = std::max(maxwg, d.nwg);
+    }
+    if (!p.single) {
+        auto carve = [&](Carver& c) {
+            for (int i = 0; i < ns; ++i) {
+                NuSeries& d = ds[i];
+                const size_t N = (size_t)d.N;
+                d.hist = (int*)c.take(sizeof(int) * (size_t)d.nwg * nbins);
+                d.off = (int*)c.take(sizeof(int) * (size_t)d.nwg * nbins);
+                d.binoff = (int*)c.take(sizeof(int) * (size_t)(nbins + 1));
+                d.flags = (int*)c.take(sizeof(int) * (size_t)d.nwg);
+                d.l0s = (int*)c.take(sizeof(int) * N);
+                d.dels = c.take(sizeof(R) * N);
+                d.c0s = c.take(sizeof(cplx<R>) * N);
+                d.idxs = (int*)c.take(sizeof(int) * N);
+                d.inter = c.take(sizeof(cplx<R>) * (size_t)d.K * p.nf);
+                d.norms = (double*)c.take(sizeof(double) * 64);
+                d.diag = (int*)c.take(64);
+            }
+        };
+        Carver m;
+        carve(m);
+        void* wsp;
+        M2N_TRY(ctx->workspace("nu_work", m.used, &wsp));
+        Carver c;
+        c.base = (char*)wsp;
+        carve(c);
+    }
+    const NuSeries* D = nullptr;
+    if (ns > 1) {
+        void* vd;
+        M2N_TRY(ctx->workspace("nu_desc", sizeof(NuSeries) * (size_t)ns, &vd));
+        M2N_TRY(ctx->stage(st, ds.data(), sizeof(NuSeries) * (size_t)ns, vd));
+        D = (const NuSeries*)vd;
+    }
+    const NuSeries& d0 = ds[0];
+    const unsigned ys = (unsigned)ns;
     if (p.single) {
         M2N_PROF(ctx, st, "k_small");
-        launch_small<R>(p, st, t, x, N, w, K, f_lo, df, dk, lambda, fmax, fw, ctx->dev_err, P, E,
-                        J);
+        M2N_TRY(launch_small<R>(p, st, dim3(1, ys), a, d0, D));
         M2N_HIP(hipGetLastError());
         return M2N_OK;
     }
-    const int nbins = p.N2 / p.B;
-    // points per binning workgroup: at least PTS_PER_WG, and few enough
-    // workgroups that the scan can stage every (workgroup, bin) count in LDS
-    int64_t ppw = PTS_PER_WG;
-    while ((N + ppw - 1) / ppw * nbins > SCAN_LDS && ppw < (int64_t(1) << 20)) ppw *= 2;
-    const int64_t nwg64 = (N + ppw - 1) / ppw;
-    if (nwg64 > (1 << 20)) {
-        set_error("N too large");
-        return M2N_ERR_ARG;
-    }
-    const int nwg = (int)nwg64;
-    const bool needE = E != nullptr;
-    void *hist, *off, *binoff, *flags, *l0s, *dels, *c0s, *idxs, *inter, *norms, *diag;
-    M2N_TRY(ctx->workspace("nu_hist", sizeof(int) * (size_t)nwg * nbins, &hist));
-    M2N_TRY(ctx->workspace("nu_off", sizeof(int) * (size_t)nwg * nbins, &off));
-    M2N_TRY(ctx->workspace("nu_binoff", sizeof(int) * (size_t)(nbins + 1), &binoff));
-    M2N_TRY(ctx->workspace("nu_flags", sizeof(int) * (size_t)nwg, &flags));
-    M2N_TRY(ctx->workspace("nu_l0", sizeof(int) * (size_t)N, &l0s));
-    M2N_TRY(ctx->workspace("nu_del", sizeof(R) * (size_t)N, &dels));
-    M2N_TRY(ctx->workspace("nu_c0", sizeof(cplx<R>) * (size_t)N, &c0s));
-    M2N_TRY(ctx->workspace("nu_idx", sizeof(int) * (size_t)N, &idxs));
-    M2N_TRY(ctx->workspace("nu_inter", sizeof(cplx<R>) * (size_t)K * p.nf, &inter));
-    M2N_TRY(ctx->workspace("nu_norms", sizeof(double) * 64, &norms));
-    M2N_TRY(ctx->workspace("nu_diag", 64, &diag));
     {
         M2N_PROF(ctx, st, "k_hist");
-        hipLaunchKernelGGL(k_hist, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf, p.w,
-                           p.N2, p.B, nbins, (int)ppw, (int*)hist, (int*)flags);
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
     }
     {
         M2N_PROF(ctx, st, "k_scan");
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const int*)hist, nwg, nbins,
-                           (int*)off, (int*)binoff, (const int*)flags, ctx->dev_err, needE ? 1 : 0,
-                           fmax, (int*)diag, (double*)norms, K);
+        hipLaunchKernelGGL(k_scan, dim3(1, ys), dim3(1024), 0, st, a, d0, D);
     }
     {
         M2N_PROF(ctx, st, "k_scatter");
-        hipLaunchKernelGGL(k_scatter<R>, dim3(nwg), dim3(NT), 0, st, t, x, N, f_lo, df, p.h, p.nf,
-                           p.w, p.N2, p.B, nbins, (int)ppw, (const int*)off, (int*)l0s, (R*)dels,
-                           (cplx<R>*)c0s, (int*)idxs);
+        hipLaunchKernelGGL(k_scatter<R>, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass1");
-        M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(K * nbins)), (const int*)l0s, (const R*)dels,
-                                (const cplx<R>*)c0s, (const int*)idxs, (const int*)binoff, w, N,
-                                (cplx<R>*)inter, needE ? 1 : 0, (double*)norms));
+        M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(maxK * nbins), ys), a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass2");
-        M2N_TRY(launch_pass2<R>(p, st, pass2_rows(p, ctx->cu_count), (const cplx<R>*)inter, K, dk,
-                                P, E, (const double*)norms, (const int*)diag, lambda, fmax, fw, J));
+        const int M = pass2_rows(p, ctx->cu_count, ns);
+        M2N_TRY(launch_pass2<R>(p, st, M, dim3((unsigned)(p.N1 / M), ys), a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
 }
 
-}  // namespace
-
-int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,
-              const double* w, int K, double f_lo, double df, int64_t I, int prec, double tol,
-              const double* weights, const double* lambda, double fmax, double fw, void* P,
-              void* E, void* J) {
-    if (!t || !x || !w || N < 1 || K < 1 || K > 64 || I < 1 || I > (int64_t(1) << 21)) {
-        set_error("bad argument (N = %lld, K = %d, I = %lld)", (long long)N, K, (long long)I);
+int check_series(const NuSeriesIn& s, int64_t I) {
+    if (!s.t || !s.x || !s.w || s.N < 1 || s.K < 1 || s.K > 64 || I < 1 ||
+        I > (int64_t(1) << 21)) {
+        set_error("bad argument (N = %lld, K = %d, I = %lld)", (long long)s.N, s.K, (long long)I);
         return M2N_ERR_ARG;
     }
-    if (N > (int64_t(1) << 30)) {
+    if (s.N > (int64_t(1) << 30)) {
         set_error("N too large");
         return M2N_ERR_ARG;
     }
-    if (!std::isfinite(f_lo) || !std::isfinite(df) || !(df > 0.0)) {
+    if (!std::isfinite(s.f_lo) || !std::isfinite(s.df) || !(s.df > 0.0)) {
         set_error("band grid must have finite f_lo and df > 0");
+        return M2N_ERR_ARG;
+    }
+    if (s.E && (!s.lambda || !(s.fmax > 0.0) || !(s.fw > 0.0))) {
+        set_error("E needs lambda, fmax > 0 and fw > 0");
+        return M2N_ERR_ARG;
+    }
+    return M2N_OK;
+}
+
+}  // namespace
+
+int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
+                    const NuSeriesIn* series, int nseries) {
+    if (nseries < 1 || !series) {
+        set_error("empty batch");
         return M2N_ERR_ARG;
     }
     if (prec != M2N_FP32 && prec != M2N_FP64) {
         set_error("prec must be M2N_FP32 or M2N_FP64");
         return M2N_ERR_ARG;
     }
-    if (E && (!lambda || !(fmax > 0.0) || !(fw > 0.0))) {
-        set_error("E needs lambda, fmax > 0 and fw > 0");
-        return M2N_ERR_ARG;
-    }
+    for (int i = 0; i < nseries; ++i) M2N_TRY(check_series(series[i], I));
     NufftPlan* p = nullptr;
     M2N_TRY(get_plan(ctx, I, prec, tol, &p));
-    if (prec == M2N_FP32)
-        return run_typed<float>(ctx, st, *p, t, x, N, w, K, f_lo, df, weights, lambda, fmax, fw,
-                                P, E, J);
-    return run_typed<double>(ctx, st, *p, t, x, N, w, K, f_lo, df, weights, lambda, fmax, fw, P,
-                             E, J);
+    if (prec == M2N_FP32) return run_typed<float>(ctx, st, *p, series, nseries);
+    return run_typed<double>(ctx, st, *p, series, nseries);
+}
+
+int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,
+              const double* w, int K, double f_lo, double df, int64_t I, int prec, double tol,
+              const double* weights, const double* lambda, double fmax, double fw, void* P,
+              void* E, void* J) {
+    NuSeriesIn s;
+    s.t = t;
+    s.x = x;
+    s.w = w;
+    s.lambda = lambda;
+    s.dk = weights;
+    s.N = N;
+    s.K = K;
+    s.f_lo = f_lo;
+    s.df = df;
+    s.fmax = fmax;
+    s.fw = fw;
+    s.P = P;
+    s.E = E;
+    s.J = J;
+    return nufft_run_batch(ctx, st, I, prec, tol, &s, 1);
 }
 
 }  // namespace m2n
