@@ -40,7 +40,60 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=16384,
                     help="bands in the oracle's timed NUDFT sample")
+    ap.add_argument("--batch-series", type=int, default=512,
+                    help="series in the batched-form measurement (0: skip)")
     return ap.parse_args()
+
+
+def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
+    """The 512-series batched form (one m2n_batch_psd call per batch) against
+    the per-series calls on the same stream, same series."""
+    import numpy as np
+    series = [workloads.batched_series(s) for s in range(nser)]
+    dev = torch.device("cuda:0")
+    specs = []
+    for s in series:
+        specs.append({"t": torch.from_numpy(s.t).to(dev), "x": torch.from_numpy(s.x).to(dev),
+                      "fmax": s.fmax, "fw": s.fw, "K": s.K, "f_lo": s.f_lo, "df": s.df,
+                      "I": s.I,
+                      "w": torch.empty((s.K, s.N), dtype=torch.float64, device=dev),
+                      "lam": torch.empty((s.K,), dtype=torch.float64, device=dev),
+                      "P": torch.empty((s.I,), dtype=torch.float32, device=dev),
+                      "E": torch.empty((s.I,), dtype=torch.float32, device=dev)})
+    work = float(sum(s.N * s.K * s.I for s in series))
+    m2n.m2n_batch_psd(ctx, specs, prec=m2n.M2N_FP32, check=False)
+    torch.cuda.synchronize()
+    ctx.check()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        m2n.m2n_batch_psd(ctx, specs, prec=m2n.M2N_FP32, check=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    tb = float(np.median(times))
+    P_batch = [sp["P"].clone() for sp in specs[:8]]
+
+    def per_series():
+        for sp in specs:
+            m2n.gpss_tapers(ctx, sp["t"], sp["fmax"], sp["fw"], sp["K"], out=(sp["w"], sp["lam"]))
+            m2n.m2nufft_psd(ctx, sp["t"], sp["x"], sp["w"], sp["lam"], sp["fmax"], sp["fw"],
+                            sp["f_lo"], sp["df"], sp["I"], prec=m2n.M2N_FP32,
+                            out=(sp["P"], sp["E"], None), check=False)
+    per_series()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_series()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    dP = max(float((a.double() - sp["P"].double()).abs().max() / sp["P"].double().abs().max())
+             for a, sp in zip(P_batch, specs[:8]))
+    return {"series": nser, "N_range": [min(s.N for s in series), max(s.N for s in series)],
+            "K_range": [min(s.K for s in series), max(s.K for s in series)], "I": series[0].I,
+            "ms_per_batch": round(tb * 1e3, 3), "psds_per_s": round(nser / tb, 1),
+            "value": round(work / tb / 1e6, 1), "unit": "Mpts*tapers*bands/s",
+            "per_series_ms": round(ts * 1e3, 3), "per_series_psds_per_s": round(nser / ts, 1),
+            "speedup_vs_per_series": round(ts / tb, 2),
+            "batch_vs_per_series_P_rel": dP}
 
 
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
@@ -179,6 +232,13 @@ def main():
                   "gate": 1e-5 if prec == m2n.M2N_FP32 else 1e-10,
                   "pass": bool(err < (1e-5 if prec == m2n.M2N_FP32 else 1e-10))}
 
+    batched = None
+    if a.batch_series > 0:
+        print("bench: batched form", file=sys.stderr, flush=True)
+        batched = batched_form(m2n, torch, workloads, ctx, a.batch_series)
+        print(f"bench: batched {batched['ms_per_batch']} ms per {a.batch_series} series",
+              file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -206,6 +266,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "batched_form": batched,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -180,6 +180,62 @@ typedef struct {
 int m2n_batch_psd(m2n_ctx *ctx, void *stream, const m2n_series *series, int nseries,
                   int prec, double nufft_tol);
 
+/*
+ * Request queue with continuous batching (the served form).
+ *
+ * Requests carry HOST inputs, which m2n_submit copies before it returns, and
+ * HOST output buffers, which must stay valid until m2n_poll or m2n_wait has
+ * reported the request done.  `slots` worker threads, each with its own
+ * context and stream, take the pending requests in arrival order -- as many
+ * as max_batch and the HBM budget admit -- and run them as one batch
+ * (m2n_batch_psd); while one slot's batch is on the GPU the next admits what
+ * arrived meanwhile.  A result is the same alone and in any mix within the
+ * NuFFT tolerance (the tapers are bitwise equal).  The queue calls are
+ * thread-safe; the parent context must outlive the queue.
+ */
+typedef struct m2n_queue m2n_queue;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* cap on the estimated device bytes of the
+                                requests in flight (0 = no cap); a request
+                                larger than the cap runs alone              */
+    int max_batch;           /* requests per batch (0 = 512)               */
+    int slots;               /* batches in flight (0 = 2, at most 4)       */
+    int prec;                /* M2N_FP32 (also when 0) or M2N_FP64         */
+    double nufft_tol;        /* as in m2nufft_psd                          */
+} m2n_queue_cfg;
+
+typedef struct {
+    const double *t, *x;     /* HOST [N], copied by m2n_submit               */
+    int64_t N;
+    int K;
+    double fmax, fw;
+    double f_lo, df;
+    int64_t I;
+    double *w, *lambda;      /* HOST outputs [K*N], [K], or NULL             */
+    void *P, *E;             /* HOST outputs [I], float (FP32) or double
+                                (FP64); E NULL = not computed                */
+} m2n_request;
+
+typedef struct {
+    int status;              /* M2N_OK or the request's error               */
+    int batch_size;          /* requests in the batch that carried it       */
+    double latency_us;       /* submit to outputs written                   */
+    double service_us;       /* duration of that batch                      */
+} m2n_result;
+
+int m2n_queue_create(m2n_ctx *ctx, const m2n_queue_cfg *cfg, m2n_queue **out);
+/* Errors: M2N_ERR_ARG (sizes), M2N_ERR_CANCELLED (queue shutting down). */
+int m2n_submit(m2n_queue *q, const m2n_request *req, uint64_t *ticket);
+/* M2N_ERR_NOT_READY while in flight; otherwise the request's status, after
+ * which the ticket is released (M2N_ERR_ARG for an unknown ticket). */
+int m2n_poll(m2n_queue *q, uint64_t ticket, m2n_result *res);
+/* As m2n_poll after waiting up to timeout_us (< 0: without limit). */
+int m2n_wait(m2n_queue *q, uint64_t ticket, m2n_result *res, int64_t timeout_us);
+/* Requests not yet taken by a slot are cancelled (M2N_ERR_CANCELLED); the
+ * batches on the GPU complete first.  Every ticket is invalid afterwards. */
+int m2n_queue_destroy(m2n_queue *q);
+
 /* Kernel timing.  While enabled, every kernel launch of the library is
  * bracketed by a pair of HIP events recorded on the launch stream;
  * m2n_profile_read waits for them and returns, per kernel name, the total

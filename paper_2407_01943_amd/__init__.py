@@ -38,7 +38,8 @@ M2N_FP64 = 2
 EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes",
             "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
-            "m2n_batch_psd"]
+            "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
+            "m2n_queue_destroy"]
 
 
 class M2NSeries(ctypes.Structure):
@@ -49,6 +50,24 @@ class M2NSeries(ctypes.Structure):
                 ("weights", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("lam", ctypes.c_void_p), ("P", ctypes.c_void_p), ("E", ctypes.c_void_p),
                 ("J", ctypes.c_void_p)]
+
+
+class M2NQueueCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
+                ("slots", ctypes.c_int), ("prec", ctypes.c_int), ("nufft_tol", ctypes.c_double)]
+
+
+class M2NRequest(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p), ("x", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int), ("fmax", ctypes.c_double), ("fw", ctypes.c_double),
+                ("f_lo", ctypes.c_double), ("df", ctypes.c_double), ("I", ctypes.c_int64),
+                ("w", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("P", ctypes.c_void_p),
+                ("E", ctypes.c_void_p)]
+
+
+class M2NResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("batch_size", ctypes.c_int),
+                ("latency_us", ctypes.c_double), ("service_us", ctypes.c_double)]
 
 
 class M2NError(RuntimeError):
@@ -89,6 +108,16 @@ def _load():
     L.m2nufft_psd.restype = i
     L.m2n_batch_psd.argtypes = [vp, vp, ctypes.POINTER(M2NSeries), i, i, d]
     L.m2n_batch_psd.restype = i
+    L.m2n_queue_create.argtypes = [vp, ctypes.POINTER(M2NQueueCfg), ctypes.POINTER(vp)]
+    L.m2n_queue_create.restype = i
+    L.m2n_submit.argtypes = [vp, ctypes.POINTER(M2NRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.m2n_submit.restype = i
+    L.m2n_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(M2NResult)]
+    L.m2n_poll.restype = i
+    L.m2n_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(M2NResult), i64]
+    L.m2n_wait.restype = i
+    L.m2n_queue_destroy.argtypes = [vp]
+    L.m2n_queue_destroy.restype = i
     return L
 
 
@@ -250,3 +279,72 @@ def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=Tru
     if check:
         ctx.check(stream)
     return outs
+
+
+class Queue:
+    """The served form: m2n_queue with continuous batching.  Inputs are host
+    numpy arrays (copied at submit); outputs are host numpy arrays owned by
+    this object until the request is collected."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes=0, max_batch=0, slots=0,
+                 prec=M2N_FP32, nufft_tol=0.0):
+        import numpy as np
+        self._np = np
+        self.ctx = ctx
+        self.prec = prec
+        cfg = M2NQueueCfg(hbm_budget_bytes, max_batch, slots, prec, nufft_tol)
+        h = ctypes.c_void_p()
+        _err(lib.m2n_queue_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)),
+             "m2n_queue_create")
+        self.handle = h
+        self._out = {}
+
+    def submit(self, t, x, fmax, fw, K, f_lo, df, I, want_E=True):
+        np = self._np
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        N = t.shape[0]
+        rdt = np.float32 if self.prec == M2N_FP32 else np.float64
+        out = {"w": np.empty((K, N)), "lam": np.empty(K), "P": np.empty(I, dtype=rdt),
+               "E": np.empty(I, dtype=rdt) if want_E else None}
+        req = M2NRequest(t.ctypes.data, x.ctypes.data, N, int(K), float(fmax), float(fw),
+                         float(f_lo), float(df), int(I), out["w"].ctypes.data,
+                         out["lam"].ctypes.data, out["P"].ctypes.data,
+                         None if out["E"] is None else out["E"].ctypes.data)
+        tk = ctypes.c_uint64()
+        _err(lib.m2n_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)), "m2n_submit")
+        self._out[tk.value] = out
+        return tk.value
+
+    def _finish(self, ticket, code, res):
+        out = self._out.pop(ticket, None)
+        _err(code, "m2n_wait")
+        out.update(status=res.status, batch_size=res.batch_size, latency_us=res.latency_us,
+                   service_us=res.service_us)
+        return out
+
+    def poll(self, ticket):
+        res = M2NResult()
+        code = lib.m2n_poll(self.handle, ticket, ctypes.byref(res))
+        if code == M2N_ERR_NOT_READY:
+            return None
+        return self._finish(ticket, code, res)
+
+    def wait(self, ticket, timeout_us=-1):
+        res = M2NResult()
+        code = lib.m2n_wait(self.handle, ticket, ctypes.byref(res), int(timeout_us))
+        if code == M2N_ERR_NOT_READY:
+            return None
+        return self._finish(ticket, code, res)
+
+    def close(self):
+        if self.handle:
+            lib.m2n_queue_destroy(self.handle)
+            self.handle = None
+            self._out.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

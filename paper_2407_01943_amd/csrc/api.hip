@@ -117,7 +117,6 @@ int Ctx::prof_flush() {
 
 using namespace m2n;
 
-struct m2n_ctx : public m2n::Ctx {};
 
 extern "C" {
 

@@ -249,3 +249,6 @@ struct ProfScope {
 #define M2N_PROF(ctx, st, name) ::m2n::ProfScope M2N_PROF_CAT(prof_scope_, __LINE__)(ctx, st, name)
 
 }  // namespace m2n
+
+// the opaque handle of the C-ABI is the context itself
+struct m2n_ctx : public m2n::Ctx {};

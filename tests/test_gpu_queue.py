@@ -1,0 +1,113 @@
+"""Served form: requests through the m2n_queue (continuous batching) give the
+same tapers bit for bit, and P / Ehat within the NuFFT tolerance, as the
+same series alone; a failing request does not fail the others; a tiny HBM
+budget serialises the batches."""
+import threading
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m2n():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_01943_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(m2n):
+    c = m2n.Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _alone(m2n, ctx, s, prec):
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(dev)
+    x = torch.from_numpy(s.x).to(dev)
+    w, lam = m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K)
+    out = m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=prec)
+    return w.cpu().numpy(), lam.cpu().numpy(), out["P"].cpu().numpy(), out["E"].cpu().numpy()
+
+
+def _submit(q, s):
+    return q.submit(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I)
+
+
+def _check(m2n, ctx, s, r, prec):
+    w, lam, P, E = _alone(m2n, ctx, s, prec)
+    assert r["status"] == m2n.M2N_OK
+    assert np.array_equal(r["w"], w) and np.array_equal(r["lam"], lam)
+    dP = float(np.max(np.abs(r["P"].astype(np.float64) - P)) / np.max(np.abs(P)))
+    assert dP < 2e-6, dP
+    assert np.max(np.abs(r["E"].astype(np.float64) - E)) < 1e-7
+    return dP
+
+
+def test_queue_same_alone_and_in_mix(m2n, ctx):
+    series = [W.batched_series(s) for s in range(24)]
+    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP32)
+    tickets = {}
+    # two submitting threads: the mix depends on timing, the results must not
+    def sub(part):
+        for i in part:
+            tickets[i] = _submit(q, series[i])
+    th = threading.Thread(target=sub, args=(range(0, 24, 2),))
+    th.start()
+    sub(range(1, 24, 2))
+    th.join()
+    res = {i: q.wait(tk) for i, tk in tickets.items()}
+    sizes = sorted(r["batch_size"] for r in res.values())
+    _say(f"case 24 requests, batch sizes seen {sizes[0]}..{sizes[-1]}")
+    assert sizes[-1] > 1
+    worst = max(_check(m2n, ctx, series[i], res[i], m2n.M2N_FP32) for i in res)
+    _say(f"  worst P difference alone vs in the mix {worst:.2e}")
+    q.close()
+
+
+def test_queue_failing_request_is_isolated(m2n, ctx):
+    good = [W.batched_series(s) for s in (30, 31, 32)]
+    bad = W.batched_series(33)
+    bad.x = bad.x.copy()
+    bad.x[5] = np.nan
+    q = m2n.Queue(ctx, slots=1, prec=m2n.M2N_FP32)
+    tk = [_submit(q, s) for s in good[:2]] + [_submit(q, bad)] + [_submit(q, good[2])]
+    out = []
+    for t in tk:
+        try:
+            out.append(q.wait(t))
+        except m2n.M2NError as e:
+            out.append(e.code)
+    assert out[2] == m2n.M2N_ERR_ARG
+    for s, r in zip(good, [out[0], out[1], out[3]]):
+        _check(m2n, ctx, s, r, m2n.M2N_FP32)
+    q.close()
+
+
+def test_queue_budget_serialises(m2n, ctx):
+    series = [W.batched_series(s) for s in (40, 41, 42)]
+    q = m2n.Queue(ctx, hbm_budget_bytes=1, slots=2, prec=m2n.M2N_FP32)
+    tk = [_submit(q, s) for s in series]
+    res = [q.wait(t) for t in tk]
+    assert all(r["batch_size"] == 1 for r in res)
+    for s, r in zip(series, res):
+        _check(m2n, ctx, s, r, m2n.M2N_FP32)
+    q.close()
+
+
+def test_queue_destroy_with_pending_requests(m2n, ctx):
+    q = m2n.Queue(ctx, slots=1, prec=m2n.M2N_FP32)
+    for s in range(6):
+        _submit(q, W.batched_series(50 + s))
+    q.close()   # pending ones are cancelled, running batches complete
