@@ -42,7 +42,88 @@ def parse():
                     help="bands in the oracle's timed NUDFT sample")
     ap.add_argument("--batch-series", type=int, default=512,
                     help="series in the batched-form measurement (0: skip)")
+    ap.add_argument("--served-seconds", type=float, default=10.0,
+                    help="length of the served-form Poisson arrival trace (0: skip)")
+    ap.add_argument("--served-rate", type=float, default=200.0, help="arrivals per second")
     return ap.parse_args()
+
+
+def served_form(m2n, torch, workloads, ctx, rate, seconds):
+    """Poisson arrivals through the request queue (continuous batching, FP32
+    NuFFT) against the unbatched per-series FP64 path on one stream, same
+    arrival trace and requests."""
+    import threading
+    import numpy as np
+    arr = workloads.poisson_arrivals(rate, seconds)
+    reqs = [workloads.served_request(r) for r in range(len(arr))]
+    n = len(reqs)
+    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP32)
+    warm = [reqs[0]] + [r for r in reqs if r.I == 2 ** 20][:1]
+    for r in warm:
+        q.wait(q.submit(r.t, r.x, r.fmax, r.fw, r.K, r.f_lo, r.df, r.I))
+    tickets = [None] * n
+    ready = [threading.Event() for _ in range(n)]
+    start = time.perf_counter() + 0.05
+
+    def submitter():
+        for i, ta in enumerate(arr):
+            dt = start + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            r = reqs[i]
+            tickets[i] = q.submit(r.t, r.x, r.fmax, r.fw, r.K, r.f_lo, r.df, r.I)
+            ready[i].set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, bsz, fails = [], [], 0
+    for i in range(n):
+        ready[i].wait()
+        try:
+            res = q.wait(tickets[i])
+            lat.append(res["latency_us"] / 1e3)
+            bsz.append(res["batch_size"])
+        except m2n.M2NError:
+            fails += 1
+    end = time.perf_counter()
+    th.join()
+    q.close()
+    wall = end - start
+
+    # baseline: per-series FP64 GPU path, FIFO on one stream, same arrivals
+    dev = torch.device("cuda:0")
+
+    def serve_one(r):
+        t = torch.from_numpy(r.t).to(dev)
+        x = torch.from_numpy(r.x).to(dev)
+        w, lam = m2n.gpss_tapers(ctx, t, r.fmax, r.fw, r.K)
+        out = m2n.m2nufft_psd(ctx, t, x, w, lam, r.fmax, r.fw, r.f_lo, r.df, r.I,
+                              prec=m2n.M2N_FP64, check=False)
+        return w.cpu(), lam.cpu(), out["P"].cpu(), out["E"].cpu()
+
+    for r in warm:
+        serve_one(r)
+    torch.cuda.synchronize()
+    blat = []
+    b0 = time.perf_counter() + 0.05
+    for i, r in enumerate(reqs):
+        dt = b0 + arr[i] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        serve_one(r)
+        blat.append((time.perf_counter() - (b0 + arr[i])) * 1e3)
+    bwall = time.perf_counter() - b0
+    lat, blat = np.array(lat), np.array(blat)
+    return {"requests": n, "rate_per_s": rate, "seconds": seconds,
+            "long_requests": int(sum(r.I == 2 ** 20 for r in reqs)), "failed": fails,
+            "psds_per_s": round(n / wall, 1), "latency_ms": {
+                "p50": round(float(np.percentile(lat, 50)), 3),
+                "p99": round(float(np.percentile(lat, 99)), 3)},
+            "mean_batch": round(float(np.mean(bsz)), 2), "max_batch": int(np.max(bsz)),
+            "baseline_fp64_per_series": {
+                "psds_per_s": round(n / bwall, 1), "latency_ms": {
+                    "p50": round(float(np.percentile(blat, 50)), 3),
+                    "p99": round(float(np.percentile(blat, 99)), 3)}}}
 
 
 def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
@@ -239,6 +320,13 @@ def main():
         print(f"bench: batched {batched['ms_per_batch']} ms per {a.batch_series} series",
               file=sys.stderr, flush=True)
 
+    served = None
+    if a.served_seconds > 0:
+        print("bench: served form", file=sys.stderr, flush=True)
+        served = served_form(m2n, torch, workloads, ctx, a.served_rate, a.served_seconds)
+        print(f"bench: served p50 {served['latency_ms']['p50']} ms p99 {served['latency_ms']['p99']} ms",
+              file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -267,6 +355,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "batched_form": batched,
+        "served_form": served,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -38,7 +38,7 @@ import numpy as np
 
 __all__ = [
     "Series", "small_gapped", "gapped_20k", "gapped_82k", "gapped_scaled",
-    "batched_series", "scheme_uniform", "scheme_jitter", "scheme_missing",
+    "batched_series", "served_request", "poisson_arrivals", "scheme_uniform", "scheme_jitter", "scheme_missing",
     "scheme_arithmetic", "jitter_stress", "white_noise", "by_name",
 ]
 
@@ -76,12 +76,13 @@ def _sinusoids(rng, tt, amps, freqs):
 
 
 def _ar2(rng, n, r=0.95, theta=0.6 * math.pi, burn=1000):
-    """AR(2) with poles r e^{+-j theta}, unit-variance innovations."""
+    """AR(2) with poles r e^{+-j theta}, unit-variance innovations:
+    y_i = a1 y_{i-1} + a2 y_{i-2} + e_i (recursive filter, zero start)."""
+    from scipy.signal import lfilter
     a1, a2 = 2.0 * r * math.cos(theta), -r * r
     e = rng.standard_normal(n + burn)
-    y = np.zeros(n + burn)
-    for i in range(2, n + burn):
-        y[i] = a1 * y[i - 1] + a2 * y[i - 2] + e[i]
+    e[:2] = 0.0
+    y = lfilter([1.0], [1.0, -a1, -a2], e)
     return y[burn:]
 
 
@@ -136,10 +137,9 @@ def gapped_scaled(L: int, K: int, I: int, seed: int = 11) -> Series:
     return _gapped_periodic(f"gapped_{L}", seed, L, K, 4.0 / L, I)
 
 
-def batched_series(s: int) -> Series:
-    """Series s of the 512-series batch (seed 3,000,000 + s)."""
-    rng = _rng(3_000_000 + s)
-    n_obs = int(round(math.exp(rng.uniform(math.log(1024), math.log(16384)))))
+def _batched_from_rng(rng, name, n_obs=None, I=2 ** 16) -> Series:
+    if n_obs is None:
+        n_obs = int(round(math.exp(rng.uniform(math.log(1024), math.log(16384)))))
     p = rng.uniform(0.05, 0.40)
     if rng.random() < 0.5:
         L = int(math.ceil(n_obs / (1.0 - p)))
@@ -164,9 +164,31 @@ def batched_series(s: int) -> Series:
     amps = 10.0 ** rng.uniform(-3.0, 0.0, size=5)
     freqs = rng.uniform(0.0, 0.5, size=5)
     sig += _sinusoids(rng, tt, amps, freqs)
-    I = 2 ** 16
-    return Series(f"batched_{s}", tt[idx].copy(), sig[idx].copy(), 0.5,
+    return Series(name, tt[idx].copy(), sig[idx].copy(), 0.5,
                   (K + 1) / (2.0 * L), K, -0.5, 1.0 / I, I, L)
+
+
+def batched_series(s: int) -> Series:
+    """Series s of the 512-series batch (seed 3,000,000 + s)."""
+    return _batched_from_rng(_rng(3_000_000 + s), f"batched_{s}")
+
+
+def served_request(r: int) -> Series:
+    """Request r of the served workload (seed 4,000,000 + r): with
+    probability 0.02 a long series (N_obs = 65,536, I = 2**20), otherwise a
+    series of the batched distribution."""
+    rng = _rng(4_000_000 + r)
+    if rng.random() < 0.02:
+        return _batched_from_rng(rng, f"served_{r}_long", n_obs=65536, I=2 ** 20)
+    return _batched_from_rng(rng, f"served_{r}")
+
+
+def poisson_arrivals(rate: float, seconds: float, seed: int = 4) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate on [0, seconds)."""
+    rng = _rng(seed)
+    n = int(rate * seconds * 1.5) + 16
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    return t[t < seconds]
 
 
 # --- the paper's four 50-point sampling schemes (Section 4) ----------------
