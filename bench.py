@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served-form Poisson arrival trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy (byte-counter calibration)")
     return ap.parse_args()
 
 
@@ -225,6 +227,16 @@ def main():
     def nufft_only():
         m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, I, prec=prec,
                         want_E=True, out=(P, E, None), check=False)
+
+    if a.calib_copy:
+        # a plain copy of known size: the HBM byte counters of the kernel
+        # that performs it calibrate the counters of the path's kernels
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(a.warmup):
         step()

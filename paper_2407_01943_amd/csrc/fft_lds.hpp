@@ -34,6 +34,28 @@ __device__ __forceinline__ void dft4(cplx<R>* u) {
     u[3] = {b.x - d.y, b.y + d.x};   // b + i d
 }
 
+// forward radix-8 butterfly in place, outputs in natural order: two
+// length-4 DFTs of the even and odd inputs, combined with w8^q, w8 = e^{-i pi/4}
+template <typename R>
+__device__ __forceinline__ void dft8(cplx<R>* u) {
+    cplx<R> e[4] = {u[0], u[2], u[4], u[6]};
+    cplx<R> o[4] = {u[1], u[3], u[5], u[7]};
+    dft4(e);
+    dft4(o);
+    const R h = (R)0.70710678118654752440;
+    const cplx<R> o1 = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};    // w8 o1
+    const cplx<R> o2 = {o[2].y, -o[2].x};                                 // -i o2
+    const cplx<R> o3 = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};   // w8^3 o3
+    u[0] = cadd(e[0], o[0]);
+    u[4] = csub(e[0], o[0]);
+    u[1] = cadd(e[1], o1);
+    u[5] = csub(e[1], o1);
+    u[2] = cadd(e[2], o2);
+    u[6] = csub(e[2], o2);
+    u[3] = cadd(e[3], o3);
+    u[7] = csub(e[3], o3);
+}
+
 template <typename R, int N, int NB, int NT, int LD, int RAD>
 __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw,
                                           int tws, int p) {
@@ -64,7 +86,8 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
         if (BF % NT == 0 || idx < BF) {
             const int b = idx / Q, j = idx - b * Q;
             const int k = j & (p - 1);
-            if (RAD == 4) dft4(v[it]);
+            if constexpr (RAD == 8) dft8(v[it]);
+            else if constexpr (RAD == 4) dft4(v[it]);
             else dft2(v[it][0], v[it][1]);
             const int base = b * LD + (j - k) * RAD + k;
 #pragma unroll
@@ -76,21 +99,22 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
-// NB forward FFTs of length N (power of two, >= 2) in LDS.  Caller must have
-// synchronised after writing buf; returns synchronised.
+// NB forward FFTs of length N (power of two, >= 2) in LDS: radix-8 stages
+// while three or more factors of two remain, then one radix-4 or radix-2
+// stage.  Caller must have synchronised after writing buf; returns
+// synchronised.
 template <typename R, int N, int NB, int NT, int LD>
 __device__ __forceinline__ void fft_lds(cplx<R>* buf, const cplx<R>* __restrict__ tw, int tws) {
     constexpr int LOG = ilog2c(N);
+    constexpr int N8 = LOG / 3, REM = LOG % 3;
     int p = 1;
-    if (LOG & 1) {
-        fft_stage<R, N, NB, NT, LD, 2>(buf, tw, tws, p);
-        p = 2;
-    }
 #pragma unroll 1
-    for (int s = 0; s < LOG / 2; ++s) {
-        fft_stage<R, N, NB, NT, LD, 4>(buf, tw, tws, p);
-        p *= 4;
+    for (int s = 0; s < N8; ++s) {
+        fft_stage<R, N, NB, NT, LD, 8>(buf, tw, tws, p);
+        p *= 8;
     }
+    if constexpr (REM == 2) fft_stage<R, N, NB, NT, LD, 4>(buf, tw, tws, p);
+    else if constexpr (REM == 1) fft_stage<R, N, NB, NT, LD, 2>(buf, tw, tws, p);
 }
 
 }  // namespace m2n

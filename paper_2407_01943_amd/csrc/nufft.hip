@@ -41,7 +41,6 @@ namespace m2n {
 namespace {
 
 constexpr int NT = 256;            // threads per workgroup, all NuFFT kernels
-constexpr int PTS_PER_WG = 1024;   // points per workgroup in the binning kernels
 constexpr int MAX_BINS = 1024;
 
 // ------------------------------------------------------------------ helpers
@@ -115,6 +114,29 @@ __device__ __forceinline__ R es_kernel(R z, R beta) {
     return exp(beta * (sqrt(a) - (R)1));
 }
 
+// FP32 spreading weights from the hardware square root and base-2
+// exponential: phi <= 1 and the exponent error (a few ulps of |beta|) gives
+// a relative error of about 1e-6 only where phi is already tiny
+template <typename R>
+__device__ __forceinline__ R es_spread(R z, R beta);
+template <>
+__device__ __forceinline__ float es_spread<float>(float z, float beta) {
+    float a = 1.0f - z * z;
+    a = a > 0.0f ? a : 0.0f;
+    return __builtin_amdgcn_exp2f(beta * 1.4426950408889634f * (__builtin_amdgcn_sqrtf(a) - 1.0f));
+}
+template <>
+__device__ __forceinline__ double es_spread<double>(double z, double beta) {
+    return es_kernel<double>(z, beta);
+}
+
+// a pointer taken out of a descriptor, marked as global memory so that
+// loads through it are global (not flat) loads
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gp(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -152,10 +174,10 @@ struct NuSeries {
     int* flags;    // [nwg]
     int* l0s;      // [N] binned first cells
     void* dels;    // [N] R offsets
-    void* c0s;     // [N] cplx<R> pre-phased samples
-    int* idxs;     // [N] sample index
+    void* cw;      // [K][N] cplx<R> tapered pre-phased samples, bin order
     void* inter;   // [K][nf] cplx<R> after pass 1
-    double* norms; // [K] sum of w_k^2 (for E)
+    double* nrm;   // [nwg][K] partial sums of w_k^2 (for E)
+    double* norms; // [K] their totals
     int* diag;     // [1] R(B) = 2 f_max I
     int64_t N;
     double f_lo, df, fmax, fw;
@@ -169,7 +191,26 @@ struct NuArgs {
     const void* tw;          // FFT twiddles
     const void* inv_phihat;  // deconvolution table
     unsigned* dev_err;
+    long long* stamp;        // phase clock of workgroup 0 (NULL: off)
 };
+
+// clock of a phase boundary in workgroup (0, 0), for kernel tuning
+__device__ __forceinline__ void phase_stamp(const NuArgs& a, int i) {
+    if (a.stamp && blockIdx.x == 0 && blockIdx.y == 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) a.stamp[i] = clock64();
+    }
+}
+
+// start and end times (100 MHz device clock) of every workgroup of series 0
+// (kernel tuning):
+// stamp[base + 2 b], stamp[base + 2 b + 1], b < 2048
+__device__ __forceinline__ void wg_stamp(const NuArgs& a, int base, int end) {
+    if (a.stamp && blockIdx.y == 0 && blockIdx.x < 2048) {
+        if (end) __syncthreads();
+        if (threadIdx.x == 0) a.stamp[base + 2 * blockIdx.x + end] = (long long)__builtin_amdgcn_s_memrealtime();
+    }
+}
 
 // this workgroup's series
 __device__ __forceinline__ NuSeries series_of(const NuSeries& d0, const NuSeries* D) {
@@ -211,7 +252,6 @@ __global__ __launch_bounds__(NT) void k_hist(NuArgs a, NuSeries d0, const NuSeri
 // K1b: one workgroup per series.  off[wg][b] = start of (wg, b) in bin-major
 // order, binoff[b] = start of bin b.  Reduces the flags: diag[0] = 1 when
 // R(B) is 2 f_max I (every t integer and 2 f_max a positive integer).
-// Clears the taper norms that pass 1 accumulates for Ehat.
 constexpr int SCAN_LDS = 12288;   // (workgroup, bin) counts staged in LDS
 __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
@@ -227,12 +267,22 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     }
     if (staged)
         for (int e = tid; e < nwg * nbins; e += blockDim.x) cnt[e] = d.hist[e];
-    for (int k = tid; k < d.K; k += blockDim.x) d.norms[k] = 0.0;
     __syncthreads();
     for (int b = tid; b < nbins; b += blockDim.x) {
-        int s = 0;
-        for (int g = 0; g < nwg; ++g) s += staged ? cnt[g * nbins + b] : d.hist[(int64_t)g * nbins + b];
-        tot[b] = s;
+        int s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int g = 0;
+        if (staged) {
+            for (; g + 3 < nwg; g += 4) {
+                s0 += cnt[g * nbins + b];
+                s1 += cnt[(g + 1) * nbins + b];
+                s2 += cnt[(g + 2) * nbins + b];
+                s3 += cnt[(g + 3) * nbins + b];
+            }
+            for (; g < nwg; ++g) s0 += cnt[g * nbins + b];
+        } else {
+            for (; g < nwg; ++g) s0 += d.hist[(int64_t)g * nbins + b];
+        }
+        tot[b] = (s0 + s1) + (s2 + s3);
     }
     int li = 1, lb = 0;
     for (int g = tid; g < nwg; g += blockDim.x) {
@@ -262,11 +312,30 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     for (int b = tid; b <= nbins; b += blockDim.x) d.binoff[b] = tot[b];
     for (int b = tid; b < nbins; b += blockDim.x) {
         int run = tot[b];
-        for (int g = 0; g < nwg; ++g) {
-            const int c = staged ? cnt[g * nbins + b] : d.hist[(int64_t)g * nbins + b];
-            if (staged) cnt[g * nbins + b] = run;
-            else d.off[(int64_t)g * nbins + b] = run;
-            run += c;
+        int g = 0;
+        if (staged) {
+            // eight counts in flight, then the running sum
+            for (; g + 7 < nwg; g += 8) {
+                int c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = cnt[(g + u) * nbins + b];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    cnt[(g + u) * nbins + b] = run;
+                    run += c[u];
+                }
+            }
+            for (; g < nwg; ++g) {
+                const int c = cnt[g * nbins + b];
+                cnt[g * nbins + b] = run;
+                run += c;
+            }
+        } else {
+            for (; g < nwg; ++g) {
+                const int c = d.hist[(int64_t)g * nbins + b];
+                d.off[(int64_t)g * nbins + b] = run;
+                run += c;
+            }
         }
     }
     __syncthreads();
@@ -281,7 +350,9 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     }
 }
 
-// K1c: scatter the points into bin order.
+// K1c: scatter the points into bin order, with the K tapered samples
+// cw[k][pos] = w_k(t_n) x_n e^{-j 2 pi (f_lo + h df) t_n} so that pass 1
+// reads its taper's values without a dependent gather.
 template <typename R>
 __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
@@ -291,7 +362,7 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
     for (int b = threadIdx.x; b < a.nbins; b += NT) cur[b] = 0;
     __syncthreads();
     R* dels = (R*)d.dels;
-    cplx<R>* c0s = (cplx<R>*)d.c0s;
+    cplx<R>* cw = (cplx<R>*)d.cw;
     const int64_t n0 = (int64_t)wg * d.ppw;
     for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
@@ -301,13 +372,31 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
         const int pos = d.off[(int64_t)wg * a.nbins + bin] + atomicAdd(&cur[bin], 1);
         d.l0s[pos] = g.l0;
         dels[pos] = (R)g.del;
-        c0s[pos] = {(R)g.cre, (R)g.cim};
-        d.idxs[pos] = (int)n;
+        for (int k = 0; k < d.K; ++k) {
+            const double wv = d.w[(int64_t)k * d.N + n];
+            cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
+        }
+    }
+    if (d.E) {
+        // this workgroup's share of sum_n w_k(t_n)^2, summed in a fixed order
+        __shared__ double red[NT / 64];
+        for (int k = 0; k < d.K; ++k) {
+            double sq = 0.0;
+            for (int j = threadIdx.x; j < d.ppw; j += NT) {
+                const int64_t n = n0 + j;
+                if (n >= d.N) break;
+                const double wv = d.w[(int64_t)k * d.N + n];
+                sq += wv * wv;
+            }
+            sq = block_sum(sq, red);
+            if (threadIdx.x == 0) d.nrm[(int64_t)wg * d.K + k] = sq;
+        }
     }
 }
 
 // -------------------------------------------------------------- pass 1
 constexpr int NT1 = 512;   // threads per pass-1 workgroup
+constexpr int MAXSEG = 8;  // column blocks a pass-1 workgroup gathers points from
 constexpr int NT2 = 512;   // threads per pass-2 workgroup
 
 // exp(-2 pi i q / nf) for 0 <= q < nf (nf a power of two: 2 q / nf is exact)
@@ -336,52 +425,75 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
     constexpr int LD = N1 + 1;
     __shared__ cplx<R> tile[B * LD];
     __shared__ cplx<R> tw[N1];
-    __shared__ double nred;
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
+    wg_stamp(a, 1024, 0);
+    phase_stamp(a, 0);
     for (int e = threadIdx.x; e < B * LD; e += NT1) tile[e] = {(R)0, (R)0};
     for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
-    if (threadIdx.x == 0) nred = 0.0;
     __syncthreads();
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
-    const double* wk = d.w + (int64_t)k * d.N;
-    const R* dels = (const R*)d.dels;
-    const cplx<R>* c0s = (const cplx<R>*)d.c0s;
-    const bool needE = d.E != nullptr;
-    double nrm = 0.0;   // sum of w_k^2 over this block's own points (for Ehat)
-    for (int q = 0; q <= a.lookback; ++q) {
-        int bb = blk - q;
-        if (bb < 0) bb += nblk;
-        const int s = d.binoff[bb], e = d.binoff[bb + 1];
-        for (int j = s + threadIdx.x; j < e; j += NT1) {
-            const int l0 = d.l0s[j];
-            const R del = dels[j];
-            const cplx<R> cin = c0s[j];
-            const double wd = wk[d.idxs[j]];
-            if (q == 0) nrm += wd * wd;
-            const cplx<R> c = cscale(cin, (R)wd);
-            for (int r = 0; r < w; ++r) {
-                int cell = l0 + r;
-                if (cell >= nf) cell -= nf;
-                const int cb = (cell & (N2 - 1)) - c0;
-                if (cb >= 0 && cb < B) {
-                    const int row = cell >> log_N2;
-                    const R phi = es_kernel<R>(((R)r + del) * two_over_w, beta);
-                    atomicAdd(&tile[cb * LD + row].x, c.x * phi);
-                    atomicAdd(&tile[cb * LD + row].y, c.y * phi);
-                }
+    const auto* dels = gp((const R*)d.dels);
+    const auto* cwk = gp((const cplx<R>*)d.cw + (int64_t)k * d.N);
+    const auto* l0s = gp((const int*)d.l0s);
+    const auto* binoff = gp((const int*)d.binoff);
+    phase_stamp(a, 1);
+    // the points of bins blk - lookback .. blk, as one flat range of
+    // segments so that every thread's loads are independent
+    // (lookback + 1 <= MAXSEG is checked when the plan is built)
+    int sb[MAXSEG], sl[MAXSEG];
+    int total = 0;
+#pragma unroll
+    for (int q = 0; q < MAXSEG; ++q) {
+        sb[q] = 0;
+        sl[q] = 0;
+        if (q <= a.lookback) {
+            int bb = blk - q;
+            if (bb < 0) bb += nblk;
+            sb[q] = binoff[bb];
+            sl[q] = binoff[bb + 1] - sb[q];
+            total += sl[q];
+        }
+    }
+    phase_stamp(a, 5);
+    for (int f = threadIdx.x; f < total; f += NT1) {
+        int j = -1, r0 = f;
+#pragma unroll
+        for (int q = 0; q < MAXSEG; ++q) {
+            if (j < 0) {
+                if (r0 < sl[q]) j = sb[q] + r0;
+                else r0 -= sl[q];
+            }
+        }
+        const int l0 = l0s[j];
+        const R del = dels[j];
+        const cplx<R> c = {cwk[j].x, cwk[j].y};
+        for (int r = 0; r < w; ++r) {
+            int cell = l0 + r;
+            if (cell >= nf) cell -= nf;
+            const int cb = (cell & (N2 - 1)) - c0;
+            if (cb >= 0 && cb < B) {
+                const int row = cell >> log_N2;
+                const R phi = es_spread<R>(((R)r + del) * two_over_w, beta);
+                atomicAdd(&tile[cb * LD + row].x, c.x * phi);
+                atomicAdd(&tile[cb * LD + row].y, c.y * phi);
             }
         }
     }
-    if (needE) {
-        for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
-        if ((threadIdx.x & 63) == 0) atomicAdd(&nred, nrm);
-    }
     __syncthreads();
-    if (needE && threadIdx.x == 0) atomicAdd(&d.norms[k], nred);
+    if (d.E && blk == 0 && threadIdx.x < 64) {
+        // norms[k] = the binning workgroups' partial sums of w_k^2, in order
+        const auto* nrm = gp((const double*)d.nrm);
+        double sq = 0.0;
+        for (int g = threadIdx.x; g < d.nwg; g += 64) sq += nrm[(int64_t)g * d.K + k];
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        if (threadIdx.x == 0) d.norms[k] = sq;
+    }
+    phase_stamp(a, 2);
     fft_lds<R, N1, B, NT1, LD>(tile, tw, 1);
+    phase_stamp(a, 3);
     // four-step twiddle exp(-2 pi i (c0 + cb) m1 / nf), then G[k][m1][l2]
     const R two_nf = (R)2 / (R)nf;
     cplx<R>* out = (cplx<R>*)d.inter + (int64_t)k * nf;
@@ -390,6 +502,8 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
         const cplx<R> twv = twiddle_nf<R>((c0 + cb) * m1, two_nf);
         out[(int64_t)m1 * N2 + c0 + cb] = cmul(tile[cb * LD + m1], twv);
     }
+    phase_stamp(a, 4);
+    wg_stamp(a, 1024, 1);
 }
 
 // -------------------------------------------------------------- pass 2
@@ -419,14 +533,19 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     R* P = (R*)d.P;
     R* E = (R*)d.E;
     cplx<R>* J = (cplx<R>*)d.J;
+    wg_stamp(a, 8192, 0);
+    phase_stamp(a, 8);
     for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
-    if (E && threadIdx.x == 0) {
-        // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I
+    if (E && threadIdx.x < 64) {
+        // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I (lane k)
         double e = 0.0;
-        const double c = 2.0 * d.fmax;
-        for (int k = 0; k < K; ++k)
-            e += fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * d.norms[k]));
-        s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
+        const int k = threadIdx.x;
+        if (k < K) {
+            const double c = 2.0 * d.fmax;
+            e = fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * d.norms[k]));
+        }
+        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+        if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
     }
     // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
@@ -441,15 +560,30 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     for (int it = 0; it < OUT_IT; ++it) acc[it] = (R)0;
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
         const int nk = K - kc0 < KC ? K - kc0 : KC;
-        for (int e = threadIdx.x; e < ROWS * N2; e += NT2) {
+        // all loads first, then the LDS stores, so that they are in flight
+        // together (a row never straddles a wavefront: the taper test is
+        // uniform per wavefront)
+        constexpr int LIT = ROWS * N2 / NT2;
+        static_assert(ROWS * N2 % NT2 == 0, "pass-2 tile");
+        cplx<R> v[LIT];
+#pragma unroll
+        for (int u = 0; u < LIT; ++u) {
+            const int e = threadIdx.x + u * NT2;
             const int r = e / N2, l2 = e - r * N2;
             const int kq = r / M, mm = r - kq * M;
-            cplx<R> v = {(R)0, (R)0};
-            if (kq < nk) v = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
-            rows[r * LD + l2] = v;
+            v[u] = {(R)0, (R)0};
+            if (kq < nk) v[u] = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
+        }
+#pragma unroll
+        for (int u = 0; u < LIT; ++u) {
+            const int e = threadIdx.x + u * NT2;
+            const int r = e / N2, l2 = e - r * N2;
+            rows[r * LD + l2] = v[u];
         }
         __syncthreads();
+        phase_stamp(a, 9);
         fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1);
+        phase_stamp(a, 10);
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
             const int e = threadIdx.x + it * NT2;
@@ -487,6 +621,8 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             }
         }
     }
+    phase_stamp(a, 11);
+    wg_stamp(a, 8192, 1);
 }
 
 // ------------------------------------------------- single-workgroup path
@@ -531,7 +667,7 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
             for (int r = 0; r < w; ++r) {
                 int cell = g.l0 + r;
                 if (cell >= NF) cell -= NF;
-                const R phi = es_kernel<R>(((R)r + del) * two_over_w, beta);
+                const R phi = es_spread<R>(((R)r + del) * two_over_w, beta);
                 atomicAdd(&grid[cell].x, c.x * phi);
                 atomicAdd(&grid[cell].y, c.y * phi);
             }
@@ -639,7 +775,7 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
         if (p.B > 32) p.B = 32;
         if (p.B > p.N2 / 2) p.B = p.N2 / 2;
         p.lookback = (p.w - 1 + p.B - 1) / p.B;
-        if (p.lookback >= p.N2 / p.B || p.N2 / p.B > MAX_BINS) {
+        if (p.lookback >= p.N2 / p.B || p.N2 / p.B > MAX_BINS || p.lookback + 1 > MAXSEG) {
             set_error("unsupported grid split (N2 = %d, B = %d, w = %d)", p.N2, p.B, p.w);
             return M2N_ERR_UNSUPPORTED;
         }
@@ -712,6 +848,10 @@ int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
 }
 
 // ---------------------------------------------------------- dispatchers
+// device buffer for the phase clocks of workgroup 0 (kernel tuning builds
+// that compile this file into a timing harness set it; NULL otherwise)
+long long* g_phase_stamp = nullptr;
+
 NuArgs make_args(Ctx* ctx, const NufftPlan& p) {
     NuArgs a{};
     a.I = p.I;
@@ -730,6 +870,7 @@ NuArgs make_args(Ctx* ctx, const NufftPlan& p) {
     a.tw = p.tw_fft.p;
     a.inv_phihat = p.inv_phihat.p;
     a.dev_err = ctx->dev_err;
+    a.stamp = g_phase_stamp;
     return a;
 }
 
@@ -848,9 +989,9 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         d.fw = s.fw;
         d.K = s.K;
         if (!p.single) {
-            // points per binning workgroup: at least PTS_PER_WG, and few enough
-            // workgroups that the scan can stage every (workgroup, bin) count
-            int64_t ppw = PTS_PER_WG;
+            // points per binning workgroup: one per thread unless the scan
+            // could then not stage every (workgroup, bin) count in LDS
+            int64_t ppw = NT;
             while ((s.N + ppw - 1) / ppw * nbins > SCAN_LDS && ppw < (int64_t(1) << 20)) ppw *= 2;
             const int64_t nwg64 = (s.N + ppw - 1) / ppw;
             if (nwg64 > (1 << 20)) {
@@ -874,10 +1015,10 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
                 d.flags = (int*)c.take(sizeof(int) * (size_t)d.nwg);
                 d.l0s = (int*)c.take(sizeof(int) * N);
                 d.dels = c.take(sizeof(R) * N);
-                d.c0s = c.take(sizeof(cplx<R>) * N);
-                d.idxs = (int*)c.take(sizeof(int) * N);
+                d.cw = c.take(sizeof(cplx<R>) * (size_t)d.K * N);
                 d.inter = c.take(sizeof(cplx<R>) * (size_t)d.K * p.nf);
-                d.norms = (double*)c.take(sizeof(double) * 64);
+                d.nrm = (double*)c.take(sizeof(double) * (size_t)d.nwg * d.K);
+                d.norms = (double*)c.take(sizeof(double) * (size_t)d.K);
                 d.diag = (int*)c.take(64);
             }
         };
