@@ -415,6 +415,49 @@ __device__ __forceinline__ cplx<double> twiddle_nf<double>(int q, double two_ove
     return {cs, -sn};
 }
 
+// One point as the owners of a tile row read it: s is the grid column of the
+// point's first cell relative to the block's first column c0 (negative when
+// the support starts left of the block), so the owner of column cb takes tap
+// r = cb - s when 0 <= r < w.
+template <typename R>
+struct SpreadRec {
+    int s;
+    R del;
+    cplx<R> c;
+};
+
+// exclusive prefix sum of cnt[0..n) in place, cnt[n] = total (NT1 threads)
+template <int N>
+__device__ __forceinline__ void scan_counts(int* cnt, int* wtot) {
+    constexpr int PER = (N + NT1 - 1) / NT1;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int v[PER];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = t * PER + q;
+        v[q] = i < N ? cnt[i] : 0;
+        sum += v[q];
+    }
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int run = incl - sum;
+    for (int i = 0; i < wv; ++i) run += wtot[i];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = t * PER + q;
+        if (i < N) cnt[i] = run;
+        run += v[q];
+    }
+    if (t == NT1 - 1) cnt[N] = run;
+    __syncthreads();
+}
+
 template <typename R, int N1, int B>
 __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
@@ -423,16 +466,26 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
     const int k = blockIdx.x / nblk;
     if (k >= d.K) return;
     constexpr int LD = N1 + 1;
+    constexpr int G = 64 / B;                               // tile rows per wavefront task
+    constexpr int TASKS = N1 * B / NT1;                     // tile cells each thread owns
+    constexpr int CAP = sizeof(R) == 4 ? NT1 : NT1 / 2;     // points sorted per chunk
+    constexpr int LIST_BYTES = CAP * (int)sizeof(SpreadRec<R>);
+    constexpr int TW_BYTES = N1 * (int)sizeof(cplx<R>);
+    constexpr int REGION = LIST_BYTES > TW_BYTES ? LIST_BYTES : TW_BYTES;
+    static_assert(64 % B == 0 && (N1 * B) % NT1 == 0, "tile split");
     __shared__ cplx<R> tile[B * LD];
-    __shared__ cplx<R> tw[N1];
+    __shared__ int rows[N1 + 1];
+    __shared__ int wtot[NT1 / 64];
+    // the chunk's row-sorted points during the spread, the twiddles after it
+    __shared__ __attribute__((aligned(16))) unsigned char region[REGION];
+    SpreadRec<R>* list = (SpreadRec<R>*)region;
+    cplx<R>* tw = (cplx<R>*)region;
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
     wg_stamp(a, 1024, 0);
     phase_stamp(a, 0);
-    for (int e = threadIdx.x; e < B * LD; e += NT1) tile[e] = {(R)0, (R)0};
-    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
-    __syncthreads();
+    for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
     const auto* dels = gp((const R*)d.dels);
@@ -457,8 +510,7 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
             total += sl[q];
         }
     }
-    phase_stamp(a, 5);
-    for (int f = threadIdx.x; f < total; f += NT1) {
+    auto locate = [&](int f) {
         int j = -1, r0 = f;
 #pragma unroll
         for (int q = 0; q < MAXSEG; ++q) {
@@ -467,21 +519,92 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
                 else r0 -= sl[q];
             }
         }
-        const int l0 = l0s[j];
-        const R del = dels[j];
-        const cplx<R> c = {cwk[j].x, cwk[j].y};
-        for (int r = 0; r < w; ++r) {
-            int cell = l0 + r;
-            if (cell >= nf) cell -= nf;
-            const int cb = (cell & (N2 - 1)) - c0;
-            if (cb >= 0 && cb < B) {
-                const int row = cell >> log_N2;
-                const R phi = es_spread<R>(((R)r + del) * two_over_w, beta);
-                atomicAdd(&tile[cb * LD + row].x, c.x * phi);
-                atomicAdd(&tile[cb * LD + row].y, c.y * phi);
+        return j;
+    };
+    phase_stamp(a, 5);
+    // Owner-computes spreading, chunk by chunk: each chunk's points are
+    // counting-sorted by the tile row they reach (integer LDS atomics), then
+    // every thread sums, in registers, the taps that land on its TASKS cells.
+    // Float atomics on LDS are avoided: they are many times slower than the
+    // sort plus a plain store per cell.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cb = lane % B, rsub = lane / B;
+    cplx<R> acc[TASKS];
+#pragma unroll
+    for (int u = 0; u < TASKS; ++u) acc[u] = {(R)0, (R)0};
+    int pl0 = 0;
+    R pdel = (R)0;
+    cplx<R> pc = {(R)0, (R)0};
+    // FP32 loads a chunk's points while the previous chunk is summed; FP64
+    // loads them at the chunk's start (the extra registers would halve the
+    // workgroups per compute unit)
+    constexpr bool PREFETCH = sizeof(R) == 4;
+    auto fetch = [&](int f, int& l0, R& del, cplx<R>& c) {
+        if (threadIdx.x < CAP && f < total) {
+            const int j = locate(f);
+            l0 = l0s[j];
+            del = dels[j];
+            c = {cwk[j].x, cwk[j].y};
+        }
+    };
+    if (PREFETCH) fetch(threadIdx.x, pl0, pdel, pc);
+    __syncthreads();   // rows[] is zero before the first count
+    const int nchunks = (total + CAP - 1) / CAP;
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int f = ch * CAP + threadIdx.x;
+        int ml0 = pl0;
+        R mdel = pdel;
+        cplx<R> mc = pc;
+        if (!PREFETCH) fetch(f, ml0, mdel, mc);
+        int s = 0, rowt = 0, slot = -1;
+        if (threadIdx.x < CAP && f < total) {
+            s = (ml0 & (N2 - 1)) - c0;
+            if (s > N2 / 2) s -= N2;
+            else if (s <= -N2 / 2) s += N2;
+            if (s < B && s > -w) {
+                int base = ml0 - s;   // cell of column c0 in the row the taps reach
+                if (base < 0) base += nf;
+                else if (base >= nf) base -= nf;
+                rowt = base >> log_N2;
+                slot = atomicAdd(&rows[rowt], 1);
             }
         }
+        __syncthreads();
+        scan_counts<N1>(rows, wtot);
+        if (slot >= 0) {
+            const int at = rows[rowt] + slot;
+            if (at < CAP) list[at] = {s, mdel, mc};
+        }
+        __syncthreads();
+        // the next chunk's point is loaded while this one is summed
+        if (PREFETCH && ch + 1 < nchunks) fetch(f + CAP, pl0, pdel, pc);
+#pragma unroll
+        for (int u = 0; u < TASKS; ++u) {
+            const int row = (u * (NT1 / 64) + wv) * G + rsub;
+            const int beg = rows[row];
+            const int end = min(rows[row + 1], CAP);
+            for (int i = beg; i < end; ++i) {
+                const SpreadRec<R> rc = list[i];
+                const int r = cb - rc.s;
+                if ((unsigned)r < (unsigned)w) {
+                    const R phi = es_spread<R>(((R)r + rc.del) * two_over_w, beta);
+                    acc[u].x += rc.c.x * phi;
+                    acc[u].y += rc.c.y * phi;
+                }
+            }
+        }
+        __syncthreads();
+        if (ch + 1 < nchunks) {
+            for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
+            __syncthreads();
+        }
     }
+#pragma unroll
+    for (int u = 0; u < TASKS; ++u) {
+        const int row = (u * (NT1 / 64) + wv) * G + rsub;
+        tile[cb * LD + row] = acc[u];
+    }
+    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     __syncthreads();
     if (d.E && blk == 0 && threadIdx.x < 64) {
         // norms[k] = the binning workgroups' partial sums of w_k^2, in order

@@ -45,6 +45,15 @@ def _submit(q, s):
     return q.submit(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I)
 
 
+WAIT_US = 60_000_000   # a request not done within a minute fails the test
+
+
+def _wait(q, ticket):
+    r = q.wait(ticket, timeout_us=WAIT_US)
+    assert r is not None, f"ticket {ticket} not done within {WAIT_US / 1e6:.0f} s"
+    return r
+
+
 def _check(m2n, ctx, s, r, prec):
     w, lam, P, E = _alone(m2n, ctx, s, prec)
     assert r["status"] == m2n.M2N_OK
@@ -67,7 +76,7 @@ def test_queue_same_alone_and_in_mix(m2n, ctx):
     th.start()
     sub(range(1, 24, 2))
     th.join()
-    res = {i: q.wait(tk) for i, tk in tickets.items()}
+    res = {i: _wait(q, tk) for i, tk in tickets.items()}
     sizes = sorted(r["batch_size"] for r in res.values())
     _say(f"case 24 requests, batch sizes seen {sizes[0]}..{sizes[-1]}")
     assert sizes[-1] > 1
@@ -86,7 +95,7 @@ def test_queue_failing_request_is_isolated(m2n, ctx):
     out = []
     for t in tk:
         try:
-            out.append(q.wait(t))
+            out.append(_wait(q, t))
         except m2n.M2NError as e:
             out.append(e.code)
     assert out[2] == m2n.M2N_ERR_ARG
@@ -99,7 +108,7 @@ def test_queue_budget_serialises(m2n, ctx):
     series = [W.batched_series(s) for s in (40, 41, 42)]
     q = m2n.Queue(ctx, hbm_budget_bytes=1, slots=2, prec=m2n.M2N_FP32)
     tk = [_submit(q, s) for s in series]
-    res = [q.wait(t) for t in tk]
+    res = [_wait(q, t) for t in tk]
     assert all(r["batch_size"] == 1 for r in res)
     for s, r in zip(series, res):
         _check(m2n, ctx, s, r, m2n.M2N_FP32)
