@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served-form Poisson arrival trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--gep-stress-n", type=int, default=16384,
+                    help="N of the dense jittered GEP stress solve (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (byte-counter calibration)")
     return ap.parse_args()
@@ -177,6 +179,76 @@ def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
             "per_series_ms": round(ts * 1e3, 3), "per_series_psds_per_s": round(nser / ts, 1),
             "speedup_vs_per_series": round(ts / tb, 2),
             "batch_vs_per_series_P_rel": dP}
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def gep_stress(m2n, torch, workloads, ctx, n, reps=3):
+    """Dense GEP on a jittered grid t_n = n + z_n, z ~ N(0, 0.1^2): R(B) is a
+    dense, well-conditioned matrix, factored by the tiled FP64 Cholesky whose
+    trailing updates run on MFMA.  Reports the solve time, the Cholesky's
+    flop rate against the FP64 matrix peak and, from dense FP64 products on
+    the device, the tapers' R(B)-orthonormality and GEP residual."""
+    s = workloads.jitter_stress(n=n)
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(dev)
+    K = s.K
+    w = torch.empty((K, s.N), dtype=torch.float64, device=dev)
+    lam = torch.empty((K,), dtype=torch.float64, device=dev)
+    m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))       # workspace, tables
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ctx.profile_reset()
+    ctx.profile(True)
+    m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    ks = ctx.profile_read()
+    kern = {k: round(v[0], 3) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][0])[:8]}
+    # algorithmic flops: Cholesky N^3/3; its trailing updates (64-wide
+    # panels): sum over panels of 64 M (M + 1), M = rows below the panel
+    Np = (s.N + 63) // 64 * 64
+    chol = s.N ** 3 / 3.0
+    syrk = sum(64.0 * M * (M + 1) for M in range(Np - 64, 0, -64))
+    syrk_ms = ks.get("k_syrk", (0.0, 1))[0]
+    # checks with dense FP64 products (verification only, not the solve)
+    tt = t.double()
+    tau = tt[:, None] - tt[None, :]
+
+    def sinc_band(f):
+        m = torch.sin(2 * math.pi * f * tau) / (math.pi * tau)
+        m.fill_diagonal_(2 * f)
+        return m
+
+    RB = sinc_band(s.fmax)
+    wT = w.T.contiguous()
+    RBw = RB @ wT
+    del RB
+    orth = float((w @ RBw / (2 * s.fw) - torch.eye(K, device=dev, dtype=torch.float64)).abs().max())
+    RA = sinc_band(s.fw)
+    RAw = RA @ wT
+    del RA, tau
+    res = float(((RAw - RBw * lam[None, :]).norm(dim=0) / (RBw * lam[None, :]).norm(dim=0)).max())
+    del RAw, RBw
+    torch.cuda.empty_cache()
+    return {"workload": f"jitter_{s.N}", "N": s.N, "K": K, "fw": s.fw, "fmax": s.fmax,
+            "ms_per_solve": round(ms, 3), "reps": reps,
+            "cholesky_flops": chol, "cholesky_tflops_per_s": round(chol / (ms * 1e-3) / 1e12, 2),
+            "frac_fp64_peak": round(chol / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "k_syrk": {"ms": round(syrk_ms, 3), "flops": syrk,
+                       "tflops_per_s": round(syrk / (syrk_ms * 1e-3) / 1e12, 2) if syrk_ms else None,
+                       "peak": FP64_PEAK_TFLOPS,
+                       "frac": round(syrk / (syrk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4) if syrk_ms else None},
+            "kernels_ms": kern, "lambda": [round(float(v), 12) for v in lam.cpu()],
+            "RB_orthonormality": orth, "gep_residual": res}
 
 
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
@@ -339,6 +411,13 @@ def main():
         print(f"bench: served p50 {served['latency_ms']['p50']} ms p99 {served['latency_ms']['p99']} ms",
               file=sys.stderr, flush=True)
 
+    stress = None
+    if a.gep_stress_n > 0:
+        print("bench: GEP stress", file=sys.stderr, flush=True)
+        stress = gep_stress(m2n, torch, workloads, ctx, a.gep_stress_n)
+        print(f"bench: GEP stress {stress['ms_per_solve']} ms, k_syrk {stress['k_syrk']['tflops_per_s']} TF/s",
+              file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -368,6 +447,7 @@ def main():
         "parity": parity,
         "batched_form": batched,
         "served_form": served,
+        "gep_stress": stress,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

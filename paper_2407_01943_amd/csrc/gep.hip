@@ -1384,12 +1384,16 @@ __global__ __launch_bounds__(GNT) void k_trsm_panel(double* __restrict__ A, int6
     if (threadIdx.x == 0) nz[ib] = any;
 }
 
-// trailing update A_ij -= L_ik L_jk^T over lower tiles kb < jb <= ib,
-// skipped when either panel tile is exactly zero
+// trailing update A_ij -= L_ik L_jk^T over the lower tiles kb < jb <= ib on
+// FP64 MFMA (16x16x4), skipped when either panel tile is exactly zero.  A
+// wavefront computes a 32 x 32 quarter of the 64 x 64 tile as transposed
+// blocks,  D[a][b] = sum_k L[rj + a][k] L[ri + b][k] = C[ri + b][rj + a],
+// so that accumulator element v of lane l is C[ri + l%16][rj + l/16 + 4v]:
+// the operand loads and the C reads and writes are all 16 consecutive
+// doubles of a column.  Operands come straight from global memory (the
+// panel stays in L2); the subtraction is folded in by negating the A operand.
 __global__ __launch_bounds__(GNT) void k_syrk(double* __restrict__ A, int64_t Np, int kb, int nblk,
                                               const int* __restrict__ nz) {
-    __shared__ double Li[TB][TB + 1];
-    __shared__ double Lj[TB][TB + 1];
     // map blockIdx.x to (ib, jb) with kb < jb <= ib < nblk
     const int m = nblk - kb - 1;
     int idx = blockIdx.x, jj = 0;
@@ -1399,35 +1403,41 @@ __global__ __launch_bounds__(GNT) void k_syrk(double* __restrict__ A, int64_t Np
     }
     const int jb = kb + 1 + jj, ib = jb + idx;
     if (!nz[ib] || !nz[jb]) return;
-    const int64_t o = (int64_t)kb * TB, ri = (int64_t)ib * TB, rj = (int64_t)jb * TB;
-    for (int e = threadIdx.x; e < TB * TB; e += GNT) {
-        const int i = e % TB, k = e / TB;
-        Li[i][k] = A[(ri + i) + (o + k) * Np];
-        Lj[i][k] = A[(rj + i) + (o + k) * Np];
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int qi = wv & 1, qj = wv >> 1;
+    if (ib == jb && qi < qj) return;   // the quarter above a diagonal tile's diagonal
+    const int li = l & 15, lk = l >> 4;
+    const int64_t o = (int64_t)kb * TB;
+    const int64_t ri = (int64_t)ib * TB + 32 * qi, rj = (int64_t)jb * TB + 32 * qj;
+    d4 acc[2][2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[bj][bi][v] = A[(ri + 16 * bi + li) + (rj + 16 * bj + lk + 4 * v) * Np];
+    const double* __restrict__ pa = A + (rj + li) + (o + lk) * Np;
+    const double* __restrict__ pb = A + (ri + li) + (o + lk) * Np;
+#pragma unroll 4
+    for (int k0 = 0; k0 < TB; k0 += 4) {
+        const int64_t off = (int64_t)k0 * Np;
+        const double a0 = -pa[off], a1 = -pa[off + 16];
+        const double b0 = pb[off], b1 = pb[off + 16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    __syncthreads();
-    // thread owns a 4 x 4 sub-tile
-    const int tr = (threadIdx.x % 16) * 4, tc = (threadIdx.x / 16) * 4;
-    double acc[4][4] = {};
-    for (int k = 0; k < TB; ++k) {
-        double a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = Li[tr + u][k];
-            b[u] = Lj[tc + u][k];
-        }
+    for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gi = ri + tr + u, gj = rj + tc + v;
-            if (ib != jb || gi >= gj) A[gi + gj * Np] -= acc[u][v];
-        }
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = ri + 16 * bi + li, gj = rj + 16 * bj + lk + 4 * v;
+                if (ib != jb || gi >= gj) A[gi + gj * Np] = acc[bj][bi][v];
+            }
 }
 
 // triangular solve with one TB x TB diagonal block for p columns:
