@@ -1312,76 +1312,88 @@ __global__ void k_gen_sinc(const double* __restrict__ t, int64_t N, int64_t Np, 
     R[i + j * Np] = v;
 }
 
-// Cholesky of the TB x TB diagonal block kb (in place, lower; upper zeroed)
-__global__ __launch_bounds__(GNT) void k_potrf(double* __restrict__ A, int64_t Np, int kb, int64_t N,
-                                               int* __restrict__ status) {
-    __shared__ double T[TB][TB + 1];
+// Cholesky of the TB x TB diagonal block kb in place (lower; upper zeroed).
+// Four wavefronts; lane i of wavefront q holds columns 16q .. 16q + 15 of row
+// i in registers.  At column j the owning wavefront takes the pivot (lane j's
+// element), scales the column and stages it in LDS; after one barrier every
+// lane updates its columns k > j from its own element l_ij and broadcast
+// reads of l_kj.  A pivot <= 0 records the first failing row in status and
+// the factorisation continues with 1 so that every launch completes.
+__global__ __launch_bounds__(TB * 4) void k_potrf(double* __restrict__ A, int64_t Np, int kb, int64_t N,
+                                                  int* __restrict__ status) {
+    constexpr int CW = TB / 4;   // columns per wavefront
+    __shared__ double col[2][TB];
+    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int64_t o = (int64_t)kb * TB;
-    for (int e = threadIdx.x; e < TB * TB; e += GNT) {
-        const int i = e % TB, j = e / TB;
-        T[i][j] = A[(o + i) + (o + j) * Np];
-    }
-    __syncthreads();
+    double r[CW];
+#pragma unroll
+    for (int u = 0; u < CW; ++u) r[u] = A[(o + i) + (o + CW * q + u) * Np];
     for (int j = 0; j < TB; ++j) {
-        if (threadIdx.x == 0) {
-            const double d = T[j][j];
+        const int buf = j & 1;
+        if (q == j / CW) {
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < CW; ++u) v = (u == j % CW) ? r[u] : v;
+            double d = rdlane(v, j);
             if (!(d > 0.0)) {
-                if (o + j < N) atomicCAS(status, 0, -(int)(o + j + 1));
-                T[j][j] = 1.0;   // keep going; the status reports the failure
-            } else {
-                T[j][j] = sqrt(d);
+                if (i == 0 && o + j < N) atomicCAS(status, 0, -(int)(o + j + 1));
+                d = 1.0;
             }
+            const double ljj = sqrt(d);
+            v = i > j ? v / ljj : (i == j ? ljj : 0.0);
+#pragma unroll
+            for (int u = 0; u < CW; ++u) r[u] = (u == j % CW) ? v : r[u];
+            col[buf][i] = v;
         }
         __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < TB; i += GNT) T[i][j] /= T[j][j];
-        __syncthreads();
-        const int rem = TB - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += GNT) {
-            const int i = j + 1 + e % rem, k = j + 1 + e / rem;
-            if (i >= k) T[i][k] -= T[i][j] * T[k][j];
-        }
-        __syncthreads();
+        const double lij = col[buf][i];
+#pragma unroll
+        for (int u = 0; u < CW; ++u)
+            if (CW * q + u > j) r[u] -= lij * col[buf][CW * q + u];
     }
-    for (int e = threadIdx.x; e < TB * TB; e += GNT) {
-        const int i = e % TB, j = e / TB;
-        A[(o + i) + (o + j) * Np] = (i >= j) ? T[i][j] : 0.0;
+#pragma unroll
+    for (int u = 0; u < CW; ++u) {
+        const int j = CW * q + u;
+        A[(o + i) + (o + j) * Np] = i >= j ? r[u] : 0.0;
     }
 }
 
-// panel: A_ik <- A_ik L_kk^{-T} for row blocks i > kb; nz[i] = tile not all zero
-__global__ __launch_bounds__(GNT) void k_trsm_panel(double* __restrict__ A, int64_t Np, int kb,
+// panel: A_ik <- A_ik L_kk^{-T} for the row blocks ib > kb, one wavefront per
+// row block (lane = row, the row in registers), column by column:
+//   x_c = a_c / L_cc,  then a_j -= x_c L_jc for j > c,
+// with L_jc read as LDS broadcasts; a column's FMAs are independent of each
+// other.  nz[ib] = the block is not all zero.
+__global__ __launch_bounds__(GNT) void k_trsm_panel(double* __restrict__ A, int64_t Np, int kb, int nblk,
                                                     int* __restrict__ nz) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double X[TB][TB + 1];
-    __shared__ int any;
-    const int ib = kb + 1 + blockIdx.x;
-    const int64_t o = (int64_t)kb * TB, r = (int64_t)ib * TB;
-    if (threadIdx.x == 0) any = 0;
+    __shared__ double L[TB * TB];   // L_kk column-major: L[j + c * TB] = L_kk[j][c]
+    const int64_t o = (int64_t)kb * TB;
     for (int e = threadIdx.x; e < TB * TB; e += GNT) {
-        const int i = e % TB, j = e / TB;
-        L[i][j] = A[(o + i) + (o + j) * Np];
-        X[i][j] = A[(r + i) + (o + j) * Np];
+        const int j = e % TB, c = e / TB;
+        L[e] = A[(o + j) + (o + c) * Np];
     }
     __syncthreads();
-    // row i of X solves x L^T = a: x_c = (a_c - sum_{j<c} x_j L_cj) / L_cc
-    if (threadIdx.x < TB) {
-        const int i = threadIdx.x;
-        int mine = 0;
-        for (int c = 0; c < TB; ++c) {
-            double s = X[i][c];
-            for (int j = 0; j < c; ++j) s -= X[i][j] * L[c][j];
-            s /= L[c][c];
-            X[i][c] = s;
-            mine |= (s != 0.0);
-        }
-        if (mine) atomicOr(&any, 1);
+    const int lane = threadIdx.x & 63;
+    const int ib = kb + 1 + (int)blockIdx.x * (GNT / 64) + (threadIdx.x >> 6);
+    if (ib >= nblk) return;
+    const int64_t r = (int64_t)ib * TB + lane;
+    double x[TB];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) x[c] = A[r + (o + c) * Np];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+        __builtin_amdgcn_sched_barrier(0);   // one column's reads in flight at a time
+        x[c] /= L[c + c * TB];
+#pragma unroll
+        for (int j = c + 1; j < TB; ++j) x[j] -= x[c] * L[j + c * TB];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < TB * TB; e += GNT) {
-        const int i = e % TB, j = e / TB;
-        A[(r + i) + (o + j) * Np] = X[i][j];
+    int mine = 0;
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+        A[r + (o + c) * Np] = x[c];
+        mine |= (x[c] != 0.0);
     }
-    if (threadIdx.x == 0) nz[ib] = any;
+    const int any = __any(mine);
+    if (lane == 0) nz[ib] = any ? 1 : 0;
 }
 
 // trailing update A_ij -= L_ik L_jk^T over the lower tiles kb < jb <= ib on
@@ -1442,34 +1454,37 @@ __global__ __launch_bounds__(GNT) void k_syrk(double* __restrict__ A, int64_t Np
 
 // triangular solve with one TB x TB diagonal block for p columns:
 //   lower (trans = 0):  L_kk X = B_k;   upper (trans = 1): L_kk^T X = B_k
+// one wavefront per column, lane = row: once x_i is known (a broadcast from
+// lane i) the lanes still to be solved subtract its contribution.
 __global__ __launch_bounds__(GNT) void k_trsv_diag(const double* __restrict__ A, int64_t Np, int kb,
                                                    int trans, double* __restrict__ Bm, int p) {
-    __shared__ double L[TB][TB + 1];
+    constexpr int LDL = TB + 1;
+    __shared__ double L[TB * LDL];   // L[i + j * LDL] = L_kk[i][j]
     const int64_t o = (int64_t)kb * TB;
     for (int e = threadIdx.x; e < TB * TB; e += GNT) {
         const int i = e % TB, j = e / TB;
-        L[i][j] = A[(o + i) + (o + j) * Np];
+        L[i + j * LDL] = A[(o + i) + (o + j) * Np];
     }
     __syncthreads();
-    const int col = threadIdx.x;
-    if (col >= p) return;
-    double x[TB];
-    double* bcol = Bm + (int64_t)col * Np + o;
-    for (int i = 0; i < TB; ++i) x[i] = bcol[i];
+    const int lane = threadIdx.x & 63;
+    const int c = (int)blockIdx.x * (GNT / 64) + (threadIdx.x >> 6);
+    if (c >= p) return;
+    double* b = Bm + (int64_t)c * Np + o;
+    double x = b[lane];
     if (!trans) {
         for (int i = 0; i < TB; ++i) {
-            double s = x[i];
-            for (int j = 0; j < i; ++j) s -= L[i][j] * x[j];
-            x[i] = s / L[i][i];
+            const double xi = rdlane(x, i) / L[i + i * LDL];
+            if (lane == i) x = xi;
+            else if (lane > i) x -= L[lane + i * LDL] * xi;
         }
     } else {
         for (int i = TB - 1; i >= 0; --i) {
-            double s = x[i];
-            for (int j = i + 1; j < TB; ++j) s -= L[j][i] * x[j];
-            x[i] = s / L[i][i];
+            const double xi = rdlane(x, i) / L[i + i * LDL];
+            if (lane == i) x = xi;
+            else if (lane < i) x -= L[i + lane * LDL] * xi;
         }
     }
-    for (int i = 0; i < TB; ++i) bcol[i] = x[i];
+    b[lane] = x;
 }
 
 // block update after a diagonal solve at kb, for every other row block ib:
@@ -1772,7 +1787,8 @@ struct Solver {
             const int kb = trans ? nblk - 1 - s : s;
             {
                 M2N_PROF(ctx, st, "k_trsv_diag");
-                hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(GNT), 0, st, RB, Np, kb, trans, Bm, p);
+                hipLaunchKernelGGL(k_trsv_diag, dim3((unsigned)((p + 3) / 4)), dim3(GNT), 0, st, RB, Np, kb,
+                                   trans, Bm, p);
             }
             const int nupd = trans ? kb : nblk - kb - 1;
             if (nupd > 0)
@@ -2183,13 +2199,14 @@ int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
         for (int kb = 0; kb < S.nblk; ++kb) {
             {
                 M2N_PROF(ctx, st, "k_potrf");
-                hipLaunchKernelGGL(k_potrf, dim3(1), dim3(GNT), 0, st, S.RB, Np, kb, N, (int*)vst);
+                hipLaunchKernelGGL(k_potrf, dim3(1), dim3(4 * TB), 0, st, S.RB, Np, kb, N, (int*)vst);
             }
             const int rem = S.nblk - kb - 1;
             if (rem > 0) {
                 {
                     M2N_PROF(ctx, st, "k_trsm_panel");
-                    hipLaunchKernelGGL(k_trsm_panel, dim3(rem), dim3(GNT), 0, st, S.RB, Np, kb, S.nz);
+                    hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 3) / 4)), dim3(GNT), 0, st, S.RB,
+                                       Np, kb, S.nblk, S.nz);
                 }
                 const int ntiles = rem * (rem + 1) / 2;
                 M2N_PROF(ctx, st, "k_syrk");
