@@ -27,6 +27,102 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the sources a NuFFT kernel is built from: measured HBM traffic is reported
+# only while their hash matches the one recorded with the counters
+NUFFT_SOURCES = ["paper_2407_01943_amd/csrc/nufft.hip", "paper_2407_01943_amd/csrc/fft_lds.hpp",
+                 "paper_2407_01943_amd/csrc/m2n_common.hpp"]
+TRAFFIC_FILE = "profiles/hbm_traffic_gapped_20k.md"
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for q in paths:
+        with open(os.path.join(ROOT, q), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("<!-- traffic "):
+                r = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                if r.get("kernel") == kernel:
+                    rec = r
+    if rec is None or rec.get("sources_sha256") != sources_sha256(NUFFT_SOURCES):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def _short(name):
+    import re
+    name = name.replace("m2n::(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name)
+
+
+def profile_summary(a):
+    """Markdown summaries of rocprofv3 databases: the kernel trace, and the
+    HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE runs calibrated by
+    the 256 MiB device copy that --calib-copy performs."""
+    import collections
+    import sqlite3
+    trace_db, fetch_db, write_db = a.profile_summary
+    out = []
+    con = sqlite3.connect(trace_db)
+    durs = collections.defaultdict(list)
+    for name, du in con.execute("select name, duration from kernels"):
+        durs[_short(name)].append(du)
+    out.append(f"# {a.summary_title}\n")
+    out.append("Commands (from the repository root on the MI355X; R = repository root):\n")
+    out.append("```\n" + a.summary_cmd.replace("\\n", "\n") + "\n```\n")
+    out.append("## Kernel trace (rocprofv3 --kernel-trace --stats)\n")
+    out.append("| kernel | dispatches | avg us | total us |\n|---|---:|---:|---:|")
+    for k, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {k} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | {sum(v) / 1e3:.1f} |")
+
+    def load(db):
+        c = sqlite3.connect(db)
+        d = collections.defaultdict(list)
+        for name, val in c.execute("select name, counter_value from pmc_events"):
+            d[_short(name)].append(val)
+        return d
+
+    F, W = load(fetch_db), load(write_db)
+    calib = 256 * 1024.0   # KiB the copy reads and writes
+    cf = calib / max(F["__amd_rocclr_copyBuffer"])
+    cw = calib / max(W["__amd_rocclr_copyBuffer"])
+    out.append("\n## HBM traffic (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE)\n")
+    out.append(f"Calibration by a 256 MiB device-to-device copy: FETCH_SIZE x {cf:.4f}, "
+               f"WRITE_SIZE x {cw:.4f} (counter KiB per dispatch to bytes moved).\n")
+    out.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated MB per dispatch |")
+    out.append("|---|---:|---:|---:|---:|")
+    recs = []
+    sha = sources_sha256(NUFFT_SOURCES)
+    for k in sorted(F, key=lambda k: -sum(F[k]) / len(F[k])):
+        if k.startswith("__amd"):
+            continue
+        f = sum(F[k]) / len(F[k])
+        w = sum(W.get(k, [0.0])) / max(1, len(W.get(k, [0.0])))
+        byts = (f * cf + w * cw) * 1024.0
+        out.append(f"| {k} | {len(F[k])} | {f:.1f} | {w:.1f} | {byts / 1e6:.3f} |")
+        if k.startswith("k_pass1") or k.startswith("k_pass2"):
+            recs.append({"kernel": k.split("<")[0], "instance": k, "bytes_per_launch": round(byts),
+                         "fetch_kib": round(f, 1), "write_kib": round(w, 1),
+                         "fetch_factor": round(cf, 4), "write_factor": round(cw, 4),
+                         "sources_sha256": sha})
+    out.append("")
+    for r in recs:
+        out.append("<!-- traffic " + json.dumps(r) + " -->")
+    with open(a.summary_out, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(f"wrote {a.summary_out}")
 
 
 def parse():
@@ -49,6 +145,11 @@ def parse():
                     help="N of the dense jittered GEP stress solve (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (byte-counter calibration)")
+    ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write a markdown summary of rocprofv3 results instead of benchmarking")
+    ap.add_argument("--summary-out", default=TRAFFIC_FILE)
+    ap.add_argument("--summary-title", default="Kernel trace and HBM traffic")
+    ap.add_argument("--summary-cmd", default="")
     return ap.parse_args()
 
 
@@ -267,6 +368,9 @@ def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
 
 def main():
     a = parse()
+    if a.profile_summary:
+        profile_summary(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is described, not built)"}))
@@ -358,16 +462,36 @@ def main():
         nf *= 2
     plan = {"nf": nf}
     pb = 4 if prec == m2n.M2N_FP32 else 8
-    # the roofline is reported for the dominant NuFFT kernel (HBM-bound)
-    roof_name = max(("k_pass1", "k_pass2"), key=lambda k: per_step.get(k, 0.0))
-    ms_k, cnt_k = kstats[roof_name]
-    avg_ms = ms_k / cnt_k
-    byts = algorithmic_bytes(roof_name, s, N, K, I, plan, pb)
-    achieved = byts / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": roof_name, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "algorithmic_bytes": byts, "avg_ms": round(avg_ms, 5),
-                "launches": cnt_k}
+    # roofline of the dominant kernel.  The lattice GEP's eigen-solver
+    # (k_sym_topk: one wavefront on the Q x Q quadrature Gram matrix) is
+    # FP64 ALU work priced against the chip's FP64 vector peak, with the
+    # algorithmic flops of Householder tridiagonalisation (4/3 Q^3) and the
+    # back-transformation of K vectors (4 Q^2 K); HBM-bound kernels are
+    # priced by their algorithmic bytes.
+    def roof(name):
+        ms_k, cnt_k = kstats[name]
+        avg = ms_k / cnt_k
+        if name.startswith("k_sym_topk"):
+            span = float(s.t[-1] - s.t[0])
+            Q = math.ceil(0.7 * 2 * math.pi * s.fw * span) + 14
+            Q = max(Q, K + 2)
+            Q += Q & 1
+            fl = 4.0 / 3.0 * Q ** 3 + 4.0 * Q * Q * K
+            ach = fl / (avg * 1e-3) / 1e12
+            return {"kernel": name, "bound": "alu", "achieved": round(ach, 6),
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP64_PEAK_TFLOPS, 8), "traffic": None,
+                    "algorithmic_flops": fl, "Q": Q, "avg_ms": round(avg, 5), "launches": cnt_k,
+                    "note": "one wavefront (1 of 1024 SIMDs): latency of the serial eigen-solve"}
+        byts = algorithmic_bytes(name, s, N, K, I, plan, pb)
+        ach = byts / (avg * 1e-3) / 1e9
+        tr = measured_traffic(name)
+        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
+                "algorithmic_bytes": byts, "avg_ms": round(avg, 5), "launches": cnt_k}
+
+    roofline = roof(dom) if (dom.startswith("k_sym_topk") or dom in ("k_pass1", "k_pass2")) else None
+    roofline_nufft = [roof(k) for k in ("k_pass1", "k_pass2") if k in kstats]
 
     # ---- parity gate and CPU baseline (oracle, bounded sample)
     cpu = None
@@ -443,6 +567,7 @@ def main():
         "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "dominant_kernel": dom,
         "roofline": roofline,
+        "roofline_nufft": roofline_nufft,
         "cpu_baseline": cpu,
         "parity": parity,
         "batched_form": batched,

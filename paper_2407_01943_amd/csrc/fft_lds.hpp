@@ -56,7 +56,7 @@ __device__ __forceinline__ void dft8(cplx<R>* u) {
     u[7] = csub(e[3], o3);
 }
 
-template <typename R, int N, int NB, int NT, int LD, int RAD>
+template <typename R, int N, int NB, int NT, int LD, int RAD, bool FIRST = false>
 __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw,
                                           int tws, int p) {
     constexpr int Q = N / RAD;              // butterflies per transform
@@ -74,7 +74,7 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
 #pragma unroll
             for (int t = 0; t < RAD; ++t) {
                 cplx<R> val = buf[b * LD + j + t * Q];
-                if (t > 0) val = cmul(val, tw[t * tstep]);
+                if (!FIRST && t > 0) val = cmul(val, tw[t * tstep]);   // first stage: k = 0
                 v[it][t] = val;
             }
         }
@@ -102,14 +102,21 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 // NB forward FFTs of length N (power of two, >= 2) in LDS: radix-8 stages
 // while three or more factors of two remain, then one radix-4 or radix-2
 // stage.  Caller must have synchronised after writing buf; returns
-// synchronised.
+// synchronised.  With first_done (N >= 8) the caller has already stored the
+// first radix-8 stage's output: when only x[0 .. N/8) can be non-zero, that
+// output is x[j] repeated at positions 8 j .. 8 j + 7.
 template <typename R, int N, int NB, int NT, int LD>
-__device__ __forceinline__ void fft_lds(cplx<R>* buf, const cplx<R>* __restrict__ tw, int tws) {
+__device__ __forceinline__ void fft_lds(cplx<R>* buf, const cplx<R>* __restrict__ tw, int tws,
+                                        bool first_done = false) {
     constexpr int LOG = ilog2c(N);
     constexpr int N8 = LOG / 3, REM = LOG % 3;
     int p = 1;
+    if constexpr (N8 > 0) {
+        if (!first_done) fft_stage<R, N, NB, NT, LD, 8, true>(buf, tw, tws, 1);
+        p = 8;
+    }
 #pragma unroll 1
-    for (int s = 0; s < N8; ++s) {
+    for (int s = 1; s < N8; ++s) {
         fft_stage<R, N, NB, NT, LD, 8>(buf, tw, tws, p);
         p *= 8;
     }

@@ -476,6 +476,7 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
     __shared__ cplx<R> tile[B * LD];
     __shared__ int rows[N1 + 1];
     __shared__ int wtot[NT1 / 64];
+    __shared__ int s_maxrow;   // largest tile row any point reaches
     // the chunk's row-sorted points during the spread, the twiddles after it
     __shared__ __attribute__((aligned(16))) unsigned char region[REGION];
     SpreadRec<R>* list = (SpreadRec<R>*)region;
@@ -486,6 +487,7 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
     wg_stamp(a, 1024, 0);
     phase_stamp(a, 0);
     for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
+    if (threadIdx.x == 0) s_maxrow = -1;
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
     const auto* dels = gp((const R*)d.dels);
@@ -569,6 +571,11 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
                 slot = atomicAdd(&rows[rowt], 1);
             }
         }
+        {
+            int mr = slot >= 0 ? rowt : -1;   // one LDS atomic per wavefront
+            for (int o = 32; o > 0; o >>= 1) mr = max(mr, __shfl_xor(mr, o, 64));
+            if (lane == 0 && mr >= 0) atomicMax(&s_maxrow, mr);
+        }
         __syncthreads();
         scan_counts<N1>(rows, wtot);
         if (slot >= 0) {
@@ -599,10 +606,18 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
             __syncthreads();
         }
     }
+    // when every point lies in the first N1 / 8 rows, the first radix-8 FFT
+    // stage only replicates each row; store its output directly
+    const bool pruned = N1 >= 8 && s_maxrow < N1 / 8;
 #pragma unroll
     for (int u = 0; u < TASKS; ++u) {
         const int row = (u * (NT1 / 64) + wv) * G + rsub;
-        tile[cb * LD + row] = acc[u];
+        if (!pruned) {
+            tile[cb * LD + row] = acc[u];
+        } else if (row < N1 / 8) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) tile[cb * LD + 8 * row + q] = acc[u];
+        }
     }
     for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     __syncthreads();
@@ -615,7 +630,7 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
         if (threadIdx.x == 0) d.norms[k] = sq;
     }
     phase_stamp(a, 2);
-    fft_lds<R, N1, B, NT1, LD>(tile, tw, 1);
+    fft_lds<R, N1, B, NT1, LD>(tile, tw, 1, pruned);
     phase_stamp(a, 3);
     // four-step twiddle exp(-2 pi i (c0 + cb) m1 / nf), then G[k][m1][l2]
     const R two_nf = (R)2 / (R)nf;
