@@ -320,15 +320,14 @@ __device__ __forceinline__ void wsum8(double (&v)[8]) {
 }
 
 // LDS of the small eigen-solver.  Row starts of Vh are 16-byte aligned so
-// that a reflector is read as double2 pairs.
+// that a Lanczos vector is read as double2 pairs.
 template <int LDA>
 struct EigShared {
     double A[MAXP][LDA];         // input; then Sturm pairs, then LU rows
-    double Vh[MAXP][MAXP + 2];   // Householder vector of step r in row r
+    double Vh[MAXP][MAXP + 2];   // Lanczos vector q_r in row r
     double X[MAXP][LDA];         // eigenvectors, X[k][i]
     double2 de[MAXP];            // (d_i, e_i) of the tridiagonal, e_{n-1} = 0
     double re[MAXP];             // 1 / e_i (0 where e_i = 0)
-    double Bh[MAXP];
     double lam[MAXP];
     double tmp[2 * MAXP];
     double Gq[16 * MAXP];        // Gram and projection coefficients of a batch
@@ -486,118 +485,132 @@ __device__ __forceinline__ double start_entry(int i, int k) {
 // On entry S.A holds the matrix (row stride LDA); on exit S.lam[0..K)
 // holds its K largest eigenvalues in descending order and S.X[k][0..n) the
 // unit eigenvectors.
-//  1. Householder reduction to tridiagonal form.  Lane i keeps row i in
-//     registers; the trailing block shifts down one register per step so
-//     that its first column always sits in a[0] and every register index is
-//     a compile-time constant.
-//  2. Multisection on a division-free Sturm count: g lanes (a power of two)
-//     bracket each wanted eigenvalue with two samples each per round and
-//     combine the brackets by lane shuffles.
+//  1. Lanczos with full re-orthogonalisation (two classical Gram-Schmidt
+//     passes against every earlier vector): A Q_m = Q_m T_m + r e_m^T.  Lane
+//     i keeps row i of A in registers; q_j goes to S.Vh[j].  The process
+//     stops once |r| <= 1e-13 |A|_F with m >= K (the rounding noise of a
+//     Gram matrix summed over 1e4..1e5 rows is about 1e-14 |A|), so T_m's
+//     eigenvalues are eigenvalues of A to that accuracy; the spectra met
+//     here (Gram matrices of band-limited bases) fall below it after about
+//     2 f_w span + 10 values, so m is well below n (17 of 32 at 2 f_w span = 8).  If the Krylov space becomes invariant
+//     before K vectors, the process continues from a new vector orthogonal
+//     to it (T_m then splits into blocks).
+//  2. Multisection on a division-free Sturm count of T_m: g lanes (a power
+//     of two) bracket each wanted eigenvalue with two samples each per round
+//     and combine the brackets by lane shuffles.
 //  3. Inverse iteration (lane = eigenvector) with partial-pivoting LU of
-//     T - lam I, each sweep followed by orthonormalisation of the vectors in
-//     index order, and Rayleigh quotients as the final eigenvalues.
-//  4. Back-transformation by the reflectors (lane = eigenvector).
+//     T_m - lam I, each sweep followed by orthonormalisation of the vectors
+//     in index order, and Rayleigh quotients as the final eigenvalues.
+//  4. Ritz vectors X = Q_m Y (lane = component).
 template <int LDA, int NP>
-__device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n, int K,
+__device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K,
                                               long long* stamp = nullptr) {
     const int lane = threadIdx.x;
     const double eps = 2.220446049250313e-16;
-    const int n8 = (n + 7) & ~7;
     if (stamp && lane == 0) {
         stamp[0] = clock64();
         stamp[5] = 0;
         stamp[6] = 0;
     }
-    // ---- 1. tridiagonalise: A <- H_k A H_k, H_k = I - beta_k v_k v_k^T
+    // ---- 1. Lanczos with full re-orthogonalisation
+    int m = n_in;
     {
         double a[NP];
+        double fro = 0.0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) a[j] = (lane < n && j < n) ? S.A[lane][j] : 0.0;
-        S.tmp[lane] = 0.0;
-        S.tmp[MAXP + lane] = 0.0;
-        __syncthreads();
-        // before step k, lane i >= k holds A(i, k..n-1) in a[0..n-k-1]
-        for (int k = 0; k + 2 < n; ++k) {
-            const int m = n - k - 1;               // order of the trailing block
-            const bool act = lane > k && lane < n;
-            const double xi = act ? a[0] : 0.0;
-            const double nx2 = wsum(xi * xi);
-            const double x0 = rdlane(a[0], k + 1);
-            if (lane == k) S.de[k].x = a[0];
-            double vi = 0.0, beta = 0.0, alpha = 0.0;
-            if (nx2 > 0.0) {
-                alpha = x0 >= 0.0 ? -sqrt(nx2) : sqrt(nx2);
-                vi = act ? xi - (lane == k + 1 ? alpha : 0.0) : 0.0;
-                // |v|^2 = 2 |x|^2 - 2 x0 alpha
-                beta = 1.0 / (nx2 - x0 * alpha);
-            }
-            if (lane == 0) {
-                S.de[k].y = alpha;
-                S.Bh[k] = beta;
-            }
-            S.Vh[k][lane] = vi;
-            // v in trailing-block coordinates; every lane writes one slot, so
-            // slots past the block hold zeros
-            const int slot = (lane - k - 1) & (MAXP - 1);
-            S.tmp[slot] = vi;
-            __syncthreads();
-            double wi = 0.0;
-            if (beta != 0.0) {
-                // all of v at once (slots past the block are zero), so the
-                // loads overlap
-                double2 u[NP / 2];
-                const double2* tp = reinterpret_cast<const double2*>(S.tmp);
+        for (int j = 0; j < NP; ++j) {
+            a[j] = (lane < n_in && j < n_in) ? S.A[lane][j] : 0.0;
+            fro += a[j] * a[j];
+        }
+        // the Gram matrices this solver receives carry summation rounding of
+        // about 1e-14 of their norm; a residual below 1e-13 |A|_F is noise
+        const double btol = 1e-13 * sqrt(wsum(fro));
+        double* wv = S.tmp;          // the vector being orthogonalised
+        double* cf = S.tmp + MAXP;   // its coefficients on q_0 .. q_j
+        // w <- w - Q_{0..j} (Q_{0..j}^T w), twice; returns the summed
+        // coefficient on q_j.  Lane l forms q_l . w from LDS, then lane i
+        // subtracts its component.
+        // Rows of Vh not yet holding a Lanczos vector are zero, so every loop
+        // below runs to NP without branches (unset rows contribute zeros).
+        auto reorth = [&](double& w, int j) {
+            double cj = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                wv[lane] = w;
+                __syncthreads();
+                const double2* qr = reinterpret_cast<const double2*>(S.Vh[lane < NP ? lane : 0]);
+                const double2* wr = reinterpret_cast<const double2*>(wv);
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-                for (int q = 0; q < NP / 2; ++q) u[q] = tp[q];
-                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-                for (int q = 0; q < NP / 2; q += 2) {
-                    const int j = 2 * q;
-                    p0 += (j + 1 < NP ? a[j + 1] : 0.0) * u[q].x;
-                    p1 += (j + 2 < NP ? a[j + 2] : 0.0) * u[q].y;
-                    p2 += (j + 3 < NP ? a[j + 3] : 0.0) * u[q + 1].x;
-                    p3 += (j + 4 < NP ? a[j + 4] : 0.0) * u[q + 1].y;
+                for (int t = 0; t < NP / 2; t += 2) {
+                    const double2 x0 = qr[t], y0 = wr[t], x1 = qr[t + 1], y1 = wr[t + 1];
+                    s0 += x0.x * y0.x;
+                    s1 += x0.y * y0.y;
+                    s2 += x1.x * y1.x;
+                    s3 += x1.y * y1.y;
                 }
-                p0 = (p0 + p2) + (p1 + p3);
-                const double pi = act ? beta * p0 : 0.0;
-                const double kc = 0.5 * beta * wsum(vi * pi);
-                wi = pi - kc * vi;
-                S.tmp[MAXP + slot] = wi;
+                cf[lane] = lane < NP ? (s0 + s2) + (s1 + s3) : 0.0;
+                __syncthreads();
+                double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+                for (int l = 0; l < NP; l += 4) {
+                    const double2 c01 = *reinterpret_cast<const double2*>(cf + l);
+                    const double2 c23 = *reinterpret_cast<const double2*>(cf + l + 2);
+                    d0 += c01.x * S.Vh[l][lane];
+                    d1 += c01.y * S.Vh[l + 1][lane];
+                    d2 += c23.x * S.Vh[l + 2][lane];
+                    d3 += c23.y * S.Vh[l + 3][lane];
+                }
+                w -= (d0 + d2) + (d1 + d3);
+                cj += cf[j];
                 __syncthreads();
             }
-            // shift the trailing block down one register and apply the
-            // rank-two update  - v w^T - w v^T
-#pragma unroll
-            for (int j0 = 0; j0 < NP; j0 += 8) {
-                if (j0 < m) {
-                    const double2* tv = reinterpret_cast<const double2*>(S.tmp + j0);
-                    const double2* tw = reinterpret_cast<const double2*>(S.tmp + MAXP + j0);
-                    double2 uv[4], uw[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        uv[q] = tv[q];
-                        uw[q] = tw[q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = j0 + 2 * q;
-                        const double an0 = j + 1 < NP ? a[j + 1] : 0.0;
-                        const double an1 = j + 2 < NP ? a[j + 2] : 0.0;
-                        a[j] = an0 - (vi * uw[q].x + wi * uv[q].x);
-                        a[j + 1] = an1 - (vi * uw[q].y + wi * uv[q].y);
-                    }
-                }
-            }
+            return cj;
+        };
+        for (int r = 0; r < NP; ++r) S.Vh[r][lane] = 0.0;
+        double q = lane < n_in ? start_entry(lane, 777) : 0.0;
+        q *= 1.0 / sqrt(wsum(q * q));
+        for (int j = 0; j < n_in; ++j) {
+            S.Vh[j][lane] = q;
             __syncthreads();
-        }
-        if (n >= 2) {
-            if (lane == n - 2) S.de[n - 2] = make_double2(a[0], a[1]);
-            if (lane == n - 1) S.de[n - 1] = make_double2(a[1], 0.0);
-        } else if (lane == 0) {
-            S.de[0] = make_double2(a[0], 0.0);
+            // w = A q_j, all of q_j loaded at once
+            double2 u[NP / 2];
+            const double2* qp = reinterpret_cast<const double2*>(S.Vh[j]);
+#pragma unroll
+            for (int t = 0; t < NP / 2; ++t) u[t] = qp[t];
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NP / 2; t += 2) {
+                p0 += a[2 * t] * u[t].x;
+                p1 += a[2 * t + 1] * u[t].y;
+                p2 += a[2 * t + 2] * u[t + 1].x;
+                p3 += a[2 * t + 3] * u[t + 1].y;
+            }
+            double w = lane < n_in ? (p0 + p2) + (p1 + p3) : 0.0;
+            // full re-orthogonalisation removes the q_j and q_{j-1}
+            // components too: alpha_j is the coefficient on q_j
+            const double alpha = reorth(w, j);
+            const double beta = sqrt(wsum(w * w));
+            if (lane == 0) S.de[j] = make_double2(alpha, 0.0);
+            if (j + 1 == n_in) break;
+            if (beta <= btol) {
+                if (j + 1 >= K) {
+                    m = j + 1;
+                    break;
+                }
+                // invariant Krylov space: continue orthogonally to it
+                w = lane < n_in ? start_entry(lane, 1000 + j) : 0.0;
+                reorth(w, j);
+                w *= 1.0 / sqrt(wsum(w * w));
+            } else {
+                if (lane == 0) S.de[j].y = beta;
+                w *= 1.0 / beta;
+            }
+            q = w;
         }
         __syncthreads();
     }
+    const int n = m;                   // order of the tridiagonal T_m
+    const int n8 = (n + 7) & ~7;
     if (stamp && lane == 0) stamp[1] = clock64();
     // ---- 2. eigenvalues by multisection
     double glo = 1e300, ghi = -1e300;
@@ -769,53 +782,30 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n, int K,
     }
     __syncthreads();
     if (stamp && lane == 0) stamp[3] = clock64();
-    // ---- 4. back-transform by the reflectors, last to first (lane = eigenvector)
-    for (int k0 = 0; k0 < K; k0 += 64) {
-        const int kk = k0 + lane;
-        const bool own = kk < K;
-        double xv[NP];
+    // ---- 4. Ritz vectors X = Q_m Y (lane = component), staged in A's storage
+    {
+        // Y padded with zeros to K4 = K rounded up to 4 rows and NP columns,
+        // so that the product runs without branches
+        double* XO = &S.A[0][0];
+        const int K4 = (K + 3) & ~3;
+        for (int k = 0; k < K4; ++k)
+            if (lane < NP && (k >= K || lane >= n)) S.X[k][lane] = 0.0;
+        __syncthreads();
+        double qc[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) xv[j] = (own && j < n) ? S.X[own ? kk : 0][j] : 0.0;
-        for (int r = n - 3; r >= 0; --r) {
-            const double beta = S.Bh[r];
-            const double* __restrict__ vr = S.Vh[r];
-            const int jlo = (r + 1) & ~7;          // v vanishes at indices <= r
-            double s0 = 0.0, s1 = 0.0;
+        for (int l = 0; l < NP; ++l) qc[l] = S.Vh[l][lane];   // rows >= n are zero
+        for (int k0 = 0; k0 < K4; k0 += 4) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int j0 = 0; j0 < NP; j0 += 8) {
-                if (j0 >= jlo && j0 < n) {
-                    const double2* vp = reinterpret_cast<const double2*>(vr + j0);
-                    double2 u[4];
+            for (int l = 0; l < NP; ++l)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) u[q] = vp[q];
+                for (int u = 0; u < 4; ++u) acc[u] += qc[l] * S.X[k0 + u][l];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        s0 += u[q].x * xv[j0 + 2 * q];
-                        s1 += u[q].y * xv[j0 + 2 * q + 1];
-                    }
-                }
-            }
-            const double sb = beta * (s0 + s1);
-#pragma unroll
-            for (int j0 = 0; j0 < NP; j0 += 8) {
-                if (j0 >= jlo && j0 < n) {
-                    const double2* vp = reinterpret_cast<const double2*>(vr + j0);
-                    double2 u[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) u[q] = vp[q];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        xv[j0 + 2 * q] -= sb * u[q].x;
-                        xv[j0 + 2 * q + 1] -= sb * u[q].y;
-                    }
-                }
-            }
+            for (int u = 0; u < 4; ++u) XO[(k0 + u) * MAXP + lane] = acc[u];
         }
-        if (own) {
-#pragma unroll
-            for (int j = 0; j < NP; ++j)
-                if (j < n) S.X[kk][j] = xv[j];
-        }
+        __syncthreads();
+        for (int k = 0; k < K; ++k)
+            if (lane < n_in) S.X[k][lane] = XO[k * MAXP + lane];
         __syncthreads();
     }
     if (stamp && lane == 0) stamp[4] = clock64();
