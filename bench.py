@@ -258,6 +258,29 @@ def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
         times.append(time.perf_counter() - t0)
     tb = float(np.median(times))
     P_batch = [sp["P"].clone() for sp in specs[:8]]
+    # per-kernel times of one batch (HIP events inside the library) and the
+    # HBM roofline of the two NuFFT passes: every taper's grid of nf FP32
+    # complex values is written once by pass 1 and read once by pass 2
+    ctx.profile_reset()
+    ctx.profile(True)
+    m2n.m2n_batch_psd(ctx, specs, prec=m2n.M2N_FP32, check=False)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    ks = ctx.profile_read()
+    kern = {k: round(v[0], 3) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][0])}
+    nf = 1
+    while nf < 2 * series[0].I:
+        nf *= 2
+    grid_bytes = float(sum(s.K for s in series)) * nf * 8
+    pts = float(sum(s.N * (4 + 4 + 8 + 4) + s.K * s.N * 8 for s in series))
+    roof = []
+    for name, byts in (("k_pass1", grid_bytes + pts), ("k_pass2", grid_bytes + 2 * 4 * series[0].I * nser)):
+        if name in ks:
+            ms = ks[name][0]
+            ach = byts / (ms * 1e-3) / 1e9
+            roof.append({"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes": byts,
+                         "ms": round(ms, 4), "launches": ks[name][1]})
 
     def per_series():
         for sp in specs:
@@ -279,7 +302,7 @@ def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
             "value": round(work / tb / 1e6, 1), "unit": "Mpts*tapers*bands/s",
             "per_series_ms": round(ts * 1e3, 3), "per_series_psds_per_s": round(nser / ts, 1),
             "speedup_vs_per_series": round(ts / tb, 2),
-            "batch_vs_per_series_P_rel": dP}
+            "batch_vs_per_series_P_rel": dP, "kernels_ms": kern, "roofline_nufft": roof}
 
 
 FP64_PEAK_TFLOPS = 78.6

@@ -58,16 +58,17 @@ __device__ __forceinline__ void dft8(cplx<R>* u) {
 
 template <typename R, int N, int NB, int NT, int LD, int RAD, bool FIRST = false>
 __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw,
-                                          int tws, int p) {
+                                          int tws, int p, int nb) {
     constexpr int Q = N / RAD;              // butterflies per transform
-    constexpr int BF = NB * Q;              // butterflies in the batch
+    constexpr int BF = NB * Q;              // butterflies in the batch (at most)
     constexpr int IT = (BF + NT - 1) / NT;
     const int tid = threadIdx.x;
+    const int bfr = nb * Q;                 // butterflies of the nb transforms present
     cplx<R> v[IT][RAD];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NT;
-        if (BF % NT == 0 || idx < BF) {
+        if (idx < bfr) {
             const int b = idx / Q, j = idx - b * Q;
             const int k = j & (p - 1);
             const int tstep = k * (N / (p * RAD)) * tws;
@@ -83,7 +84,7 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NT;
-        if (BF % NT == 0 || idx < BF) {
+        if (idx < bfr) {
             const int b = idx / Q, j = idx - b * Q;
             const int k = j & (p - 1);
             if constexpr (RAD == 8) dft8(v[it]);
@@ -104,24 +105,25 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 // stage.  Caller must have synchronised after writing buf; returns
 // synchronised.  With first_done (N >= 8) the caller has already stored the
 // first radix-8 stage's output: when only x[0 .. N/8) can be non-zero, that
-// output is x[j] repeated at positions 8 j .. 8 j + 7.
+// output is x[j] repeated at positions 8 j .. 8 j + 7.  Only the first nb
+// (<= NB) transforms are computed.
 template <typename R, int N, int NB, int NT, int LD>
 __device__ __forceinline__ void fft_lds(cplx<R>* buf, const cplx<R>* __restrict__ tw, int tws,
-                                        bool first_done = false) {
+                                        bool first_done = false, int nb = NB) {
     constexpr int LOG = ilog2c(N);
     constexpr int N8 = LOG / 3, REM = LOG % 3;
     int p = 1;
     if constexpr (N8 > 0) {
-        if (!first_done) fft_stage<R, N, NB, NT, LD, 8, true>(buf, tw, tws, 1);
+        if (!first_done) fft_stage<R, N, NB, NT, LD, 8, true>(buf, tw, tws, 1, nb);
         p = 8;
     }
 #pragma unroll 1
     for (int s = 1; s < N8; ++s) {
-        fft_stage<R, N, NB, NT, LD, 8>(buf, tw, tws, p);
+        fft_stage<R, N, NB, NT, LD, 8>(buf, tw, tws, p, nb);
         p *= 8;
     }
-    if constexpr (REM == 2) fft_stage<R, N, NB, NT, LD, 4>(buf, tw, tws, p);
-    else if constexpr (REM == 1) fft_stage<R, N, NB, NT, LD, 2>(buf, tw, tws, p);
+    if constexpr (REM == 2) fft_stage<R, N, NB, NT, LD, 4>(buf, tw, tws, p, nb);
+    else if constexpr (REM == 1) fft_stage<R, N, NB, NT, LD, 2>(buf, tw, tws, p, nb);
 }
 
 }  // namespace m2n

@@ -459,7 +459,8 @@ __device__ __forceinline__ void scan_counts(int* cnt, int* wtot) {
 }
 
 template <typename R, int N1, int B>
-__global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
+// FP32: four waves per SIMD (two workgroups per compute unit)
+__global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     const int nblk = a.N2 / B;
     const int blk = blockIdx.x % nblk;
@@ -468,19 +469,20 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
     constexpr int LD = N1 + 1;
     constexpr int G = 64 / B;                               // tile rows per wavefront task
     constexpr int TASKS = N1 * B / NT1;                     // tile cells each thread owns
-    constexpr int CAP = sizeof(R) == 4 ? NT1 : NT1 / 2;     // points sorted per chunk
-    constexpr int LIST_BYTES = CAP * (int)sizeof(SpreadRec<R>);
-    constexpr int TW_BYTES = N1 * (int)sizeof(cplx<R>);
-    constexpr int REGION = LIST_BYTES > TW_BYTES ? LIST_BYTES : TW_BYTES;
-    static_assert(64 % B == 0 && (N1 * B) % NT1 == 0, "tile split");
-    __shared__ cplx<R> tile[B * LD];
+    // points sorted per chunk: the sorted list lives in the tile's storage,
+    // which the spread does not touch before its final store
+    constexpr int TILE_BYTES = B * LD * (int)sizeof(cplx<R>);
+    constexpr int CAP_T = TILE_BYTES / (int)sizeof(SpreadRec<R>) / NT1 * NT1;
+    constexpr int CAP = CAP_T < 4 * NT1 ? CAP_T : 4 * NT1;
+    constexpr int PPT = CAP / NT1;                          // points per thread per chunk
+    static_assert(64 % B == 0 && (N1 * B) % NT1 == 0 && PPT >= 1 && CAP <= 2048 && N1 <= 1024 && B <= 32,
+                  "tile split and the packed point keys");
+    __shared__ __attribute__((aligned(16))) cplx<R> tile[B * LD];
     __shared__ int rows[N1 + 1];
     __shared__ int wtot[NT1 / 64];
     __shared__ int s_maxrow;   // largest tile row any point reaches
-    // the chunk's row-sorted points during the spread, the twiddles after it
-    __shared__ __attribute__((aligned(16))) unsigned char region[REGION];
-    SpreadRec<R>* list = (SpreadRec<R>*)region;
-    cplx<R>* tw = (cplx<R>*)region;
+    __shared__ cplx<R> tw[N1];
+    SpreadRec<R>* list = reinterpret_cast<SpreadRec<R>*>(tile);
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
@@ -524,67 +526,72 @@ __global__ __launch_bounds__(NT1) void k_pass1(NuArgs a, NuSeries d0, const NuSe
         return j;
     };
     phase_stamp(a, 5);
-    // Owner-computes spreading, chunk by chunk: each chunk's points are
-    // counting-sorted by the tile row they reach (integer LDS atomics), then
-    // every thread sums, in registers, the taps that land on its TASKS cells.
-    // Float atomics on LDS are avoided: they are many times slower than the
-    // sort plus a plain store per cell.
+    // Owner-computes spreading, chunk by chunk (one chunk holds CAP points,
+    // normally the whole window): each chunk's points are counting-sorted by
+    // the tile row they reach (integer LDS atomics), then every thread sums,
+    // in registers, the taps that land on its TASKS cells.  Float atomics on
+    // LDS are avoided: they are many times slower than the sort plus a plain
+    // store per cell.
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cb = lane % B, rsub = lane / B;
     cplx<R> acc[TASKS];
 #pragma unroll
     for (int u = 0; u < TASKS; ++u) acc[u] = {(R)0, (R)0};
-    int pl0 = 0;
-    R pdel = (R)0;
-    cplx<R> pc = {(R)0, (R)0};
-    // FP32 loads a chunk's points while the previous chunk is summed; FP64
-    // loads them at the chunk's start (the extra registers would halve the
-    // workgroups per compute unit)
-    constexpr bool PREFETCH = sizeof(R) == 4;
-    auto fetch = [&](int f, int& l0, R& del, cplx<R>& c) {
-        if (threadIdx.x < CAP && f < total) {
-            const int j = locate(f);
-            l0 = l0s[j];
-            del = dels[j];
-            c = {cwk[j].x, cwk[j].y};
-        }
-    };
-    if (PREFETCH) fetch(threadIdx.x, pl0, pdel, pc);
     __syncthreads();   // rows[] is zero before the first count
     const int nchunks = (total + CAP - 1) / CAP;
     for (int ch = 0; ch < nchunks; ++ch) {
-        const int f = ch * CAP + threadIdx.x;
-        int ml0 = pl0;
-        R mdel = pdel;
-        cplx<R> mc = pc;
-        if (!PREFETCH) fetch(f, ml0, mdel, mc);
-        int s = 0, rowt = 0, slot = -1;
-        if (threadIdx.x < CAP && f < total) {
-            s = (ml0 & (N2 - 1)) - c0;
-            if (s > N2 / 2) s -= N2;
-            else if (s <= -N2 / 2) s += N2;
-            if (s < B && s > -w) {
-                int base = ml0 - s;   // cell of column c0 in the row the taps reach
-                if (base < 0) base += nf;
-                else if (base >= nf) base -= nf;
-                rowt = base >> log_N2;
-                slot = atomicAdd(&rows[rowt], 1);
+        // this thread's points of the chunk: all loads first
+        int pl0[PPT];
+        R pdel[PPT];
+        cplx<R> pcv[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int f = ch * CAP + p * NT1 + threadIdx.x;
+            pl0[p] = -1;
+            pdel[p] = (R)0;
+            pcv[p] = {(R)0, (R)0};
+            if (f < total) {
+                const int j = locate(f);
+                pl0[p] = l0s[j];
+                pdel[p] = dels[j];
+                pcv[p] = {cwk[j].x, cwk[j].y};
             }
         }
-        {
-            int mr = slot >= 0 ? rowt : -1;   // one LDS atomic per wavefront
-            for (int o = 32; o > 0; o >>= 1) mr = max(mr, __shfl_xor(mr, o, 64));
-            if (lane == 0 && mr >= 0) atomicMax(&s_maxrow, mr);
+        // target row of each point and its slot in that row, packed as
+        // slot << 16 | row << 6 | (s + 16)  (slot < 2048, row < 1024,
+        // -16 < s < 32), -1 for a point that reaches no column of the block
+        int pk[PPT];
+        int mr = -1;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            pk[p] = -1;
+            if (pl0[p] >= 0) {
+                int sc = (pl0[p] & (N2 - 1)) - c0;
+                if (sc > N2 / 2) sc -= N2;
+                else if (sc <= -N2 / 2) sc += N2;
+                if (sc < B && sc > -w) {
+                    int base = pl0[p] - sc;   // cell of column c0 in the row the taps reach
+                    if (base < 0) base += nf;
+                    else if (base >= nf) base -= nf;
+                    const int row = base >> log_N2;
+                    const int slot = atomicAdd(&rows[row], 1);
+                    pk[p] = (slot << 16) | (row << 6) | (sc + 16);
+                    mr = max(mr, row);
+                }
+            }
         }
+        for (int o = 32; o > 0; o >>= 1) mr = max(mr, __shfl_xor(mr, o, 64));
+        if (lane == 0 && mr >= 0) atomicMax(&s_maxrow, mr);   // one LDS atomic per wavefront
         __syncthreads();
         scan_counts<N1>(rows, wtot);
-        if (slot >= 0) {
-            const int at = rows[rowt] + slot;
-            if (at < CAP) list[at] = {s, mdel, mc};
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            if (pk[p] >= 0) {
+                const int at = rows[(pk[p] >> 6) & 1023] + (pk[p] >> 16);
+                if (at < CAP) list[at] = {(pk[p] & 63) - 16, pdel[p], pcv[p]};
+            }
         }
         __syncthreads();
-        // the next chunk's point is loaded while this one is summed
-        if (PREFETCH && ch + 1 < nchunks) fetch(f + CAP, pl0, pdel, pc);
 #pragma unroll
         for (int u = 0; u < TASKS; ++u) {
             const int row = (u * (NT1 / 64) + wv) * G + rsub;
@@ -720,7 +727,7 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
         }
         __syncthreads();
         phase_stamp(a, 9);
-        fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1);
+        fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1, false, nk * M);   // the nk tapers present
         phase_stamp(a, 10);
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
