@@ -190,10 +190,20 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
             bsz.append(res["batch_size"])
         except m2n.M2NError:
             fails += 1
+        if (i + 1) % 2000 == 0:
+            print(f"bench: served {i + 1}/{n}", file=sys.stderr, flush=True)
     end = time.perf_counter()
     th.join()
-    q.close()
     wall = end - start
+    # saturation: the first requests submitted at once, so that the queue
+    # forms batches as fast as the device drains them
+    nb = min(n, 2000)
+    b_start = time.perf_counter()
+    btk = [q.submit(r.t, r.x, r.fmax, r.fw, r.K, r.f_lo, r.df, r.I) for r in reqs[:nb]]
+    bres = [q.wait(tk) for tk in btk]
+    b_wall = time.perf_counter() - b_start
+    q.close()
+    print(f"bench: served trace done, burst of {nb} in {b_wall:.2f} s", file=sys.stderr, flush=True)
 
     # baseline: per-series FP64 GPU path, FIFO on one stream, same arrivals
     dev = torch.device("cuda:0")
@@ -217,6 +227,8 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
             time.sleep(dt)
         serve_one(r)
         blat.append((time.perf_counter() - (b0 + arr[i])) * 1e3)
+        if (i + 1) % 2000 == 0:
+            print(f"bench: baseline {i + 1}/{n}", file=sys.stderr, flush=True)
     bwall = time.perf_counter() - b0
     lat, blat = np.array(lat), np.array(blat)
     return {"requests": n, "rate_per_s": rate, "seconds": seconds,
@@ -225,6 +237,8 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
                 "p50": round(float(np.percentile(lat, 50)), 3),
                 "p99": round(float(np.percentile(lat, 99)), 3)},
             "mean_batch": round(float(np.mean(bsz)), 2), "max_batch": int(np.max(bsz)),
+            "burst": {"requests": nb, "psds_per_s": round(nb / b_wall, 1),
+                      "mean_batch": round(float(np.mean([r["batch_size"] for r in bres])), 1)},
             "baseline_fp64_per_series": {
                 "psds_per_s": round(n / bwall, 1), "latency_ms": {
                     "p50": round(float(np.percentile(blat, 50)), 3),
