@@ -961,26 +961,32 @@ __global__ __launch_bounds__(64) void k_small_rr(double* __restrict__ acc, int p
 // With aux != 0 two more columns hold 1 and (t_c - t_n) / span, whose
 // products with F give the sign sums of the tapers.  Rows n >= N are zero.
 // Column-major with leading dimension Np; grid (Np / 256, nq + aux).
-__global__ void k_lr_basis(LrSeries d0, const LrSeries* D) {
+// one sample per thread, LR_QB quadrature nodes per workgroup row
+// (blockIdx.y); the auxiliary columns go with the last row; padding rows zero
+constexpr int LR_QB = 4;
+__global__ __launch_bounds__(256) void k_lr_basis(LrSeries d0, const LrSeries* D) {
     const LrSeries d = lr_of(d0, D, blockIdx.z);
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int q = blockIdx.y;
-    const int aux = d.pF > d.Qn ? 1 : 0;
-    if (n >= d.Np || q >= d.nq + aux) return;
-    double c = 0.0, s = 0.0;
-    if (q < d.nq) {
-        if (n < d.N) {
-            sincospi(2.0 * d.fw * d.glx[q] * (d.t[n] - d.tc), &s, &c);
+    const int q0 = (int)blockIdx.y * LR_QB;
+    if (n >= d.Np || q0 >= d.nq + (d.pF > d.Qn ? 1 : 0)) return;
+    const bool live = n < d.N;
+    const double tn = live ? d.t[n] : d.tc;
+    const int q1 = q0 + LR_QB < d.nq ? q0 + LR_QB : d.nq;
+    for (int q = q0; q < q1; ++q) {
+        double c = 0.0, s = 0.0;
+        if (live) {
+            sincospi(2.0 * d.fw * d.glx[q] * (tn - d.tc), &s, &c);
             const double sq = sqrt(2.0 * d.fw * d.glx[MAXP + q]);
             c *= sq;
             s *= sq;
         }
-    } else if (n < d.N) {
-        c = 1.0;
-        s = (d.tc - d.t[n]) / d.span;
+        d.F[(int64_t)(2 * q) * d.Np + n] = c;
+        d.F[(int64_t)(2 * q + 1) * d.Np + n] = s;
     }
-    d.F[(int64_t)(2 * q) * d.Np + n] = c;
-    d.F[(int64_t)(2 * q + 1) * d.Np + n] = s;
+    if (d.pF > d.Qn && q0 + LR_QB > d.nq) {
+        d.F[(int64_t)(2 * d.nq) * d.Np + n] = live ? 1.0 : 0.0;
+        d.F[(int64_t)(2 * d.nq + 1) * d.Np + n] = live ? (d.tc - tn) / d.span : 0.0;
+    }
 }
 
 // Y[k * ldy + n] = s_k * sum_j F[j][n] Z[j + k Qn] for k < K, n < ldy, with
@@ -2039,7 +2045,7 @@ int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* st
     const int ns = (int)idx.size();
     if (ns == 0) return M2N_OK;
     std::vector<LrSeries> ds(ns);
-    int maxq = 0, maxpF = 0, maxcol = 0, maxred = 0;
+    int maxq = 0, maxpF = 0, maxred = 0;
     int64_t maxNp = 0, maxN = 0;
     for (int j = 0; j < ns; ++j) {
         const GepIn& g = in[idx[j]];
@@ -2072,7 +2078,6 @@ int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* st
         M2N_TRY(gl_table(ctx, d.Qn, &d.glx));
         maxq = std::max(maxq, d.Qn);
         maxpF = std::max(maxpF, d.pF);
-        maxcol = std::max(maxcol, d.nq + 1);
         maxred = std::max(maxred, d.nred);
         maxNp = std::max(maxNp, d.Np);
         maxN = std::max(maxN, d.N);
@@ -2107,7 +2112,7 @@ int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* st
     const unsigned ys = (unsigned)ns;
     {
         M2N_PROF(ctx, st, "k_lr_basis");
-        hipLaunchKernelGGL(k_lr_basis, dim3((unsigned)((maxNp + 255) / 256), (unsigned)maxcol, ys),
+        hipLaunchKernelGGL(k_lr_basis, dim3((unsigned)((maxNp + 255) / 256), (unsigned)((maxq / 2 + 1 + LR_QB - 1) / LR_QB), ys),
                            dim3(256), 0, st, d0, D);
     }
     M2N_HIP(hipGetLastError());
@@ -2250,7 +2255,7 @@ int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
         d.Y = Y;
         {
             M2N_PROF(ctx, st, "k_lr_basis");
-            dim3 gq((unsigned)((Np + 255) / 256), (unsigned)d.nq, 1);
+            dim3 gq((unsigned)((Np + 255) / 256), (unsigned)((d.nq + LR_QB - 1) / LR_QB), 1);
             hipLaunchKernelGGL(k_lr_basis, gq, dim3(256), 0, st, d, (const LrSeries*)nullptr);
         }
         M2N_HIP(hipGetLastError());
