@@ -2070,17 +2070,24 @@ int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* st
         d.nq = d.Qn / 2;
         d.fuse = 1;
         d.nchunks = (int)((d.Np + GRAM_ROWS - 1) / GRAM_ROWS);
-        d.nred = d.nchunks < 512 ? d.nchunks : 512;   // one chunk per wavefront up to 512
-        d.cpw = (d.nchunks + d.nred - 1) / d.nred;
-        d.nred = (d.nchunks + d.cpw - 1) / d.cpw;
         d.theta = g.lambda;
         d.Y = g.w;
         M2N_TRY(gl_table(ctx, d.Qn, &d.glx));
         maxq = std::max(maxq, d.Qn);
         maxpF = std::max(maxpF, d.pF);
-        maxred = std::max(maxred, d.nred);
         maxNp = std::max(maxNp, d.Np);
         maxN = std::max(maxN, d.N);
+    }
+    // 64-row chunks per Gram wavefront: one for a single series (up to 512
+    // wavefronts), more in a batch so that about 2048 wavefronts run and
+    // few partial Gram matrices are written and summed
+    int64_t chunks = 0;
+    for (auto& d : ds) chunks += d.nchunks;
+    const int cpw_b = (int)std::max<int64_t>(1, chunks / 2048);
+    for (auto& d : ds) {
+        d.cpw = std::max(cpw_b, (d.nchunks + 511) / 512);
+        d.nred = (d.nchunks + d.cpw - 1) / d.cpw;
+        maxred = std::max(maxred, d.nred);
     }
     // workspace: F, Gram partials, Gram, Z per series (256-byte aligned)
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
