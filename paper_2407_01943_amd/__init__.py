@@ -246,13 +246,10 @@ def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64
     return {"P": P, "E": E, "J": J}
 
 
-def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=True,
-                  want_J=False, stream=None, check=True):
-    """Tapers and PSD of many series in batched launches.  `series` is a list of
-    dicts with device tensors t, x and the numbers fmax, fw, K, f_lo, df, I
-    (optional "weights", "want_E", and "w", "lam", "P", "E", "J" output
-    tensors).
-    Returns a list of {"w", "lam", "P", "E", "J"}."""
+def batch_descriptors(series, prec=M2N_FP32, want_E=True, want_J=False):
+    """The m2n_series array of a batch and its output tensors, built once so
+    that repeated m2n_batch_psd calls on the same tensors skip the per-series
+    Python work.  `series` is as for m2n_batch_psd.  Returns (array, outputs)."""
     rdt = torch.float32 if prec == M2N_FP32 else torch.float64
     cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
     arr = (M2NSeries * len(series))()
@@ -274,7 +271,18 @@ def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=Tru
                            lam.data_ptr(), P.data_ptr(), None if E is None else E.data_ptr(),
                            None if J is None else J.data_ptr())
         outs.append({"w": w, "lam": lam, "P": P, "E": E, "J": J})
-    _err(lib.m2n_batch_psd(ctx.handle, _stream(stream), arr, len(series), int(prec),
+    return arr, outs
+
+
+def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=True,
+                  want_J=False, stream=None, check=True, prepared=None):
+    """Tapers and PSD of many series in batched launches.  `series` is a list of
+    dicts with device tensors t, x and the numbers fmax, fw, K, f_lo, df, I
+    (optional "weights", "want_E", and "w", "lam", "P", "E", "J" output
+    tensors); `prepared` is the result of batch_descriptors for the same list.
+    Returns a list of {"w", "lam", "P", "E", "J"}."""
+    arr, outs = prepared if prepared is not None else batch_descriptors(series, prec, want_E, want_J)
+    _err(lib.m2n_batch_psd(ctx.handle, _stream(stream), arr, len(outs), int(prec),
                            float(nufft_tol)), "m2n_batch_psd")
     if check:
         ctx.check(stream)
