@@ -27,10 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# the sources a NuFFT kernel is built from: measured HBM traffic is reported
-# only while their hash matches the one recorded with the counters
+# the sources each kernel family is built from: measured HBM traffic of a
+# kernel is reported only while the hash of its family's sources matches the
+# one recorded with the counters
 NUFFT_SOURCES = ["paper_2407_01943_amd/csrc/nufft.hip", "paper_2407_01943_amd/csrc/fft_lds.hpp",
                  "paper_2407_01943_amd/csrc/m2n_common.hpp"]
+GEP_SOURCES = ["paper_2407_01943_amd/csrc/gep.hip", "paper_2407_01943_amd/csrc/fft_lds.hpp",
+               "paper_2407_01943_amd/csrc/m2n_common.hpp"]
 TRAFFIC_FILE = "profiles/hbm_traffic_gapped_20k.md"
 
 
@@ -43,11 +46,24 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
+def kernel_sources(kernel):
+    """The source family that defines `kernel` (a __global__ function name),
+    or None."""
+    import re
+    pat = re.compile(r"void\s+" + re.escape(kernel) + r"\s*\(")
+    for fam in (NUFFT_SOURCES, GEP_SOURCES):
+        with open(os.path.join(ROOT, fam[0])) as f:
+            if pat.search(f.read()):
+                return fam
+    return None
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when there is none or the kernel's sources changed since."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
-    if not os.path.exists(path):
+    fam = kernel_sources(kernel)
+    if not os.path.exists(path) or fam is None:
         return None
     rec = None
     with open(path) as f:
@@ -56,7 +72,7 @@ def measured_traffic(kernel):
                 r = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
                 if r.get("kernel") == kernel:
                     rec = r
-    if rec is None or rec.get("sources_sha256") != sources_sha256(NUFFT_SOURCES):
+    if rec is None or rec.get("sources_sha256") != sources_sha256(fam):
         return None
     return rec["bytes_per_launch"]
 
@@ -104,7 +120,6 @@ def profile_summary(a):
     out.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated MB per dispatch |")
     out.append("|---|---:|---:|---:|---:|")
     recs = []
-    sha = sources_sha256(NUFFT_SOURCES)
     for k in sorted(F, key=lambda k: -sum(F[k]) / len(F[k])):
         if k.startswith("__amd"):
             continue
@@ -112,11 +127,12 @@ def profile_summary(a):
         w = sum(W.get(k, [0.0])) / max(1, len(W.get(k, [0.0])))
         byts = (f * cf + w * cw) * 1024.0
         out.append(f"| {k} | {len(F[k])} | {f:.1f} | {w:.1f} | {byts / 1e6:.3f} |")
-        if k.startswith("k_pass1") or k.startswith("k_pass2"):
+        fam = kernel_sources(k.split("<")[0])
+        if fam is not None:
             recs.append({"kernel": k.split("<")[0], "instance": k, "bytes_per_launch": round(byts),
                          "fetch_kib": round(f, 1), "write_kib": round(w, 1),
                          "fetch_factor": round(cf, 4), "write_factor": round(cw, 4),
-                         "sources_sha256": sha})
+                         "sources_sha256": sources_sha256(fam)})
     out.append("")
     for r in recs:
         out.append("<!-- traffic " + json.dumps(r) + " -->")
@@ -504,9 +520,10 @@ def main():
     # roofline of the dominant kernel.  The lattice GEP's eigen-solver
     # (k_sym_topk: one wavefront on the Q x Q quadrature Gram matrix) is
     # FP64 ALU work priced against the chip's FP64 vector peak, with the
-    # algorithmic flops of Householder tridiagonalisation (4/3 Q^3) and the
-    # back-transformation of K vectors (4 Q^2 K); HBM-bound kernels are
-    # priced by their algorithmic bytes.
+    # textbook flop count of a dense symmetric top-K eigenproblem
+    # (Householder tridiagonalisation 4/3 Q^3 plus the back-transformation
+    # of K vectors 4 Q^2 K), whatever method the kernel uses; HBM-bound
+    # kernels are priced by their algorithmic bytes.
     def roof(name):
         ms_k, cnt_k = kstats[name]
         avg = ms_k / cnt_k
@@ -519,7 +536,7 @@ def main():
             ach = fl / (avg * 1e-3) / 1e12
             return {"kernel": name, "bound": "alu", "achieved": round(ach, 6),
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / FP64_PEAK_TFLOPS, 8), "traffic": None,
+                    "frac": round(ach / FP64_PEAK_TFLOPS, 8), "traffic": measured_traffic(name),
                     "algorithmic_flops": fl, "Q": Q, "avg_ms": round(avg, 5), "launches": cnt_k,
                     "note": "one wavefront (1 of 1024 SIMDs): latency of the serial eigen-solve"}
         byts = algorithmic_bytes(name, s, N, K, I, plan, pb)
