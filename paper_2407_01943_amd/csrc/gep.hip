@@ -300,6 +300,24 @@ __device__ __forceinline__ double rdlane(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// two independent wave sums, interleaved
+__device__ __forceinline__ void wsum2(double (&v)[2]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0xb1, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0x4e, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0x114, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0x118, 0xf>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0x142, 0xa>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] += dpp_d<0x143, 0xc>(v[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] = rdlane(v[u], 63);
+}
+
 // eight independent wave sums, interleaved so that the DPP steps of one
 // hide the latency of the others
 __device__ __forceinline__ void wsum8(double (&v)[8]) {
@@ -527,48 +545,63 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         const double btol = 1e-13 * sqrt(wsum(fro));
         double* wv = S.tmp;          // the vector being orthogonalised
         double* cf = S.tmp + MAXP;   // its coefficients on q_0 .. q_j
-        // w <- w - Q_{0..j} (Q_{0..j}^T w), twice; returns the summed
-        // coefficient on q_j.  Lane l forms q_l . w from LDS, then lane i
-        // subtracts its component.
-        // Rows of Vh not yet holding a Lanczos vector are zero, so every loop
-        // below runs to NP without branches (unset rows contribute zeros).
-        auto reorth = [&](double& w, int j) {
-            double cj = 0.0;
-            for (int pass = 0; pass < 2; ++pass) {
-                wv[lane] = w;
-                __syncthreads();
-                const double2* qr = reinterpret_cast<const double2*>(S.Vh[lane < NP ? lane : 0]);
-                const double2* wr = reinterpret_cast<const double2*>(wv);
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // One classical Gram-Schmidt pass, w <- w - Q_{0..j} (Q_{0..j}^T w):
+        // lane l forms q_l . w from LDS (rows of Vh not yet holding a Lanczos
+        // vector are zero), then lane i subtracts its component, over the
+        // rows 0..j in blocks of eight.  Every operand of a block is loaded
+        // before the first product so that the LDS reads overlap.  Returns
+        // the coefficient on q_j; `cc` receives this lane's coefficient
+        // (lane l: on q_l, zero beyond j).
+        auto cgs = [&](double& w, int j, double& cc) {
+            wv[lane] = w;
+            __syncthreads();
+            const double2* qr = reinterpret_cast<const double2*>(S.Vh[lane < NP ? lane : 0]);
+            const double2* wr = reinterpret_cast<const double2*>(wv);
+            double2 x[NP / 2], y[NP / 2];
 #pragma unroll
-                for (int t = 0; t < NP / 2; t += 2) {
-                    const double2 x0 = qr[t], y0 = wr[t], x1 = qr[t + 1], y1 = wr[t + 1];
-                    s0 += x0.x * y0.x;
-                    s1 += x0.y * y0.y;
-                    s2 += x1.x * y1.x;
-                    s3 += x1.y * y1.y;
-                }
-                cf[lane] = lane < NP ? (s0 + s2) + (s1 + s3) : 0.0;
-                __syncthreads();
-                double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-#pragma unroll
-                for (int l = 0; l < NP; l += 4) {
-                    const double2 c01 = *reinterpret_cast<const double2*>(cf + l);
-                    const double2 c23 = *reinterpret_cast<const double2*>(cf + l + 2);
-                    d0 += c01.x * S.Vh[l][lane];
-                    d1 += c01.y * S.Vh[l + 1][lane];
-                    d2 += c23.x * S.Vh[l + 2][lane];
-                    d3 += c23.y * S.Vh[l + 3][lane];
-                }
-                w -= (d0 + d2) + (d1 + d3);
-                cj += cf[j];
-                __syncthreads();
+            for (int t = 0; t < NP / 2; ++t) {
+                x[t] = qr[t];
+                y[t] = wr[t];
             }
+            __builtin_amdgcn_sched_barrier(0);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NP / 2; t += 2) {
+                s0 += x[t].x * y[t].x;
+                s1 += x[t].y * y[t].y;
+                s2 += x[t + 1].x * y[t + 1].x;
+                s3 += x[t + 1].y * y[t + 1].y;
+            }
+            cc = lane < NP ? (s0 + s2) + (s1 + s3) : 0.0;
+            cf[lane] = cc;
+            __syncthreads();
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+            for (int l0 = 0; l0 <= j; l0 += 8) {
+                double2 c[4];
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[u] = *reinterpret_cast<const double2*>(cf + l0 + 2 * u);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = S.Vh[l0 + u][lane];
+                __builtin_amdgcn_sched_barrier(0);
+                d0 += c[0].x * v[0];
+                d1 += c[0].y * v[1];
+                d2 += c[1].x * v[2];
+                d3 += c[1].y * v[3];
+                d0 += c[2].x * v[4];
+                d1 += c[2].y * v[5];
+                d2 += c[3].x * v[6];
+                d3 += c[3].y * v[7];
+            }
+            w -= (d0 + d2) + (d1 + d3);
+            const double cj = cf[j];
+            __syncthreads();
             return cj;
         };
         for (int r = 0; r < NP; ++r) S.Vh[r][lane] = 0.0;
         double q = lane < n_in ? start_entry(lane, 777) : 0.0;
         q *= 1.0 / sqrt(wsum(q * q));
+        double qprev = 0.0, bprev = 0.0;
         for (int j = 0; j < n_in; ++j) {
             S.Vh[j][lane] = q;
             __syncthreads();
@@ -585,13 +618,26 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
                 p2 += a[2 * t + 2] * u[t + 1].x;
                 p3 += a[2 * t + 3] * u[t + 1].y;
             }
-            double w = lane < n_in ? (p0 + p2) + (p1 + p3) : 0.0;
-            // full re-orthogonalisation removes the q_j and q_{j-1}
-            // components too: alpha_j is the coefficient on q_j
-            const double alpha = reorth(w, j);
-            const double beta = sqrt(wsum(w * w));
+            double w = lane < n_in ? (p0 + p2) + (p1 + p3) - bprev * qprev : 0.0;
+            // three-term recurrence, then one re-orthogonalisation pass
+            // against every earlier vector; a second pass only when the
+            // first removed more than half of the norm (|w'|^2 < |c|^2, the
+            // Daniel-Gragg-Kaufman-Stewart test), which keeps Q_m orthogonal
+            // to rounding.  alpha_j accumulates every coefficient on q_j.
+            double alpha = wsum(q * w);
+            w -= alpha * q;
+            double cc;
+            alpha += cgs(w, j, cc);
+            double s2[2] = {w * w, cc * cc};
+            wsum2(s2);
+            if (s2[0] < s2[1]) {
+                alpha += cgs(w, j, cc);
+                s2[0] = wsum(w * w);
+            }
+            const double beta = sqrt(s2[0]);
             if (lane == 0) S.de[j] = make_double2(alpha, 0.0);
             if (j + 1 == n_in) break;
+            qprev = q;
             if (beta <= btol) {
                 if (j + 1 >= K) {
                     m = j + 1;
@@ -599,11 +645,14 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
                 }
                 // invariant Krylov space: continue orthogonally to it
                 w = lane < n_in ? start_entry(lane, 1000 + j) : 0.0;
-                reorth(w, j);
+                cgs(w, j, cc);
+                cgs(w, j, cc);
                 w *= 1.0 / sqrt(wsum(w * w));
+                bprev = 0.0;
             } else {
                 if (lane == 0) S.de[j].y = beta;
                 w *= 1.0 / beta;
+                bprev = beta;
             }
             q = w;
         }
