@@ -514,11 +514,14 @@ __device__ __forceinline__ double start_entry(int i, int k) {
 //     before K vectors, the process continues from a new vector orthogonal
 //     to it (T_m then splits into blocks).
 //  2. Multisection on a division-free Sturm count of T_m: g lanes (a power
-//     of two) bracket each wanted eigenvalue with two samples each per round
-//     and combine the brackets by lane shuffles.
-//  3. Inverse iteration (lane = eigenvector) with partial-pivoting LU of
-//     T_m - lam I, each sweep followed by orthonormalisation of the vectors
-//     in index order, and Rayleigh quotients as the final eigenvalues.
+//     of two) bracket each wanted eigenvalue, and the next one, with two
+//     samples each per round and combine the brackets by lane shuffles.
+//  3. Eigenvectors of T_m (lane = eigenvector).  When the wanted
+//     eigenvalues and the next one are at least 1e-8 |T| apart: twisted
+//     factorisations of T_m - lam I and one Cholesky QR pass.  Otherwise
+//     inverse iteration with partial-pivoting LU of T_m - lam I, each sweep
+//     followed by orthonormalisation of the vectors in index order.
+//     Rayleigh quotients give the final eigenvalues.
 //  4. Ritz vectors X = Q_m Y (lane = component).
 template <int LDA, int NP>
 __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K,
@@ -661,7 +664,10 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
     const int n = m;                   // order of the tridiagonal T_m
     const int n8 = (n + 7) & ~7;
     if (stamp && lane == 0) stamp[1] = clock64();
-    // ---- 2. eigenvalues by multisection
+    // ---- 2. eigenvalues by multisection: the K wanted ones and, when T_m
+    //         has it, the next one (its distance to the K-th decides the
+    //         eigenvector method)
+    const int Kb = K < n ? K + 1 : K;
     double glo = 1e300, ghi = -1e300;
     if (lane < n) {
         const double2 dl = S.de[lane];
@@ -685,11 +691,11 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         }
         __syncthreads();
         int g = 64;
-        while (g > 1 && g * K > 64) g >>= 1;
+        while (g > 1 && g * Kb > 64) g >>= 1;
         const int grp = lane / g, sub = lane - grp * g;
         const int idx = n - 1 - grp;
-        const bool live = grp < K;
-        const double tol = 1e-14 * tnorm;
+        const bool live = grp < Kb;
+        const double tol = 1e-15 * tnorm;
         // invariant: count(l) <= idx < count(h)
         double l = glo - 2.0 * eps * tnorm, h = ghi + 2.0 * eps * tnorm;
         for (int round = 0; round < 200; ++round) {
@@ -716,93 +722,169 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         __syncthreads();
     }
     if (stamp && lane == 0) stamp[2] = clock64();
-    // ---- 3. inverse iteration in batches of 16 eigenvectors (lane =
-    //         eigenvector); the LU rows of T - lam I live in A's storage,
-    //         [i][lane], each pivot stored as its reciprocal
-    double* U1 = &S.A[0][0];
-    double* U2 = U1 + 16 * MAXP;
-    double* U3 = U2 + 16 * MAXP;
-    double* Bv = U3 + 16 * MAXP;
     const double tiny = fmax(eps * tnorm, 1e-290);
-    for (int kb = 0; kb < K; kb += 16) {
-        const int kk = kb + lane;
-        const bool mine = lane < 16 && kk < K;
-        const int kend = kb + 16 < K ? kb + 16 : K;
-        if (mine)
-            for (int i = 0; i < n; ++i) S.X[kk][i] = start_entry(i, kk);
-        for (int it = 0; it < INVIT_SWEEPS; ++it) {
-            long long ts0 = 0;
-            if (stamp) ts0 = clock64();
-            if (mine) {
-                double sh = S.lam[kk];
-                for (int j = 0; j < kk; ++j)
-                    if (fabs(sh - S.lam[j]) < 10.0 * tiny) sh = S.lam[j] - 10.0 * tiny * (kk - j);
-                // forward elimination with partial pivoting, branch-free; the
-                // current row (c1, c2) and right-hand side cb are carried in
-                // registers and the next row's operands are fetched one step
-                // ahead
-                const double2 d0 = S.de[0];
-                double c1 = d0.x - sh, c2 = d0.y, sub = d0.y;
-                double cb = S.X[kk][0];
-                double2 nxt = n > 1 ? S.de[1] : make_double2(0.0, 0.0);
-                double rsub = S.re[0];
-                double nb = n > 1 ? S.X[kk][1] : 0.0;
-                for (int i = 0; i + 1 < n; ++i) {
-                    double2 nxt2 = make_double2(0.0, 0.0);
-                    double rsub2 = 0.0, nb2 = 0.0;
-                    if (i + 2 < n) {
-                        nxt2 = S.de[i + 2];
-                        rsub2 = S.re[i + 1];
-                        nb2 = S.X[kk][i + 2];
-                    }
-                    const double nd = nxt.x - sh, ne = nxt.y;
-                    const bool swap = fabs(sub) > fabs(c1);
-                    const double rp = recip(c1 != 0.0 ? c1 : tiny);
-                    const double mult = swap ? c1 * rsub : sub * rp;
-                    U1[i * 16 + lane] = swap ? rsub : rp;
-                    U2[i * 16 + lane] = swap ? nd : c2;
-                    U3[i * 16 + lane] = swap ? ne : 0.0;
-                    Bv[i * 16 + lane] = swap ? nb : cb;
-                    const double p1 = swap ? c2 : nd, q1 = swap ? nd : c2;
-                    const double pb = swap ? cb : nb, qb = swap ? nb : cb;
-                    c1 = p1 - mult * q1;
-                    c2 = swap ? -mult * ne : ne;
-                    cb = pb - mult * qb;
-                    sub = ne;
-                    nxt = nxt2;
-                    rsub = rsub2;
-                    nb = nb2;
+    double mingap = 1e300;
+    for (int k = 0; k + 1 < Kb; ++k) mingap = fmin(mingap, S.lam[k] - S.lam[k + 1]);
+    if (mingap >= 1e-8 * tnorm) {
+        // ---- 3a. separated eigenvalues: each eigenvector from a twisted
+        //          factorisation of T - lam I (lane = eigenvector, batches of
+        //          16).  With T - lam I = L D+ L^T = U D- U^T, the twist index
+        //          r minimises |gamma_r| = |D+_r + D-_r - (d_r - lam)|, and
+        //          z_r = 1, z_i = -(e_i / D+_i) z_{i+1} above r,
+        //          z_i = -(e_{i-1} / D-_i) z_{i-1} below r, solves
+        //          (T - lam I) z = gamma_r e_r.  Its error is that of one
+        //          inverse-iteration step from the best unit start vector,
+        //          rounding over the gap; one Cholesky QR pass restores
+        //          orthonormality to rounding.  Pivots that vanish are
+        //          replaced by eps |T|.
+        double* Dp = &S.A[0][0];
+        double* Dm = Dp + 16 * MAXP;
+        double* Rp = Dm + 16 * MAXP;
+        double* Rm = Rp + 16 * MAXP;
+        for (int kb = 0; kb < K; kb += 16) {
+            const int kk = kb + lane;
+            const int kend = kb + 16 < K ? kb + 16 : K;
+            if (lane < 16 && kk < K) {
+                const double lm = S.lam[kk];
+                double dp = S.de[0].x - lm, dm = S.de[n - 1].x - lm;
+                double rp = recip(dp != 0.0 ? dp : tiny), rm = recip(dm != 0.0 ? dm : tiny);
+                Dp[lane] = dp;
+                Rp[lane] = rp;
+                Dm[(n - 1) * 16 + lane] = dm;
+                Rm[(n - 1) * 16 + lane] = rm;
+                for (int i = 1; i < n; ++i) {
+                    const double2 a = S.de[i];
+                    const double ep = S.de[i - 1].y;
+                    const int ib = n - 1 - i;
+                    const double2 b = S.de[ib];
+                    dp = (a.x - lm) - ep * ep * rp;
+                    dm = (b.x - lm) - b.y * b.y * rm;
+                    rp = recip(dp != 0.0 ? dp : tiny);
+                    rm = recip(dm != 0.0 ? dm : tiny);
+                    Dp[i * 16 + lane] = dp;
+                    Rp[i * 16 + lane] = rp;
+                    Dm[ib * 16 + lane] = dm;
+                    Rm[ib * 16 + lane] = rm;
                 }
-                const double rl = recip(c1 != 0.0 ? c1 : tiny);
-                // back substitution, the next row fetched one step ahead
-                double x1 = 0.0, x2 = 0.0;
-                double f1 = rl, f2 = 0.0, f3 = 0.0, fb = cb;
-                for (int i = n - 1; i >= 0; --i) {
-                    double g1 = 0.0, g2 = 0.0, g3 = 0.0, gb = 0.0;
-                    if (i > 0) {
-                        g1 = U1[(i - 1) * 16 + lane];
-                        g2 = U2[(i - 1) * 16 + lane];
-                        g3 = U3[(i - 1) * 16 + lane];
-                        gb = Bv[(i - 1) * 16 + lane];
+                int r = 0;
+                double gbest = 1e300;
+                for (int i = 0; i < n; ++i) {
+                    const double gi = fabs(Dp[i * 16 + lane] + Dm[i * 16 + lane] - (S.de[i].x - lm));
+                    if (gi < gbest) {
+                        gbest = gi;
+                        r = i;
                     }
-                    const double v = (fb - f2 * x1 - f3 * x2) * f1;
-                    S.X[kk][i] = v;
-                    x2 = x1;
-                    x1 = v;
-                    f1 = g1;
-                    f2 = g2;
-                    f3 = g3;
-                    fb = gb;
                 }
+                S.X[kk][r] = 1.0;
+                double zu = 1.0, zd = 1.0, nrm = 1.0;
+                for (int st = 1; st < n; ++st) {
+                    const int iu = r - st, id = r + st;
+                    if (iu >= 0) {
+                        zu = -S.de[iu].y * Rp[iu * 16 + lane] * zu;
+                        S.X[kk][iu] = zu;
+                        nrm += zu * zu;
+                    }
+                    if (id < n) {
+                        zd = -S.de[id - 1].y * Rm[id * 16 + lane] * zd;
+                        S.X[kk][id] = zd;
+                        nrm += zd * zd;
+                    }
+                }
+                const double sc = 1.0 / sqrt(nrm);
+                for (int i = 0; i < n; ++i) S.X[kk][i] *= sc;
             }
             __syncthreads();
-            long long ts1 = 0;
-            if (stamp) ts1 = clock64();
-            // one Cholesky QR pass between sweeps, two after the last
-            orth_batch(S, n, kb, kend, it + 1 < INVIT_SWEEPS ? 1 : 2);
-            if (stamp && lane == 0) {
-                stamp[5] += ts1 - ts0;
-                stamp[6] += clock64() - ts1;
+            orth_batch(S, n, kb, kend, 1);
+        }
+    } else {
+        // ---- 3b. eigenvalues within 1e-8 |T| of each other: inverse
+        //         iteration in batches of 16 eigenvectors (lane =
+        //         eigenvector); the LU rows of T - lam I live in A's storage,
+        //         [i][lane], each pivot stored as its reciprocal
+        double* U1 = &S.A[0][0];
+        double* U2 = U1 + 16 * MAXP;
+        double* U3 = U2 + 16 * MAXP;
+        double* Bv = U3 + 16 * MAXP;
+        for (int kb = 0; kb < K; kb += 16) {
+            const int kk = kb + lane;
+            const bool mine = lane < 16 && kk < K;
+            const int kend = kb + 16 < K ? kb + 16 : K;
+            if (mine)
+                for (int i = 0; i < n; ++i) S.X[kk][i] = start_entry(i, kk);
+            for (int it = 0; it < INVIT_SWEEPS; ++it) {
+                long long ts0 = 0;
+                if (stamp) ts0 = clock64();
+                if (mine) {
+                    double sh = S.lam[kk];
+                    for (int j = 0; j < kk; ++j)
+                        if (fabs(sh - S.lam[j]) < 10.0 * tiny) sh = S.lam[j] - 10.0 * tiny * (kk - j);
+                    // forward elimination with partial pivoting, branch-free; the
+                    // current row (c1, c2) and right-hand side cb are carried in
+                    // registers and the next row's operands are fetched one step
+                    // ahead
+                    const double2 d0 = S.de[0];
+                    double c1 = d0.x - sh, c2 = d0.y, sub = d0.y;
+                    double cb = S.X[kk][0];
+                    double2 nxt = n > 1 ? S.de[1] : make_double2(0.0, 0.0);
+                    double rsub = S.re[0];
+                    double nb = n > 1 ? S.X[kk][1] : 0.0;
+                    for (int i = 0; i + 1 < n; ++i) {
+                        double2 nxt2 = make_double2(0.0, 0.0);
+                        double rsub2 = 0.0, nb2 = 0.0;
+                        if (i + 2 < n) {
+                            nxt2 = S.de[i + 2];
+                            rsub2 = S.re[i + 1];
+                            nb2 = S.X[kk][i + 2];
+                        }
+                        const double nd = nxt.x - sh, ne = nxt.y;
+                        const bool swap = fabs(sub) > fabs(c1);
+                        const double rp = recip(c1 != 0.0 ? c1 : tiny);
+                        const double mult = swap ? c1 * rsub : sub * rp;
+                        U1[i * 16 + lane] = swap ? rsub : rp;
+                        U2[i * 16 + lane] = swap ? nd : c2;
+                        U3[i * 16 + lane] = swap ? ne : 0.0;
+                        Bv[i * 16 + lane] = swap ? nb : cb;
+                        const double p1 = swap ? c2 : nd, q1 = swap ? nd : c2;
+                        const double pb = swap ? cb : nb, qb = swap ? nb : cb;
+                        c1 = p1 - mult * q1;
+                        c2 = swap ? -mult * ne : ne;
+                        cb = pb - mult * qb;
+                        sub = ne;
+                        nxt = nxt2;
+                        rsub = rsub2;
+                        nb = nb2;
+                    }
+                    const double rl = recip(c1 != 0.0 ? c1 : tiny);
+                    // back substitution, the next row fetched one step ahead
+                    double x1 = 0.0, x2 = 0.0;
+                    double f1 = rl, f2 = 0.0, f3 = 0.0, fb = cb;
+                    for (int i = n - 1; i >= 0; --i) {
+                        double g1 = 0.0, g2 = 0.0, g3 = 0.0, gb = 0.0;
+                        if (i > 0) {
+                            g1 = U1[(i - 1) * 16 + lane];
+                            g2 = U2[(i - 1) * 16 + lane];
+                            g3 = U3[(i - 1) * 16 + lane];
+                            gb = Bv[(i - 1) * 16 + lane];
+                        }
+                        const double v = (fb - f2 * x1 - f3 * x2) * f1;
+                        S.X[kk][i] = v;
+                        x2 = x1;
+                        x1 = v;
+                        f1 = g1;
+                        f2 = g2;
+                        f3 = g3;
+                        fb = gb;
+                    }
+                }
+                __syncthreads();
+                long long ts1 = 0;
+                if (stamp) ts1 = clock64();
+                // one Cholesky QR pass between sweeps, two after the last
+                orth_batch(S, n, kb, kend, it + 1 < INVIT_SWEEPS ? 1 : 2);
+                if (stamp && lane == 0) {
+                    stamp[5] += ts1 - ts0;
+                    stamp[6] += clock64() - ts1;
+                }
             }
         }
     }

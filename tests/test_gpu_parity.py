@@ -200,6 +200,31 @@ def test_gep_dense_subspace_fallback(m2n, ctx, orc):
     _gep_subspace_case(m2n, ctx, orc, s, 0.06, 35)
 
 
+@pytest.mark.parametrize("N,NW,K", [(1200, 4, 7), (1200, 5, 9), (2000, 6, 11)])
+def test_gep_lattice_dpss_clusters(m2n, ctx, orc, N, NW, K):
+    """Uniform sampling (the DPSS case): the top concentrations crowd
+    towards 1.  Smallest gaps 2.7e-8 (NW = 4, eigenvectors from twisted
+    factorisations), 7.3e-11 and 1.8e-13 (NW = 5, 6: inverse iteration).
+    Within such clusters single eigenvectors are ill-conditioned, so the
+    comparison is through the eigenvalues, the PSD of a series and
+    R(B)-orthonormality."""
+    t = np.arange(N, dtype=np.float64)
+    x = np.random.default_rng(N + NW).standard_normal(N)
+    fw, fmax, I = NW / N, 0.5, 4096
+    _say(f"gep dpss N={N} NW={NW} K={K}")
+    w_ref, lam_ref = orc.gpss_tapers(t, fmax, fw, K, method="lanczos")
+    w, lam = m2n.gpss_tapers(ctx, _dev(t), fmax, fw, K)
+    el = np.abs(lam.cpu().numpy() - lam_ref).max()
+    P = m2n.m2nufft_psd(ctx, _dev(t), _dev(x), w, None, fmax, fw, -0.5, 1.0 / I, I, prec=2,
+                        want_E=False)["P"].cpu().numpy()
+    P_ref = orc.psd(orc.nudft(t, x, w_ref, -0.5, 1.0 / I, I=I))
+    eP = psd_err(P, P_ref)
+    wn = w.cpu().numpy()
+    eG = np.abs(wn @ wn.T - 2 * fw * np.eye(K)).max()     # R(B) = 2 f_max I = I
+    _say(f"  lambda {el:.3e}  P {eP:.3e}  orthonormality {eG:.3e}")
+    assert el < 1e-12 and eP < 1e-10 and eG < 1e-12
+
+
 def test_gep_dense_medium(m2n, ctx, orc):
     s = W.jitter_stress(n=300, seed=42, K=5)
     _gep_case(m2n, ctx, orc, s.t, s.fmax, 2.5 / 300, 5)
