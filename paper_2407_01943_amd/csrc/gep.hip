@@ -212,43 +212,52 @@ __global__ __launch_bounds__(64) void k_gram_mfma(LrSeries d0, const LrSeries* D
 }
 
 // acc[i] = sum over the nwg partials of entry i, in a fixed order.  A
-// workgroup takes 64 entries; its four wavefronts sum interleaved groups
-// of eight partials with all eight loads in flight, then combine in LDS.
+// workgroup of NW wavefronts takes 64 entries; each wavefront sums
+// interleaved groups of U partials with all U loads in flight, then the
+// wavefronts combine in LDS.
+template <int NW, int U>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nwg, int len,
                                              double* __restrict__ acc, int blk) {
-    __shared__ double red[4][64];
+    __shared__ double red[NW][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blk * 64 + lane;
     const int ic = i < len ? i : len - 1;
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) s[u] = 0.0;
-    for (int g0 = 8 * wv; g0 < nwg; g0 += 32) {
-        double v[8];
+    for (int g0 = U * wv; g0 < nwg; g0 += U * NW) {
+        double v[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int g = g0 + u < nwg ? g0 + u : nwg - 1;
             v[u] = part[(int64_t)g * len + ic];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += g0 + u < nwg ? v[u] : 0.0;
+        for (int u = 0; u < U; ++u) s[u % 8] += g0 + u < nwg ? v[u] : 0.0;
     }
     red[wv][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
-    if (wv == 0 && i < len) acc[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (wv == 0 && i < len) {
+        static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
+        double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        if constexpr (NW == 8) t += (red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]);
+        acc[i] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nwg, int len,
                                                       double* __restrict__ acc) {
-    sum_partials(part, nwg, len, acc, blockIdx.x);
+    sum_partials<4, 8>(part, nwg, len, acc, blockIdx.x);
 }
 
 // the Gram matrix of each low-rank series from its partials
-__global__ __launch_bounds__(256) void k_gram_reduce(LrSeries d0, const LrSeries* D) {
+// (NW wavefronts with U loads each in flight: wide for many partials)
+template <int NW, int U>
+__global__ __launch_bounds__(64 * NW) void k_gram_reduce(LrSeries d0, const LrSeries* D) {
     const LrSeries d = lr_of(d0, D, blockIdx.y);
     const int len = d.pF * d.pF;
     if ((int)blockIdx.x * 64 >= len) return;
-    sum_partials(d.gpart, d.nred, len, d.G, blockIdx.x);
+    sum_partials<NW, U>(d.gpart, d.nred, len, d.G, blockIdx.x);
 }
 
 // ------------------------------------ top eigenpairs of a small symmetric
@@ -283,14 +292,6 @@ __device__ __forceinline__ double wsum_shfl(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ __forceinline__ double wmax(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wmin(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 // a double from lane l (l wave-uniform)
 __device__ __forceinline__ double rdlane(double v, int l) {
@@ -298,6 +299,38 @@ __device__ __forceinline__ double rdlane(double v, int l) {
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// a double moved across lanes by a DPP pattern; lanes without a source
+// keep their own value (neutral for max and min)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_keep(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+    const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double(((long long)rhi << 32) | (unsigned int)rlo);
+}
+
+// max and min over the 64 lanes with the DPP pattern of wsum (every lane
+// reaches lane 63 once), returned to every lane
+__device__ __forceinline__ double wmax(double v) {
+    v = fmax(v, dpp_keep<0xb1, 0xf>(v));
+    v = fmax(v, dpp_keep<0x4e, 0xf>(v));
+    v = fmax(v, dpp_keep<0x114, 0xf>(v));
+    v = fmax(v, dpp_keep<0x118, 0xf>(v));
+    v = fmax(v, dpp_keep<0x142, 0xa>(v));
+    v = fmax(v, dpp_keep<0x143, 0xc>(v));
+    return rdlane(v, 63);
+}
+__device__ __forceinline__ double wmin(double v) {
+    v = fmin(v, dpp_keep<0xb1, 0xf>(v));
+    v = fmin(v, dpp_keep<0x4e, 0xf>(v));
+    v = fmin(v, dpp_keep<0x114, 0xf>(v));
+    v = fmin(v, dpp_keep<0x118, 0xf>(v));
+    v = fmin(v, dpp_keep<0x142, 0xa>(v));
+    v = fmin(v, dpp_keep<0x143, 0xc>(v));
+    return rdlane(v, 63);
 }
 
 // two independent wave sums, interleaved
@@ -435,43 +468,79 @@ __device__ __forceinline__ void orth_batch(EigShared<LDA>& S, int n, int kb, int
 // Numbers of eigenvalues of the tridiagonal below s0 and below s1: sign
 // changes of p_i = (d_i - s) p_{i-1} - e_{i-1}^2 p_{i-2}, p_{-1} = 1,
 // p_{-2} = 0, with exact power-of-two rescaling every four steps.  dq[i] =
-// (d_i, e_{i-1}^2) for i < n8 (padding rows add no sign change).  Two
-// chains per lane hide the latency of the recurrence.
+// (d_i, e_{i-1}^2) for i < n4 (padding rows add no sign change).  Two
+// chains per lane hide the latency of the recurrence; a sign change is the
+// xor of consecutive sign bits.
 template <int NP>
-__device__ __forceinline__ void sturm_below2(const double2* dq, int n8, double s0, double s1,
+__device__ __forceinline__ void sturm_below2(const double2* dq, int n4, double s0, double s1,
                                              int& c0, int& c1) {
     double pp0 = 0.0, pc0 = 1.0, pp1 = 0.0, pc1 = 1.0;
-    unsigned n0 = 0, n1 = 0;
+    unsigned n0 = 0, n1 = 0, g0 = 0, g1 = 0;
 #pragma unroll
-    for (int j0 = 0; j0 < NP; j0 += 8) {
-        if (j0 < n8) {
-            double2 q[8];
+    for (int j0 = 0; j0 < NP; j0 += 4) {
+        if (j0 < n4) {
+            double2 q[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) q[u] = dq[j0 + u];
+            for (int u = 0; u < 4; ++u) q[u] = dq[j0 + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const double a0 = (q[u].x - s0) * pc0 - q[u].y * pp0;
                 const double a1 = (q[u].x - s1) * pc1 - q[u].y * pp1;
-                n0 += (unsigned)(__double2hiint(a0) ^ __double2hiint(pc0)) >> 31;
-                n1 += (unsigned)(__double2hiint(a1) ^ __double2hiint(pc1)) >> 31;
+                const unsigned h0 = (unsigned)__double2hiint(a0) >> 31;
+                const unsigned h1 = (unsigned)__double2hiint(a1) >> 31;
+                n0 += h0 ^ g0;
+                n1 += h1 ^ g1;
+                g0 = h0;
+                g1 = h1;
                 pp0 = pc0;
                 pc0 = a0;
                 pp1 = pc1;
                 pc1 = a1;
-                if ((u & 3) == 3) {
-                    const double m0 = fmax(fabs(pc0), fabs(pp0)), m1 = fmax(fabs(pc1), fabs(pp1));
-                    const double f0 = m0 > 0x1p+400 ? 0x1p-400 : (m0 < 0x1p-400 ? 0x1p+400 : 1.0);
-                    const double f1 = m1 > 0x1p+400 ? 0x1p-400 : (m1 < 0x1p-400 ? 0x1p+400 : 1.0);
-                    pc0 *= f0;
-                    pp0 *= f0;
-                    pc1 *= f1;
-                    pp1 *= f1;
-                }
             }
+            const double m0 = fmax(fabs(pc0), fabs(pp0)), m1 = fmax(fabs(pc1), fabs(pp1));
+            const double f0 = m0 > 0x1p+400 ? 0x1p-400 : (m0 < 0x1p-400 ? 0x1p+400 : 1.0);
+            const double f1 = m1 > 0x1p+400 ? 0x1p-400 : (m1 < 0x1p-400 ? 0x1p+400 : 1.0);
+            pc0 *= f0;
+            pp0 *= f0;
+            pc1 *= f1;
+            pp1 *= f1;
         }
     }
     c0 = (int)n0;
     c1 = (int)n1;
+}
+
+// max of mx and min of mn over aligned groups of g lanes (g a power of two):
+// quad permutes for partners 1 and 2, row shifts for 4 and 8 (the partner
+// lies on one side or the other within the row), lane shuffles beyond
+__device__ __forceinline__ void group_maxmin(double& mx, double& mn, int g) {
+    const int lane = threadIdx.x;
+    if (g > 1) {
+        mx = fmax(mx, dpp_d<0xb1, 0xf>(mx));
+        mn = fmin(mn, dpp_d<0xb1, 0xf>(mn));
+    }
+    if (g > 2) {
+        mx = fmax(mx, dpp_d<0x4e, 0xf>(mx));
+        mn = fmin(mn, dpp_d<0x4e, 0xf>(mn));
+    }
+    if (g > 4) {
+        const bool up = (lane & 4) != 0;
+        const double xa = dpp_d<0x104, 0xf>(mx), xb = dpp_d<0x114, 0xf>(mx);
+        const double na = dpp_d<0x104, 0xf>(mn), nb = dpp_d<0x114, 0xf>(mn);
+        mx = fmax(mx, up ? xb : xa);
+        mn = fmin(mn, up ? nb : na);
+    }
+    if (g > 8) {
+        const bool up = (lane & 8) != 0;
+        const double xa = dpp_d<0x108, 0xf>(mx), xb = dpp_d<0x118, 0xf>(mx);
+        const double na = dpp_d<0x108, 0xf>(mn), nb = dpp_d<0x118, 0xf>(mn);
+        mx = fmax(mx, up ? xb : xa);
+        mn = fmin(mn, up ? nb : na);
+    }
+    for (int o = 16; o < g; o <<= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+    }
 }
 
 // sweeps of inverse iteration: with shifts within a few ulps of |T| of the
@@ -662,7 +731,7 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         __syncthreads();
     }
     const int n = m;                   // order of the tridiagonal T_m
-    const int n8 = (n + 7) & ~7;
+    const int n4 = (n + 3) & ~3;
     if (stamp && lane == 0) stamp[1] = clock64();
     // ---- 2. eigenvalues by multisection: the K wanted ones and, when T_m
     //         has it, the next one (its distance to the K-th decides the
@@ -681,7 +750,7 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
     const double tnorm = fmax(fmax(fabs(glo), fabs(ghi)), 1e-300);
     {
         double2* dq = reinterpret_cast<double2*>(&S.A[0][0]);
-        if (lane < n8) {
+        if (lane < n4) {
             if (lane < n) {
                 const double ep = lane > 0 ? S.de[lane - 1].y : 0.0;
                 dq[lane] = make_double2(S.de[lane].x, lane > 0 ? fmax(ep * ep, 1e-200) : 0.0);
@@ -698,21 +767,19 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         const double tol = 1e-15 * tnorm;
         // invariant: count(l) <= idx < count(h)
         double l = glo - 2.0 * eps * tnorm, h = ghi + 2.0 * eps * tnorm;
+        const double rsec = 1.0 / (double)(2 * g + 1);
         for (int round = 0; round < 200; ++round) {
             if (__all(!live || h - l <= tol)) break;
-            const double st = (h - l) / (double)(2 * g + 1);
+            const double st = (h - l) * rsec;
             const double s0 = l + (double)(2 * sub + 1) * st, s1 = l + (double)(2 * sub + 2) * st;
             int c0, c1;
-            sturm_below2<NP>(dq, n8, s0, s1, c0, c1);
+            sturm_below2<NP>(dq, n4, s0, s1, c0, c1);
             double nl = l, nh = h;
             if (c0 > idx) nh = fmin(nh, s0);
             else nl = fmax(nl, s0);
             if (c1 > idx) nh = fmin(nh, s1);
             else nl = fmax(nl, s1);
-            for (int o = 1; o < g; o <<= 1) {
-                nl = fmax(nl, __shfl_xor(nl, o, 64));
-                nh = fmin(nh, __shfl_xor(nh, o, 64));
-            }
+            group_maxmin(nl, nh, g);
             if (h - l > tol) {
                 l = nl;
                 h = nh;
@@ -735,39 +802,54 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
         //          (T - lam I) z = gamma_r e_r.  Its error is that of one
         //          inverse-iteration step from the best unit start vector,
         //          rounding over the gap; one Cholesky QR pass restores
-        //          orthonormality to rounding.  Pivots that vanish are
-        //          replaced by eps |T|.
-        double* Dp = &S.A[0][0];
-        double* Dm = Dp + 16 * MAXP;
-        double* Rp = Dm + 16 * MAXP;
-        double* Rm = Rp + 16 * MAXP;
+        //          orthonormality to rounding and normalises (z is stored
+        //          unscaled).  Pivots that vanish are replaced by eps |T|.
+        //          The bisection values are kept as the eigenvalues (within
+        //          1e-15 |T|).
+        double* Fp = &S.A[0][0];         // -e_i / D+_i
+        double* Gm = Fp + 16 * MAXP;     // -e_{i-1} / D-_i
+        double* Dp = Gm + 16 * MAXP;     // D+_i
+        double* Dm = Dp + 16 * MAXP;     // D-_i
         for (int kb = 0; kb < K; kb += 16) {
             const int kk = kb + lane;
             const int kend = kb + 16 < K ? kb + 16 : K;
+            long long ts0 = 0;
+            if (stamp) ts0 = clock64();
             if (lane < 16 && kk < K) {
                 const double lm = S.lam[kk];
+                // forward (i) and backward (ib = n - 1 - i) pivots together,
+                // the next step's tridiagonal entries fetched one step ahead
                 double dp = S.de[0].x - lm, dm = S.de[n - 1].x - lm;
-                double rp = recip(dp != 0.0 ? dp : tiny), rm = recip(dm != 0.0 ? dm : tiny);
+                double ea = S.de[0].y;
+                double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+                if (n > 1) {
+                    a = S.de[1];
+                    b = S.de[n - 2];
+                }
                 Dp[lane] = dp;
-                Rp[lane] = rp;
                 Dm[(n - 1) * 16 + lane] = dm;
-                Rm[(n - 1) * 16 + lane] = rm;
                 for (int i = 1; i < n; ++i) {
-                    const double2 a = S.de[i];
-                    const double ep = S.de[i - 1].y;
                     const int ib = n - 1 - i;
-                    const double2 b = S.de[ib];
-                    dp = (a.x - lm) - ep * ep * rp;
+                    double2 a2 = make_double2(0.0, 0.0), b2 = make_double2(0.0, 0.0);
+                    if (i + 1 < n) {
+                        a2 = S.de[i + 1];
+                        b2 = S.de[ib - 1];
+                    }
+                    const double rp = recip(dp != 0.0 ? dp : tiny);
+                    const double rm = recip(dm != 0.0 ? dm : tiny);
+                    Fp[(i - 1) * 16 + lane] = -ea * rp;
+                    Gm[(ib + 1) * 16 + lane] = -b.y * rm;
+                    dp = (a.x - lm) - ea * ea * rp;
                     dm = (b.x - lm) - b.y * b.y * rm;
-                    rp = recip(dp != 0.0 ? dp : tiny);
-                    rm = recip(dm != 0.0 ? dm : tiny);
                     Dp[i * 16 + lane] = dp;
-                    Rp[i * 16 + lane] = rp;
                     Dm[ib * 16 + lane] = dm;
-                    Rm[ib * 16 + lane] = rm;
+                    ea = a.y;
+                    a = a2;
+                    b = b2;
                 }
                 int r = 0;
                 double gbest = 1e300;
+#pragma unroll 4
                 for (int i = 0; i < n; ++i) {
                     const double gi = fabs(Dp[i * 16 + lane] + Dm[i * 16 + lane] - (S.de[i].x - lm));
                     if (gi < gbest) {
@@ -776,25 +858,28 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
                     }
                 }
                 S.X[kk][r] = 1.0;
-                double zu = 1.0, zd = 1.0, nrm = 1.0;
+                double zu = 1.0, zd = 1.0;
+#pragma unroll 4
                 for (int st = 1; st < n; ++st) {
                     const int iu = r - st, id = r + st;
                     if (iu >= 0) {
-                        zu = -S.de[iu].y * Rp[iu * 16 + lane] * zu;
+                        zu *= Fp[iu * 16 + lane];
                         S.X[kk][iu] = zu;
-                        nrm += zu * zu;
                     }
                     if (id < n) {
-                        zd = -S.de[id - 1].y * Rm[id * 16 + lane] * zd;
+                        zd *= Gm[id * 16 + lane];
                         S.X[kk][id] = zd;
-                        nrm += zd * zd;
                     }
                 }
-                const double sc = 1.0 / sqrt(nrm);
-                for (int i = 0; i < n; ++i) S.X[kk][i] *= sc;
             }
             __syncthreads();
+            long long ts1 = 0;
+            if (stamp) ts1 = clock64();
             orth_batch(S, n, kb, kend, 1);
+            if (stamp && lane == 0) {
+                stamp[5] += ts1 - ts0;
+                stamp[6] += clock64() - ts1;
+            }
         }
     } else {
         // ---- 3b. eigenvalues within 1e-8 |T| of each other: inverse
@@ -887,31 +972,32 @@ __device__ __forceinline__ void sym_topk_wave(EigShared<LDA>& S, int n_in, int K
                 }
             }
         }
-    }
-    // eigenvalue = Rayleigh quotient of the tridiagonal on the final vector
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        double s[8];
-        const double2 dl = lane < n ? S.de[lane] : make_double2(0.0, 0.0);
-        const double em = (lane > 0 && lane < n) ? S.de[lane - 1].y : 0.0;
+        // eigenvalue = Rayleigh quotient of the tridiagonal on the final
+        // vector (the shifts of close eigenvalues were moved apart above)
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            double s[8];
+            const double2 dl = lane < n ? S.de[lane] : make_double2(0.0, 0.0);
+            const double em = (lane > 0 && lane < n) ? S.de[lane - 1].y : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u;
-            double tx = 0.0, xi = 0.0;
-            if (k < K && lane < n) {
-                xi = S.X[k][lane];
-                tx = dl.x * xi;
-                if (lane > 0) tx += em * S.X[k][lane - 1];
-                if (lane + 1 < n) tx += dl.y * S.X[k][lane + 1];
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u;
+                double tx = 0.0, xi = 0.0;
+                if (k < K && lane < n) {
+                    xi = S.X[k][lane];
+                    tx = dl.x * xi;
+                    if (lane > 0) tx += em * S.X[k][lane - 1];
+                    if (lane + 1 < n) tx += dl.y * S.X[k][lane + 1];
+                }
+                s[u] = xi * tx;
             }
-            s[u] = xi * tx;
-        }
-        wsum8(s);
-        __syncthreads();
+            wsum8(s);
+            __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (lane == 0 && k0 + u < K) S.lam[k0 + u] = s[u];
+            for (int u = 0; u < 8; ++u)
+                if (lane == 0 && k0 + u < K) S.lam[k0 + u] = s[u];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (stamp && lane == 0) stamp[3] = clock64();
     // ---- 4. Ritz vectors X = Q_m Y (lane = component), staged in A's storage
     {
@@ -2020,8 +2106,9 @@ int launch_gram_mfma(Ctx* ctx, hipStream_t st, int maxpF, int maxred, int ns, co
     }
     {
         M2N_PROF(ctx, st, "k_gram_reduce");
-        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((maxpF * maxpF + 63) / 64), (unsigned)ns),
-                           dim3(256), 0, st, d0, D);
+        const dim3 g((unsigned)((maxpF * maxpF + 63) / 64), (unsigned)ns);
+        if (maxred > 64) hipLaunchKernelGGL((k_gram_reduce<8, 16>), g, dim3(512), 0, st, d0, D);
+        else hipLaunchKernelGGL((k_gram_reduce<4, 8>), g, dim3(256), 0, st, d0, D);
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
