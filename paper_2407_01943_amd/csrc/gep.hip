@@ -212,33 +212,35 @@ __global__ __launch_bounds__(64) void k_gram_mfma(LrSeries d0, const LrSeries* D
 }
 
 // acc[i] = sum over the nwg partials of entry i, in a fixed order.  A
-// workgroup of NW wavefronts takes 64 entries; each wavefront sums
-// interleaved groups of U partials with all U loads in flight, then the
-// wavefronts combine in LDS.
+// workgroup takes 64 entries; its first NW wavefronts sum interleaved groups
+// of U partials with all U loads in flight, then combine in LDS (the order
+// depends only on NW, U and nwg; further wavefronts only join the barrier).
 template <int NW, int U>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nwg, int len,
                                              double* __restrict__ acc, int blk) {
+    static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
     __shared__ double red[NW][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blk * 64 + lane;
     const int ic = i < len ? i : len - 1;
-    double s[8];
+    if (wv < NW) {
+        double s[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = 0.0;
-    for (int g0 = U * wv; g0 < nwg; g0 += U * NW) {
-        double v[U];
+        for (int u = 0; u < 8; ++u) s[u] = 0.0;
+        for (int g0 = U * wv; g0 < nwg; g0 += U * NW) {
+            double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int g = g0 + u < nwg ? g0 + u : nwg - 1;
-            v[u] = part[(int64_t)g * len + ic];
+            for (int u = 0; u < U; ++u) {
+                const int g = g0 + u < nwg ? g0 + u : nwg - 1;
+                v[u] = part[(int64_t)g * len + ic];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s[u % 8] += g0 + u < nwg ? v[u] : 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) s[u % 8] += g0 + u < nwg ? v[u] : 0.0;
+        red[wv][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
-    red[wv][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     if (wv == 0 && i < len) {
-        static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
         double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
         if constexpr (NW == 8) t += (red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]);
         acc[i] = t;
@@ -250,14 +252,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     sum_partials<4, 8>(part, nwg, len, acc, blockIdx.x);
 }
 
-// the Gram matrix of each low-rank series from its partials
-// (NW wavefronts with U loads each in flight: wide for many partials)
-template <int NW, int U>
-__global__ __launch_bounds__(64 * NW) void k_gram_reduce(LrSeries d0, const LrSeries* D) {
+// the Gram matrix of each low-rank series from its partials; a series with
+// more than 64 partials sums them on eight wavefronts with sixteen loads in
+// flight each, otherwise on four with eight (the order depends only on the
+// series' own partials, not on the rest of a batch)
+__global__ __launch_bounds__(512) void k_gram_reduce(LrSeries d0, const LrSeries* D) {
     const LrSeries d = lr_of(d0, D, blockIdx.y);
     const int len = d.pF * d.pF;
     if ((int)blockIdx.x * 64 >= len) return;
-    sum_partials<NW, U>(d.gpart, d.nred, len, d.G, blockIdx.x);
+    if (d.nred > 64) sum_partials<8, 16>(d.gpart, d.nred, len, d.G, blockIdx.x);
+    else sum_partials<4, 8>(d.gpart, d.nred, len, d.G, blockIdx.x);
 }
 
 // ------------------------------------ top eigenpairs of a small symmetric
@@ -2106,9 +2110,8 @@ int launch_gram_mfma(Ctx* ctx, hipStream_t st, int maxpF, int maxred, int ns, co
     }
     {
         M2N_PROF(ctx, st, "k_gram_reduce");
-        const dim3 g((unsigned)((maxpF * maxpF + 63) / 64), (unsigned)ns);
-        if (maxred > 64) hipLaunchKernelGGL((k_gram_reduce<8, 16>), g, dim3(512), 0, st, d0, D);
-        else hipLaunchKernelGGL((k_gram_reduce<4, 8>), g, dim3(256), 0, st, d0, D);
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((maxpF * maxpF + 63) / 64), (unsigned)ns),
+                           dim3(512), 0, st, d0, D);
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;

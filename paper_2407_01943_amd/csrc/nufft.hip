@@ -399,22 +399,6 @@ constexpr int NT1 = 512;   // threads per pass-1 workgroup
 constexpr int MAXSEG = 8;  // column blocks a pass-1 workgroup gathers points from
 constexpr int NT2 = 512;   // threads per pass-2 workgroup
 
-// exp(-2 pi i q / nf) for 0 <= q < nf (nf a power of two: 2 q / nf is exact)
-template <typename R>
-__device__ __forceinline__ cplx<R> twiddle_nf(int q, R two_over_nf);
-template <>
-__device__ __forceinline__ cplx<float> twiddle_nf<float>(int q, float two_over_nf) {
-    float sn, cs;
-    sincospif((float)q * two_over_nf, &sn, &cs);
-    return {cs, -sn};
-}
-template <>
-__device__ __forceinline__ cplx<double> twiddle_nf<double>(int q, double two_over_nf) {
-    double sn, cs;
-    sincospi((double)q * two_over_nf, &sn, &cs);
-    return {cs, -sn};
-}
-
 // One point as the owners of a tile row read it: s is the grid column of the
 // point's first cell relative to the block's first column c0 (negative when
 // the support starts left of the block), so the owner of column cb takes tap
@@ -526,6 +510,16 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
         return j;
     };
     phase_stamp(a, 5);
+    // FP32: the length-N1 FFT twiddles are fetched now and stored to LDS
+    // after the spread, so that their latency overlaps the point loads (in
+    // FP64 the registers held across the spread cost more than they save)
+    static_assert(N1 <= 2 * NT1, "two twiddles per thread at most");
+    constexpr bool TW_EARLY = sizeof(R) == 4;
+    cplx<R> twp0 = {(R)0, (R)0}, twp1 = {(R)0, (R)0};
+    if constexpr (TW_EARLY) {
+        if ((int)threadIdx.x < N1) twp0 = tw_g[threadIdx.x * a.tws1];
+        if ((int)threadIdx.x + NT1 < N1) twp1 = tw_g[(threadIdx.x + NT1) * a.tws1];
+    }
     // Owner-computes spreading, chunk by chunk (one chunk holds CAP points,
     // normally the whole window): each chunk's points are counting-sorted by
     // the tile row they reach (integer LDS atomics), then every thread sums,
@@ -626,7 +620,12 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
             for (int q = 0; q < 8; ++q) tile[cb * LD + 8 * row + q] = acc[u];
         }
     }
-    for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
+    if constexpr (TW_EARLY) {
+        if ((int)threadIdx.x < N1) tw[threadIdx.x] = twp0;
+        if ((int)threadIdx.x + NT1 < N1) tw[threadIdx.x + NT1] = twp1;
+    } else {
+        for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
+    }
     __syncthreads();
     if (d.E && blk == 0 && threadIdx.x < 64) {
         // norms[k] = the binning workgroups' partial sums of w_k^2, in order
@@ -639,13 +638,30 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
     phase_stamp(a, 2);
     fft_lds<R, N1, B, NT1, LD>(tile, tw, 1, pruned);
     phase_stamp(a, 3);
-    // four-step twiddle exp(-2 pi i (c0 + cb) m1 / nf), then G[k][m1][l2]
-    const R two_nf = (R)2 / (R)nf;
+    // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, then
+    // G[k][m1][l2].  A thread keeps one column cb and steps m1 by S = NT1 / B,
+    // so its twiddle advances by the fixed factor exp(-2 pi i c S / nf): two
+    // sine-cosine pairs per thread and a complex product per element, all in
+    // FP64 (the product chain adds about IT ulps)
     cplx<R>* out = (cplx<R>*)d.inter + (int64_t)k * nf;
-    for (int e = threadIdx.x; e < B * N1; e += NT1) {
-        const int cb = e % B, m1 = e / B;
-        const cplx<R> twv = twiddle_nf<R>((c0 + cb) * m1, two_nf);
-        out[(int64_t)m1 * N2 + c0 + cb] = cmul(tile[cb * LD + m1], twv);
+    {
+        constexpr int S = NT1 / B, IT = B * N1 / NT1;
+        const int cb = threadIdx.x % B, m0 = threadIdx.x / B;
+        const int c = c0 + cb;
+        const double two_nf = 2.0 / (double)nf;
+        const double xt = (double)((c * m0) & (nf - 1)) * two_nf;
+        const double xr = (double)((c * S) & (nf - 1)) * two_nf;
+        double tr = cospi(xt), ti = -sinpi(xt);
+        const double fr = cospi(xr), fi = -sinpi(xr);
+#pragma unroll 4
+        for (int it = 0; it < IT; ++it) {
+            const int m1 = m0 + it * S;
+            const cplx<R> twv = {(R)tr, (R)ti};
+            out[(int64_t)m1 * N2 + c] = cmul(tile[cb * LD + m1], twv);
+            const double nr = tr * fr - ti * fi;
+            ti = tr * fi + ti * fr;
+            tr = nr;
+        }
     }
     phase_stamp(a, 4);
     wg_stamp(a, 1024, 1);
