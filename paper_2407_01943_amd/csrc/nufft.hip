@@ -137,6 +137,18 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gp(const T
     return (const __attribute__((address_space(1))) T*)p;
 }
 
+// inclusive scan over the 64 lanes with DPP: row shifts by 1, 2, 4 and 8
+// within rows of 16, then each row total broadcast into the following rows
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -298,11 +310,7 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
         for (int c0 = 0; c0 < nbins; c0 += 64) {
             const int b = c0 + tid;
             int v = b < nbins ? tot[b] : 0;
-            int incl = v;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(incl, o, 64);
-                if (tid >= o) incl += u;
-            }
+            const int incl = wave_incl_scan(v);
             if (b < nbins) tot[b] = carry + incl - v;
             carry += __shfl(incl, 63, 64);
         }
@@ -423,11 +431,7 @@ __device__ __forceinline__ void scan_counts(int* cnt, int* wtot) {
         v[q] = i < N ? cnt[i] : 0;
         sum += v[q];
     }
-    int incl = sum;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += u;
-    }
+    const int incl = wave_incl_scan(sum);
     if (lane == 63) wtot[wv] = incl;
     __syncthreads();
     int run = incl - sum;
@@ -586,11 +590,17 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
             }
         }
         __syncthreads();
+        // rows past the largest one any point reaches are empty (a test
+        // uniform over the wavefront); the point loop is unrolled so that
+        // its LDS reads overlap
+        const int maxrow = s_maxrow;
 #pragma unroll
         for (int u = 0; u < TASKS; ++u) {
+            if ((u * (NT1 / 64) + wv) * G > maxrow) continue;
             const int row = (u * (NT1 / 64) + wv) * G + rsub;
             const int beg = rows[row];
             const int end = min(rows[row + 1], CAP);
+#pragma unroll 4
             for (int i = beg; i < end; ++i) {
                 const SpreadRec<R> rc = list[i];
                 const int r = cb - rc.s;
