@@ -403,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
 }
 
 // -------------------------------------------------------------- pass 1
-constexpr int NT1 = 512;   // threads per pass-1 workgroup
+constexpr int NT1 = 256;   // threads per pass-1 workgroup
 constexpr int MAXSEG = 8;  // column blocks a pass-1 workgroup gathers points from
 constexpr int NT2 = 512;   // threads per pass-2 workgroup
 
@@ -447,7 +447,7 @@ __device__ __forceinline__ void scan_counts(int* cnt, int* wtot) {
 }
 
 template <typename R, int N1, int B>
-// FP32: four waves per SIMD (two workgroups per compute unit)
+// FP32: four waves per SIMD (four workgroups of four waves per compute unit)
 __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     const int nblk = a.N2 / B;
@@ -517,12 +517,15 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
     // FP32: the length-N1 FFT twiddles are fetched now and stored to LDS
     // after the spread, so that their latency overlaps the point loads (in
     // FP64 the registers held across the spread cost more than they save)
-    static_assert(N1 <= 2 * NT1, "two twiddles per thread at most");
     constexpr bool TW_EARLY = sizeof(R) == 4;
-    cplx<R> twp0 = {(R)0, (R)0}, twp1 = {(R)0, (R)0};
+    constexpr int TWP = (N1 + NT1 - 1) / NT1;
+    cplx<R> twp[TWP];
     if constexpr (TW_EARLY) {
-        if ((int)threadIdx.x < N1) twp0 = tw_g[threadIdx.x * a.tws1];
-        if ((int)threadIdx.x + NT1 < N1) twp1 = tw_g[(threadIdx.x + NT1) * a.tws1];
+#pragma unroll
+        for (int q = 0; q < TWP; ++q) {
+            const int j = threadIdx.x + q * NT1;
+            twp[q] = j < N1 ? tw_g[j * a.tws1] : cplx<R>{(R)0, (R)0};
+        }
     }
     // Owner-computes spreading, chunk by chunk (one chunk holds CAP points,
     // normally the whole window): each chunk's points are counting-sorted by
@@ -631,8 +634,11 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a,
         }
     }
     if constexpr (TW_EARLY) {
-        if ((int)threadIdx.x < N1) tw[threadIdx.x] = twp0;
-        if ((int)threadIdx.x + NT1 < N1) tw[threadIdx.x + NT1] = twp1;
+#pragma unroll
+        for (int q = 0; q < TWP; ++q) {
+            const int j = threadIdx.x + q * NT1;
+            if (j < N1) tw[j] = twp[q];
+        }
     } else {
         for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     }
@@ -942,9 +948,13 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
             set_error("band count too large for this build (nf = %d)", p.nf);
             return M2N_ERR_UNSUPPORTED;
         }
-        p.B = 65536 / (p.N1 * cs);
+        // pass 1: B columns of N1 values per workgroup, a 32 KB tile (four
+        // workgroups per compute unit; narrow blocks waste fewer lanes of
+        // the spread, whose points cover w of the B columns), B >= 4
+        p.B = 32768 / (p.N1 * cs);
         if (p.B > 32) p.B = 32;
         if (p.B > p.N2 / 2) p.B = p.N2 / 2;
+        if (p.B < 4) p.B = 4;
         p.lookback = (p.w - 1 + p.B - 1) / p.B;
         if (p.lookback >= p.N2 / p.B || p.N2 / p.B > MAX_BINS || p.lookback + 1 > MAXSEG) {
             set_error("unsupported grid split (N2 = %d, B = %d, w = %d)", p.N2, p.B, p.w);
@@ -1080,9 +1090,9 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a,
         return M2N_OK;                                                                     \
     }
     if constexpr (sizeof(R) == 4) {
-        M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 32) M2N_P1(512, 16) M2N_P1(1024, 8)
-    } else {
         M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 16) M2N_P1(512, 8) M2N_P1(1024, 4)
+    } else {
+        M2N_P1(64, 32) M2N_P1(128, 16) M2N_P1(256, 8) M2N_P1(512, 4) M2N_P1(1024, 4)
     }
 #undef M2N_P1
     set_error("no pass-1 kernel for N1 = %d, B = %d", p.N1, p.B);
