@@ -158,6 +158,28 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// a double moved across lanes by a DPP pattern (both halves); lanes whose
+// source is out of range or whose row is masked off receive 0
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_dbl(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 64 lanes in a fixed order (quad permutes, row shifts, row
+// broadcasts); the total lands in lane 63
+__device__ __forceinline__ double wave_sum_to63(double v) {
+    v += dpp_dbl<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_dbl<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_dbl<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_dbl<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_dbl<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_dbl<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // block-wide sum for NT threads; every thread gets the result
 __device__ __forceinline__ double block_sum(double v, double* scratch /* >= NT/64 */) {
     v = wave_sum(v);
@@ -272,29 +294,55 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     __shared__ int s_int, s_bad;
     const int tid = threadIdx.x;
     const int nwg = d.nwg, nbins = a.nbins;
-    const bool staged = (int64_t)nwg * nbins <= SCAN_LDS;
+    // staged: the counts held bin-major, cnt[b * nwgp + g], with an odd row
+    // length so that both the wavefront reads along g and the strided
+    // writes are free of bank conflicts
+    const int nwgp = nwg | 1;
+    const bool staged = (int64_t)nwgp * nbins <= SCAN_LDS;
     if (tid == 0) {
         s_int = 1;
         s_bad = 0;
     }
-    if (staged)
-        for (int e = tid; e < nwg * nbins; e += blockDim.x) cnt[e] = d.hist[e];
-    __syncthreads();
-    for (int b = tid; b < nbins; b += blockDim.x) {
-        int s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        int g = 0;
-        if (staged) {
-            for (; g + 3 < nwg; g += 4) {
-                s0 += cnt[g * nbins + b];
-                s1 += cnt[(g + 1) * nbins + b];
-                s2 += cnt[(g + 2) * nbins + b];
-                s3 += cnt[(g + 3) * nbins + b];
-            }
-            for (; g < nwg; ++g) s0 += cnt[g * nbins + b];
-        } else {
-            for (; g < nwg; ++g) s0 += d.hist[(int64_t)g * nbins + b];
+    if (staged) {
+        // all of a thread's loads in flight at once (blockDim.x = 1024)
+        constexpr int SU = SCAN_LDS / 1024;
+        int v[SU];
+#pragma unroll
+        for (int i = 0; i < SU; ++i) {
+            const int e = tid + i * 1024;
+            v[i] = e < nwg * nbins ? d.hist[e] : 0;
         }
-        tot[b] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+        for (int i = 0; i < SU; ++i) {
+            const int e = tid + i * 1024;
+            if (e < nwg * nbins) {
+                const int g = e / nbins, b = e - g * nbins;
+                cnt[b * nwgp + g] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (staged) {
+        // per bin, the exclusive scan along the workgroups (one wavefront per
+        // bin, 64 workgroups per step); tot[b] = the bin's total
+        const int lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
+        for (int b = wv; b < nbins; b += nw) {
+            int carry = 0;
+            for (int g0 = 0; g0 < nwg; g0 += 64) {
+                const int g = g0 + lane;
+                const int c = g < nwg ? cnt[b * nwgp + g] : 0;
+                const int incl = wave_incl_scan(c);
+                if (g < nwg) cnt[b * nwgp + g] = carry + incl - c;
+                carry += __builtin_amdgcn_readlane(incl, 63);
+            }
+            if (lane == 0) tot[b] = carry;
+        }
+    } else {
+        for (int b = tid; b < nbins; b += blockDim.x) {
+            int s0 = 0;
+            for (int g = 0; g < nwg; ++g) s0 += d.hist[(int64_t)g * nbins + b];
+            tot[b] = s0;
+        }
     }
     int li = 1, lb = 0;
     for (int g = tid; g < nwg; g += blockDim.x) {
@@ -318,37 +366,21 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     }
     __syncthreads();
     for (int b = tid; b <= nbins; b += blockDim.x) d.binoff[b] = tot[b];
-    for (int b = tid; b < nbins; b += blockDim.x) {
-        int run = tot[b];
-        int g = 0;
-        if (staged) {
-            // eight counts in flight, then the running sum
-            for (; g + 7 < nwg; g += 8) {
-                int c[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) c[u] = cnt[(g + u) * nbins + b];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    cnt[(g + u) * nbins + b] = run;
-                    run += c[u];
-                }
-            }
-            for (; g < nwg; ++g) {
-                const int c = cnt[g * nbins + b];
-                cnt[g * nbins + b] = run;
-                run += c;
-            }
-        } else {
-            for (; g < nwg; ++g) {
+    if (staged) {
+        for (int e = tid; e < nwg * nbins; e += blockDim.x) {
+            const int g = e / nbins, b = e - g * nbins;
+            d.off[e] = tot[b] + cnt[b * nwgp + g];
+        }
+    } else {
+        for (int b = tid; b < nbins; b += blockDim.x) {
+            int run = tot[b];
+            for (int g = 0; g < nwg; ++g) {
                 const int c = d.hist[(int64_t)g * nbins + b];
                 d.off[(int64_t)g * nbins + b] = run;
                 run += c;
             }
         }
     }
-    __syncthreads();
-    if (staged)
-        for (int e = tid; e < nwg * nbins; e += blockDim.x) d.off[e] = cnt[e];
     if (tid == 0) {
         const double c = 2.0 * d.fmax;
         const int dg = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
@@ -372,6 +404,13 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
     R* dels = (R*)d.dels;
     cplx<R>* cw = (cplx<R>*)d.cw;
     const int64_t n0 = (int64_t)wg * d.ppw;
+    // with Ê and at most KR tapers, this workgroup's share of
+    // sum_n w_k(t_n)^2 is accumulated while the tapers are read
+    constexpr int KR = 16;
+    const bool fuse = d.E && d.K <= KR;
+    double sq[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) sq[k] = 0.0;
     for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= d.N) break;
@@ -380,12 +419,41 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
         const int pos = d.off[(int64_t)wg * a.nbins + bin] + atomicAdd(&cur[bin], 1);
         d.l0s[pos] = g.l0;
         dels[pos] = (R)g.del;
-        for (int k = 0; k < d.K; ++k) {
-            const double wv = d.w[(int64_t)k * d.N + n];
-            cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
+        if (fuse) {
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                if (k < d.K) {
+                    const double wv = d.w[(int64_t)k * d.N + n];
+                    cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
+                    sq[k] += wv * wv;
+                }
+            }
+        } else {
+            for (int k = 0; k < d.K; ++k) {
+                const double wv = d.w[(int64_t)k * d.N + n];
+                cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
+            }
         }
     }
-    if (d.E) {
+    if (fuse) {
+        // wavefront sums, then the wavefronts in order
+        __shared__ double redk[NT / 64][KR];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            if (k < d.K) {
+                const double v = wave_sum_to63(sq[k]);
+                if (lane == 63) redk[wv][k] = v;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < d.K) {
+            double v = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / 64; ++i) v += redk[i][threadIdx.x];
+            d.nrm[(int64_t)wg * d.K + threadIdx.x] = v;
+        }
+    } else if (d.E) {
         // this workgroup's share of sum_n w_k(t_n)^2, summed in a fixed order
         __shared__ double red[NT / 64];
         for (int k = 0; k < d.K; ++k) {
@@ -447,8 +515,9 @@ __device__ __forceinline__ void scan_counts(int* cnt, int* wtot) {
 }
 
 template <typename R, int N1, int B>
-// FP32: four waves per SIMD (four workgroups of four waves per compute unit)
-__global__ __launch_bounds__(NT1, sizeof(R) == 4 ? 4 : 1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
+// FP32: four waves per SIMD (four workgroups of four waves per compute unit),
+// two for the longest columns (N1 = 1024: 64 KB tiles, two per compute unit)
+__global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void k_pass1(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     const int nblk = a.N2 / B;
     const int blk = blockIdx.x % nblk;
@@ -950,10 +1019,13 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
         }
         // pass 1: B columns of N1 values per workgroup, a 32 KB tile (four
         // workgroups per compute unit; narrow blocks waste fewer lanes of
-        // the spread, whose points cover w of the B columns), B >= 4
+        // the spread, whose points cover w of the B columns).  B >= 8 in
+        // FP32 and >= 4 in FP64: narrower blocks multiply the bins of the
+        // counting sort (measured slower at N1 = 1024)
         p.B = 32768 / (p.N1 * cs);
         if (p.B > 32) p.B = 32;
         if (p.B > p.N2 / 2) p.B = p.N2 / 2;
+        if (p.B < 8 && sizeof(R) == 4) p.B = 8;
         if (p.B < 4) p.B = 4;
         p.lookback = (p.w - 1 + p.B - 1) / p.B;
         if (p.lookback >= p.N2 / p.B || p.N2 / p.B > MAX_BINS || p.lookback + 1 > MAXSEG) {
@@ -1090,7 +1162,7 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a,
         return M2N_OK;                                                                     \
     }
     if constexpr (sizeof(R) == 4) {
-        M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 16) M2N_P1(512, 8) M2N_P1(1024, 4)
+        M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 16) M2N_P1(512, 8) M2N_P1(1024, 8)
     } else {
         M2N_P1(64, 32) M2N_P1(128, 16) M2N_P1(256, 8) M2N_P1(512, 4) M2N_P1(1024, 4)
     }
