@@ -10,6 +10,8 @@ adds the two one-line steps that are clearer in numpy:
 
 * ``psd``: P(A_i) = sum_k d_k |J_k(A_i)|^2 with d_k = 1/K (Sec. 3.2, the
   estimator of the integrated spectrum; Table 3 step 5);
+* ``ftest``, ``f_critical``: the Thomson F-statistic from the eigencoefficients
+  and the critical value of F(2, 2K-2) (Sec. 3.4);
 * ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order.
 
 Parity pins: tests/test_oracle_pins.py.  Readings where the paper is silent
@@ -201,6 +203,37 @@ def psd(J, weights=None):
     K = J.shape[0]
     d = np.full(K, 1.0 / K) if weights is None else np.asarray(weights, dtype=np.float64)
     return (d[:, None] * np.abs(J) ** 2).sum(axis=0)
+
+
+def ftest(J, w):
+    """Thomson F-statistic of every band (Sec. 3.4, "Thomson F-test for
+    Nonuniform Signal", Eq. (f_stat) and the amplitude estimate after it):
+        W_k(0) = sum_n w_k(t_n)               (the tapers' DC gains),
+        C_i    = sum_k J_k(i) W_k(0) / sum_k W_k(0)^2,
+        F_i    = |C_i|^2 (K - 1) sum_k W_k(0)^2 / sum_k |J_k(i) - C_i W_k(0)|^2.
+    J: K x nb complex eigencoefficients, w: K x N real tapers.  Returns
+    (F, C).  A band whose eigencoefficients are exactly proportional to
+    W(0) has a zero denominator and F = inf."""
+    J = np.asarray(J, dtype=np.complex128)
+    w = np.asarray(w, dtype=np.float64)
+    K = J.shape[0]
+    W0 = w.sum(axis=1)
+    sww = float((W0 ** 2).sum())
+    C = (J * W0[:, None]).sum(axis=0) / sww
+    num = np.abs(C) ** 2 * (K - 1) * sww
+    den = (np.abs(J - C[None, :] * W0[:, None]) ** 2).sum(axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = np.where(den > 0.0, num / np.where(den > 0.0, den, 1.0), np.inf)
+    return F, C
+
+
+def f_critical(p, K):
+    """Critical value of F(2, 2K - 2) at upper-tail probability p (Sec. 3.4:
+    F_s follows F(2, 2K-2); the level is chosen as p, for instance the
+    Rayleigh level 1/N).  With nu = 2K - 2 the upper tail of F(2, nu) is
+    (1 + 2 F / nu)^(-nu / 2), so F_p = (nu / 2)(p^(-2 / nu) - 1)."""
+    nu = 2.0 * K - 2.0
+    return 0.5 * nu * (float(p) ** (-2.0 / nu) - 1.0)
 
 
 def ehat(t, w, lam, fmax, fw, f_lo, df, I=None, bands=None):

@@ -335,3 +335,110 @@ def test_sinusoid_peak_band(orc):
     top = np.argmax(out["P"])
     fc = s.f_lo + top * s.df
     assert abs(abs(fc) - 0.05) <= s.fw
+
+
+# --------------------------------------------------------------------------
+# Thomson F-test (Sec. 3.4)
+# --------------------------------------------------------------------------
+def _ftest_levels():
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "ftest_levels.txt")
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                p, K = line.split()[:2]
+                rows.append((float(p), int(K)))
+    return rows
+
+
+def test_f_critical_matches_inverse_f_distribution(orc):
+    # the paper's levels (p = 0.05, 0.01, 1/240, 1/688; F(2, 10)) against the
+    # library's inverse survival function of the F distribution
+    import scipy.stats as ss
+    rows = _ftest_levels()
+    assert len(rows) == 4
+    for p, K in rows:
+        Fp = orc.f_critical(p, K)
+        assert abs(Fp - ss.f.isf(p, 2, 2 * K - 2)) < 1e-9 * Fp
+        assert abs(ss.f.sf(Fp, 2, 2 * K - 2) - p) < 1e-12
+    # ordering of the paper's three lines: 0.05 < 0.01 < Rayleigh level
+    vals = [orc.f_critical(p, K) for p, K in rows]
+    assert vals[0] < vals[1] < vals[2] < vals[3]
+
+
+def test_ftest_amplitude_and_residual_are_least_squares(orc):
+    # C_i is the least-squares amplitude of J_k(i) ~ C W_k(0), and the
+    # denominator of F is that fit's residual: checked with lstsq per band
+    rng = np.random.default_rng(91)
+    K, N, nb = 6, 40, 17
+    w = rng.standard_normal((K, N))
+    J = rng.standard_normal((K, nb)) + 1j * rng.standard_normal((K, nb))
+    F, C = orc.ftest(J, w)
+    W0 = w.sum(axis=1).astype(np.complex128)
+    for i in range(nb):
+        c, res, _, _ = np.linalg.lstsq(W0[:, None], J[:, i], rcond=None)
+        assert abs(C[i] - c[0]) < 1e-12 * max(1.0, abs(c[0]))
+        ref = abs(c[0]) ** 2 * (K - 1) * np.real(np.vdot(W0, W0)) / res[0]
+        assert abs(F[i] - ref) < 1e-10 * ref
+
+
+def test_ftest_exact_line_and_scale_invariance(orc):
+    rng = np.random.default_rng(92)
+    K, N = 5, 30
+    w = rng.standard_normal((K, N))
+    W0 = w.sum(axis=1)
+    J = np.outer(W0, [1.5 - 0.5j, -2.0 + 0.25j])    # exactly proportional to W(0)
+    F, C = orc.ftest(J, w)
+    assert np.all(F > 1e25)                          # residual at rounding level (or exactly 0: inf)
+    assert np.allclose(C, [1.5 - 0.5j, -2.0 + 0.25j], rtol=1e-14, atol=0)
+    Jn = rng.standard_normal((K, 9)) + 1j * rng.standard_normal((K, 9))
+    F1, _ = orc.ftest(Jn, w)
+    F2, _ = orc.ftest((3.0 - 4.0j) * Jn, 7.0 * w)   # a complex gain and a taper scale
+    assert np.allclose(F1, F2, rtol=1e-12, atol=0)
+
+
+def test_ftest_detects_a_line_on_the_lattice(orc):
+    # a sinusoid on a band centre in white noise: its band is the largest F
+    # and exceeds the Rayleigh level 1/N
+    N, K, NW = 600, 6, 3.5
+    t = np.arange(N, dtype=np.float64)
+    fw = NW / N
+    w, _ = orc.gpss_tapers(t, 0.5, fw, K)
+    I = 1200
+    f_lo, df = -0.5, 1.0 / I
+    i0 = 900                                          # f = 0.25
+    rng = np.random.default_rng(93)
+    x = rng.standard_normal(N) + 0.6 * np.cos(2 * np.pi * (f_lo + i0 * df) * t + 0.3)
+    bands = np.arange(620, 1180, dtype=np.int64)      # f in (0.017, 0.483): 2 f > f_w
+    F, _ = orc.ftest(orc.nudft(t, x, w, f_lo, df, bands=bands), w)
+    assert bands[np.argmax(F)] == i0
+    assert F.max() > orc.f_critical(1.0 / N, K)
+
+
+def test_ftest_null_distribution(orc):
+    # white Gaussian noise: F ~ F(2, 2K-2) (Sec. 3.4).  Bands 4 f_w apart
+    # are nearly independent; the exceedance rate at p = 0.05 and the mean
+    # nu / (nu - 2) are checked against binomial and sampling errors
+    N, K, NW = 512, 6, 3.5
+    t = np.arange(N, dtype=np.float64)
+    fw = NW / N
+    w, _ = orc.gpss_tapers(t, 0.5, fw, K)
+    I = N
+    f_lo, df = -0.5, 1.0 / I
+    step = int(math.ceil(4 * fw / df))
+    bands = np.arange(N // 2 + step, N - step, step, dtype=np.int64)   # 0 < f < 1/2
+    rng = np.random.default_rng(94)
+    Fs = []
+    for _ in range(80):
+        x = rng.standard_normal(N)
+        Fs.append(orc.ftest(orc.nudft(t, x, w, f_lo, df, bands=bands), w)[0])
+    Fs = np.concatenate(Fs)
+    n = Fs.size
+    rate = np.mean(Fs > orc.f_critical(0.05, K))
+    assert abs(rate - 0.05) < 4 * math.sqrt(0.05 * 0.95 / n)
+    nu = 2 * K - 2
+    mean_ref = nu / (nu - 2)
+    sd_ref = math.sqrt(2 * nu ** 2 * (2 + nu - 2) / (2 * (nu - 2) ** 2 * (nu - 4)))
+    assert abs(Fs.mean() - mean_ref) < 4 * sd_ref / math.sqrt(n)
