@@ -501,6 +501,22 @@ def main():
     ms_nufft = e0.elapsed_time(e1) / reps
     print(f"bench: step {ms_step:.3f} ms, nufft {ms_nufft:.4f} ms", file=sys.stderr, flush=True)
 
+    # ---- the same with the Thomson F-statistic fused into the average
+    Fb = torch.empty((I,), dtype=rdt, device=dev)
+
+    def nufft_ftest():
+        m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, I, prec=prec,
+                        want_E=True, out=(P, E, None, Fb), check=False)
+
+    nufft_ftest()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        nufft_ftest()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_nufft_f = e0.elapsed_time(e1) / reps
+
     # ---- timed pass 2: per-kernel HIP events inside the library
     ctx.profile_reset()
     ctx.profile(True)
@@ -618,6 +634,9 @@ def main():
         "psds_per_s": round(1e3 / ms_step, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "ftest": {"nufft_ms_with_F": round(ms_nufft_f, 5),
+                  "extra_ms": round(ms_nufft_f - ms_nufft, 5),
+                  "note": "Thomson F-statistic fused into the band average (pass 2)"},
         "nufft_only": {"ms": round(ms_nufft, 5),
                        "value": round(N * K * I / (ms_nufft * 1e-3) / 1e6, 1)},
         "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},

@@ -138,6 +138,15 @@ int m2nufft_eigcoeffs(m2n_ctx *ctx, void *stream, const double *t,
  *                   of the identity (t on a lattice of spacing beta with
  *                   2 f_max beta a positive integer), else M2N_ERR_UNSUPPORTED
  *   J       [K*I]   device out or NULL, as in m2nufft_eigcoeffs
+ *   F       [I]     device out or NULL (same type as P): the Thomson
+ *                   F-statistic of every band (Sec. 3.4), with the tapers'
+ *                   DC gains W_k(0) = sum_n w_k(t_n) and C_i = sum_k J_k(i)
+ *                   W_k(0) / sum_k W_k(0)^2:
+ *                     F_i = |C_i|^2 (K-1) sum_k W_k(0)^2
+ *                           / sum_k |J_k(i) - C_i W_k(0)|^2,
+ *                   F(2, 2K-2) distributed for noise; needs K >= 2
+ *                   (M2N_ERR_ARG otherwise).  +inf where the residual
+ *                   vanishes.
  *
  * Stream-ordered and asynchronous once the plan exists.
  */
@@ -145,7 +154,7 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                 int64_t N, const double *w, const double *lambda, int K,
                 double fmax, double fw, double f_lo, double df, int64_t I,
                 int prec, double nufft_tol, const double *weights, void *P,
-                void *E, void *J);
+                void *E, void *J, void *F);
 
 /*
  * m2n_batch_psd -- gpss_tapers followed by m2nufft_psd for many series, in
@@ -158,7 +167,8 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
  *   series  [nseries] HOST array of descriptors; every pointer inside is a
  *           device pointer with the layout of the per-series calls:
  *             t, x [N]; w [K*N] out; lambda [K] out; weights [K] or NULL;
- *             P [I] out; E [I] out or NULL; J [K*I] out or NULL
+ *             P [I] out; E [I] out or NULL; J [K*I] out or NULL;
+ *             F [I] out or NULL (the F-statistic, as in m2nufft_psd)
  *   prec, nufft_tol as in m2nufft_psd (one value for the whole batch)
  *
  * Errors name the offending series in m2n_last_error().  Stream-ordered
@@ -175,6 +185,7 @@ typedef struct {
     const double *weights;
     double *w, *lambda;
     void *P, *E, *J;
+    void *F;
 } m2n_series;
 
 int m2n_batch_psd(m2n_ctx *ctx, void *stream, const m2n_series *series, int nseries,

@@ -49,7 +49,7 @@ class M2NSeries(ctypes.Structure):
                 ("f_lo", ctypes.c_double), ("df", ctypes.c_double), ("I", ctypes.c_int64),
                 ("weights", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("lam", ctypes.c_void_p), ("P", ctypes.c_void_p), ("E", ctypes.c_void_p),
-                ("J", ctypes.c_void_p)]
+                ("J", ctypes.c_void_p), ("F", ctypes.c_void_p)]
 
 
 class M2NQueueCfg(ctypes.Structure):
@@ -104,7 +104,7 @@ def _load():
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
     L.m2nufft_eigcoeffs.restype = i
     L.m2nufft_psd.argtypes = [vp, vp, vp, vp, i64, vp, vp, i, d, d, d, d, i64, i, d,
-                              vp, vp, vp, vp]
+                              vp, vp, vp, vp, vp]
     L.m2nufft_psd.restype = i
     L.m2n_batch_psd.argtypes = [vp, vp, ctypes.POINTER(M2NSeries), i, i, d]
     L.m2n_batch_psd.restype = i
@@ -220,9 +220,11 @@ def m2nufft_eigcoeffs(ctx: Context, t, x, w, f_lo, df, I, prec=M2N_FP64, nufft_t
 
 def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64,
                 nufft_tol=0.0, weights=None, want_E=True, want_J=False, stream=None,
-                out=None, check=True):
-    """Table 3 steps 4-5 fused, plus the Appendix B suboptimality estimate.
-    Returns {"P": [I], "E": [I] or None, "J": [K, I] or None}."""
+                out=None, check=True, want_F=False):
+    """Table 3 steps 4-5 fused, plus the Appendix B suboptimality estimate and,
+    with want_F, the Thomson F-statistic (Sec. 3.4).  `out` is (P, E, J) or
+    (P, E, J, F).  Returns {"P": [I], "E": [I] or None, "J": [K, I] or None,
+    "F": [I] or None}."""
     t, x, w = _dev(t), _dev(x), _dev(w)
     K, N = w.shape
     rdt = torch.float32 if prec == M2N_FP32 else torch.float64
@@ -231,22 +233,25 @@ def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64
         P = torch.empty((I,), dtype=rdt, device=t.device)
         E = torch.empty((I,), dtype=rdt, device=t.device) if want_E else None
         J = torch.empty((K, I), dtype=cdt, device=t.device) if want_J else None
+        F = torch.empty((I,), dtype=rdt, device=t.device) if want_F else None
     else:
-        P, E, J = out
+        P, E, J = out[:3]
+        F = out[3] if len(out) > 3 else None
     if lam is not None:
         lam = _dev(lam)
     if weights is not None:
         weights = _dev(weights)
     _err(lib.m2nufft_psd(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w),
                          _ptr(lam), K, float(fmax), float(fw), float(f_lo), float(df), int(I),
-                         int(prec), float(nufft_tol), _ptr(weights), _ptr(P), _ptr(E), _ptr(J)),
+                         int(prec), float(nufft_tol), _ptr(weights), _ptr(P), _ptr(E), _ptr(J),
+                         _ptr(F)),
          "m2nufft_psd")
     if check:
         ctx.check(stream)
-    return {"P": P, "E": E, "J": J}
+    return {"P": P, "E": E, "J": J, "F": F}
 
 
-def batch_descriptors(series, prec=M2N_FP32, want_E=True, want_J=False):
+def batch_descriptors(series, prec=M2N_FP32, want_E=True, want_J=False, want_F=False):
     """The m2n_series array of a batch and its output tensors, built once so
     that repeated m2n_batch_psd calls on the same tensors skip the per-series
     Python work.  `series` is as for m2n_batch_psd.  Returns (array, outputs)."""
@@ -264,24 +269,27 @@ def batch_descriptors(series, prec=M2N_FP32, want_E=True, want_J=False):
         wE = s.get("want_E", want_E)
         E = s.get("E") if s.get("E") is not None else (torch.empty((I,), dtype=rdt, device=dev) if wE else None)
         J = s.get("J") if s.get("J") is not None else (torch.empty((K, I), dtype=cdt, device=dev) if want_J else None)
+        wF = s.get("want_F", want_F)
+        F = s.get("F") if s.get("F") is not None else (torch.empty((I,), dtype=rdt, device=dev) if wF else None)
         wt = s.get("weights")
         arr[j] = M2NSeries(t.data_ptr(), x.data_ptr(), N, K, float(s["fmax"]), float(s["fw"]),
                            float(s["f_lo"]), float(s["df"]), I,
                            None if wt is None else _dev(wt).data_ptr(), w.data_ptr(),
                            lam.data_ptr(), P.data_ptr(), None if E is None else E.data_ptr(),
-                           None if J is None else J.data_ptr())
-        outs.append({"w": w, "lam": lam, "P": P, "E": E, "J": J})
+                           None if J is None else J.data_ptr(), None if F is None else F.data_ptr())
+        outs.append({"w": w, "lam": lam, "P": P, "E": E, "J": J, "F": F})
     return arr, outs
 
 
 def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=True,
-                  want_J=False, stream=None, check=True, prepared=None):
+                  want_J=False, stream=None, check=True, prepared=None, want_F=False):
     """Tapers and PSD of many series in batched launches.  `series` is a list of
     dicts with device tensors t, x and the numbers fmax, fw, K, f_lo, df, I
-    (optional "weights", "want_E", and "w", "lam", "P", "E", "J" output
+    (optional "weights", "want_E", "want_F", and "w", "lam", "P", "E", "J", "F" output
     tensors); `prepared` is the result of batch_descriptors for the same list.
     Returns a list of {"w", "lam", "P", "E", "J"}."""
-    arr, outs = prepared if prepared is not None else batch_descriptors(series, prec, want_E, want_J)
+    arr, outs = prepared if prepared is not None else batch_descriptors(series, prec, want_E, want_J,
+                                                                        want_F)
     _err(lib.m2n_batch_psd(ctx.handle, _stream(stream), arr, len(outs), int(prec),
                            float(nufft_tol)), "m2n_batch_psd")
     if check:

@@ -286,20 +286,20 @@ int m2nufft_eigcoeffs(m2n_ctx* ctx, void* stream, const double* t, const double*
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
-                     nullptr, nullptr, 0.0, 0.0, nullptr, nullptr, J);
+                     nullptr, nullptr, 0.0, 0.0, nullptr, nullptr, J, nullptr);
 }
 
 int m2nufft_psd(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
                 const double* w, const double* lambda, int K, double fmax, double fw,
                 double f_lo, double df, int64_t I, int prec, double nufft_tol,
-                const double* weights, void* P, void* E, void* J) {
+                const double* weights, void* P, void* E, void* J, void* F) {
     if (!ctx || !P) {
         set_error("NULL argument");
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
-                     weights, lambda, fmax, fw, P, E, J);
+                     weights, lambda, fmax, fw, P, E, J, F);
 }
 
 int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nseries, int prec,
@@ -353,6 +353,7 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
         n.P = s.P;
         n.E = s.E;
         n.J = s.J;
+        n.F = s.F;
         groups[s.I].push_back(n);
     }
     for (auto& kv : groups)

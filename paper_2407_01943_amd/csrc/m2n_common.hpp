@@ -105,6 +105,7 @@ struct NuSeriesIn {
     void* P = nullptr;
     void* E = nullptr;
     void* J = nullptr;
+    void* F = nullptr;   // Thomson F-statistic [I] or NULL
 };
 
 // FP64 complex FFT plan of length M (lattice convolution in the GEP)
@@ -129,7 +130,7 @@ int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
               int64_t N, const double* w, int K, double f_lo, double df,
               int64_t I, int prec, double tol, const double* weights,
               const double* lambda, double fmax, double fw, void* P, void* E,
-              void* J);
+              void* J, void* F);
 // many series with one band count I and precision in one set of launches
 int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
                     const NuSeriesIn* series, int nseries);

@@ -180,6 +180,17 @@ __device__ __forceinline__ double wave_sum_to63(double v) {
     return v;
 }
 
+// Thomson F-statistic of one band from S_JW = sum_k J_k W_k(0), S_JJ =
+// sum_k |J_k|^2 and S_WW = sum_k W_k(0)^2: with q = |S_JW|^2 / S_WW (the
+// power of the fitted line C W(0)) the residual is S_JJ - q, and
+// F = (K - 1) q / (S_JJ - q); +inf where the residual vanishes
+template <typename R>
+__device__ __forceinline__ R f_statistic(cplx<R> sjw, R sjj, R sww, int K) {
+    const R q = (sjw.x * sjw.x + sjw.y * sjw.y) / sww;
+    const R res = sjj - q;
+    return res > (R)0 ? (R)(K - 1) * q / res : (R)INFINITY;
+}
+
 // block-wide sum for NT threads; every thread gets the result
 __device__ __forceinline__ double block_sum(double v, double* scratch /* >= NT/64 */) {
     v = wave_sum(v);
@@ -202,6 +213,7 @@ struct NuSeries {
     void* P;
     void* E;
     void* J;
+    void* F;       // Thomson F-statistic or NULL
     int* hist;     // [nwg][nbins] counts
     int* off;      // [nwg][nbins] scatter offsets
     int* binoff;   // [nbins + 1]
@@ -212,6 +224,8 @@ struct NuSeries {
     void* inter;   // [K][nf] cplx<R> after pass 1
     double* nrm;   // [nwg][K] partial sums of w_k^2 (for E)
     double* norms; // [K] their totals
+    double* wsp;   // [nwg][K] partial sums of w_k (for F)
+    double* wsums; // [K] their totals, the tapers' DC gains W_k(0)
     int* diag;     // [1] R(B) = 2 f_max I
     int64_t N;
     double f_lo, df, fmax, fw;
@@ -393,7 +407,9 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
 // K1c: scatter the points into bin order, with the K tapered samples
 // cw[k][pos] = w_k(t_n) x_n e^{-j 2 pi (f_lo + h df) t_n} so that pass 1
 // reads its taper's values without a dependent gather.
-template <typename R>
+// SW: the batch asks for the F-statistic, so the sums of w_k are needed too
+// (a separate instance keeps their registers out of the common case)
+template <typename R, bool SW>
 __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     const int wg = blockIdx.x;
@@ -404,13 +420,18 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
     R* dels = (R*)d.dels;
     cplx<R>* cw = (cplx<R>*)d.cw;
     const int64_t n0 = (int64_t)wg * d.ppw;
-    // with Ê and at most KR tapers, this workgroup's share of
-    // sum_n w_k(t_n)^2 is accumulated while the tapers are read
+    // with Ê or the F-statistic and at most KR tapers, this workgroup's
+    // shares of sum_n w_k(t_n)^2 and sum_n w_k(t_n) are accumulated while
+    // the tapers are read
     constexpr int KR = 16;
-    const bool fuse = d.E && d.K <= KR;
-    double sq[KR];
+    constexpr int KW = SW ? KR : 1;
+    const bool need = d.E || d.F;
+    const bool fuse = need && d.K <= KR;
+    double sq[KR], sw[KW];
 #pragma unroll
     for (int k = 0; k < KR; ++k) sq[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) sw[k] = 0.0;
     for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= d.N) break;
@@ -426,6 +447,7 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
                     const double wv = d.w[(int64_t)k * d.N + n];
                     cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
                     sq[k] += wv * wv;
+                    if constexpr (SW) sw[k] += wv;
                 }
             }
         } else {
@@ -437,35 +459,49 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
     }
     if (fuse) {
         // wavefront sums, then the wavefronts in order
-        __shared__ double redk[NT / 64][KR];
+        __shared__ double redk[NT / 64][KR], redw[NT / 64][KR];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
             if (k < d.K) {
                 const double v = wave_sum_to63(sq[k]);
                 if (lane == 63) redk[wv][k] = v;
+                if constexpr (SW) {
+                    const double u = wave_sum_to63(sw[k]);
+                    if (lane == 63) redw[wv][k] = u;
+                }
             }
         }
         __syncthreads();
         if ((int)threadIdx.x < d.K) {
-            double v = 0.0;
+            double v = 0.0, u = 0.0;
 #pragma unroll
-            for (int i = 0; i < NT / 64; ++i) v += redk[i][threadIdx.x];
+            for (int i = 0; i < NT / 64; ++i) {
+                v += redk[i][threadIdx.x];
+                if constexpr (SW) u += redw[i][threadIdx.x];
+            }
             d.nrm[(int64_t)wg * d.K + threadIdx.x] = v;
+            if constexpr (SW) d.wsp[(int64_t)wg * d.K + threadIdx.x] = u;
         }
-    } else if (d.E) {
-        // this workgroup's share of sum_n w_k(t_n)^2, summed in a fixed order
+    } else if (need) {
+        // this workgroup's shares of sum_n w_k(t_n)^2 and sum_n w_k(t_n),
+        // summed in a fixed order
         __shared__ double red[NT / 64];
         for (int k = 0; k < d.K; ++k) {
-            double sq = 0.0;
+            double sq = 0.0, s1 = 0.0;
             for (int j = threadIdx.x; j < d.ppw; j += NT) {
                 const int64_t n = n0 + j;
                 if (n >= d.N) break;
                 const double wv = d.w[(int64_t)k * d.N + n];
                 sq += wv * wv;
+                s1 += wv;
             }
             sq = block_sum(sq, red);
-            if (threadIdx.x == 0) d.nrm[(int64_t)wg * d.K + k] = sq;
+            s1 = block_sum(s1, red);
+            if (threadIdx.x == 0) {
+                d.nrm[(int64_t)wg * d.K + k] = sq;
+                d.wsp[(int64_t)wg * d.K + k] = s1;
+            }
         }
     }
 }
@@ -712,13 +748,24 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     }
     __syncthreads();
-    if (d.E && blk == 0 && threadIdx.x < 64) {
-        // norms[k] = the binning workgroups' partial sums of w_k^2, in order
+    if ((d.E || d.F) && blk == 0 && threadIdx.x < 64) {
+        // norms[k] and wsums[k] = the binning workgroups' partial sums of
+        // w_k^2 and of w_k, in order
         const auto* nrm = gp((const double*)d.nrm);
-        double sq = 0.0;
-        for (int g = threadIdx.x; g < d.nwg; g += 64) sq += nrm[(int64_t)g * d.K + k];
-        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
-        if (threadIdx.x == 0) d.norms[k] = sq;
+        const auto* wsp = gp((const double*)d.wsp);
+        double sq = 0.0, s1 = 0.0;
+        for (int g = threadIdx.x; g < d.nwg; g += 64) {
+            sq += nrm[(int64_t)g * d.K + k];
+            s1 += wsp[(int64_t)g * d.K + k];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            sq += __shfl_xor(sq, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+        }
+        if (threadIdx.x == 0) {
+            d.norms[k] = sq;
+            d.wsums[k] = s1;
+        }
     }
     phase_stamp(a, 2);
     fft_lds<R, N1, B, NT1, LD>(tile, tw, 1, pruned);
@@ -765,6 +812,8 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     __shared__ cplx<R> rows[ROWS * LD];
     __shared__ cplx<R> tw[N2];
     __shared__ R s_eval;
+    __shared__ R s_wk[64];   // W_k(0), for F
+    __shared__ R s_sww;
     const int K = d.K, N1 = a.N1, nf = a.nf;
     const int64_t I = a.I, h = a.h;
     // workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous
@@ -779,6 +828,7 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     R* P = (R*)d.P;
     R* E = (R*)d.E;
     cplx<R>* J = (cplx<R>*)d.J;
+    R* Fo = (R*)d.F;
     wg_stamp(a, 8192, 0);
     phase_stamp(a, 8);
     for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
@@ -793,6 +843,15 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
         for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
         if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
     }
+    if (Fo && threadIdx.x < 64) {
+        // the tapers' DC gains W_k(0) and sum_k W_k(0)^2 (lane k)
+        const int k = threadIdx.x;
+        const double wk = k < K ? d.wsums[k] : 0.0;
+        s_wk[k] = (R)wk;
+        double ww = wk * wk;
+        for (int o = 32; o > 0; o >>= 1) ww += __shfl_xor(ww, o, 64);
+        if (threadIdx.x == 0) s_sww = (R)ww;
+    }
     // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
     if (npos > N2) npos = N2;
@@ -801,9 +860,14 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     const int nneg = N2 - m2neg0;
     int nout = M * (npos + nneg);
     if (nout > OUT_IT * NT2) nout = OUT_IT * NT2;   // cannot happen for nf >= 2 I
-    R acc[OUT_IT];
+    R acc[OUT_IT], sjj[OUT_IT];
+    cplx<R> sjw[OUT_IT];
 #pragma unroll
-    for (int it = 0; it < OUT_IT; ++it) acc[it] = (R)0;
+    for (int it = 0; it < OUT_IT; ++it) {
+        acc[it] = (R)0;
+        sjj[it] = (R)0;
+        sjw[it] = {(R)0, (R)0};
+    }
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
         const int nk = K - kc0 < KC ? K - kc0 : KC;
         // all loads first, then the LDS stores, so that they are in flight
@@ -844,8 +908,15 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
                     for (int kq = 0; kq < nk; ++kq) {
                         const cplx<R> v = cscale(rows[(kq * M + mm) * LD + m2], sc);
                         const R dd = d.dk ? (R)d.dk[kc0 + kq] : (R)1 / (R)K;
-                        acc[it] += dd * (v.x * v.x + v.y * v.y);
+                        const R vv = v.x * v.x + v.y * v.y;
+                        acc[it] += dd * vv;
                         if (J) J[(int64_t)(kc0 + kq) * I + i] = v;
+                        if (Fo) {
+                            const R wk = s_wk[kc0 + kq];
+                            sjw[it].x += v.x * wk;
+                            sjw[it].y += v.y * wk;
+                            sjj[it] += vv;
+                        }
                     }
                 }
             }
@@ -864,6 +935,7 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             if (i >= 0 && i < I) {
                 if (P) P[i] = acc[it];
                 if (E) E[i] = s_eval;
+                if (Fo) Fo[i] = f_statistic<R>(sjw[it], sjj[it], s_sww, K);
             }
         }
     }
@@ -890,17 +962,23 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
     R* P = (R*)d.P;
     R* E = (R*)d.E;
     cplx<R>* J = (cplx<R>*)d.J;
-    R acc[OUT_IT];
+    R* Fo = (R*)d.F;
+    R acc[OUT_IT], sjj[OUT_IT];
+    cplx<R> sjw[OUT_IT];
 #pragma unroll
-    for (int it = 0; it < OUT_IT; ++it) acc[it] = (R)0;
+    for (int it = 0; it < OUT_IT; ++it) {
+        acc[it] = (R)0;
+        sjj[it] = (R)0;
+        sjw[it] = {(R)0, (R)0};
+    }
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
-    double esum = 0.0;
+    double esum = 0.0, sww = 0.0;
     for (int k = 0; k < K; ++k) {
         for (int e = threadIdx.x; e < NF; e += NT) grid[e] = {(R)0, (R)0};
         __syncthreads();
         const double* wk = d.w + (int64_t)k * N;
-        double nrm = 0.0;
+        double nrm = 0.0, wsum = 0.0;
         int my_int = 1, my_bad = 0;
         for (int64_t n = threadIdx.x; n < N; n += NT) {
             const Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, h, NF, w);
@@ -908,6 +986,7 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
             my_bad |= g.ok ? 0 : 1;
             const double wv = wk[n];
             nrm += wv * wv;
+            wsum += wv;
             const cplx<R> c = {(R)(g.cre * wv), (R)(g.cim * wv)};
             const R del = (R)g.del;
             for (int r = 0; r < w; ++r) {
@@ -921,6 +1000,10 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
         if (!my_int) atomicAnd(&s_int, 0);
         if (my_bad) atomicOr(&s_bad, 1);
         nrm = block_sum(nrm, red);   // contains barriers
+        if (Fo) {
+            wsum = block_sum(wsum, red);   // W_k(0), the taper's DC gain
+            sww += wsum * wsum;
+        }
         if (E && d.lambda) {
             const double c = 2.0 * d.fmax;
             esum += fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * nrm));
@@ -935,8 +1018,14 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
                 const int64_t m = kk < 0 ? kk + NF : kk;
                 const R sc = inv_phihat[kk < 0 ? -kk : kk];
                 const cplx<R> v = cscale(grid[m], sc);
-                acc[it] += dd * (v.x * v.x + v.y * v.y);
+                const R vv = v.x * v.x + v.y * v.y;
+                acc[it] += dd * vv;
                 if (J) J[(int64_t)k * I + i] = v;
+                if (Fo) {
+                    sjw[it].x += v.x * (R)wsum;
+                    sjw[it].y += v.y * (R)wsum;
+                    sjj[it] += vv;
+                }
             }
         }
         __syncthreads();
@@ -954,6 +1043,7 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
         if (i < I) {
             if (P) P[i] = acc[it];
             if (E) E[i] = ev;
+            if (Fo) Fo[i] = f_statistic<R>(sjw[it], sjj[it], (R)sww, K);
         }
     }
 }
@@ -1235,6 +1325,7 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         d.P = s.P;
         d.E = s.E;
         d.J = s.J;
+        d.F = s.F;
         d.N = s.N;
         d.f_lo = s.f_lo;
         d.df = s.df;
@@ -1272,6 +1363,8 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
                 d.inter = c.take(sizeof(cplx<R>) * (size_t)d.K * p.nf);
                 d.nrm = (double*)c.take(sizeof(double) * (size_t)d.nwg * d.K);
                 d.norms = (double*)c.take(sizeof(double) * (size_t)d.K);
+                d.wsp = (double*)c.take(sizeof(double) * (size_t)d.nwg * d.K);
+                d.wsums = (double*)c.take(sizeof(double) * (size_t)d.K);
                 d.diag = (int*)c.take(64);
             }
         };
@@ -1308,7 +1401,10 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
     }
     {
         M2N_PROF(ctx, st, "k_scatter");
-        hipLaunchKernelGGL(k_scatter<R>, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
+        bool anyF = false;
+        for (const NuSeries& d : ds) anyF = anyF || d.F != nullptr;
+        if (anyF) hipLaunchKernelGGL((k_scatter<R, true>), dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
+        else hipLaunchKernelGGL((k_scatter<R, false>), dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
     }
     M2N_HIP(hipGetLastError());
     {
@@ -1343,6 +1439,10 @@ int check_series(const NuSeriesIn& s, int64_t I) {
         set_error("E needs lambda, fmax > 0 and fw > 0");
         return M2N_ERR_ARG;
     }
+    if (s.F && s.K < 2) {
+        set_error("the F-statistic needs K >= 2 tapers (F(2, 2K-2))");
+        return M2N_ERR_ARG;
+    }
     return M2N_OK;
 }
 
@@ -1368,7 +1468,7 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
 int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,
               const double* w, int K, double f_lo, double df, int64_t I, int prec, double tol,
               const double* weights, const double* lambda, double fmax, double fw, void* P,
-              void* E, void* J) {
+              void* E, void* J, void* F) {
     NuSeriesIn s;
     s.t = t;
     s.x = x;
@@ -1384,6 +1484,7 @@ int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_
     s.P = P;
     s.E = E;
     s.J = J;
+    s.F = F;
     return nufft_run_batch(ctx, st, I, prec, tol, &s, 1);
 }
 

@@ -48,3 +48,45 @@ def test_last_error_is_empty_string_initially():
     lib = ctypes.CDLL(LIB)
     lib.m2n_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.m2n_last_error(), bytes)
+
+
+def _header_src():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.sub(r"//[^\n]*", "", src)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libm2n.so not built")
+def test_binding_argument_counts_match_header():
+    # every prototype's parameter count equals the binding's argtypes length
+    import paper_2407_01943_amd as m2n
+    src = _header_src()
+    L = m2n.lib
+    checked = 0
+    for name in declared_functions():
+        m = re.search(r"\b" + name + r"\s*\(([^)]*)\)\s*;", src, flags=re.S)
+        assert m, name
+        params = m.group(1).strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        argtypes = getattr(L, name).argtypes
+        if argtypes is None:
+            continue
+        assert len(argtypes) == n, (name, len(argtypes), n)
+        checked += 1
+    assert checked >= 10
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libm2n.so not built")
+def test_series_struct_matches_header():
+    # the ctypes mirror of m2n_series has the header's fields, in order
+    import paper_2407_01943_amd as m2n
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*m2n_series\s*;", _header_src(), flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        if decl.strip():
+            # "const double *t, *x" -> t, x: the last word of each declarator
+            fields += [part.split()[-1].lstrip("*") for part in decl.split(",")]
+    names = [f[0] for f in m2n.M2NSeries._fields_]
+    assert len(names) == len(fields), (names, fields)
+    for a, b in zip(names, fields):
+        assert a == b or (a, b) == ("lam", "lambda"), (a, b)
