@@ -291,12 +291,6 @@ __device__ __forceinline__ double wsum(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// reference butterfly sum (used to check the DPP pattern)
-__device__ __forceinline__ double wsum_shfl(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // a double from lane l (l wave-uniform)
 __device__ __forceinline__ double rdlane(double v, int l) {
     const long long b = __double_as_longlong(v);
