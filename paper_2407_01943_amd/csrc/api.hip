@@ -87,6 +87,16 @@ int Ctx::stage(hipStream_t st, const void* src, size_t bytes, void* dst_dev) {
     return M2N_OK;
 }
 
+int Ctx::aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join) {
+    if (!aux) M2N_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    if (!aux_fork) M2N_HIP(hipEventCreateWithFlags(&aux_fork, hipEventDisableTiming));
+    if (!aux_join) M2N_HIP(hipEventCreateWithFlags(&aux_join, hipEventDisableTiming));
+    *s = aux;
+    *fork = aux_fork;
+    *join = aux_join;
+    return M2N_OK;
+}
+
 hipEvent_t Ctx::take_event() {
     if (!ev_pool.empty()) {
         hipEvent_t e = ev_pool.back();
@@ -179,6 +189,9 @@ void m2n_destroy(m2n_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->aux_fork) (void)hipEventDestroy(ctx->aux_fork);
+    if (ctx->aux_join) (void)hipEventDestroy(ctx->aux_join);
     if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
 }

@@ -1615,16 +1615,19 @@ __global__ __launch_bounds__(GNT) void k_trsm_panel(double* __restrict__ A, int6
 // the operand loads and the C reads and writes are all 16 consecutive
 // doubles of a column.  Operands come straight from global memory (the
 // panel stays in L2); the subtraction is folded in by negating the A operand.
-__global__ __launch_bounds__(GNT) void k_syrk(double* __restrict__ A, int64_t Np, int kb, int nblk,
-                                              const int* __restrict__ nz) {
-    // map blockIdx.x to (ib, jb) with kb < jb <= ib < nblk
-    const int m = nblk - kb - 1;
+// The tiles updated are those of the column blocks jb >= jlo (> kb), as many
+// as the grid holds, column by column: one launch can take the next column
+// block alone and another the rest.
+__global__ __launch_bounds__(GNT) void k_syrk(double* __restrict__ A, int64_t Np, int kb, int jlo,
+                                              int nblk, const int* __restrict__ nz) {
+    // map blockIdx.x to (ib, jb) with jlo <= jb <= ib < nblk
+    const int m = nblk - jlo;
     int idx = blockIdx.x, jj = 0;
     while (idx >= m - jj) {
         idx -= m - jj;
         ++jj;
     }
-    const int jb = kb + 1 + jj, ib = jb + idx;
+    const int jb = jlo + jj, ib = jb + idx;
     if (!nz[ib] || !nz[jb]) return;
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int qi = wv & 1, qj = wv >> 1;
@@ -2402,7 +2405,7 @@ int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
         S.nblk = (int)(Np / TB);
         void *vRB, *vnz, *vst;
         M2N_TRY(ctx->workspace("gep_RB", sizeof(double) * (size_t)Np * Np, &vRB));
-        M2N_TRY(ctx->workspace("gep_nz", sizeof(int) * (size_t)S.nblk, &vnz));
+        M2N_TRY(ctx->workspace("gep_nz", sizeof(int) * (size_t)S.nblk * 2, &vnz));
         M2N_TRY(ctx->workspace("gep_status", 64, &vst));
         S.RB = (double*)vRB;
         S.nz = (int*)vnz;
@@ -2413,21 +2416,50 @@ int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
             hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
         }
         M2N_HIP(hipGetLastError());
-        for (int kb = 0; kb < S.nblk; ++kb) {
-            {
-                M2N_PROF(ctx, st, "k_potrf");
-                hipLaunchKernelGGL(k_potrf, dim3(1), dim3(4 * TB), 0, st, S.RB, Np, kb, N, (int*)vst);
-            }
+        // Right-looking with a look-ahead of one panel: the update of column
+        // block kb + 1 by panel kb runs first on st, then the rest of that
+        // update on the second stream while st factors panel kb + 1 (the
+        // panel kernels use a few compute units; the rest of the update
+        // fills the others); st waits for it before panel kb + 1's update.
+        // The zero-tile flags of panel kb are nz[(kb & 1) nblk + ib], so that
+        // panel kb + 1's flags do not overwrite those still being read.
+        hipStream_t s2 = nullptr;
+        hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+        M2N_TRY(ctx->aux_stream(&s2, &ev_fork, &ev_join));
+        auto potrf = [&](int kb) {
+            M2N_PROF(ctx, st, "k_potrf");
+            hipLaunchKernelGGL(k_potrf, dim3(1), dim3(4 * TB), 0, st, S.RB, Np, kb, N, (int*)vst);
+        };
+        auto trsm = [&](int kb) {
             const int rem = S.nblk - kb - 1;
-            if (rem > 0) {
-                {
-                    M2N_PROF(ctx, st, "k_trsm_panel");
-                    hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 3) / 4)), dim3(GNT), 0, st, S.RB,
-                                       Np, kb, S.nblk, S.nz);
-                }
-                const int ntiles = rem * (rem + 1) / 2;
+            M2N_PROF(ctx, st, "k_trsm_panel");
+            hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 3) / 4)), dim3(GNT), 0, st, S.RB, Np,
+                               kb, S.nblk, S.nz + (kb & 1) * S.nblk);
+        };
+        potrf(0);
+        if (S.nblk > 1) trsm(0);
+        for (int kb = 0; kb + 1 < S.nblk; ++kb) {
+            const int rem = S.nblk - kb - 1;
+            const int* nzk = S.nz + (kb & 1) * S.nblk;
+            {
                 M2N_PROF(ctx, st, "k_syrk");
-                hipLaunchKernelGGL(k_syrk, dim3(ntiles), dim3(GNT), 0, st, S.RB, Np, kb, S.nblk, S.nz);
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)rem), dim3(GNT), 0, st, S.RB, Np, kb, kb + 1,
+                                   S.nblk, nzk);
+            }
+            if (rem > 1) {
+                M2N_HIP(hipEventRecord(ev_fork, st));
+                M2N_HIP(hipStreamWaitEvent(s2, ev_fork, 0));
+                {
+                    M2N_PROF(ctx, s2, "k_syrk");
+                    hipLaunchKernelGGL(k_syrk, dim3((unsigned)((rem - 1) * rem / 2)), dim3(GNT), 0, s2, S.RB,
+                                       Np, kb, kb + 2, S.nblk, nzk);
+                }
+                M2N_HIP(hipEventRecord(ev_join, s2));
+            }
+            potrf(kb + 1);
+            if (rem > 1) {
+                trsm(kb + 1);
+                M2N_HIP(hipStreamWaitEvent(st, ev_join, 0));
             }
         }
         M2N_HIP(hipGetLastError());

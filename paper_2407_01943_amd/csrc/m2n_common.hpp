@@ -181,6 +181,12 @@ struct Ctx {
     hipEvent_t take_event();
     int prof_flush();
 
+    // a second stream (default priority) and two events for work that
+    // overlaps the caller's stream, created on first use
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_fork = nullptr, aux_join = nullptr;
+    int aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);
+
     // grow-only named workspace; returns M2N_OK / M2N_ERR_OOM / M2N_ERR_HIP
     int workspace(const char* name, size_t bytes, void** out);
     int alloc(DevBuf& b, size_t bytes);
