@@ -12,7 +12,10 @@ adds the two one-line steps that are clearer in numpy:
   estimator of the integrated spectrum; Table 3 step 5);
 * ``ftest``, ``f_critical``: the Thomson F-statistic from the eigencoefficients
   and the critical value of F(2, 2K-2) (Sec. 3.4);
-* ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order.
+* ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order;
+* ``subband_tapers``, ``subband_eigcoeffs``, ``fix_phase``: one sub-band of
+  the multiband partition (Sec. 2.4, Sec. 3.1-3.2): complex tapers of the
+  nominal band at fc0 and their eigencoefficients on relative frequencies.
 
 Parity pins: tests/test_oracle_pins.py.  Readings where the paper is silent
 (sign of a taper, the suboptimality estimate) are stated at each function.
@@ -57,6 +60,8 @@ def lib():
         L.or_gpss_matrix.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d]
         L.or_band_matrix.restype = None
         L.or_band_matrix.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, _d, _d]
+        L.or_subband_matrix.restype = None
+        L.or_subband_matrix.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, _d]
         L.or_apply_sinc.restype = None
         L.or_apply_sinc.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_long, _d]
         L.or_cholesky.restype = ctypes.c_long
@@ -127,6 +132,16 @@ def band_matrix(t, fc, fw):
     return re + 1j * im
 
 
+def subband_matrix(t, fmin, fmax):
+    """Real R(B^q) of the sub-band f_min <= |f| <= f_max (Sec. 2.4): the
+    integral of e^{j 2 pi f tau} over [-f_max, -f_min] and [f_min, f_max]."""
+    t = _f64(t)
+    N = t.shape[0]
+    R = np.empty((N, N))
+    lib().or_subband_matrix(_p(t), N, float(fmin), float(fmax), _p(R))
+    return R
+
+
 def apply_sinc(t, f, V):
     """R(f) @ V without storing R(f) (V is N x nv)."""
     t = _f64(t)
@@ -180,6 +195,73 @@ def gpss_tapers(t, fmax, fw, K, method="auto"):
     if st < 0:
         raise OracleError(st, "gpss_tapers")
     return w, lam
+
+
+def fix_phase(t, fc0, w):
+    """Phase reading for complex tapers (the paper leaves it open): with
+    v_n = w_n e^{-j 2 pi fc0 (t_n - tbar)}, tbar = (t_1 + t_N)/2,
+    a = sum_n v_n and b = sum_n (tbar - t_n) v_n / (t_N - t_1), the one of
+    larger modulus is made real and positive.  For fc0 = 0 and real tapers it
+    is the sign reading of the full-band tapers.  w is [K, N] complex."""
+    t = _f64(t)
+    N = t.shape[0]
+    tbar = 0.5 * (t[0] + t[-1])
+    span = t[-1] - t[0] if N > 1 else 1.0
+    u = fc0 * (t - tbar)
+    demod = np.exp(-2j * np.pi * (u - np.round(u)))
+    out = np.array(w, dtype=np.complex128)
+    for k in range(out.shape[0]):
+        v = out[k] * demod
+        a = v.sum()
+        b = ((tbar - t) * v).sum() / span
+        key = a if abs(a) >= abs(b) else b
+        if abs(key) > 0.0:
+            out[k] *= np.conj(key) / abs(key)
+    return out
+
+
+def subband_tapers(t, fmin, fmax, fw, fc0, K):
+    """The K largest solutions of R(A0) w = lambda R(B^q) w for the nominal
+    band |f - fc0| <= fw inside the sub-band f_min <= |f| <= f_max (Sec. 2.4
+    sub-band matrix; Sec. 3.2 GEP at the nominal band), scaled to
+    w^* R(B^q) w = 2 f_w, phase by ``fix_phase``.
+
+    Steps: R(B^q) = L L^T (real Cholesky, or_cholesky); R(A0) is complex
+    Hermitian (Sec. 3.2, e^{j 2 pi fc0 tau} times the sinc of f_w), and
+    C = L^{-1} R(A0) L^{-T} by two triangular solves (L is real, so L^{-T} is
+    also L^{-*}); the eigenpairs of C come from LAPACK's Hermitian solver;
+    w = sqrt(2 f_w) L^{-T} z.  Returns (w [K, N] complex, lam [K]).
+    """
+    import scipy.linalg as sla
+    t = _f64(t)
+    L = cholesky(subband_matrix(t, fmin, fmax))
+    RA = band_matrix(t, fc0, fw)
+    M = sla.solve_triangular(L, RA, lower=True)            # L^{-1} R(A0)
+    C = sla.solve_triangular(L, M.T, lower=True).T         # (L^{-1} M^T)^T = M L^{-T}
+    C = 0.5 * (C + C.conj().T)
+    th, Z = np.linalg.eigh(C)
+    idx = np.argsort(th)[::-1][:K]
+    w = np.sqrt(2.0 * fw) * sla.solve_triangular(L.T, Z[:, idx], lower=False)
+    return fix_phase(t, fc0, w.T), th[idx].copy()
+
+
+def subband_eigcoeffs(t, x, w, f_lo, df, I=None, bands=None):
+    """J_k(A_i) = sum_n conj(w_k(t_n)) x(t_n) e^{-j 2 pi df_i t_n} on the
+    relative frequencies df_i = f_lo + i df of a sub-band (Sec. 3.2
+    eigencoefficients with the shift of the nominal band; the NuFFT runs on
+    the frequencies relative to fc0).  Direct summation; the phase df_i t_n
+    is reduced modulo 1 before the exponential.  w is [K, N] complex."""
+    t, x = _f64(t), _f64(x)
+    w = np.atleast_2d(np.asarray(w, dtype=np.complex128))
+    if bands is None:
+        bands = np.arange(I, dtype=np.int64)
+    bands = np.asarray(bands, dtype=np.int64)
+    y = np.conj(w) * x[None, :]
+    J = np.empty((w.shape[0], bands.shape[0]), dtype=np.complex128)
+    for j, i in enumerate(bands):
+        u = (f_lo + i * df) * t
+        J[:, j] = y @ np.exp(-2j * np.pi * (u - np.round(u)))
+    return J
 
 
 def nudft(t, x, w, f_lo, df, I=None, bands=None):

@@ -15,6 +15,9 @@
  *                       diagonal 2 f                        (Sec. 2.1, R(B))
  *   or_band_matrix      R(A)_{nm} = sin(2 pi f_w tau)/(pi tau) e^{j 2 pi f_c tau}
  *                                                           (Sec. 2.3, R(A))
+ *   or_subband_matrix   R(B^q)_{nm} = 2 cos(pi (f_max + f_min) tau)
+ *                       sin(pi (f_max - f_min) tau) / (pi tau), diagonal
+ *                       2 (f_max - f_min)   (Sec. 2.4, sub-band GPSS matrix)
  *   or_apply_sinc       Y = R(f) V without storing R(f)
  *   or_cholesky         R(B) = L L^T, unblocked, row oriented
  *   or_reduce           C = L^{-1} R(A0) L^{-T}  (GEP -> standard problem)
@@ -82,6 +85,13 @@ double or_sinpi(double u)
     return sin(OR_PI * r);
 }
 
+/* cos(pi u), reduced modulo 2 first (exact in binary64) */
+static double or_cospi(double u)
+{
+    double r = u - 2.0 * nearbyint(0.5 * u);   /* r in [-1, 1] */
+    return cos(OR_PI * r);
+}
+
 /* sin(2 pi f tau) / (pi tau), with the tau -> 0 limit 2 f */
 static double sinc_kernel(double f, double tau)
 {
@@ -120,6 +130,21 @@ void or_band_matrix(const double *t, long N, double fc, double fw,
             cis2pi(hi, lo, &c, &s);
             Rre[n * N + m] = a * c;
             Rim[n * N + m] = a * s;
+        }
+}
+
+/* R(B^q) of the sub-band f_min <= |f| <= f_max as a dense N x N row-major
+ * matrix: the integral of e^{j 2 pi f tau} over both halves of the sub-band,
+ * 2 cos(pi (f_max + f_min) tau) sin(pi (f_max - f_min) tau) / (pi tau). */
+void or_subband_matrix(const double *t, long N, double fmin, double fmax, double *R)
+{
+    const double fs = fmax + fmin, fd = fmax - fmin;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n)
+        for (long m = 0; m < N; ++m) {
+            double tau = t[n] - t[m];
+            R[n * N + m] = (tau == 0.0) ? 2.0 * fd
+                : 2.0 * or_cospi(fs * tau) * or_sinpi(fd * tau) / (OR_PI * tau);
         }
 }
 
