@@ -83,8 +83,9 @@ size_t m2n_workspace_bytes(const m2n_ctx *ctx);
  *   t       [N]     device, FP64, strictly increasing sampling times
  *   fmax            signal band half-width, > f_w
  *   fw              nominal band half-width, > 0
- *   fc0             nominal band centre; only 0 is implemented (else
- *                   M2N_ERR_UNSUPPORTED)
+ *   fc0             nominal band centre; only 0 is implemented here (else
+ *                   M2N_ERR_UNSUPPORTED); a centre fc0 != 0 gives complex
+ *                   tapers: gpss_tapers_subband
  *   w       [K*N]   device, FP64 out: taper k at w + k*N, w_k^T R(B) w_k = 2 f_w;
  *                   sign: the larger in magnitude of sum_n w_k(t_n) and
  *                   sum_n (tbar - t_n) w_k(t_n) is positive, tbar = (t_1+t_N)/2
@@ -103,6 +104,68 @@ size_t m2n_workspace_bytes(const m2n_ctx *ctx);
 int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                 double fmax, double fw, double fc0, int K,
                 double *w, double *lambda);
+
+/*
+ * gpss_tapers_subband -- one sub-band of the multiband partition (Sec. 2.4
+ * sub-band matrix, Appendix A; Sec. 3.1 nominal band; Sec. 3.2 GEP at A0):
+ * the K largest solutions of R(A0) w = lambda R(B^q) w, where B^q is
+ * f_min <= |f| <= f_max with R(B^q)(tau) = 2 cos(pi (f_max + f_min) tau)
+ * sin(pi (f_max - f_min) tau) / (pi tau), and A0 is |f - fc0| <= f_w with the
+ * complex Hermitian R(A0)(tau) = e^{j 2 pi fc0 tau} sin(2 pi f_w tau) / (pi tau).
+ * The tapers are complex.
+ *
+ *   t       [N]     device, FP64, strictly increasing sampling times
+ *   fmin, fmax      sub-band edges, 0 <= fmin < fmax
+ *   fw, fc0         nominal band; it must lie inside the sub-band:
+ *                   |fc0| + fw <= fmax and, when fmin > 0, |fc0| - fw >= fmin
+ *   K               1 <= K <= min(N, 32)
+ *   w       [2*K*N] device, FP64 out, planar complex: Re w_k at w + k*N,
+ *                   Im w_k at w + (K + k)*N; w_k^* R(B^q) w_k = 2 f_w; phase:
+ *                   with v_n = w_k(t_n) e^{-j 2 pi fc0 (t_n - tbar)},
+ *                   a = sum v_n and b = sum (tbar - t_n) v_n / (t_N - t_1),
+ *                   the one of larger modulus is real and positive
+ *                   (tbar = (t_1 + t_N)/2; for fc0 = 0 and real tapers this is
+ *                   the sign rule of gpss_tapers)
+ *   lambda  [K]     device, FP64 out, descending
+ *
+ * R(B^q) is always factored densely (N <= 65536).  It is positive definite
+ * in exact arithmetic, but numerically singular when the sampling is denser
+ * than the sub-band's Landau rate 2 (f_max - f_min) over much of the span:
+ * then the Cholesky fails with M2N_ERR_NOT_PD (no silent regularisation).
+ * R(A0) enters through its quadrature factor of complex rank Q =
+ * ceil(0.7 * 2 pi f_w (t_N - t_1)) + 14 (even), limited to Q <= 32, i.e.
+ * f_w (t_N - t_1) <= 4 (else M2N_ERR_UNSUPPORTED).  Blocks until the tapers
+ * are complete.  Errors: M2N_ERR_ARG, M2N_ERR_T_ORDER, M2N_ERR_NOT_PD,
+ * M2N_ERR_UNSUPPORTED.
+ */
+int gpss_tapers_subband(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
+                        double fmin, double fmax, double fw, double fc0, int K,
+                        double *w, double *lambda);
+
+/*
+ * m2nufft_psd_subband -- Table 3 steps 4 and 5 for one sub-band (Sec. 3.2:
+ * eigencoefficients of the shifted tapers on frequencies relative to fc0):
+ *   J_k(i) = sum_n conj(w_k(t_n)) x(t_n) e^{-j 2 pi (f_lo + i df) t_n},
+ *   P_i    = sum_k d_k |J_k(i)|^2,
+ * where f_lo + i df is the offset of band i's centre from fc0.
+ *
+ *   t, x    [N]     device, FP64
+ *   w       [2*K*N] device, FP64 planar complex tapers (gpss_tapers_subband)
+ *   K               1 <= K <= 32
+ *   f_lo, df, I, prec, nufft_tol   as in m2nufft_eigcoeffs
+ *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
+ *   P       [I]     device out, float (FP32) or double (FP64)
+ *   J       [K*I]   device out or NULL, complex (float2 / double2)
+ *
+ * The 2K real and imaginary parts go through the NuFFT as 2K real tapers
+ * (context workspace 2*K*I complex values), then one kernel forms J and P.
+ * Stream-ordered and asynchronous once the NuFFT plan exists.
+ */
+int m2nufft_psd_subband(m2n_ctx *ctx, void *stream, const double *t,
+                        const double *x, int64_t N, const double *w, int K,
+                        double f_lo, double df, int64_t I, int prec,
+                        double nufft_tol, const double *weights, void *P,
+                        void *J);
 
 /*
  * m2nufft_eigcoeffs -- Table 3 step 4 (Sec. 3.2 eigencoefficients) as a

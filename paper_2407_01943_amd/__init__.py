@@ -39,7 +39,7 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
-            "m2n_queue_destroy"]
+            "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband"]
 
 
 class M2NSeries(ctypes.Structure):
@@ -102,6 +102,10 @@ def _load():
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
     L.gpss_tapers.restype = i
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
+    L.gpss_tapers_subband.restype = i
+    L.gpss_tapers_subband.argtypes = [vp, vp, vp, i64, d, d, d, d, i, vp, vp]
+    L.m2nufft_psd_subband.restype = i
+    L.m2nufft_psd_subband.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp, vp, vp]
     L.m2nufft_eigcoeffs.restype = i
     L.m2nufft_psd.argtypes = [vp, vp, vp, vp, i64, vp, vp, i, d, d, d, d, i64, i, d,
                               vp, vp, vp, vp, vp]
@@ -201,6 +205,54 @@ def gpss_tapers(ctx: Context, t, fmax, fw, K, fc0=0.0, stream=None, out=None):
     _err(lib.gpss_tapers(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw),
                          float(fc0), int(K), _ptr(w), _ptr(lam)), "gpss_tapers")
     return w, lam
+
+
+def gpss_tapers_subband(ctx: Context, t, fmin, fmax, fw, fc0, K, stream=None, out=None):
+    """One sub-band f_min <= |f| <= f_max, nominal band |f - fc0| <= f_w
+    (Sec. 2.4, Sec. 3.2): planar complex tapers [2K, N] (real parts, then
+    imaginary parts) and lambda [K].  ``as_complex`` turns w into [K, N]."""
+    t = _dev(t)
+    N = t.shape[0]
+    if out is None:
+        w = torch.empty((2 * K, N), dtype=torch.float64, device=t.device)
+        lam = torch.empty((K,), dtype=torch.float64, device=t.device)
+    else:
+        w, lam = out
+    _err(lib.gpss_tapers_subband(ctx.handle, _stream(stream), _ptr(t), N, float(fmin), float(fmax),
+                                 float(fw), float(fc0), int(K), _ptr(w), _ptr(lam)),
+         "gpss_tapers_subband")
+    return w, lam
+
+
+def as_complex(w):
+    """[2K, N] planar tapers -> complex128 [K, N] (a copy)."""
+    K = w.shape[0] // 2
+    return torch.complex(w[:K], w[K:])
+
+
+def m2nufft_psd_subband(ctx: Context, t, x, w, f_lo, df, I, prec=M2N_FP64, nufft_tol=0.0,
+                        weights=None, want_J=False, stream=None, out=None, check=True):
+    """Eigencoefficients and PSD of one sub-band on frequencies f_lo + i df
+    relative to its nominal centre.  w is planar [2K, N].  `out` is (P, J).
+    Returns {"P": [I], "J": [K, I] or None}."""
+    t, x, w = _dev(t), _dev(x), _dev(w)
+    K2, N = w.shape
+    K = K2 // 2
+    rdt = torch.float32 if prec == M2N_FP32 else torch.float64
+    cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
+    if out is None:
+        P = torch.empty((I,), dtype=rdt, device=t.device)
+        J = torch.empty((K, I), dtype=cdt, device=t.device) if want_J else None
+    else:
+        P, J = out
+    if weights is not None:
+        weights = _dev(weights)
+    _err(lib.m2nufft_psd_subband(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w), K,
+                                 float(f_lo), float(df), int(I), int(prec), float(nufft_tol),
+                                 _ptr(weights), _ptr(P), _ptr(J)), "m2nufft_psd_subband")
+    if check:
+        ctx.check(stream)
+    return {"P": P, "J": J}
 
 
 def m2nufft_eigcoeffs(ctx: Context, t, x, w, f_lo, df, I, prec=M2N_FP64, nufft_tol=0.0,

@@ -290,6 +290,43 @@ int gpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double f
     return gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
 }
 
+int gpss_tapers_subband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmin,
+                        double fmax, double fw, double fc0, int K, double* w, double* lambda) {
+    if (!ctx || !t || !w || !lambda) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    if (N < 1 || K < 1 || K > 32 || K > N) {
+        set_error("need 1 <= K <= min(N, 32) (N = %lld, K = %d)", (long long)N, K);
+        return M2N_ERR_ARG;
+    }
+    if (!std::isfinite(fmin) || !std::isfinite(fmax) || !std::isfinite(fw) || !std::isfinite(fc0) ||
+        !(fmin >= 0.0) || !(fmin < fmax) || !(fw > 0.0)) {
+        set_error("need 0 <= fmin < fmax and fw > 0 (fmin = %g, fmax = %g, fw = %g)", fmin, fmax, fw);
+        return M2N_ERR_ARG;
+    }
+    const double ac = std::fabs(fc0);
+    if (!(ac + fw <= fmax) || (fmin > 0.0 && !(ac - fw >= fmin))) {
+        set_error("the nominal band |f - %g| <= %g is not inside the sub-band %g <= |f| <= %g", fc0, fw,
+                  fmin, fmax);
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return gep_subband(ctx, (hipStream_t)stream, t, N, fmin, fmax, fw, fc0, K, w, lambda);
+}
+
+int m2nufft_psd_subband(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
+                        const double* w, int K, double f_lo, double df, int64_t I, int prec,
+                        double nufft_tol, const double* weights, void* P, void* J) {
+    if (!ctx || !P) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return subband_psd_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol, weights, P,
+                           J);
+}
+
 int m2nufft_eigcoeffs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
                       const double* w, int K, double f_lo, double df, int64_t I, int prec,
                       double nufft_tol, void* J) {

@@ -20,6 +20,7 @@
 //    C V = L^{-1} (R(A0) (L^{-T} V)) by blocked triangular solves and a GEMM.
 // Everything is FP64.  The only host round trips are the residual norms read
 // once per iteration and the Cholesky status.
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -50,6 +51,11 @@ __device__ __forceinline__ double sinpi_red(double u) {
 __device__ __forceinline__ double sinc_band(double f, double tau) {
     if (tau == 0.0) return 2.0 * f;
     return sinpi_red(2.0 * f * tau) / (M_PI * tau);
+}
+
+// cos(pi u) with u first reduced to [-1, 1] (exact)
+__device__ __forceinline__ double cospi_red(double u) {
+    return cospi(u - 2.0 * rint(0.5 * u));
 }
 
 // ----------------------------------------------------------- random start
@@ -1523,6 +1529,25 @@ __global__ void k_gen_sinc(const double* __restrict__ t, int64_t N, int64_t Np, 
     R[i + j * Np] = v;
 }
 
+// R[i + j Np] = R(B^q)(t_i - t_j) of the sub-band f_min <= |f| <= f_max
+// (Sec. 2.4): 2 cos(pi (f_max + f_min) tau) sin(pi (f_max - f_min) tau) / (pi tau),
+// diagonal 2 (f_max - f_min); padding: diag 1, else 0
+__global__ void k_gen_subband(const double* __restrict__ t, int64_t N, int64_t Np, double fmin,
+                              double fmax, double* __restrict__ R) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (i >= Np) return;
+    double v;
+    if (i < N && j < N) {
+        const double tau = t[i] - t[j];
+        v = tau == 0.0 ? 2.0 * (fmax - fmin)
+                       : 2.0 * cospi_red((fmax + fmin) * tau) * sinpi_red((fmax - fmin) * tau) / (M_PI * tau);
+    } else {
+        v = (i == j) ? 1.0 : 0.0;
+    }
+    R[i + j * Np] = v;
+}
+
 // Cholesky of the TB x TB diagonal block kb in place (lower; upper zeroed).
 // Four wavefronts; lane i of wavefront q holds columns 16q .. 16q + 15 of row
 // i in registers.  At column j the owning wavefront takes the pivot (lane j's
@@ -1825,6 +1850,235 @@ __global__ __launch_bounds__(GNT) void k_finalize(const double* __restrict__ Y, 
     const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
     if (n >= N) return;
     for (int k = 0; k < K; ++k) w[(int64_t)k * N + n] = sg[k] * Y[(int64_t)k * Np + n];
+}
+
+// ------------------------------------------------------------ one sub-band
+// The nominal band |f - fc0| <= f_w of a sub-band has the complex Hermitian
+// R(A0) = e^{j 2 pi fc0 tau} sin(2 pi f_w tau) / (pi tau) (Sec. 3.2).  With D =
+// diag(e^{j 2 pi fc0 (t_n - tc)}) and the real basis F0 of the band centred at
+// 0 (k_lr_basis), R(A0) = (D F0)(D F0)^* to quadrature accuracy.  Columns
+// j < Qn of F hold Re(D) F0_j, columns Qn + j hold Im(D) F0_j.
+__global__ __launch_bounds__(256) void k_sb_basis(LrSeries d, double fc0) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= d.Np) return;
+    const bool live = n < d.N;
+    const double tn = live ? d.t[n] : d.tc;
+    double cm = 0.0, sm = 0.0;
+    if (live) {
+        const double u = fc0 * (tn - d.tc);
+        sincospi(2.0 * (u - rint(u)), &sm, &cm);
+    }
+    const int64_t im = (int64_t)d.Qn * d.Np;
+    for (int q = 0; q < d.nq; ++q) {
+        double c = 0.0, s = 0.0;
+        if (live) {
+            sincospi(2.0 * d.fw * d.glx[q] * (tn - d.tc), &s, &c);
+            const double sq = sqrt(2.0 * d.fw * d.glx[MAXP + q]);
+            c *= sq;
+            s *= sq;
+        }
+        double* f = d.F + (int64_t)(2 * q) * d.Np + n;
+        f[0] = cm * c;
+        f[d.Np] = cm * s;
+        f[im] = sm * c;
+        f[im + d.Np] = sm * s;
+    }
+}
+
+constexpr int HQ = MAXP / 2;   // largest complex rank of the sub-band path
+
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Eigen-decomposition of the complex Hermitian Gram G = X^* X (q x q) of the
+// sub-band path by cyclic Jacobi on one wavefront, lane i holding row i.  P is
+// the real Gram of [Xr Xi] (2q x 2q, row-major): G = (P_rr + P_ii) +
+// j (P_ri - P_ir).  Rotation (p, r) with G_pr = m e^{j phi}: U = diag(1,
+// e^{-j phi}) [[c, s], [-s, c]], t = s / c the smaller root of t^2 + 2 tau t
+// - 1 = 0 with tau = (G_rr - G_pp) / (2 m), so that (U^* G U)_pr = 0.  Sweeps
+// stop when the off-diagonal mass is below 1e-32 of the total (60 at most).
+// Out: theta [K] descending; Z (2q x 2K, column-major) for the real expansion
+// [Xr Xi] Z: column k = [zr; -zi] / sqrt(theta_k) and column K + k =
+// [zi; zr] / sqrt(theta_k) give the real and imaginary parts of
+// X z_k / sqrt(theta_k).
+__global__ __launch_bounds__(64) void k_herm_jacobi(const double* __restrict__ P, int q, int K,
+                                                    double* __restrict__ theta, double* __restrict__ Z) {
+    __shared__ double Gr[HQ][HQ + 1], Gi[HQ][HQ + 1], Vr[HQ][HQ + 1], Vi[HQ][HQ + 1];
+    const int l = threadIdx.x;
+    const int p2 = 2 * q;
+    for (int e = l; e < q * q; e += 64) {
+        const int a = e / q, b = e % q;
+        Gr[a][b] = P[a * p2 + b] + P[(q + a) * p2 + q + b];
+        Gi[a][b] = P[a * p2 + q + b] - P[(q + a) * p2 + b];
+        Vr[a][b] = a == b ? 1.0 : 0.0;
+        Vi[a][b] = 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        if (l < q)
+            for (int b = 0; b < q; ++b) {
+                const double v = Gr[l][b] * Gr[l][b] + Gi[l][b] * Gi[l][b];
+                tot += v;
+                if (b != l) off += v;
+            }
+        off = wave_sum64(off);
+        tot = wave_sum64(tot);
+        if (!(off > 1e-32 * tot)) break;
+        for (int p = 0; p + 1 < q; ++p)
+            for (int r = p + 1; r < q; ++r) {
+                const double a = Gr[p][p], dd = Gr[r][r], br = Gr[p][r], bi = Gi[p][r];
+                const double m = sqrt(br * br + bi * bi);
+                if (!(m > 1e-300)) continue;   // the same on every lane
+                const double cph = br / m, sph = bi / m;
+                const double tau = (dd - a) / (2.0 * m);
+                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
+                double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
+                double vpr = 0.0, vpi = 0.0, vqr = 0.0, vqi = 0.0;
+                if (l < q) {
+                    // e^{-j phi} G_lr and e^{-j phi} V_lr
+                    const double gr = Gr[l][r], gi = Gi[l][r];
+                    const double er = cph * gr + sph * gi, ei = cph * gi - sph * gr;
+                    xr = c * Gr[l][p] - s * er;
+                    xi = c * Gi[l][p] - s * ei;
+                    yr = s * Gr[l][p] + c * er;
+                    yi = s * Gi[l][p] + c * ei;
+                    const double v2r = Vr[l][r], v2i = Vi[l][r];
+                    const double fr = cph * v2r + sph * v2i, fi = cph * v2i - sph * v2r;
+                    vpr = c * Vr[l][p] - s * fr;
+                    vpi = c * Vi[l][p] - s * fi;
+                    vqr = s * Vr[l][p] + c * fr;
+                    vqi = s * Vi[l][p] + c * fi;
+                }
+                __syncthreads();
+                if (l < q) {
+                    Vr[l][p] = vpr;
+                    Vi[l][p] = vpi;
+                    Vr[l][r] = vqr;
+                    Vi[l][r] = vqi;
+                    if (l == p) {
+                        Gr[p][p] = a - tt * m;
+                        Gr[p][r] = 0.0;
+                        Gi[p][r] = 0.0;
+                        Gr[r][p] = 0.0;
+                        Gi[r][p] = 0.0;
+                    } else if (l == r) {
+                        Gr[r][r] = dd + tt * m;
+                    } else {
+                        Gr[l][p] = xr;
+                        Gi[l][p] = xi;
+                        Gr[l][r] = yr;
+                        Gi[l][r] = yi;
+                        Gr[p][l] = xr;
+                        Gi[p][l] = -xi;
+                        Gr[r][l] = yr;
+                        Gi[r][l] = -yi;
+                    }
+                }
+                __syncthreads();
+            }
+    }
+    // the K largest, ties to the lower index
+    double ev = l < q ? Gr[l][l] : -DBL_MAX;
+    for (int k = 0; k < K; ++k) {
+        double bv = ev;
+        int bx = l;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int ox = __shfl_xor(bx, o, 64);
+            if (ov > bv || (ov == bv && ox < bx)) {
+                bv = ov;
+                bx = ox;
+            }
+        }
+        if (l == 0) theta[k] = bv;
+        if (l < q) {
+            const double sc = bv > 0.0 ? 1.0 / sqrt(bv) : 0.0;
+            const double zr = Vr[l][bx] * sc, zi = Vi[l][bx] * sc;
+            Z[l + (int64_t)k * p2] = zr;
+            Z[q + l + (int64_t)k * p2] = -zi;
+            Z[l + (int64_t)(K + k) * p2] = zi;
+            Z[q + l + (int64_t)(K + k) * p2] = zr;
+        }
+        if (l == bx) ev = -DBL_MAX;
+    }
+}
+
+// per-workgroup partial sums for the phase of complex taper k (real part in
+// row k of Y, imaginary part in row K + k): with v_n = y_n e^{-j 2 pi fc0
+// (t_n - tbar)}, a = sum v_n and b = sum (tbar - t_n) v_n / span
+__global__ __launch_bounds__(GNT) void k_phase_sums(const double* __restrict__ Y, int64_t Np, int64_t N,
+                                                    int K, const double* __restrict__ t, double fc0,
+                                                    double* __restrict__ part) {
+    __shared__ double red[GNT / 64][4 * HQ];
+    const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
+    const double tbar = 0.5 * (t[0] + t[N - 1]);
+    const double span = N > 1 ? (t[N - 1] - t[0]) : 1.0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double cm = 1.0, sm = 0.0, lev = 0.0;
+    if (n < N) {
+        const double u = fc0 * (t[n] - tbar);
+        sincospi(2.0 * (u - rint(u)), &sm, &cm);
+        lev = (tbar - t[n]) / span;
+    }
+    for (int k = 0; k < K; ++k) {
+        double ar = 0.0, ai = 0.0;
+        if (n < N) {
+            const double wr = Y[(int64_t)k * Np + n], wi = Y[(int64_t)(K + k) * Np + n];
+            ar = wr * cm + wi * sm;
+            ai = wi * cm - wr * sm;
+        }
+        double br = lev * ar, bi = lev * ai;
+        ar = wave_sum64(ar);
+        ai = wave_sum64(ai);
+        br = wave_sum64(br);
+        bi = wave_sum64(bi);
+        if (lane == 0) {
+            red[wv][4 * k] = ar;
+            red[wv][4 * k + 1] = ai;
+            red[wv][4 * k + 2] = br;
+            red[wv][4 * k + 3] = bi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 * K) {
+        double s = 0.0;
+        for (int w = 0; w < GNT / 64; ++w) s += red[w][threadIdx.x];
+        part[(int64_t)blockIdx.x * 4 * K + threadIdx.x] = s;
+    }
+}
+
+// planar complex tapers: w[k N + n] = Re, w[(K + k) N + n] = Im of
+// scale * y_k * conj(key_k) / |key_k|, key_k the one of a_k, b_k with the
+// larger modulus (a_k on ties); lambda[k] = theta[k]
+__global__ __launch_bounds__(GNT) void k_finalize_c(const double* __restrict__ Y, int64_t Np, int64_t N,
+                                                    int K, double scale, const double* __restrict__ part,
+                                                    int nwg, const double* __restrict__ theta,
+                                                    double* __restrict__ w, double* __restrict__ lambda) {
+    __shared__ double phr[HQ], phi[HQ];
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int g = 0; g < nwg; ++g)
+            for (int c = 0; c < 4; ++c) a[c] += part[(int64_t)g * 4 * K + 4 * k + c];
+        const double ma = sqrt(a[0] * a[0] + a[1] * a[1]), mb = sqrt(a[2] * a[2] + a[3] * a[3]);
+        const bool useb = !(ma >= mb);
+        const double kr = useb ? a[2] : a[0], ki = useb ? a[3] : a[1], mk = useb ? mb : ma;
+        phr[k] = mk > 0.0 ? scale * kr / mk : scale;
+        phi[k] = mk > 0.0 ? -scale * ki / mk : 0.0;
+        if (blockIdx.x == 0) lambda[k] = theta[k];
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)blockIdx.x * GNT + threadIdx.x;
+    if (n >= N) return;
+    for (int k = 0; k < K; ++k) {
+        const double yr = Y[(int64_t)k * Np + n], yi = Y[(int64_t)(K + k) * Np + n];
+        w[(int64_t)k * N + n] = phr[k] * yr - phi[k] * yi;
+        w[(int64_t)(K + k) * N + n] = phr[k] * yi + phi[k] * yr;
+    }
 }
 
 // ------------------------------------------------------------ host side
@@ -2352,6 +2606,92 @@ int gep_lattice_batch(Ctx* ctx, hipStream_t st, const GepIn* in, const TStat* st
 }
 
 // One series by the dense (R(B) not c I) or wide-band (Q + 2 > 64) paths.
+// R(B) = L L^T in S.RB by the tiled Cholesky (zero tiles skipped): the full
+// band |f| <= f_max when fmin = 0, else the sub-band f_min <= |f| <= f_max.
+// Blocks on the pivot status; M2N_ERR_NOT_PD when a pivot is <= 0.
+int factor_dense(Ctx* ctx, hipStream_t st, Solver& S, const double* td, int64_t N, double fmin,
+                 double fmax) {
+    const int64_t Np = S.Np;
+    if (Np > 65536) {
+        set_error("dense GEP limited to N <= 65536 in this build");
+        return M2N_ERR_UNSUPPORTED;
+    }
+    S.nblk = (int)(Np / TB);
+    void *vRB, *vnz, *vst;
+    M2N_TRY(ctx->workspace("gep_RB", sizeof(double) * (size_t)Np * Np, &vRB));
+    M2N_TRY(ctx->workspace("gep_nz", sizeof(int) * (size_t)S.nblk * 2, &vnz));
+    M2N_TRY(ctx->workspace("gep_status", 64, &vst));
+    S.RB = (double*)vRB;
+    S.nz = (int*)vnz;
+    M2N_HIP(hipMemsetAsync(vst, 0, 64, st));
+    {
+        dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
+        if (fmin == 0.0) {
+            M2N_PROF(ctx, st, "k_gen_sinc");
+            hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
+        } else {
+            M2N_PROF(ctx, st, "k_gen_subband");
+            hipLaunchKernelGGL(k_gen_subband, gs, dim3(256), 0, st, td, N, Np, fmin, fmax, S.RB);
+        }
+    }
+    M2N_HIP(hipGetLastError());
+    // Right-looking with a look-ahead of one panel: the update of column
+    // block kb + 1 by panel kb runs first on st, then the rest of that
+    // update on the second stream while st factors panel kb + 1 (the
+    // panel kernels use a few compute units; the rest of the update
+    // fills the others); st waits for it before panel kb + 1's update.
+    // The zero-tile flags of panel kb are nz[(kb & 1) nblk + ib], so that
+    // panel kb + 1's flags do not overwrite those still being read.
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    M2N_TRY(ctx->aux_stream(&s2, &ev_fork, &ev_join));
+    auto potrf = [&](int kb) {
+        M2N_PROF(ctx, st, "k_potrf");
+        hipLaunchKernelGGL(k_potrf, dim3(1), dim3(4 * TB), 0, st, S.RB, Np, kb, N, (int*)vst);
+    };
+    auto trsm = [&](int kb) {
+        const int rem = S.nblk - kb - 1;
+        M2N_PROF(ctx, st, "k_trsm_panel");
+        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 3) / 4)), dim3(GNT), 0, st, S.RB, Np,
+                           kb, S.nblk, S.nz + (kb & 1) * S.nblk);
+    };
+    potrf(0);
+    if (S.nblk > 1) trsm(0);
+    for (int kb = 0; kb + 1 < S.nblk; ++kb) {
+        const int rem = S.nblk - kb - 1;
+        const int* nzk = S.nz + (kb & 1) * S.nblk;
+        {
+            M2N_PROF(ctx, st, "k_syrk");
+            hipLaunchKernelGGL(k_syrk, dim3((unsigned)rem), dim3(GNT), 0, st, S.RB, Np, kb, kb + 1,
+                               S.nblk, nzk);
+        }
+        if (rem > 1) {
+            M2N_HIP(hipEventRecord(ev_fork, st));
+            M2N_HIP(hipStreamWaitEvent(s2, ev_fork, 0));
+            {
+                M2N_PROF(ctx, s2, "k_syrk");
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)((rem - 1) * rem / 2)), dim3(GNT), 0, s2, S.RB,
+                                   Np, kb, kb + 2, S.nblk, nzk);
+            }
+            M2N_HIP(hipEventRecord(ev_join, s2));
+        }
+        potrf(kb + 1);
+        if (rem > 1) {
+            trsm(kb + 1);
+            M2N_HIP(hipStreamWaitEvent(st, ev_join, 0));
+        }
+    }
+    M2N_HIP(hipGetLastError());
+    int hstatus = 0;
+    M2N_HIP(hipMemcpyAsync(&hstatus, vst, sizeof(int), hipMemcpyDeviceToHost, st));
+    M2N_HIP(hipStreamSynchronize(st));
+    if (hstatus != 0) {
+        set_error("R(B) is not numerically positive definite (Cholesky pivot %d)", -hstatus - 1);
+        return M2N_ERR_NOT_PD;
+    }
+    return M2N_OK;
+}
+
 int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
     const double* t_dev = g.t;
     const int64_t N = g.N;
@@ -2397,81 +2737,7 @@ int gep_general(Ctx* ctx, hipStream_t st, const GepIn& g, const TStat& r) {
     };
 
     // dense path: R(B) = L L^T by the tiled Cholesky (zero tiles skipped)
-    auto factor_RB = [&]() -> int {
-        if (Np > 65536) {
-            set_error("dense GEP limited to N <= 65536 in this build");
-            return M2N_ERR_UNSUPPORTED;
-        }
-        S.nblk = (int)(Np / TB);
-        void *vRB, *vnz, *vst;
-        M2N_TRY(ctx->workspace("gep_RB", sizeof(double) * (size_t)Np * Np, &vRB));
-        M2N_TRY(ctx->workspace("gep_nz", sizeof(int) * (size_t)S.nblk * 2, &vnz));
-        M2N_TRY(ctx->workspace("gep_status", 64, &vst));
-        S.RB = (double*)vRB;
-        S.nz = (int*)vnz;
-        M2N_HIP(hipMemsetAsync(vst, 0, 64, st));
-        {
-            M2N_PROF(ctx, st, "k_gen_sinc");
-            dim3 gs((unsigned)((Np + 255) / 256), (unsigned)Np);
-            hipLaunchKernelGGL(k_gen_sinc, gs, dim3(256), 0, st, td, N, Np, fmax, 1.0, S.RB);
-        }
-        M2N_HIP(hipGetLastError());
-        // Right-looking with a look-ahead of one panel: the update of column
-        // block kb + 1 by panel kb runs first on st, then the rest of that
-        // update on the second stream while st factors panel kb + 1 (the
-        // panel kernels use a few compute units; the rest of the update
-        // fills the others); st waits for it before panel kb + 1's update.
-        // The zero-tile flags of panel kb are nz[(kb & 1) nblk + ib], so that
-        // panel kb + 1's flags do not overwrite those still being read.
-        hipStream_t s2 = nullptr;
-        hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-        M2N_TRY(ctx->aux_stream(&s2, &ev_fork, &ev_join));
-        auto potrf = [&](int kb) {
-            M2N_PROF(ctx, st, "k_potrf");
-            hipLaunchKernelGGL(k_potrf, dim3(1), dim3(4 * TB), 0, st, S.RB, Np, kb, N, (int*)vst);
-        };
-        auto trsm = [&](int kb) {
-            const int rem = S.nblk - kb - 1;
-            M2N_PROF(ctx, st, "k_trsm_panel");
-            hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 3) / 4)), dim3(GNT), 0, st, S.RB, Np,
-                               kb, S.nblk, S.nz + (kb & 1) * S.nblk);
-        };
-        potrf(0);
-        if (S.nblk > 1) trsm(0);
-        for (int kb = 0; kb + 1 < S.nblk; ++kb) {
-            const int rem = S.nblk - kb - 1;
-            const int* nzk = S.nz + (kb & 1) * S.nblk;
-            {
-                M2N_PROF(ctx, st, "k_syrk");
-                hipLaunchKernelGGL(k_syrk, dim3((unsigned)rem), dim3(GNT), 0, st, S.RB, Np, kb, kb + 1,
-                                   S.nblk, nzk);
-            }
-            if (rem > 1) {
-                M2N_HIP(hipEventRecord(ev_fork, st));
-                M2N_HIP(hipStreamWaitEvent(s2, ev_fork, 0));
-                {
-                    M2N_PROF(ctx, s2, "k_syrk");
-                    hipLaunchKernelGGL(k_syrk, dim3((unsigned)((rem - 1) * rem / 2)), dim3(GNT), 0, s2, S.RB,
-                                       Np, kb, kb + 2, S.nblk, nzk);
-                }
-                M2N_HIP(hipEventRecord(ev_join, s2));
-            }
-            potrf(kb + 1);
-            if (rem > 1) {
-                trsm(kb + 1);
-                M2N_HIP(hipStreamWaitEvent(st, ev_join, 0));
-            }
-        }
-        M2N_HIP(hipGetLastError());
-        int hstatus = 0;
-        M2N_HIP(hipMemcpyAsync(&hstatus, vst, sizeof(int), hipMemcpyDeviceToHost, st));
-        M2N_HIP(hipStreamSynchronize(st));
-        if (hstatus != 0) {
-            set_error("R(B) is not numerically positive definite (Cholesky pivot %d)", -hstatus - 1);
-            return M2N_ERR_NOT_PD;
-        }
-        return M2N_OK;
-    };
+    auto factor_RB = [&]() -> int { return factor_dense(ctx, st, S, td, N, 0.0, fmax); };
 
     double scale;   // w = scale * (L^{-T}) y
     if (lowrank) {
@@ -2636,6 +2902,116 @@ int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int ns) {
     for (int i = 0; i < ns; ++i) (lattice_lowrank(in[i], stat[i]) ? lat : other).push_back(i);
     M2N_TRY(gep_lattice_batch(ctx, st, in, stat.data(), lat));
     for (int i : other) M2N_TRY(gep_general(ctx, st, in[i], stat[i]));
+    return M2N_OK;
+}
+
+// One sub-band f_min <= |f| <= f_max with the nominal band |f - fc0| <= f_w:
+// R(A0) w = lambda R(B^q) w (Sec. 2.4, Sec. 3.2) with complex tapers.
+// R(B^q) = L L^T (real, dense); X = L^{-1} [Re(D F0) Im(D F0)] (2 Qn real
+// columns); the complex Gram X^* X by k_herm_jacobi; y_k = X z_k / sqrt(theta_k)
+// (real and imaginary parts as 2K real columns); w_k = sqrt(2 f_w) L^{-T} y_k
+// (L is real) with the phase of k_finalize_c.  w is planar: real parts
+// [K x N], then imaginary parts [K x N].
+int gep_subband(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmin, double fmax,
+                double fw, double fc0, int K, double* w_out, double* lambda_out) {
+    GepIn g;
+    g.t = t_dev;
+    g.N = N;
+    g.fmax = fmax;
+    g.fw = fw;
+    g.K = K;
+    g.w = w_out;
+    g.lambda = lambda_out;
+    std::vector<TStat> stat;
+    M2N_TRY(t_check(ctx, st, &g, 1, stat));
+    M2N_TRY(t_status(stat[0], 0));
+    const TStat& r = stat[0];
+    const double span = N > 1 ? r.tN - r.t0 : 0.0;
+    const int Qn = quad_rank(fw, span, K);
+    if (2 * Qn > MAXP) {
+        set_error("sub-band nominal band too wide for the complex low-rank path: quadrature rank %d "
+                  "> %d (needs f_w (t_N - t_1) <= 4)", Qn, HQ);
+        return M2N_ERR_UNSUPPORTED;
+    }
+    Solver S;
+    S.ctx = ctx;
+    S.st = st;
+    S.N = N;
+    S.Np = (N + TB - 1) / TB * TB;
+    S.K = K;
+    S.lattice = false;
+    const int64_t Np = S.Np;
+    const int64_t nchunks = (Np + GRAM_ROWS - 1) / GRAM_ROWS;
+    const int row_wg = (int)((Np + GNT - 1) / GNT);
+    LrSeries d;
+    std::memset(&d, 0, sizeof(d));
+    d.t = t_dev;
+    d.N = N;
+    d.Np = Np;
+    d.ldy = Np;
+    d.tc = 0.5 * (r.t0 + r.tN);
+    d.span = span > 0.0 ? span : 1.0;
+    d.fw = fw;
+    d.scale = 1.0;
+    d.c = 1.0;
+    d.K = K;
+    d.Qn = Qn;
+    d.pF = 2 * Qn;
+    d.nq = Qn / 2;
+    d.fuse = 1;
+    d.nchunks = (int)nchunks;
+    d.nred = d.nchunks < 512 ? d.nchunks : 512;
+    d.cpw = (d.nchunks + d.nred - 1) / d.nred;
+    d.nred = (d.nchunks + d.cpw - 1) / d.cpw;
+    M2N_TRY(gl_table(ctx, Qn, &d.glx));
+    void *vF, *vgp, *vQ, *vth, *vgacc, *vY, *vpart;
+    M2N_TRY(ctx->workspace("gep_F", sizeof(double) * (size_t)d.pF * Np, &vF));
+    M2N_TRY(ctx->workspace("gep_gpart", sizeof(double) * (size_t)d.nred * d.pF * d.pF, &vgp));
+    M2N_TRY(ctx->workspace("gep_Q", sizeof(double) * MAXP * MAXP, &vQ));
+    M2N_TRY(ctx->workspace("gep_th", sizeof(double) * MAXP, &vth));
+    M2N_TRY(ctx->workspace("gep_gacc", sizeof(double) * 2 * MAXP * MAXP, &vgacc));
+    M2N_TRY(ctx->workspace("gep_Y", sizeof(double) * (size_t)MAXP * Np, &vY));
+    M2N_TRY(ctx->workspace("gep_part", sizeof(double) * ((size_t)row_wg * 4 * K + 64), &vpart));
+    d.F = (double*)vF;
+    d.gpart = (double*)vgp;
+    d.G = (double*)vgacc;
+    d.Z = (double*)vQ;
+    d.theta = (double*)vth;
+    d.Y = (double*)vY;
+    {
+        M2N_PROF(ctx, st, "k_sb_basis");
+        hipLaunchKernelGGL(k_sb_basis, dim3((unsigned)((Np + 255) / 256)), dim3(256), 0, st, d, fc0);
+    }
+    M2N_HIP(hipGetLastError());
+    M2N_TRY(factor_dense(ctx, st, S, t_dev, N, fmin, fmax));
+    S.p = 2 * Qn;
+    M2N_TRY(S.trsv(d.F, 0));   // X = L^{-1} F
+    M2N_TRY(launch_gram_mfma(ctx, st, d.pF, d.nred, 1, d, nullptr));
+    {
+        M2N_PROF(ctx, st, "k_herm_jacobi");
+        hipLaunchKernelGGL(k_herm_jacobi, dim3(1), dim3(64), 0, st, (const double*)d.G, Qn, K, d.theta, d.Z);
+    }
+    M2N_HIP(hipGetLastError());
+    LrSeries e = d;   // the real expansion: 2 Qn columns into 2 K
+    e.Qn = 2 * Qn;
+    e.K = 2 * K;
+    M2N_TRY(launch_lr_expand(ctx, st, e.Qn, (Np + 63) / 64, 1, e, nullptr));
+    S.p = 2 * K;
+    M2N_TRY(S.trsv(d.Y, 1));   // w = L^{-T} y
+    {
+        M2N_PROF(ctx, st, "k_phase_sums");
+        hipLaunchKernelGGL(k_phase_sums, dim3(row_wg), dim3(GNT), 0, st, (const double*)d.Y, Np, N, K, t_dev,
+                           fc0, (double*)vpart);
+    }
+    {
+        M2N_PROF(ctx, st, "k_finalize_c");
+        const int fin_wg = (int)((N + GNT - 1) / GNT);
+        hipLaunchKernelGGL(k_finalize_c, dim3(fin_wg), dim3(GNT), 0, st, (const double*)d.Y, Np, N, K,
+                           std::sqrt(2.0 * fw), (const double*)vpart, row_wg, (const double*)d.theta, w_out,
+                           lambda_out);
+    }
+    M2N_HIP(hipGetLastError());
+    M2N_HIP(hipStreamSynchronize(st));
     return M2N_OK;
 }
 

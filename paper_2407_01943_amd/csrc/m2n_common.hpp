@@ -138,6 +138,14 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
 // GEP entries (defined in gep.hip)
 int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N,
             double fmax, double fw, int K, double* w, double* lambda);
+// one sub-band f_min <= |f| <= f_max, nominal band centre fc0: complex tapers,
+// planar (real parts K x N, then imaginary parts K x N)
+int gep_subband(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fmin,
+                double fmax, double fw, double fc0, int K, double* w, double* lambda);
+// eigencoefficients and PSD of one sub-band's complex tapers (subband.hip)
+int subband_psd_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,
+                    const double* w, int K, double f_lo, double df, int64_t I, int prec, double tol,
+                    const double* weights, void* P, void* J);
 // one series of a taper solve (device pointers; w is K x N, lambda K)
 struct GepIn {
     const double* t = nullptr;

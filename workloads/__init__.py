@@ -269,7 +269,7 @@ def multiband(n: int = 1024, seed: int = 21, I: int = 4096):
     span = t[-1] - t[0]
     fw = 3.5 / span
     half = 0.125 - fw
-    x = (np.cos(2.0 * np.pi * 0.1 * t + 0.3) + 0.5 * np.cos(2.0 * np.pi * 0.41 * t + 1.1)
+    x = (np.cos(2.0 * np.pi * 0.1 * t + 0.3) + np.cos(2.0 * np.pi * 0.41 * t + 1.1)
          + rng.standard_normal(n))
     s = Series(f"multiband_{n}", t, x, 0.5, fw, 6, -half, 2.0 * half / I, I, 0)
     return s, [SubBand(0.0, 0.25, 0.125), SubBand(0.25, 0.5, 0.375)]
