@@ -159,6 +159,8 @@ def parse():
     ap.add_argument("--served-rate", type=float, default=200.0, help="arrivals per second")
     ap.add_argument("--gep-stress-n", type=int, default=16384,
                     help="N of the dense jittered GEP stress solve (0: skip)")
+    ap.add_argument("--multiband-n", type=int, default=4096,
+                    help="samples of the multiband form (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (byte-counter calibration)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
@@ -407,6 +409,91 @@ def gep_stress(m2n, torch, workloads, ctx, n, reps=3):
             "RB_orthonormality": orth, "gep_residual": res}
 
 
+def multiband_form(m2n, torch, workloads, ctx, n, I, reps=3):
+    """The multiband partition on a band-pass sampled series (two sub-bands
+    [0, 1/4] and [1/4, 1/2] of f_max = 1/2, nominal centres 1/8 and 3/8):
+    per sub-band, the complex taper solve (dense FP64 Cholesky of the
+    sub-band matrix, complex Hermitian reduction) and the relative-frequency
+    PSD in FP32.  Reports times, the trailing update's FP64 MFMA rate, the
+    one-solve kernel times, and from dense FP64 products on the device the
+    tapers' R(B^q)-orthonormality and GEP residual."""
+    s, sbs = workloads.multiband(n=n, I=I)
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(dev)
+    x = torch.from_numpy(s.x).to(dev)
+    K, N = s.K, s.N
+    Np = (N + 63) // 64 * 64
+    syrk = sum(64.0 * M * (M + 1) for M in range(Np - 64, 0, -64))
+    out = []
+    kern_all = {}
+    stream = torch.cuda.current_stream()
+    for sb in sbs:
+        w = torch.empty((2 * K, N), dtype=torch.float64, device=dev)
+        lam = torch.empty((K,), dtype=torch.float64, device=dev)
+        P = torch.empty((I,), dtype=torch.float32, device=dev)
+        m2n.gpss_tapers_subband(ctx, t, sb.fmin, sb.fmax, s.fw, sb.fc0, K, out=(w, lam))
+        m2n.m2nufft_psd_subband(ctx, t, x, w, s.f_lo, s.df, I, prec=m2n.M2N_FP32, out=(P, None))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            m2n.gpss_tapers_subband(ctx, t, sb.fmin, sb.fmax, s.fw, sb.fc0, K, out=(w, lam))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_tap = e0.elapsed_time(e1) / reps
+        e0.record(stream)
+        for _ in range(10 * reps):
+            m2n.m2nufft_psd_subband(ctx, t, x, w, s.f_lo, s.df, I, prec=m2n.M2N_FP32, out=(P, None),
+                                    check=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_psd = e0.elapsed_time(e1) / (10 * reps)
+        ctx.profile_reset()
+        ctx.profile(True)
+        m2n.gpss_tapers_subband(ctx, t, sb.fmin, sb.fmax, s.fw, sb.fc0, K, out=(w, lam))
+        m2n.m2nufft_psd_subband(ctx, t, x, w, s.f_lo, s.df, I, prec=m2n.M2N_FP32, out=(P, None))
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        ks = ctx.profile_read()
+        for k, v in ks.items():
+            kern_all[k] = kern_all.get(k, 0.0) + v[0]
+        syrk_ms = ks.get("k_syrk", (0.0, 1))[0]
+        # checks with dense FP64 products (verification only)
+        wc = torch.complex(w[:K], w[K:])
+        tau = t[:, None] - t[None, :]
+        ntau = torch.where(tau == 0, torch.ones_like(tau), tau)
+        RB = torch.where(tau == 0, torch.full_like(tau, 2 * (sb.fmax - sb.fmin)),
+                         2 * torch.cos(math.pi * (sb.fmax + sb.fmin) * tau)
+                         * torch.sin(math.pi * (sb.fmax - sb.fmin) * tau) / (math.pi * ntau))
+        RBw = RB.to(torch.complex128) @ wc.T
+        del RB
+        orth = float((wc.conj() @ RBw / (2 * s.fw) - torch.eye(K, device=dev)).abs().max())
+        RA = torch.where(tau == 0, torch.full_like(tau, 2 * s.fw),
+                         torch.sin(2 * math.pi * s.fw * tau) / (math.pi * ntau)).to(torch.complex128)
+        RA = RA * torch.exp(2j * math.pi * sb.fc0 * tau)
+        RAw = RA @ wc.T
+        del RA, tau, ntau
+        lamc = lam.to(torch.complex128)
+        res = float(((RAw - RBw * lamc[None, :]).norm(dim=0) / (RBw * lamc[None, :]).norm(dim=0)).max())
+        del RAw, RBw
+        torch.cuda.empty_cache()
+        out.append({"fmin": sb.fmin, "fmax": sb.fmax, "fc0": sb.fc0,
+                    "tapers_ms": round(ms_tap, 3), "psd_ms": round(ms_psd, 4),
+                    "psd_value": round(N * K * I / (ms_psd * 1e-3) / 1e6, 1),
+                    "k_syrk": {"ms": round(syrk_ms, 3), "flops": syrk,
+                               "tflops_per_s": round(syrk / (syrk_ms * 1e-3) / 1e12, 2) if syrk_ms else None,
+                               "frac": round(syrk / (syrk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+                               if syrk_ms else None},
+                    "k_herm_jacobi_ms": round(ks.get("k_herm_jacobi", (0.0, 1))[0], 4),
+                    "lambda": [round(float(v), 12) for v in lam.cpu()],
+                    "RB_orthonormality": orth, "gep_residual": res})
+    kern = {k: round(v / len(sbs), 4) for k, v in sorted(kern_all.items(), key=lambda kv: -kv[1])[:10]}
+    return {"workload": s.name, "N": N, "Q": len(sbs), "K": K, "fw": s.fw, "I": I,
+            "psd_prec": "fp32", "unit_psd_value": "Mpts*tapers*bands/s (complex tapers)",
+            "ms_all_subbands": round(sum(o["tapers_ms"] + o["psd_ms"] for o in out), 3),
+            "subbands": out, "kernels_ms_per_subband": kern}
+
+
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
     """Bytes each kernel must move per launch (its compulsory traffic)."""
     cs = 2 * prec_bytes                      # one complex grid value
@@ -614,6 +701,13 @@ def main():
         print(f"bench: GEP stress {stress['ms_per_solve']} ms, k_syrk {stress['k_syrk']['tflops_per_s']} TF/s",
               file=sys.stderr, flush=True)
 
+    multiband = None
+    if a.multiband_n > 0:
+        print("bench: multiband", file=sys.stderr, flush=True)
+        multiband = multiband_form(m2n, torch, workloads, ctx, a.multiband_n, 2 ** 15)
+        print(f"bench: multiband {multiband['ms_all_subbands']} ms for {multiband['Q']} sub-bands",
+              file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -648,6 +742,7 @@ def main():
         "batched_form": batched,
         "served_form": served,
         "gep_stress": stress,
+        "multiband": multiband,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -1892,96 +1892,135 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
-// Eigen-decomposition of the complex Hermitian Gram G = X^* X (q x q) of the
-// sub-band path by cyclic Jacobi on one wavefront, lane i holding row i.  P is
-// the real Gram of [Xr Xi] (2q x 2q, row-major): G = (P_rr + P_ii) +
-// j (P_ri - P_ir).  Rotation (p, r) with G_pr = m e^{j phi}: U = diag(1,
-// e^{-j phi}) [[c, s], [-s, c]], t = s / c the smaller root of t^2 + 2 tau t
-// - 1 = 0 with tau = (G_rr - G_pp) / (2 m), so that (U^* G U)_pr = 0.  Sweeps
-// stop when the off-diagonal mass is below 1e-32 of the total (60 at most).
+// Eigen-decomposition of the complex Hermitian Gram G = X^* X (q x q, q even)
+// of the sub-band path by Jacobi with the round-robin parallel ordering: each
+// of the q - 1 steps of a sweep rotates q / 2 disjoint pairs at once (G <- G U,
+// V <- V U by columns, then G <- U^* G by rows), four wavefronts sharing the
+// updates.  P is the real Gram of [Xr Xi] (2q x 2q, row-major): G = (P_rr +
+// P_ii) + j (P_ri - P_ir).  Rotation (p, r), p < r, with G_pr = m e^{j phi}:
+// U = diag(1, e^{-j phi}) [[c, s], [-s, c]], t = s / c the smaller root of
+// t^2 + 2 tau t - 1 = 0 with tau = (G_rr - G_pp) / (2 m), so that
+// (U^* G U)_pr = 0.  A pair is rotated only when m > 1e-16 sqrt(G_pp G_rr);
+// the sweeps stop after one without a rotation (60 at most).
 // Out: theta [K] descending; Z (2q x 2K, column-major) for the real expansion
 // [Xr Xi] Z: column k = [zr; -zi] / sqrt(theta_k) and column K + k =
 // [zi; zr] / sqrt(theta_k) give the real and imaginary parts of
 // X z_k / sqrt(theta_k).
-__global__ __launch_bounds__(64) void k_herm_jacobi(const double* __restrict__ P, int q, int K,
-                                                    double* __restrict__ theta, double* __restrict__ Z) {
+constexpr int HJ_NT = 256;
+__global__ __launch_bounds__(HJ_NT) void k_herm_jacobi(const double* __restrict__ P, int q, int K,
+                                                       double* __restrict__ theta, double* __restrict__ Z) {
     __shared__ double Gr[HQ][HQ + 1], Gi[HQ][HQ + 1], Vr[HQ][HQ + 1], Vi[HQ][HQ + 1];
-    const int l = threadIdx.x;
-    const int p2 = 2 * q;
-    for (int e = l; e < q * q; e += 64) {
+    __shared__ double rc[HQ / 2], rs[HQ / 2], rer[HQ / 2], rei[HQ / 2], rda[HQ / 2], rdd[HQ / 2];
+    __shared__ int rp[HQ / 2], rr[HQ / 2], rot[HQ / 2];
+    __shared__ int nrot;
+    const int tid = threadIdx.x;
+    const int p2 = 2 * q, h = q / 2, m = q - 1;
+    for (int e = tid; e < q * q; e += HJ_NT) {
         const int a = e / q, b = e % q;
         Gr[a][b] = P[a * p2 + b] + P[(q + a) * p2 + q + b];
         Gi[a][b] = P[a * p2 + q + b] - P[(q + a) * p2 + b];
         Vr[a][b] = a == b ? 1.0 : 0.0;
         Vi[a][b] = 0.0;
     }
+    if (tid == 0) nrot = 0;
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        if (l < q)
-            for (int b = 0; b < q; ++b) {
-                const double v = Gr[l][b] * Gr[l][b] + Gi[l][b] * Gi[l][b];
-                tot += v;
-                if (b != l) off += v;
-            }
-        off = wave_sum64(off);
-        tot = wave_sum64(tot);
-        if (!(off > 1e-32 * tot)) break;
-        for (int p = 0; p + 1 < q; ++p)
-            for (int r = p + 1; r < q; ++r) {
+        for (int st = 0; st < m; ++st) {
+            if (tid < h) {
+                const int k = tid;
+                int p = k == 0 ? 0 : 1 + (st + k) % m;
+                int r = 1 + (st - k + m) % m;
+                if (p > r) {
+                    const int x = p;
+                    p = r;
+                    r = x;
+                }
                 const double a = Gr[p][p], dd = Gr[r][r], br = Gr[p][r], bi = Gi[p][r];
-                const double m = sqrt(br * br + bi * bi);
-                if (!(m > 1e-300)) continue;   // the same on every lane
-                const double cph = br / m, sph = bi / m;
-                const double tau = (dd - a) / (2.0 * m);
-                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
-                double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
-                double vpr = 0.0, vpi = 0.0, vqr = 0.0, vqi = 0.0;
-                if (l < q) {
-                    // e^{-j phi} G_lr and e^{-j phi} V_lr
-                    const double gr = Gr[l][r], gi = Gi[l][r];
-                    const double er = cph * gr + sph * gi, ei = cph * gi - sph * gr;
-                    xr = c * Gr[l][p] - s * er;
-                    xi = c * Gi[l][p] - s * ei;
-                    yr = s * Gr[l][p] + c * er;
-                    yi = s * Gi[l][p] + c * ei;
-                    const double v2r = Vr[l][r], v2i = Vi[l][r];
-                    const double fr = cph * v2r + sph * v2i, fi = cph * v2i - sph * v2r;
-                    vpr = c * Vr[l][p] - s * fr;
-                    vpi = c * Vi[l][p] - s * fi;
-                    vqr = s * Vr[l][p] + c * fr;
-                    vqi = s * Vi[l][p] + c * fi;
+                const double mm = sqrt(br * br + bi * bi);
+                double c = 1.0, sn = 0.0, cph = 1.0, sph = 0.0, tt = 0.0;
+                const bool doit = mm > 1e-16 * sqrt(fabs(a * dd)) && mm > 1e-300;
+                if (doit) {
+                    cph = br / mm;
+                    sph = bi / mm;
+                    const double tau = (dd - a) / (2.0 * mm);
+                    tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * c;
+                    atomicAdd(&nrot, 1);
                 }
-                __syncthreads();
-                if (l < q) {
-                    Vr[l][p] = vpr;
-                    Vi[l][p] = vpi;
-                    Vr[l][r] = vqr;
-                    Vi[l][r] = vqi;
-                    if (l == p) {
-                        Gr[p][p] = a - tt * m;
-                        Gr[p][r] = 0.0;
-                        Gi[p][r] = 0.0;
-                        Gr[r][p] = 0.0;
-                        Gi[r][p] = 0.0;
-                    } else if (l == r) {
-                        Gr[r][r] = dd + tt * m;
-                    } else {
-                        Gr[l][p] = xr;
-                        Gi[l][p] = xi;
-                        Gr[l][r] = yr;
-                        Gi[l][r] = yi;
-                        Gr[p][l] = xr;
-                        Gi[p][l] = -xi;
-                        Gr[r][l] = yr;
-                        Gi[r][l] = -yi;
-                    }
-                }
-                __syncthreads();
+                rp[k] = p;
+                rr[k] = r;
+                rc[k] = c;
+                rs[k] = sn;
+                rer[k] = cph;
+                rei[k] = sph;
+                rda[k] = a - tt * mm;
+                rdd[k] = dd + tt * mm;
+                rot[k] = doit;
             }
+            __syncthreads();
+            // columns p, r of G and V: x U  (e^{-j phi} applied to column r)
+            for (int e = tid; e < h * q; e += HJ_NT) {
+                const int k = e / q, i = e % q;
+                if (!rot[k]) continue;
+                const int p = rp[k], r = rr[k];
+                const double c = rc[k], sn = rs[k], cph = rer[k], sph = rei[k];
+                double gr = Gr[i][r], gi = Gi[i][r];
+                double er = cph * gr + sph * gi, ei = cph * gi - sph * gr;
+                double gpr = Gr[i][p], gpi = Gi[i][p];
+                Gr[i][p] = c * gpr - sn * er;
+                Gi[i][p] = c * gpi - sn * ei;
+                Gr[i][r] = sn * gpr + c * er;
+                Gi[i][r] = sn * gpi + c * ei;
+                gr = Vr[i][r];
+                gi = Vi[i][r];
+                er = cph * gr + sph * gi;
+                ei = cph * gi - sph * gr;
+                gpr = Vr[i][p];
+                gpi = Vi[i][p];
+                Vr[i][p] = c * gpr - sn * er;
+                Vi[i][p] = c * gpi - sn * ei;
+                Vr[i][r] = sn * gpr + c * er;
+                Vi[i][r] = sn * gpi + c * ei;
+            }
+            __syncthreads();
+            // rows p, r of G: U^* x  (e^{j phi} applied to row r)
+            for (int e = tid; e < h * q; e += HJ_NT) {
+                const int k = e / q, j = e % q;
+                if (!rot[k]) continue;
+                const int p = rp[k], r = rr[k];
+                const double c = rc[k], sn = rs[k], cph = rer[k], sph = rei[k];
+                const double hr = Gr[r][j], hi = Gi[r][j];
+                const double fr = cph * hr - sph * hi, fi = cph * hi + sph * hr;
+                const double gpr = Gr[p][j], gpi = Gi[p][j];
+                Gr[p][j] = c * gpr - sn * fr;
+                Gi[p][j] = c * gpi - sn * fi;
+                Gr[r][j] = sn * gpr + c * fr;
+                Gi[r][j] = sn * gpi + c * fi;
+            }
+            __syncthreads();
+            if (tid < h && rot[tid]) {
+                const int p = rp[tid], r = rr[tid];
+                Gr[p][p] = rda[tid];
+                Gr[r][r] = rdd[tid];
+                Gi[p][p] = 0.0;
+                Gi[r][r] = 0.0;
+                Gr[p][r] = 0.0;
+                Gi[p][r] = 0.0;
+                Gr[r][p] = 0.0;
+                Gi[r][p] = 0.0;
+            }
+            __syncthreads();
+        }
+        const int nr = nrot;
+        __syncthreads();
+        if (tid == 0) nrot = 0;
+        __syncthreads();
+        if (nr == 0) break;
     }
-    // the K largest, ties to the lower index
+    if (tid >= 64) return;
+    // the K largest, ties to the lower index (wavefront 0)
+    const int l = tid;
     double ev = l < q ? Gr[l][l] : -DBL_MAX;
     for (int k = 0; k < K; ++k) {
         double bv = ev;
@@ -2989,7 +3028,7 @@ int gep_subband(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double
     M2N_TRY(launch_gram_mfma(ctx, st, d.pF, d.nred, 1, d, nullptr));
     {
         M2N_PROF(ctx, st, "k_herm_jacobi");
-        hipLaunchKernelGGL(k_herm_jacobi, dim3(1), dim3(64), 0, st, (const double*)d.G, Qn, K, d.theta, d.Z);
+        hipLaunchKernelGGL(k_herm_jacobi, dim3(1), dim3(HJ_NT), 0, st, (const double*)d.G, Qn, K, d.theta, d.Z);
     }
     M2N_HIP(hipGetLastError());
     LrSeries e = d;   // the real expansion: 2 Qn columns into 2 K
