@@ -1582,10 +1582,14 @@ __global__ __launch_bounds__(TB * 4) void k_potrf(double* __restrict__ A, int64_
             col[buf][i] = v;
         }
         __syncthreads();
+        // all CW broadcasts in flight together, then a branch-free update
+        // (a predicated read per column would wait on each one in turn)
         const double lij = col[buf][i];
+        double cv[CW];
 #pragma unroll
-        for (int u = 0; u < CW; ++u)
-            if (CW * q + u > j) r[u] -= lij * col[buf][CW * q + u];
+        for (int u = 0; u < CW; ++u) cv[u] = col[buf][CW * q + u];
+#pragma unroll
+        for (int u = 0; u < CW; ++u) r[u] = (CW * q + u > j) ? r[u] - lij * cv[u] : r[u];
     }
 #pragma unroll
     for (int u = 0; u < CW; ++u) {
@@ -1710,13 +1714,17 @@ __global__ __launch_bounds__(GNT) void k_trsv_diag(const double* __restrict__ A,
     if (c >= p) return;
     double* b = Bm + (int64_t)c * Np + o;
     double x = b[lane];
+    // fully unrolled so that the LDS reads, which do not depend on x, are
+    // issued ahead of the division chain
     if (!trans) {
+#pragma unroll
         for (int i = 0; i < TB; ++i) {
             const double xi = rdlane(x, i) / L[i + i * LDL];
             if (lane == i) x = xi;
             else if (lane > i) x -= L[lane + i * LDL] * xi;
         }
     } else {
+#pragma unroll
         for (int i = TB - 1; i >= 0; --i) {
             const double xi = rdlane(x, i) / L[i + i * LDL];
             if (lane == i) x = xi;
