@@ -13,6 +13,8 @@ adds the two one-line steps that are clearer in numpy:
 * ``ftest``, ``f_critical``: the Thomson F-statistic from the eigencoefficients
   and the critical value of F(2, 2K-2) (Sec. 3.4);
 * ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order;
+* ``idpss_tapers``: the interpolated-DPSS tapers of Table 3 step 3 (fc0 = 0):
+  uniform-grid DPSS, natural cubic spline to t, R(B) normalisation;
 * ``subband_tapers``, ``subband_eigcoeffs``, ``fix_phase``: one sub-band of
   the multiband partition (Sec. 2.4, Sec. 3.1-3.2): complex tapers of the
   nominal band at fc0 and their eigencoefficients on relative frequencies.
@@ -195,6 +197,43 @@ def gpss_tapers(t, fmax, fw, K, method="auto"):
     if st < 0:
         raise OracleError(st, "gpss_tapers")
     return w, lam
+
+
+def fix_sign(t, w):
+    """The sign reading of the full-band tapers, for rows of w [K, N]: the larger
+    in magnitude of sum w and sum (tbar - t) w / (t_N - t_1) is made positive."""
+    t = _f64(t)
+    tbar = 0.5 * (t[0] + t[-1])
+    span = t[-1] - t[0] if t.shape[0] > 1 else 1.0
+    out = np.array(w, dtype=np.float64)
+    for k in range(out.shape[0]):
+        s1 = out[k].sum()
+        s2 = ((tbar - t) * out[k]).sum() / span
+        if (s1 if abs(s1) >= abs(s2) else s2) < 0.0:
+            out[k] = -out[k]
+    return out
+
+
+def idpss_tapers(t, fmax, fw, K):
+    """Interpolated-DPSS tapers (Table 3 step 3, the branch for fc0 = 0):
+    (a) the DPSS of length N and half-bandwidth f_w on the uniform grid
+    u_m = t_1 + m D, D = (t_N - t_1) / (N - 1) (scipy's tridiagonal solver;
+    half-bandwidth f_w D in cycles per grid step), (b) a natural cubic spline
+    from u to t (scipy), (c) the scale that makes w^T R(B) w = 2 f_w, with R(B)
+    from or_gpss_matrix; sign by ``fix_sign``.  Returns (w [K, N], lam [K]),
+    lam the concentrations of the uniform-grid DPSS."""
+    import scipy.signal.windows as sw
+    from scipy.interpolate import CubicSpline
+    t = _f64(t)
+    N = t.shape[0]
+    D = (t[-1] - t[0]) / (N - 1)
+    u = t[0] + D * np.arange(N)
+    v, lam = sw.dpss(N, N * fw * D, Kmax=K, return_ratios=True)
+    v = np.atleast_2d(v)
+    w = CubicSpline(u, v.T, bc_type="natural")(t).T
+    q = np.einsum("kn,nm,km->k", w, gpss_matrix(t, fmax), w)
+    w = w * np.sqrt(2.0 * fw / q)[:, None]
+    return fix_sign(t, w), np.atleast_1d(lam).copy()
 
 
 def fix_phase(t, fc0, w):
