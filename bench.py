@@ -161,6 +161,7 @@ def parse():
                     help="N of the dense jittered GEP stress solve (0: skip)")
     ap.add_argument("--multiband-n", type=int, default=4096,
                     help="samples of the multiband form (0 skips it)")
+    ap.add_argument("--no-idpss", action="store_true", help="skip the interpolated-DPSS form")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (byte-counter calibration)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
@@ -494,6 +495,67 @@ def multiband_form(m2n, torch, workloads, ctx, n, I, reps=3):
             "subbands": out, "kernels_ms_per_subband": kern}
 
 
+def idpss_form(m2n, torch, workloads, ctx, s_main, reps=5):
+    """Interpolated-DPSS tapers (Table 3 step 3 for fc0 = 0) next to the GEP
+    branch: on the main workload (a gapped unit grid, so R(B) = I and the
+    scale is O(N)) and on the jittered grid of the GEP stress (R(B) dense, the
+    scale an O(N^2) FP64 quadratic form).  Reports both solve times, the
+    kernel times of one interpolated solve, and the concentration
+    w^T R(A0) w / w^T R(B) w of each interpolated taper on the actual grid next
+    to the GEP eigenvalues: the suboptimality the paper trades for speed."""
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, s in (("main", s_main), ("jitter", workloads.jitter_stress(n=16384))):
+        t = torch.from_numpy(s.t).to(dev)
+        K = s.K
+        w = torch.empty((K, s.N), dtype=torch.float64, device=dev)
+        lam = torch.empty((K,), dtype=torch.float64, device=dev)
+        wg = torch.empty_like(w)
+        lg = torch.empty_like(lam)
+        m2n.idpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))
+        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(wg, lg))
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = {}
+        for label, fn, r in (("idpss", lambda: m2n.idpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam)), reps),
+                             ("gep", lambda: m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(wg, lg)),
+                              reps if name == "main" else 1)):
+            e0.record(stream)
+            for _ in range(r):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[label] = e0.elapsed_time(e1) / r
+        ctx.profile_reset()
+        ctx.profile(True)
+        m2n.idpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        ks = ctx.profile_read()
+        # concentration of each interpolated taper on the actual grid,
+        # w^T R(A0) w / w^T R(B) w, by dense FP64 products in row chunks
+        # (verification only); the GEP tapers reach lambda
+        qa = torch.zeros(K, dtype=torch.float64, device=dev)
+        qb = torch.zeros(K, dtype=torch.float64, device=dev)
+        for r0 in range(0, s.N, 2048):
+            tau = t[r0:r0 + 2048, None] - t[None, :]
+            ntau = torch.where(tau == 0, torch.ones_like(tau), tau)
+            for f, q in ((s.fw, qa), (s.fmax, qb)):
+                R = torch.where(tau == 0, torch.full_like(tau, 2 * f),
+                                torch.sin(2 * math.pi * f * tau) / (math.pi * ntau))
+                q += (w[:, r0:r0 + 2048] * (R @ w.T).T).sum(dim=1)
+            del tau, ntau, R
+        conc = (qa / qb).cpu().numpy()
+        torch.cuda.empty_cache()
+        out[name] = {"workload": s.name, "N": s.N, "K": K, "fw": s.fw,
+                     "idpss_ms": round(times["idpss"], 4), "gep_ms": round(times["gep"], 4),
+                     "kernels_ms": {k: round(v[0], 4) for k, v in sorted(ks.items(), key=lambda kv: -kv[1][0])[:8]},
+                     "concentration_idpss": [round(float(v), 9) for v in conc],
+                     "lambda_gep": [round(float(v), 9) for v in lg.cpu()]}
+    return out
+
+
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
     """Bytes each kernel must move per launch (its compulsory traffic)."""
     cs = 2 * prec_bytes                      # one complex grid value
@@ -708,6 +770,13 @@ def main():
         print(f"bench: multiband {multiband['ms_all_subbands']} ms for {multiband['Q']} sub-bands",
               file=sys.stderr, flush=True)
 
+    idpss = None
+    if not a.no_idpss:
+        print("bench: interpolated DPSS", file=sys.stderr, flush=True)
+        idpss = idpss_form(m2n, torch, workloads, ctx, s)
+        print(f"bench: idpss {idpss['main']['idpss_ms']} ms (GEP {idpss['main']['gep_ms']} ms) on {s.name}",
+              file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -743,6 +812,7 @@ def main():
         "served_form": served,
         "gep_stress": stress,
         "multiband": multiband,
+        "idpss": idpss,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -106,6 +106,32 @@ int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                 double *w, double *lambda);
 
 /*
+ * idpss_tapers -- the interpolated-DPSS branch of Table 3 step 3 (nominal band
+ * centred at 0; Sec. 3.3): tapers that approximate the GPSS tapers without a
+ * GEP on t.
+ *   (a) the DPSS of length N and half-bandwidth f_w D on the uniform grid
+ *       t_1 + m D, D = (t_N - t_1) / (N - 1);
+ *   (b) the natural cubic spline through those values, evaluated at t_n;
+ *   (c) the scale w_k^T R(B) w_k = 2 f_w (R(B) of the band |f| <= f_max);
+ *       sign as in gpss_tapers.
+ *
+ *   t       [N]     device, FP64, strictly increasing, N >= 2
+ *   fmax, fw        0 < fw < fmax; f_w D < 1/2
+ *   K               1 <= K <= min(N, 32)
+ *   w       [K*N]   device, FP64 out, taper k at w + k*N
+ *   lambda  [K]     device, FP64 out: the concentrations of the uniform-grid
+ *                   DPSS, descending (the interpolated tapers solve no GEP)
+ *
+ * The scale costs O(N) when R(B) is a multiple of the identity (every t_n an
+ * integer and 2 f_max a positive integer), else an O(N^2) FP64 quadratic
+ * form.  The call waits for its check of t (one round trip) and for the DPSS
+ * solve's; the rest is stream-ordered.  Errors: M2N_ERR_ARG (bad sizes or
+ * bands, non-finite t), M2N_ERR_T_ORDER.
+ */
+int idpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
+                 double fmax, double fw, int K, double *w, double *lambda);
+
+/*
  * gpss_tapers_subband -- one sub-band of the multiband partition (Sec. 2.4
  * sub-band matrix, Appendix A; Sec. 3.1 nominal band; Sec. 3.2 GEP at A0):
  * the K largest solutions of R(A0) w = lambda R(B^q) w, where B^q is

@@ -39,7 +39,8 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
-            "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband"]
+            "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
+            "idpss_tapers"]
 
 
 class M2NSeries(ctypes.Structure):
@@ -102,6 +103,8 @@ def _load():
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
     L.gpss_tapers.restype = i
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
+    L.idpss_tapers.restype = i
+    L.idpss_tapers.argtypes = [vp, vp, vp, i64, d, d, i, vp, vp]
     L.gpss_tapers_subband.restype = i
     L.gpss_tapers_subband.argtypes = [vp, vp, vp, i64, d, d, d, d, i, vp, vp]
     L.m2nufft_psd_subband.restype = i
@@ -204,6 +207,21 @@ def gpss_tapers(ctx: Context, t, fmax, fw, K, fc0=0.0, stream=None, out=None):
         w, lam = out
     _err(lib.gpss_tapers(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw),
                          float(fc0), int(K), _ptr(w), _ptr(lam)), "gpss_tapers")
+    return w, lam
+
+
+def idpss_tapers(ctx: Context, t, fmax, fw, K, stream=None, out=None):
+    """Interpolated-DPSS tapers (Table 3 step 3 for fc0 = 0): w [K, N] and the
+    uniform-grid DPSS concentrations [K]."""
+    t = _dev(t)
+    N = t.shape[0]
+    if out is None:
+        w = torch.empty((K, N), dtype=torch.float64, device=t.device)
+        lam = torch.empty((K,), dtype=torch.float64, device=t.device)
+    else:
+        w, lam = out
+    _err(lib.idpss_tapers(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw), int(K),
+                          _ptr(w), _ptr(lam)), "idpss_tapers")
     return w, lam
 
 

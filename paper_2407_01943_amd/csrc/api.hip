@@ -9,6 +9,10 @@ namespace m2n {
 
 static thread_local char g_err[512] = "";
 
+// interpolated-DPSS tapers (idpss.hip)
+int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
+              double* w, double* lambda);
+
 void set_error(const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -288,6 +292,16 @@ int gpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double f
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
+}
+
+int idpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,
+                 double* w, double* lambda) {
+    if (!ctx || !t || !w || !lambda) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return idpss_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
 }
 
 int gpss_tapers_subband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmin,
