@@ -169,6 +169,33 @@ int gpss_tapers_subband(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                         double *w, double *lambda);
 
 /*
+ * gpss_tapers_multiband -- gpss_tapers_subband for Q sub-bands at once (the
+ * multiband partition of Sec. 3.1; the sub-bands are independent).  Each
+ * sub-band runs on a child context of ctx (own workspace, streams and pinned
+ * records, created on first use with ctx's device and memory budget, released
+ * by m2n_destroy(ctx)) and a stream of its own, from a host thread of its
+ * own, so that the dense factorisations of different sub-bands overlap on the
+ * GPU.  Results equal the one-sub-band calls bitwise.
+ *
+ *   t       [N]     device, FP64 (ready on `stream`: the sub-bands wait for it)
+ *   fw, K           as in gpss_tapers_subband (shared by all sub-bands)
+ *   sb      [Q]     HOST array: f_min, f_max, fc0 and the device outputs w
+ *                   [2*K*N] (planar complex) and lambda [K] of each sub-band
+ *   Q               1 <= Q <= 16
+ *
+ * Blocks until every sub-band is complete.  Errors as gpss_tapers_subband;
+ * the message names the first failing sub-band.  Kernel timings of the child
+ * contexts are not reported by m2n_profile_read(ctx).
+ */
+typedef struct {
+    double fmin, fmax, fc0;
+    double *w, *lambda;
+} m2n_subband;
+
+int gpss_tapers_multiband(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
+                          double fw, int K, const m2n_subband *sb, int Q);
+
+/*
  * m2nufft_psd_subband -- Table 3 steps 4 and 5 for one sub-band (Sec. 3.2:
  * eigencoefficients of the shifted tapers on frequencies relative to fc0):
  *   J_k(i) = sum_n conj(w_k(t_n)) x(t_n) e^{-j 2 pi (f_lo + i df) t_n},

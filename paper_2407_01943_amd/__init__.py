@@ -40,7 +40,13 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
-            "idpss_tapers"]
+            "idpss_tapers", "gpss_tapers_multiband"]
+
+
+class M2NSubBand(ctypes.Structure):
+    """m2n_subband of include/m2n.h (host array, device output pointers)."""
+    _fields_ = [("fmin", ctypes.c_double), ("fmax", ctypes.c_double), ("fc0", ctypes.c_double),
+                ("w", ctypes.c_void_p), ("lam", ctypes.c_void_p)]
 
 
 class M2NSeries(ctypes.Structure):
@@ -103,6 +109,8 @@ def _load():
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
     L.gpss_tapers.restype = i
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
+    L.gpss_tapers_multiband.restype = i
+    L.gpss_tapers_multiband.argtypes = [vp, vp, vp, i64, d, i, ctypes.POINTER(M2NSubBand), i]
     L.idpss_tapers.restype = i
     L.idpss_tapers.argtypes = [vp, vp, vp, i64, d, d, i, vp, vp]
     L.gpss_tapers_subband.restype = i
@@ -240,6 +248,22 @@ def gpss_tapers_subband(ctx: Context, t, fmin, fmax, fw, fc0, K, stream=None, ou
                                  float(fw), float(fc0), int(K), _ptr(w), _ptr(lam)),
          "gpss_tapers_subband")
     return w, lam
+
+
+def gpss_tapers_multiband(ctx: Context, t, subbands, fw, K, stream=None):
+    """Several sub-bands at once; `subbands` is a list of (fmin, fmax, fc0).
+    Returns a list of (planar w [2K, N], lambda [K]), one per sub-band."""
+    t = _dev(t)
+    N = t.shape[0]
+    outs = [(torch.empty((2 * K, N), dtype=torch.float64, device=t.device),
+             torch.empty((K,), dtype=torch.float64, device=t.device)) for _ in subbands]
+    arr = (M2NSubBand * len(subbands))()
+    for a, (fmin, fmax, fc0), (w, lam) in zip(arr, subbands, outs):
+        a.fmin, a.fmax, a.fc0 = float(fmin), float(fmax), float(fc0)
+        a.w, a.lam = w.data_ptr(), lam.data_ptr()
+    _err(lib.gpss_tapers_multiband(ctx.handle, _stream(stream), _ptr(t), N, float(fw), int(K), arr,
+                                   len(subbands)), "gpss_tapers_multiband")
+    return outs
 
 
 def as_complex(w):

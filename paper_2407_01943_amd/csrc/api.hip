@@ -9,6 +9,9 @@ namespace m2n {
 
 static thread_local char g_err[512] = "";
 
+// several sub-bands at once on child contexts (subband.hip)
+int multiband_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fw, int K, const m2n_subband* sb,
+                  int Q);
 // interpolated-DPSS tapers (idpss.hip)
 int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
               double* w, double* lambda);
@@ -193,6 +196,8 @@ void m2n_destroy(m2n_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto sst : ctx->sub_streams) (void)hipStreamDestroy(sst);
+    for (auto c : ctx->subs) m2n_destroy(static_cast<m2n_ctx*>(c));
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->aux_fork) (void)hipEventDestroy(ctx->aux_fork);
     if (ctx->aux_join) (void)hipEventDestroy(ctx->aux_join);
@@ -327,6 +332,22 @@ int gpss_tapers_subband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, 
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return gep_subband(ctx, (hipStream_t)stream, t, N, fmin, fmax, fw, fc0, K, w, lambda);
+}
+
+int gpss_tapers_multiband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fw, int K,
+                          const m2n_subband* sb, int Q) {
+    if (!ctx || !t || !sb || Q < 1 || Q > 16) {
+        set_error("NULL argument or Q outside 1..16");
+        return M2N_ERR_ARG;
+    }
+    for (int q = 0; q < Q; ++q) {
+        if (!sb[q].w || !sb[q].lambda) {
+            set_error("sub-band %d: NULL output", q);
+            return M2N_ERR_ARG;
+        }
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return multiband_run(ctx, (hipStream_t)stream, t, N, fw, K, sb, Q);
 }
 
 int m2nufft_psd_subband(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,

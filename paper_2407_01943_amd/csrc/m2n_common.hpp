@@ -194,6 +194,10 @@ struct Ctx {
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork = nullptr, aux_join = nullptr;
     int aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);
+    // child contexts (own workspace, streams and pinned records) and their
+    // streams for sub-bands solved at once; created on first use
+    std::vector<Ctx*> subs;
+    std::vector<hipStream_t> sub_streams;
 
     // grow-only named workspace; returns M2N_OK / M2N_ERR_OOM / M2N_ERR_HIP
     int workspace(const char* name, size_t bytes, void** out);

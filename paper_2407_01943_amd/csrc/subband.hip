@@ -8,6 +8,8 @@
 // tapered series.  The 2K real parts go through the full-band NuFFT as 2K
 // tapers; k_sb_combine forms J_k and P_i = sum_k d_k |J_k(i)|^2.
 #include <cmath>
+#include <string>
+#include <thread>
 
 #include "m2n_common.hpp"
 
@@ -60,6 +62,63 @@ int subband_psd_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, 
         hipLaunchKernelGGL(k_sb_combine<double>, g, dim3(256), 0, st, (const cplx<double>*)vJ, K, I, weights,
                            (double*)P, (cplx<double>*)J);
     M2N_HIP(hipGetLastError());
+    return M2N_OK;
+}
+
+// Q sub-bands at once (Sec. 3.1: the sub-bands are independent).  Each runs
+// gpss_tapers_subband's path on a child context of its own (workspace, aux
+// stream, pinned records) and a stream of its own, from a host thread of its
+// own: one dense factorisation leaves most compute units idle, so the panel
+// chains of different sub-bands overlap.  The child streams first wait for
+// the caller's stream (t may still be in flight there); the call returns once
+// every sub-band is complete.  The first failing sub-band's error is
+// reported with its index.
+int multiband_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fw, int K, const m2n_subband* sb,
+                  int Q) {
+    while ((int)ctx->subs.size() < Q) {
+        m2n_ctx* c = nullptr;
+        M2N_TRY(m2n_create(ctx->device, ctx->budget, &c));
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            m2n_destroy(c);
+            set_error("hipStreamCreateWithFlags failed");
+            return M2N_ERR_HIP;
+        }
+        ctx->subs.push_back(c);
+        ctx->sub_streams.push_back(s);
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    hipEvent_t ready = nullptr;
+    M2N_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    if (hipEventRecord(ready, st) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        set_error("hipEventRecord failed");
+        return M2N_ERR_HIP;
+    }
+    std::vector<int> rc((size_t)Q, M2N_OK);
+    std::vector<std::string> msg((size_t)Q);
+    std::vector<std::thread> th;
+    th.reserve((size_t)Q);
+    for (int q = 0; q < Q; ++q) {
+        th.emplace_back([&, q]() {
+            if (hipSetDevice(ctx->device) != hipSuccess ||
+                hipStreamWaitEvent(ctx->sub_streams[q], ready, 0) != hipSuccess) {
+                rc[q] = M2N_ERR_HIP;
+                msg[q] = "stream setup failed";
+                return;
+            }
+            rc[q] = gep_subband(ctx->subs[q], ctx->sub_streams[q], t, N, sb[q].fmin, sb[q].fmax, fw, sb[q].fc0,
+                                K, sb[q].w, sb[q].lambda);
+            if (rc[q] != M2N_OK) msg[q] = m2n_last_error();   // the worker's own error text
+        });
+    }
+    for (auto& x : th) x.join();
+    (void)hipEventDestroy(ready);
+    for (int q = 0; q < Q; ++q)
+        if (rc[q] != M2N_OK) {
+            set_error("sub-band %d: %s", q, msg[q].c_str());
+            return rc[q];
+        }
     return M2N_OK;
 }
 

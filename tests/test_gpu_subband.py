@@ -150,3 +150,25 @@ def test_subband_errors(m2n, ctx):
     with pytest.raises(m2n.M2NError) as ei:          # t not increasing
         m2n.gpss_tapers_subband(ctx, _dev(t[::-1].copy()), 0.0, 0.5, 0.01, 0.2, 4)
     assert ei.value.code == m2n.M2N_ERR_T_ORDER
+
+
+def test_multiband_equals_single_calls(m2n, ctx):
+    """All sub-bands at once (child contexts, own streams) give bitwise the
+    one-sub-band results."""
+    s, sbs = W.multiband(n=700)
+    _say("multiband entry, two sub-bands, n=700")
+    outs = m2n.gpss_tapers_multiband(ctx, _dev(s.t), [(b.fmin, b.fmax, b.fc0) for b in sbs], s.fw, s.K)
+    torch.cuda.synchronize()
+    for (w, lam), b in zip(outs, sbs):
+        w1, l1 = m2n.gpss_tapers_subband(ctx, _dev(s.t), b.fmin, b.fmax, s.fw, b.fc0, s.K)
+        torch.cuda.synchronize()
+        assert torch.equal(w, w1) and torch.equal(lam, l1)
+
+
+def test_multiband_error_names_the_subband(m2n, ctx):
+    t = np.arange(512, dtype=np.float64)
+    _say("multiband entry, second sub-band not positive definite")
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.gpss_tapers_multiband(ctx, _dev(t), [(0.0, 0.5, 0.2), (0.1, 0.2, 0.15)], 2.0 / 512, 4)
+    assert ei.value.code == m2n.M2N_ERR_NOT_PD
+    assert "sub-band 1" in str(ei.value)
