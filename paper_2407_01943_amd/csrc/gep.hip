@@ -1564,32 +1564,36 @@ __global__ __launch_bounds__(TB * 4) void k_potrf(double* __restrict__ A, int64_
     double r[CW];
 #pragma unroll
     for (int u = 0; u < CW; ++u) r[u] = A[(o + i) + (o + CW * q + u) * Np];
-    for (int j = 0; j < TB; ++j) {
-        const int buf = j & 1;
-        if (q == j / CW) {
-            double v = 0.0;
+    // column j = CW qq + u with u unrolled, so that the owner's pivot column
+    // is a register of static index (no select chains over r)
+#pragma unroll 1
+    for (int qq = 0; qq < 4; ++qq) {
 #pragma unroll
-            for (int u = 0; u < CW; ++u) v = (u == j % CW) ? r[u] : v;
-            double d = rdlane(v, j);
-            if (!(d > 0.0)) {
-                if (i == 0 && o + j < N) atomicCAS(status, 0, -(int)(o + j + 1));
-                d = 1.0;
+        for (int u = 0; u < CW; ++u) {
+            const int j = CW * qq + u;
+            const int buf = u & 1;
+            if (q == qq) {
+                double v = r[u];
+                double d = rdlane(v, j);
+                if (!(d > 0.0)) {
+                    if (i == 0 && o + j < N) atomicCAS(status, 0, -(int)(o + j + 1));
+                    d = 1.0;
+                }
+                const double ljj = sqrt(d);
+                v = i > j ? v / ljj : (i == j ? ljj : 0.0);
+                r[u] = v;
+                col[buf][i] = v;
             }
-            const double ljj = sqrt(d);
-            v = i > j ? v / ljj : (i == j ? ljj : 0.0);
+            __syncthreads();
+            // all CW broadcasts in flight together, then a branch-free update
+            // (a predicated read per column would wait on each one in turn)
+            const double lij = col[buf][i];
+            double cv[CW];
 #pragma unroll
-            for (int u = 0; u < CW; ++u) r[u] = (u == j % CW) ? v : r[u];
-            col[buf][i] = v;
+            for (int uu = 0; uu < CW; ++uu) cv[uu] = col[buf][CW * q + uu];
+#pragma unroll
+            for (int uu = 0; uu < CW; ++uu) r[uu] = (CW * q + uu > j) ? r[uu] - lij * cv[uu] : r[uu];
         }
-        __syncthreads();
-        // all CW broadcasts in flight together, then a branch-free update
-        // (a predicated read per column would wait on each one in turn)
-        const double lij = col[buf][i];
-        double cv[CW];
-#pragma unroll
-        for (int u = 0; u < CW; ++u) cv[u] = col[buf][CW * q + u];
-#pragma unroll
-        for (int u = 0; u < CW; ++u) r[u] = (CW * q + u > j) ? r[u] - lij * cv[u] : r[u];
     }
 #pragma unroll
     for (int u = 0; u < CW; ++u) {
