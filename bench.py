@@ -571,6 +571,46 @@ def idpss_form(m2n, torch, workloads, ctx, s_main, reps=5):
     return out
 
 
+def schemes_form(m2n, torch, workloads, ctx, n_spectra=1000):
+    """The timing experiment's shape (Sec. 4): 1,000 spectra of 50-point
+    series, a quarter on each of the four sampling schemes (uniform, jitter,
+    missing data, arithmetic), f_w = 0.05, K = 4, 64 bands, one series per
+    call: interpolated-DPSS tapers then the FP64 NuFFT and average, and the
+    same with the GEP tapers.  Reports spectra per second (host round trips
+    included: each taper call waits for its t check) and, for the GEP tapers,
+    the series whose R(B) is numerically singular (samples denser than the
+    band needs, as in the arithmetic scheme): their Cholesky stops with
+    NOT_PD, while the interpolated branch needs no factorisation."""
+    dev = torch.device("cuda:0")
+    makers = [workloads.scheme_uniform, workloads.scheme_jitter, workloads.scheme_missing,
+              workloads.scheme_arithmetic]
+    series = [makers[i % 4](seed=100 + i) for i in range(n_spectra)]
+    data = [(torch.from_numpy(q.t).to(dev), torch.from_numpy(q.x).to(dev), q) for q in series]
+    out = {}
+    for label, taper in (("idpss", m2n.idpss_tapers), ("gep", m2n.gpss_tapers)):
+        def one(t, x, q):
+            try:
+                w, lam = taper(ctx, t, q.fmax, q.fw, q.K)
+            except m2n.M2NError as e:
+                if e.code != m2n.M2N_ERR_NOT_PD:
+                    raise
+                return 0
+            m2n.m2nufft_psd(ctx, t, x, w, lam, q.fmax, q.fw, q.f_lo, q.df, q.I, prec=m2n.M2N_FP64,
+                            want_E=False, check=False)
+            return 1
+        for t, x, q in data[:8]:
+            one(t, x, q)
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        done = sum(one(t, x, q) for t, x, q in data)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - h0
+        out[label] = {"seconds": round(sec, 4), "spectra": done, "not_pd": n_spectra - done,
+                      "spectra_per_s": round(done / sec, 1)}
+    return {"spectra": n_spectra, "N": 50, "K": 4, "fw": 0.05, "I": 64,
+            "schemes": ["uniform", "jitter", "missing", "arithmetic"], **out}
+
+
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
     """Bytes each kernel must move per launch (its compulsory traffic)."""
     cs = 2 * prec_bytes                      # one complex grid value
@@ -792,6 +832,13 @@ def main():
         print(f"bench: idpss {idpss['main']['idpss_ms']} ms (GEP {idpss['main']['gep_ms']} ms) on {s.name}",
               file=sys.stderr, flush=True)
 
+    schemes = None
+    if not a.no_idpss:
+        print("bench: sampling-scheme spectra", file=sys.stderr, flush=True)
+        schemes = schemes_form(m2n, torch, workloads, ctx)
+        print(f"bench: schemes {schemes['idpss']['spectra_per_s']} spectra/s (interpolated DPSS), "
+              f"{schemes['gep']['spectra_per_s']} (GEP)", file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -828,6 +875,7 @@ def main():
         "gep_stress": stress,
         "multiband": multiband,
         "idpss": idpss,
+        "schemes_1000": schemes,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

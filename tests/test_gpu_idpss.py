@@ -108,3 +108,21 @@ def test_idpss_errors(m2n, ctx):
     with pytest.raises(m2n.M2NError) as ei:
         m2n.idpss_tapers(ctx, _dev(t[::-1].copy()), 0.5, 0.01, 2)
     assert ei.value.code == m2n.M2N_ERR_T_ORDER
+
+
+def test_idpss_with_ftest(m2n, ctx, orc):
+    """Interpolated tapers are real, so the F-statistic of the full-band path
+    applies; its coherence gamma = F / (F + K - 1) against the oracle's."""
+    s = W.small_gapped()
+    K = 4
+    fw = 2.5 / (s.t[-1] - s.t[0])
+    _say("idpss with F-test, small_gapped")
+    w, lam = m2n.idpss_tapers(ctx, _dev(s.t), s.fmax, fw, K)
+    out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), w, lam, s.fmax, fw, s.f_lo, s.df, s.I,
+                          prec=m2n.M2N_FP64, want_E=False, want_F=True)
+    F = out["F"].cpu().numpy()
+    wo, _ = orc.idpss_tapers(s.t, s.fmax, fw, K)
+    Fo, _ = orc.ftest(orc.nudft(s.t, s.x, wo, s.f_lo, s.df, s.I), wo)
+    g = np.where(np.isinf(F), 1.0, F / (F + K - 1))
+    go = np.where(np.isinf(Fo), 1.0, Fo / (Fo + K - 1))
+    assert np.abs(g - go).max() < 1e-10
