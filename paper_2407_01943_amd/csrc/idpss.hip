@@ -154,7 +154,9 @@ __device__ __forceinline__ double id_sinc(double f, double tau) {
 // partial quadratic forms w_k^T R(B) w_k: workgroup (bx, by, bz) takes rows
 // n in [bx IT, (bx + 1) IT) against columns m in chunk by of cm columns for
 // the tapers k in [QK bz, QK bz + QK), staged through LDS QT columns at a
-// time; acc_k(n) = sum_m w_k(m) R(B)_{nm}, then the workgroup sums
+// time.  R(B) is symmetric, so only m >= n is summed, off-diagonal pairs
+// twice: acc_k(n) = w_k(n) R(B)_nn + 2 sum_{m > n} w_k(m) R(B)_{nm}; tiles
+// wholly below the workgroup's rows are skipped.  The workgroup then sums
 // w_k(n) acc_k(n) into part[(by gx + bx) K + k]
 constexpr int QK = 8;
 __global__ __launch_bounds__(IT) void k_id_quad(const double* __restrict__ t, int64_t N, int K, double fmax,
@@ -172,8 +174,10 @@ __global__ __launch_bounds__(IT) void k_id_quad(const double* __restrict__ t, in
     for (int k = 0; k < QK; ++k) acc[k] = 0.0;
     const int64_t m0 = (int64_t)blockIdx.y * cm;
     const int64_t m1 = m0 + cm < N ? m0 + cm : N;
+    const int64_t rlo = (int64_t)blockIdx.x * IT;   // first row of the workgroup
     for (int64_t mb = m0; mb < m1; mb += QT) {
         const int cnt = (int)(m1 - mb < QT ? m1 - mb : QT);
+        if (mb + cnt <= rlo) continue;   // every m < every n of this workgroup (uniform)
         __syncthreads();
         for (int e = threadIdx.x; e < QT; e += IT) ts[e] = e < cnt ? t[mb + e] : 0.0;
         for (int e = threadIdx.x; e < QK * QT; e += IT) {
@@ -183,7 +187,9 @@ __global__ __launch_bounds__(IT) void k_id_quad(const double* __restrict__ t, in
         __syncthreads();
         if (n < N)
             for (int j = 0; j < cnt; ++j) {
-                const double s = id_sinc(fmax, tn - ts[j]);
+                const int64_t m = mb + j;
+                if (m < n) continue;
+                const double s = (m == n ? 1.0 : 2.0) * id_sinc(fmax, tn - ts[j]);
 #pragma unroll
                 for (int k = 0; k < QK; ++k) acc[k] += ws[k][j] * s;
             }
@@ -312,7 +318,7 @@ int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax,
     const double* quad = nullptr;
     int nquad = 0;
     if (!lattice) {
-        const int64_t cm = 4096;
+        const int64_t cm = 1024;
         const int nc = (int)((N + cm - 1) / cm);
         void* vq;
         M2N_TRY(ctx->workspace("id_quad", sizeof(double) * (size_t)nb * nc * K, &vq));
