@@ -76,17 +76,23 @@ def test_binding_argument_counts_match_header():
     assert checked >= 10
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libm2n.so not built")
-def test_series_struct_matches_header():
-    # the ctypes mirror of m2n_series has the header's fields, in order
-    import paper_2407_01943_amd as m2n
-    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*m2n_series\s*;", _header_src(), flags=re.S).group(1)
+def _struct_fields(tag):
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + tag + r"\s*;", _header_src(), flags=re.S).group(1)
     fields = []
     for decl in body.split(";"):
         if decl.strip():
             # "const double *t, *x" -> t, x: the last word of each declarator
             fields += [part.split()[-1].lstrip("*") for part in decl.split(",")]
-    names = [f[0] for f in m2n.M2NSeries._fields_]
+    return fields
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libm2n.so not built")
+@pytest.mark.parametrize("tag,cls", [("m2n_series", "M2NSeries"), ("m2n_subband", "M2NSubBand")])
+def test_structs_match_header(tag, cls):
+    # the ctypes mirrors of the header's structs have its fields, in order
+    import paper_2407_01943_amd as m2n
+    fields = _struct_fields(tag)
+    names = [f[0] for f in getattr(m2n, cls)._fields_]
     assert len(names) == len(fields), (names, fields)
     for a, b in zip(names, fields):
         assert a == b or (a, b) == ("lam", "lambda"), (a, b)
