@@ -13,6 +13,7 @@ adds the two one-line steps that are clearer in numpy:
 * ``ftest``, ``f_critical``: the Thomson F-statistic from the eigencoefficients
   and the critical value of F(2, 2K-2) (Sec. 3.4);
 * ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order;
+* ``nudft_freqs``: eigencoefficients at an arbitrary list of band centres;
 * ``idpss_tapers``: the interpolated-DPSS tapers of Table 3 step 3 (fc0 = 0):
   uniform-grid DPSS, natural cubic spline to t, R(B) normalisation;
 * ``subband_tapers``, ``subband_eigcoeffs``, ``fix_phase``: one sub-band of
@@ -300,6 +301,22 @@ def subband_eigcoeffs(t, x, w, f_lo, df, I=None, bands=None):
     for j, i in enumerate(bands):
         u = (f_lo + i * df) * t
         J[:, j] = y @ np.exp(-2j * np.pi * (u - np.round(u)))
+    return J
+
+
+def nudft_freqs(t, x, w, freqs):
+    """J_k(i) = sum_n w_k(t_n) x(t_n) e^{-j 2 pi f_i t_n} at an arbitrary list
+    of band centres f_i (Sec. 3.2 eigencoefficients; the band centres of an
+    analysis need not be equally spaced), by direct summation with the phase
+    f_i t_n reduced modulo 1 before the exponential.  Real tapers [K, N]."""
+    t, x = _f64(t), _f64(x)
+    w = np.atleast_2d(_f64(w))
+    freqs = _f64(np.atleast_1d(freqs))
+    y = w * x[None, :]
+    J = np.empty((w.shape[0], freqs.shape[0]), dtype=np.complex128)
+    for i, f in enumerate(freqs):
+        u = f * t
+        J[:, i] = y @ np.exp(-2j * np.pi * (u - np.round(u)))
     return J
 
 

@@ -442,3 +442,21 @@ def test_ftest_null_distribution(orc):
     mean_ref = nu / (nu - 2)
     sd_ref = math.sqrt(2 * nu ** 2 * (2 + nu - 2) / (2 * (nu - 2) ** 2 * (nu - 4)))
     assert abs(Fs.mean() - mean_ref) < 4 * sd_ref / math.sqrt(n)
+
+
+def test_nudft_freqs_matches_progression_and_fft(orc):
+    """Eigencoefficients at a list of band centres: equal to the pinned
+    progression form at the same centres (any order, repeats allowed), and on
+    a uniform grid equal to numpy's FFT at the DFT frequencies."""
+    s = W.small_gapped()
+    w, _ = orc.gpss_tapers(s.t, s.fmax, s.fw, 3, method="jacobi")
+    rng = np.random.default_rng(3)
+    bands = rng.integers(0, s.I, size=40)
+    J0 = orc.nudft(s.t, s.x, w, s.f_lo, s.df, bands=bands)
+    J1 = orc.nudft_freqs(s.t, s.x, w, s.f_lo + bands * s.df)
+    assert np.abs(J1 - J0).max() < 1e-12 * np.abs(J0).max()
+    N = 64
+    t = np.arange(N, dtype=np.float64)
+    x = rng.standard_normal(N)
+    J2 = orc.nudft_freqs(t, x, np.ones((1, N)), np.arange(N) / N)
+    assert np.abs(J2[0] - np.fft.fft(x)).max() < 1e-12 * np.abs(np.fft.fft(x)).max()
