@@ -611,6 +611,31 @@ def schemes_form(m2n, torch, workloads, ctx, n_spectra=1000):
             "schemes": ["uniform", "jitter", "missing", "arithmetic"], **out}
 
 
+def psd_at_form(m2n, torch, ctx, s, w, n_centres=4096, reps=10):
+    """P at an arbitrary list of band centres (direct FP64 summation) on the
+    main workload's tapers: time per call and the rate in sample-centre pairs
+    per second (each pair one reduced sincos and 2K FMAs)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(dev)
+    x = torch.from_numpy(s.x).to(dev)
+    rng = np.random.default_rng(7)
+    freqs = torch.from_numpy(rng.uniform(-0.5, 0.5, n_centres)).to(dev)
+    m2n.m2nufft_psd_at(ctx, t, x, w, freqs, check=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        m2n.m2nufft_psd_at(ctx, t, x, w, freqs, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = float(s.N) * n_centres
+    return {"workload": s.name, "N": s.N, "K": int(w.shape[0]), "centres": n_centres, "ms": round(ms, 4),
+            "pairs_per_s": round(pairs / (ms * 1e-3), 1)}
+
+
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):
     """Bytes each kernel must move per launch (its compulsory traffic)."""
     cs = 2 * prec_bytes                      # one complex grid value
@@ -839,6 +864,13 @@ def main():
         print(f"bench: schemes {schemes['idpss']['spectra_per_s']} spectra/s (interpolated DPSS), "
               f"{schemes['gep']['spectra_per_s']} (GEP)", file=sys.stderr, flush=True)
 
+    print("bench: band-centre list", file=sys.stderr, flush=True)
+    wl = torch.empty((s.K, s.N), dtype=torch.float64, device=torch.device("cuda:0"))
+    ll = torch.empty((s.K,), dtype=torch.float64, device=torch.device("cuda:0"))
+    m2n.gpss_tapers(ctx, torch.from_numpy(s.t).cuda(), s.fmax, s.fw, s.K, out=(wl, ll))
+    psd_at = psd_at_form(m2n, torch, ctx, s, wl)
+    print(f"bench: band-centre list {psd_at['ms']} ms for {psd_at['centres']} centres", file=sys.stderr, flush=True)
+
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
         "metric": "tapered NuFFT Mpts*tapers*bands/s + PSDs/s at 1e-5 rel err; p50/p99 latency",
@@ -876,6 +908,7 @@ def main():
         "multiband": multiband,
         "idpss": idpss,
         "schemes_1000": schemes,
+        "psd_at": psd_at,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -106,6 +106,26 @@ int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                 double *w, double *lambda);
 
 /*
+ * m2nufft_psd_at -- Table 3 steps 4 and 5 at an arbitrary list of band
+ * centres (Sec. 3.2; the centres need not be equally spaced), by direct FP64
+ * summation: J_k(i) = sum_n w_k(t_n) x(t_n) e^{-j 2 pi f_i t_n} and
+ * P_i = sum_k d_k |J_k(i)|^2.  Costs N*I complex exponentials: meant for a
+ * modest number of centres (for many equally spaced ones use m2nufft_psd).
+ *
+ *   t, x    [N]     device, FP64
+ *   w       [K*N]   device, FP64 real tapers, 1 <= K <= 16
+ *   freqs   [I]     device, FP64 band centres, any order, repeats allowed
+ *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
+ *   P       [I]     device out, FP64
+ *   J       [K*I]   device out or NULL, double2
+ *
+ * Stream-ordered and asynchronous.  Errors: M2N_ERR_ARG.
+ */
+int m2nufft_psd_at(m2n_ctx *ctx, void *stream, const double *t, const double *x,
+                   int64_t N, const double *w, int K, const double *freqs,
+                   int64_t I, const double *weights, double *P, void *J);
+
+/*
  * idpss_tapers -- the interpolated-DPSS branch of Table 3 step 3 (nominal band
  * centred at 0; Sec. 3.3): tapers that approximate the GPSS tapers without a
  * GEP on t.

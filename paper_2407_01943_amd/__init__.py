@@ -40,7 +40,7 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
-            "idpss_tapers", "gpss_tapers_multiband"]
+            "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at"]
 
 
 class M2NSubBand(ctypes.Structure):
@@ -109,6 +109,8 @@ def _load():
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
     L.gpss_tapers.restype = i
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
+    L.m2nufft_psd_at.restype = i
+    L.m2nufft_psd_at.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
     L.gpss_tapers_multiband.restype = i
     L.gpss_tapers_multiband.argtypes = [vp, vp, vp, i64, d, i, ctypes.POINTER(M2NSubBand), i]
     L.idpss_tapers.restype = i
@@ -216,6 +218,23 @@ def gpss_tapers(ctx: Context, t, fmax, fw, K, fc0=0.0, stream=None, out=None):
     _err(lib.gpss_tapers(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw),
                          float(fc0), int(K), _ptr(w), _ptr(lam)), "gpss_tapers")
     return w, lam
+
+
+def m2nufft_psd_at(ctx: Context, t, x, w, freqs, weights=None, want_J=False, stream=None, check=True):
+    """P (and J) at an arbitrary list of band centres, by direct FP64
+    summation.  Returns {"P": [I], "J": [K, I] or None}."""
+    t, x, w, freqs = _dev(t), _dev(x), _dev(w), _dev(freqs)
+    K, N = w.shape
+    I = freqs.shape[0]
+    P = torch.empty((I,), dtype=torch.float64, device=t.device)
+    J = torch.empty((K, I), dtype=torch.complex128, device=t.device) if want_J else None
+    if weights is not None:
+        weights = _dev(weights)
+    _err(lib.m2nufft_psd_at(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w), K, _ptr(freqs), I,
+                            _ptr(weights), _ptr(P), _ptr(J)), "m2nufft_psd_at")
+    if check:
+        ctx.check(stream)
+    return {"P": P, "J": J}
 
 
 def idpss_tapers(ctx: Context, t, fmax, fw, K, stream=None, out=None):

@@ -12,6 +12,9 @@ static thread_local char g_err[512] = "";
 // several sub-bands at once on child contexts (subband.hip)
 int multiband_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fw, int K, const m2n_subband* sb,
                   int Q);
+// eigencoefficients at a list of band centres (nudft_list.hip)
+int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
+                   const double* freqs, int64_t I, const double* weights, double* P, void* J);
 // interpolated-DPSS tapers (idpss.hip)
 int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
               double* w, double* lambda);
@@ -297,6 +300,16 @@ int gpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double f
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
+}
+
+int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N, const double* w,
+                   int K, const double* freqs, int64_t I, const double* weights, double* P, void* J) {
+    if (!ctx) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
 }
 
 int idpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,
