@@ -126,6 +126,29 @@ int m2nufft_psd_at(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                    int64_t I, const double *weights, double *P, void *J);
 
 /*
+ * m2nufft_psd_at_noalloc -- m2nufft_psd_at for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, layouts and results (the sample
+ * chunks' partial sums are added in the same chunk order; when they would not
+ * fit, fewer and longer chunks are used, which changes the FP64 rounding
+ * only).  The partial sums live in a library-owned device array of 16 MiB
+ * per GPU (M2N_NOALLOC_SCRATCH_BYTES), held from m2n_create until the
+ * process ends; the call allocates nothing, grows no workspace and records no
+ * timing events.
+ *
+ * Limits and sharing: K * I * 16 bytes must not exceed the array (K = 16
+ * allows I <= 65536), else M2N_ERR_ARG.  Every call on one GPU uses the same
+ * array: calls that overlap on one GPU (different streams, threads or
+ * contexts without ordering between them) race and give wrong results.
+ * Stream-ordered and asynchronous.  Errors: M2N_ERR_ARG.
+ */
+#define M2N_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int m2nufft_psd_at_noalloc(m2n_ctx *ctx, void *stream, const double *t,
+                           const double *x, int64_t N, const double *w, int K,
+                           const double *freqs, int64_t I,
+                           const double *weights, double *P, void *J);
+
+/*
  * idpss_tapers -- the interpolated-DPSS branch of Table 3 step 3 (nominal band
  * centred at 0; Sec. 3.3): tapers that approximate the GPSS tapers without a
  * GEP on t.

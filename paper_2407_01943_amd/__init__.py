@@ -40,7 +40,8 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
-            "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at"]
+            "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at",
+            "m2nufft_psd_at_noalloc"]
 
 
 class M2NSubBand(ctypes.Structure):
@@ -111,6 +112,8 @@ def _load():
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
     L.m2nufft_psd_at.restype = i
     L.m2nufft_psd_at.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
+    L.m2nufft_psd_at_noalloc.restype = i
+    L.m2nufft_psd_at_noalloc.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
     L.gpss_tapers_multiband.restype = i
     L.gpss_tapers_multiband.argtypes = [vp, vp, vp, i64, d, i, ctypes.POINTER(M2NSubBand), i]
     L.idpss_tapers.restype = i
@@ -235,6 +238,17 @@ def m2nufft_psd_at(ctx: Context, t, x, w, freqs, weights=None, want_J=False, str
     if check:
         ctx.check(stream)
     return {"P": P, "J": J}
+
+
+def m2nufft_psd_at_noalloc(ctx: Context, t, x, w, freqs, P, J=None, weights=None, stream=None):
+    """m2nufft_psd_at into caller-allocated outputs P [I] (float64) and J
+    [K, I] (complex128 or None); the library allocates nothing (its partial
+    sums use a fixed per-device scratch array)."""
+    K, N = w.shape
+    I = freqs.shape[0]
+    _err(lib.m2nufft_psd_at_noalloc(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w), K,
+                                    _ptr(freqs), I, _ptr(weights), _ptr(P), _ptr(J)),
+         "m2nufft_psd_at_noalloc")
 
 
 def idpss_tapers(ctx: Context, t, fmax, fw, K, stream=None, out=None):

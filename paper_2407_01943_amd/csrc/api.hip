@@ -15,6 +15,11 @@ int multiband_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double f
 // eigencoefficients at a list of band centres (nudft_list.hip)
 int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
                    const double* freqs, int64_t I, const double* weights, double* P, void* J);
+// the same with its partial sums in the per-device scratch array (no allocation)
+int nudft_list_run_noalloc(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w,
+                           int K, const double* freqs, int64_t I, const double* weights, double* P, void* J);
+// device address of that array, looked up once per device (device current)
+int noalloc_scratch_init(int device);
 // interpolated-DPSS tapers (idpss.hip)
 int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
               double* w, double* lambda);
@@ -172,6 +177,12 @@ int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx** out) {
     }
     (void)hipMemset(e, 0, 256);
     c->dev_err = (unsigned*)e;
+    const int st = noalloc_scratch_init(hip_device);
+    if (st != M2N_OK) {
+        (void)hipFree(e);
+        delete c;
+        return st;
+    }
     *out = c;
     return M2N_OK;
 }
@@ -310,6 +321,17 @@ int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x,
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
+}
+
+int m2nufft_psd_at_noalloc(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
+                           const double* w, int K, const double* freqs, int64_t I, const double* weights,
+                           double* P, void* J) {
+    if (!ctx) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return nudft_list_run_noalloc(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
 }
 
 int idpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,

@@ -10,7 +10,14 @@
 // product and its rounding error (FMA) and reduced modulo 1 before sincospi.
 // The chunks' partial sums go to a workspace and k_nudft_reduce adds them in
 // chunk order (deterministic) and forms J and P.
+//
+// The allocation-free variant puts those partial sums in `scratch`, a
+// file-scope device array of NOALLOC_SCRATCH_BYTES that every device holds
+// once for the life of the process; its device address is looked up once per
+// device (noalloc_scratch_init, called by m2n_create) and only that address
+// is handed to the kernels.
 #include <cmath>
+#include <mutex>
 
 #include "m2n_common.hpp"
 
@@ -100,31 +107,111 @@ __global__ __launch_bounds__(LT) void k_nudft_reduce(const cplx<double>* __restr
 
 }  // namespace
 
-int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
-                   const double* freqs, int64_t I, const double* weights, double* P, void* J) {
+namespace {
+
+// samples per chunk (a multiple of LS) and chunk count, so that about 1,024
+// workgroups run; at most max_chunks chunks
+void chunking(int64_t N, int64_t I, int64_t max_chunks, int64_t* nchunk_out, int64_t* nc_out) {
+    const int64_t bx = (I + LT - 1) / LT;
+    int64_t nchunk = (1024 + bx - 1) / bx;
+    if (nchunk > max_chunks) nchunk = max_chunks;
+    const int64_t tiles = (N + LS - 1) / LS;
+    if (nchunk > tiles) nchunk = tiles;
+    if (nchunk < 1) nchunk = 1;
+    const int64_t nc = (tiles + nchunk - 1) / nchunk * LS;
+    *nc_out = nc;
+    *nchunk_out = (N + nc - 1) / nc;
+}
+
+int check_args(const double* t, const double* x, const double* w, const double* freqs, const double* P, int64_t N,
+               int K, int64_t I) {
     if (!t || !x || !w || !freqs || !P || N < 1 || K < 1 || K > LK || I < 1) {
         set_error("bad argument (N = %lld, K = %d (<= %d), I = %lld)", (long long)N, K, LK, (long long)I);
         return M2N_ERR_ARG;
     }
-    // sample chunks of a multiple of LS so that about 1,024 workgroups run
+    return M2N_OK;
+}
+
+void launch_list(hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
+                 const double* freqs, int64_t I, const double* weights, double* P, void* J, int64_t nchunk,
+                 int64_t nc, cplx<double>* part) {
     const int64_t bx = (I + LT - 1) / LT;
-    int64_t nchunk = (1024 + bx - 1) / bx;
-    const int64_t tiles = (N + LS - 1) / LS;
-    if (nchunk > tiles) nchunk = tiles;
-    const int64_t nc = (tiles + nchunk - 1) / nchunk * LS;
-    nchunk = (N + nc - 1) / nc;
+    hipLaunchKernelGGL(k_nudft_list, dim3((unsigned)bx, (unsigned)nchunk), dim3(LT), 0, st, t, x, w, N, K, freqs, I,
+                       nc, part);
+    hipLaunchKernelGGL(k_nudft_reduce, dim3((unsigned)bx), dim3(LT), 0, st, (const cplx<double>*)part, (int)nchunk, K,
+                       I, weights, P, (cplx<double>*)J);
+}
+
+// ------------------------------------------------ allocation-free variant
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+constexpr int MAX_DEVICES = 64;
+__device__ __align__(256) cplx<double> scratch[NOALLOC_SCRATCH_BYTES / sizeof(cplx<double>)];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+
+int noalloc_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error("device %d out of range for the scratch table", device);
+        return M2N_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return M2N_OK;
+    int cur = -1;
+    M2N_HIP(hipGetDevice(&cur));
+    if (cur != device) {
+        set_error("scratch lookup for device %d while device %d is current", device, cur);
+        return M2N_ERR_ARG;
+    }
+    void* p = nullptr;
+    M2N_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+        set_error("no device address for the scratch array");
+        return M2N_ERR_HIP;
+    }
+    g_scratch_ptr[device] = p;
+    return M2N_OK;
+}
+
+size_t noalloc_scratch_bytes() { return NOALLOC_SCRATCH_BYTES; }
+
+int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
+                   const double* freqs, int64_t I, const double* weights, double* P, void* J) {
+    M2N_TRY(check_args(t, x, w, freqs, P, N, K, I));
+    int64_t nchunk, nc;
+    chunking(N, I, INT64_MAX, &nchunk, &nc);
     void* vp;
     M2N_TRY(ctx->workspace("nl_part", sizeof(cplx<double>) * (size_t)nchunk * K * I, &vp));
     {
         M2N_PROF(ctx, st, "k_nudft_list");
-        hipLaunchKernelGGL(k_nudft_list, dim3((unsigned)bx, (unsigned)nchunk), dim3(LT), 0, st, t, x, w, N, K, freqs,
-                           I, nc, (cplx<double>*)vp);
+        launch_list(st, t, x, N, w, K, freqs, I, weights, P, J, nchunk, nc, (cplx<double>*)vp);
     }
-    {
-        M2N_PROF(ctx, st, "k_nudft_reduce");
-        hipLaunchKernelGGL(k_nudft_reduce, dim3((unsigned)bx), dim3(LT), 0, st, (const cplx<double>*)vp, (int)nchunk,
-                           K, I, weights, P, (cplx<double>*)J);
+    M2N_HIP(hipGetLastError());
+    return M2N_OK;
+}
+
+// The same sums with the partial results in the per-device scratch array: no
+// allocation, no workspace growth, no timing events.  Fewer sample chunks
+// when K I nchunk complex values would not fit (the reduction order is still
+// the chunk order).
+int nudft_list_run_noalloc(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w,
+                           int K, const double* freqs, int64_t I, const double* weights, double* P, void* J) {
+    M2N_TRY(check_args(t, x, w, freqs, P, N, K, I));
+    const size_t per_chunk = sizeof(cplx<double>) * (size_t)K * (size_t)I;
+    if (per_chunk > NOALLOC_SCRATCH_BYTES) {
+        set_error("K I = %lld complex partial sums exceed the %zu-byte scratch of the allocation-free call",
+                  (long long)K * (long long)I, NOALLOC_SCRATCH_BYTES);
+        return M2N_ERR_ARG;
     }
+    void* ptr = ctx->device >= 0 && ctx->device < MAX_DEVICES ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!ptr) {
+        set_error("scratch array of device %d not initialised", ctx->device);
+        return M2N_ERR_HIP;
+    }
+    int64_t nchunk, nc;
+    chunking(N, I, (int64_t)(NOALLOC_SCRATCH_BYTES / per_chunk), &nchunk, &nc);
+    launch_list(st, t, x, N, w, K, freqs, I, weights, P, J, nchunk, nc, (cplx<double>*)ptr);
     M2N_HIP(hipGetLastError());
     return M2N_OK;
 }
