@@ -293,9 +293,24 @@ int m2nufft_eigcoeffs(m2n_ctx *ctx, void *stream, const double *t,
  *   fmax, fw        band parameters the tapers were built for (needed for E)
  *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
  *   P       [I]     device out, float (FP32) or double (FP64)
- *   E       [I]     device out or NULL; implemented when R(B) is a multiple
- *                   of the identity (t on a lattice of spacing beta with
- *                   2 f_max beta a positive integer), else M2N_ERR_UNSUPPORTED
+ *   E       [I]     device out or NULL: Ehat_i for any strictly increasing
+ *                   t.  Where R(B) is a multiple of the identity (every t_n an
+ *                   integer, 2 f_max a positive integer) D_k(i) = 2 f_max
+ *                   |w_k|^2 for every band and the NuFFT pass writes it.
+ *                   Elsewhere D_k(i) is the integral of the taper's spectral
+ *                   window |W_k(f)|^2, W_k(f) = sum_n w_k(t_n) e^{-j 2 pi f t_n},
+ *                   over [f_i - f_max, f_i + f_max] (equal to the quadratic
+ *                   form): Gauss-Legendre sums over cells of width df, the
+ *                   window samples from batched NuFFTs of the bare tapers on
+ *                   I + floor(2 f_max / df) - 1 band centres per node (work
+ *                   space about (nodes * K * (I + 2 f_max / df)) reals; the
+ *                   node count grows with df (t_N - t_1)).  Needs
+ *                   I + 2 f_max / df <= 2^21 + 1 and df (t_N - t_1) <= about
+ *                   20 there (else M2N_ERR_UNSUPPORTED), and t strictly
+ *                   increasing (else M2N_ERR_T_ORDER).  The call launches a
+ *                   check of t first and reads it once the NuFFT is queued
+ *                   (the host waits for the check, the device does not wait
+ *                   for the host).
  *   J       [K*I]   device out or NULL, as in m2nufft_eigcoeffs
  *   F       [I]     device out or NULL (same type as P): the Thomson
  *                   F-statistic of every band (Sec. 3.4), with the tapers'
@@ -307,7 +322,8 @@ int m2nufft_eigcoeffs(m2n_ctx *ctx, void *stream, const double *t,
  *                   (M2N_ERR_ARG otherwise).  +inf where the residual
  *                   vanishes.
  *
- * Stream-ordered and asynchronous once the plan exists.
+ * Stream-ordered and asynchronous once the plan exists (with E, the call
+ * returns after the device has passed the check of t).
  */
 int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                 int64_t N, const double *w, const double *lambda, int K,

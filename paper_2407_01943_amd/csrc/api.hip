@@ -205,6 +205,7 @@ void m2n_destroy(m2n_ctx* ctx) {
     if (ctx->hinfo) (void)hipHostFree(ctx->hinfo);
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->hstage_ev) (void)hipEventDestroy(ctx->hstage_ev);
+    if (ctx->tcheck_ev) (void)hipEventDestroy(ctx->tcheck_ev);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -281,11 +282,6 @@ int m2n_check(m2n_ctx* ctx, void* stream) {
         if (v & DEVERR_NONFINITE) {
             set_error("non-finite sampling time or sample value");
             return M2N_ERR_ARG;
-        }
-        if (v & DEVERR_E_UNSUPPORTED) {
-            set_error("Ehat is implemented only when R(B) is a multiple of the identity "
-                      "(integer t and integer 2 f_max)");
-            return M2N_ERR_UNSUPPORTED;
         }
     }
     return M2N_OK;

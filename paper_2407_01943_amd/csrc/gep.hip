@@ -2480,10 +2480,11 @@ struct TStat {
     double t0 = 0, tN = 0;
 };
 
-// Check the sampling times of every series on the device (one launch) and
-// wait for the records: one host round trip for the whole set.
-int t_check(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TStat>& out) {
-    std::vector<TaSeries> ds(ns);
+// Launch the check of the sampling times of every series (one launch); the
+// records land in the pinned host record and are read by t_check_read once
+// the stream has passed the launch.
+int t_check_launch(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TaSeries>& ds) {
+    ds.assign(ns, TaSeries());
     size_t ninfo = 0;
     int maxblk = 1;
     for (int i = 0; i < ns; ++i) {
@@ -2519,7 +2520,11 @@ int t_check(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TStat
         hipLaunchKernelGGL(k_t_analyze, dim3((unsigned)maxblk, (unsigned)ns), dim3(256), 0, st, ds[0], D);
     }
     M2N_HIP(hipGetLastError());
-    M2N_HIP(hipStreamSynchronize(st));
+    return M2N_OK;
+}
+
+void t_check_read(const std::vector<TaSeries>& ds, std::vector<TStat>& out) {
+    const int ns = (int)ds.size();
     out.assign(ns, TStat());
     for (int i = 0; i < ns; ++i) {
         TStat& r = out[i];
@@ -2532,6 +2537,15 @@ int t_check(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TStat
         r.t0 = ds[i].hdr[0];
         r.tN = ds[i].hdr[1];
     }
+}
+
+// Check the sampling times of every series on the device (one launch) and
+// wait for the records: one host round trip for the whole set.
+int t_check(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<TStat>& out) {
+    std::vector<TaSeries> ds;
+    M2N_TRY(t_check_launch(ctx, st, in, ns, ds));
+    M2N_HIP(hipStreamSynchronize(st));
+    t_check_read(ds, out);
     return M2N_OK;
 }
 
@@ -3077,6 +3091,33 @@ int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N, double fma
     g.w = w_out;
     g.lambda = lambda_out;
     return gep_run_batch(ctx, st, &g, 1);
+}
+
+// The t check for callers outside this file: launched on `st`, `done`
+// recorded after it; the summaries are read (after waiting for `done`) by the
+// returned function.
+int t_check_begin(Ctx* ctx, hipStream_t st, const double* const* t, const int64_t* N, int ns, hipEvent_t done,
+                  std::function<void(std::vector<TSummary>&)>* read) {
+    std::vector<GepIn> in((size_t)ns);
+    for (int i = 0; i < ns; ++i) {
+        in[i].t = t[i];
+        in[i].N = N[i];
+    }
+    auto ds = std::make_shared<std::vector<TaSeries>>();
+    M2N_TRY(t_check_launch(ctx, st, in.data(), ns, *ds));
+    M2N_HIP(hipEventRecord(done, st));
+    *read = [ds, done](std::vector<TSummary>& out) {
+        (void)hipEventSynchronize(done);
+        std::vector<TStat> r;
+        t_check_read(*ds, r);
+        out.assign(r.size(), TSummary());
+        for (size_t i = 0; i < r.size(); ++i) {
+            out[i].flags = r[i].flags;
+            out[i].t0 = r[i].t0;
+            out[i].tN = r[i].tN;
+        }
+    };
+    return M2N_OK;
 }
 
 }  // namespace m2n

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -62,7 +63,6 @@ void set_error(const char* fmt, ...);
 // Device-side sticky error bits (OR-ed by kernels, read by m2n_check).
 enum : unsigned {
     DEVERR_NONFINITE = 1u,     // a non-finite t or x reached a kernel
-    DEVERR_E_UNSUPPORTED = 2u, // Ehat asked for a non-diagonal R(B)
 };
 
 // ---------------------------------------------------------- device buffers
@@ -158,6 +158,19 @@ struct GepIn {
 // many series: one t check for all, the lattice low-rank ones in one set of
 // launches, the rest one by one
 int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
+// what the t check found for one series: flags bit 0 a non-finite t_n, bit 1
+// a step t_n <= t_{n-1}, bit 2 a t_n that is not an integer; t_0 and t_{N-1}
+struct TSummary {
+    int flags = 0;
+    double t0 = 0, tN = 0;
+};
+// launch the t check of ns series on st and record `done` after it; *read
+// waits for `done` and fills one summary per series (gep.hip)
+int t_check_begin(Ctx* ctx, hipStream_t st, const double* const* t, const int64_t* N, int ns, hipEvent_t done,
+                  std::function<void(std::vector<TSummary>&)>* read);
+// Ehat of one series whose R(B) is not a multiple of the identity: D_k(i) by
+// quadrature of |W_k|^2 over every band's window (ehat.hip); span = t_N - t_1
+int ehat_general(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol, const NuSeriesIn& s, double span);
 
 // ----------------------------------------------------------------- context
 struct Ctx {
@@ -191,6 +204,7 @@ struct Ctx {
 
     // a second stream (default priority) and two events for work that
     // overlaps the caller's stream, created on first use
+    hipEvent_t tcheck_ev = nullptr;     // marks the t check of an Ehat request
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork = nullptr, aux_join = nullptr;
     int aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);

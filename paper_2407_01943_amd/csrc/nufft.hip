@@ -400,7 +400,6 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
         const int dg = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
         d.diag[0] = dg;
         if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
-        if (d.E && !dg) atomicOr(a.dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
     }
 }
 
@@ -1035,7 +1034,6 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
     const R ev = diag ? (R)(esum / (double)K) : (R)NAN;
     if (threadIdx.x == 0) {
         if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
-        if (E && !diag) atomicOr(a.dev_err, (unsigned)DEVERR_E_UNSUPPORTED);
     }
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) {
@@ -1461,8 +1459,42 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
     for (int i = 0; i < nseries; ++i) M2N_TRY(check_series(series[i], I));
     NufftPlan* p = nullptr;
     M2N_TRY(get_plan(ctx, I, prec, tol, &p));
-    if (prec == M2N_FP32) return run_typed<float>(ctx, st, *p, series, nseries);
-    return run_typed<double>(ctx, st, *p, series, nseries);
+    // Ehat: where R(B) is a multiple of the identity the NuFFT pass writes
+    // it (band-constant); elsewhere the window quadrature overwrites it.  The
+    // t check that tells them apart is launched first and read once the
+    // NuFFT is queued, so the device does not wait for the host.
+    std::vector<int> eidx;
+    for (int i = 0; i < nseries; ++i)
+        if (series[i].E) eidx.push_back(i);
+    std::function<void(std::vector<TSummary>&)> read_t;
+    if (!eidx.empty()) {
+        std::vector<const double*> tp;
+        std::vector<int64_t> Np;
+        for (int i : eidx) {
+            tp.push_back(series[i].t);
+            Np.push_back(series[i].N);
+        }
+        if (!ctx->tcheck_ev) M2N_HIP(hipEventCreateWithFlags(&ctx->tcheck_ev, hipEventDisableTiming));
+        M2N_TRY(t_check_begin(ctx, st, tp.data(), Np.data(), (int)eidx.size(), ctx->tcheck_ev, &read_t));
+    }
+    if (prec == M2N_FP32) M2N_TRY(run_typed<float>(ctx, st, *p, series, nseries));
+    else M2N_TRY(run_typed<double>(ctx, st, *p, series, nseries));
+    if (eidx.empty()) return M2N_OK;
+    std::vector<TSummary> ts;
+    read_t(ts);
+    for (size_t e = 0; e < eidx.size(); ++e) {
+        const NuSeriesIn& s = series[eidx[e]];
+        const TSummary& r = ts[e];
+        if (r.flags & 1) continue;   // non-finite t: flagged by the NuFFT kernels
+        if (r.flags & 2) {
+            set_error("series %d: Ehat needs strictly increasing sampling times", eidx[e]);
+            return M2N_ERR_T_ORDER;
+        }
+        const double c = 2.0 * s.fmax;
+        const bool diag = !(r.flags & 4) && c == std::rint(c) && c >= 1.0;
+        if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, tol, s, s.N > 1 ? r.tN - r.t0 : 0.0));
+    }
+    return M2N_OK;
 }
 
 int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,

@@ -313,6 +313,32 @@ def test_ehat_nonlattice_matches_rayleigh_quotient(orc):
         assert abs(E[b] - np.mean(np.abs(lam - np.array(lh)))) < 1e-12
 
 
+def test_ehat_d_is_spectral_window_integral(orc):
+    # Appendix B with R(B) written as an integral over the signal band:
+    # D_k(i) = int_{df_i - f_max}^{df_i + f_max} |W_k(f)|^2 df, W_k the taper's
+    # spectral window.  Brute-force quadrature in f (composite Gauss-Legendre,
+    # W_k summed directly) against the oracle's quadratic form, on the paper's
+    # 5n/6 and arithmetic schemes and at a band count whose window ends inside
+    # a band spacing (f_max = 0.3)
+    xg, wg = np.polynomial.legendre.leggauss(40)
+    for s, fmax in ((W.scheme_missing(), 0.5), (W.scheme_arithmetic(), 0.5), (W.scheme_missing(), 0.3)):
+        if fmax == 0.5:
+            w, lam = orc.gpss_tapers(s.t, fmax, s.fw, s.K)
+        else:   # R(B) of f_max = 0.3 is numerically singular on this grid: any tapers
+            w = np.random.default_rng(7).standard_normal((s.K, s.N)) * 0.05
+            lam = np.full(s.K, 0.9)
+        bands = np.array([0, 17, 40, 63], dtype=np.int64)
+        _, D = orc.ehat(s.t, w, lam, fmax, s.fw, -0.5, 1.0 / 64, bands=bands)
+        for b, i in enumerate(bands):
+            fc = -0.5 + i / 64.0
+            edges = np.linspace(fc - fmax, fc + fmax, 201)
+            f = (0.5 * (edges[:-1] + edges[1:])[:, None] + 0.5 * np.diff(edges)[:, None] * xg).ravel()
+            wt = (0.5 * np.diff(edges)[:, None] * wg).ravel()
+            Wf = np.exp(-2j * np.pi * np.outer(f, s.t)) @ w.T          # [nf, K]
+            Dq = (wt[:, None] * np.abs(Wf) ** 2).sum(axis=0)
+            np.testing.assert_allclose(D[:, b], Dq, rtol=1e-12)
+
+
 def test_unbiased_for_white_noise(orc):
     # P7 (Sec. 3.3): E[P(A_i)] = 2 f_w sigma^2 for white noise on the lattice
     s = W.small_gapped()

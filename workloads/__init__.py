@@ -221,11 +221,12 @@ def scheme_jitter(seed: int = 11, n: int = 50, sigma: float = 0.1) -> Series:
     return _scheme("jitter", t, seed)
 
 
-def scheme_missing(seed: int = 12) -> Series:
-    """t_n = 5n/6 for n = 1..60 with 10 samples removed at random."""
+def scheme_missing(seed: int = 12, L: int = 60, n_keep: int = 50) -> Series:
+    """t_n = 5n/6 for n = 1..L with L - n_keep samples removed at random
+    (the paper's scheme has L = 60, n_keep = 50)."""
     rng = _rng(seed + 1000)
-    n = np.arange(1, 61, dtype=np.float64)
-    keep = np.sort(rng.choice(60, size=50, replace=False))
+    n = np.arange(1, L + 1, dtype=np.float64)
+    keep = np.sort(rng.choice(L, size=n_keep, replace=False))
     return _scheme("missing", 5.0 * n[keep] / 6.0, seed)
 
 
