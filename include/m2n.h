@@ -150,7 +150,7 @@ int m2nufft_psd_at_noalloc(m2n_ctx *ctx, void *stream, const double *t,
 
 /*
  * idpss_tapers -- the interpolated-DPSS branch of Table 3 step 3 (nominal band
- * centred at 0; Sec. 3.3): tapers that approximate the GPSS tapers without a
+ * centred at 0; Table 3 in Sec. 3.7): tapers that approximate the GPSS tapers without a
  * GEP on t.
  *   (a) the DPSS of length N and half-bandwidth f_w D on the uniform grid
  *       t_1 + m D, D = (t_N - t_1) / (N - 1);
@@ -313,7 +313,7 @@ int m2nufft_eigcoeffs(m2n_ctx *ctx, void *stream, const double *t,
  *                   for the host).
  *   J       [K*I]   device out or NULL, as in m2nufft_eigcoeffs
  *   F       [I]     device out or NULL (same type as P): the Thomson
- *                   F-statistic of every band (Sec. 3.4), with the tapers'
+ *                   F-statistic of every band (Sec. 3.6), with the tapers'
  *                   DC gains W_k(0) = sum_n w_k(t_n) and C_i = sum_k J_k(i)
  *                   W_k(0) / sum_k W_k(0)^2:
  *                     F_i = |C_i|^2 (K-1) sum_k W_k(0)^2

@@ -11,7 +11,7 @@ adds the two one-line steps that are clearer in numpy:
 * ``psd``: P(A_i) = sum_k d_k |J_k(A_i)|^2 with d_k = 1/K (Sec. 3.2, the
   estimator of the integrated spectrum; Table 3 step 5);
 * ``ftest``, ``f_critical``: the Thomson F-statistic from the eigencoefficients
-  and the critical value of F(2, 2K-2) (Sec. 3.4);
+  and the critical value of F(2, 2K-2) (Sec. 3.6);
 * ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order;
 * ``nudft_freqs``: eigencoefficients at an arbitrary list of band centres;
 * ``idpss_tapers``: the interpolated-DPSS tapers of Table 3 step 3 (fc0 = 0):
@@ -76,7 +76,11 @@ def lib():
         L.or_lanczos.restype = ctypes.c_int
         L.or_lanczos.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, _d, _d,
-                                 ctypes.c_uint64]
+                                 ctypes.c_uint64, ctypes.c_int]
+        L.or_fft.restype = None
+        L.or_fft.argtypes = [_d, _d, ctypes.c_long, ctypes.c_int]
+        L.or_apply_sinc_toeplitz.restype = ctypes.c_int
+        L.or_apply_sinc_toeplitz.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_long, _d]
         L.or_gpss_tapers.restype = ctypes.c_long
         L.or_gpss_tapers.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_int, _d, _d]
@@ -183,16 +187,47 @@ def jacobi_eigh(A, max_sweeps=100):
     return ev, V
 
 
+def is_lattice(t, fmax):
+    """Every t_n an integer and 2 f_max a positive integer (R(B) = 2 f_max I)."""
+    t = np.asarray(t, dtype=np.float64)
+    c = 2.0 * float(fmax)
+    return bool(np.all(t == np.rint(t)) and np.all(np.abs(t) <= 1e15) and c == round(c) and c >= 1.0)
+
+
+def fft(x, sign=-1):
+    """The oracle's own radix-2 FFT (length a power of two)."""
+    x = np.asarray(x, dtype=np.complex128)
+    re, im = _f64(x.real.copy()), _f64(x.imag.copy())
+    lib().or_fft(_p(re), _p(im), x.shape[0], int(sign))
+    return re + 1j * im
+
+
+def apply_sinc_toeplitz(t, f, V):
+    """R(f) @ V for integer t through the lattice Toeplitz convolution."""
+    t = _f64(t)
+    V = _f64(np.atleast_2d(V.T).T) if V.ndim == 1 else _f64(V)
+    N, nv = V.shape
+    Y = np.empty((N, nv))
+    st = lib().or_apply_sinc_toeplitz(_p(t), N, float(f), _p(V), nv, _p(Y))
+    if st < 0:
+        raise OracleError(st, "apply_sinc_toeplitz")
+    return Y
+
+
 def gpss_tapers(t, fmax, fw, K, method="auto"):
     """The K largest solutions of R(A0) w = lambda R(B) w (Sec. 3.2), with
     w_k^T R(B) w_k = 2 f_w (Sec. 2.2) and the sign reading of fix_sign.
 
-    method: "jacobi" (dense reduction + cyclic Jacobi), "lanczos", or "auto"
-    (Jacobi up to N = 600).  Returns (w [K, N], lam [K]).
+    method: "jacobi" (dense reduction + cyclic Jacobi), "lanczos", "lattice"
+    (integer t and integer 2 f_max: R(B) = 2 f_max I, Lanczos with the
+    Toeplitz operator, no N x N matrix) or "auto" (Jacobi up to N = 600, then
+    "lattice" where it applies, else "lanczos").  Returns (w [K, N], lam [K]).
     """
     t = _f64(t)
     N = t.shape[0]
-    m = {"jacobi": 0, "lanczos": 1}.get(method, 0 if N <= 600 else 1)
+    if method == "auto" and N > 600 and is_lattice(t, fmax):
+        method = "lattice"
+    m = {"jacobi": 0, "lanczos": 1, "lattice": 2}.get(method, 0 if N <= 600 else 1)
     w, lam = np.empty((K, N)), np.empty(K)
     st = lib().or_gpss_tapers(_p(t), N, float(fmax), float(fw), int(K), m, _p(w), _p(lam))
     if st < 0:
@@ -344,7 +379,7 @@ def psd(J, weights=None):
 
 
 def ftest(J, w):
-    """Thomson F-statistic of every band (Sec. 3.4, "Thomson F-test for
+    """Thomson F-statistic of every band (Sec. 3.6, "Thomson F-test for
     Nonuniform Signal", Eq. (f_stat) and the amplitude estimate after it):
         W_k(0) = sum_n w_k(t_n)               (the tapers' DC gains),
         C_i    = sum_k J_k(i) W_k(0) / sum_k W_k(0)^2,
@@ -366,7 +401,7 @@ def ftest(J, w):
 
 
 def f_critical(p, K):
-    """Critical value of F(2, 2K - 2) at upper-tail probability p (Sec. 3.4:
+    """Critical value of F(2, 2K - 2) at upper-tail probability p (Sec. 3.6:
     F_s follows F(2, 2K-2); the level is chosen as p, for instance the
     Rayleigh level 1/N).  With nu = 2K - 2 the upper tail of F(2, nu) is
     (1 + 2 F / nu)^(-nu / 2), so F_p = (nu / 2)(p^(-2 / nu) - 1)."""
@@ -392,14 +427,15 @@ def ehat(t, w, lam, fmax, fw, f_lo, df, I=None, bands=None):
     return E, D
 
 
-def lanczos(t, fw, K, L=None, cdiag=1.0, mmax=400, tol=1e-14, seed=0x5EED):
-    """Top-K eigenpairs of L^{-1} R(A0) L^{-T} (L None: R(B) = cdiag I)."""
+def lanczos(t, fw, K, L=None, cdiag=1.0, mmax=400, tol=1e-14, seed=0x5EED, toeplitz=False):
+    """Top-K eigenpairs of L^{-1} R(A0) L^{-T} (L None: R(B) = cdiag I).
+    toeplitz: apply R(A0) as the lattice Toeplitz convolution (integer t)."""
     t = _f64(t)
     N = t.shape[0]
     ev, y = np.empty(K), np.empty((N, K))
     Lp = _p(_f64(L)) if L is not None else ctypes.cast(None, _d)
     st = lib().or_lanczos(_p(t), N, float(fw), Lp, float(cdiag), K, int(mmax),
-                          float(tol), _p(ev), _p(y), seed)
+                          float(tol), _p(ev), _p(y), seed, 1 if toeplitz else 0)
     if st < 0:
         raise OracleError(st, "lanczos")
     return ev, y

@@ -19,6 +19,11 @@
  *                       sin(pi (f_max - f_min) tau) / (pi tau), diagonal
  *                       2 (f_max - f_min)   (Sec. 2.4, sub-band GPSS matrix)
  *   or_apply_sinc       Y = R(f) V without storing R(f)
+ *   or_fft              radix-2 complex FFT (its own, for the lattice matvec)
+ *   or_apply_sinc_toeplitz  Y = R(f) V for integer t as a Toeplitz
+ *                       convolution on the lattice, by circular convolution
+ *                       through or_fft (same numbers as or_apply_sinc up to
+ *                       rounding; O(S log S) instead of O(N^2))
  *   or_cholesky         R(B) = L L^T, unblocked, row oriented
  *   or_reduce           C = L^{-1} R(A0) L^{-T}  (GEP -> standard problem)
  *   or_jacobi           full eigen-decomposition by cyclic Jacobi
@@ -184,6 +189,118 @@ void or_apply_sinc(const double *t, long N, double f, const double *V,
 }
 
 /* ------------------------------------------------------------------ */
+/* Radix-2 complex FFT in place, M a power of two:                      */
+/*   X_k = sum_j x_j exp(sgn * 2 pi i j k / M)                          */
+/* Iterative Cooley-Tukey: bit-reversal permutation, then log2(M)       */
+/* butterfly stages; each twiddle is the cosine and sine of the exact    */
+/* fraction k / len (reduced as in or_sinpi).                            */
+/* ------------------------------------------------------------------ */
+void or_fft(double *re, double *im, long M, int sgn)
+{
+    for (long i = 1, j = 0; i < M; ++i) {
+        long bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double a = re[i]; re[i] = re[j]; re[j] = a;
+            a = im[i]; im[i] = im[j]; im[j] = a;
+        }
+    }
+    for (long len = 2; len <= M; len <<= 1) {
+        long half = len / 2;
+        for (long k = 0; k < half; ++k) {
+            double u = 2.0 * (double)k / (double)len;
+            double c = or_cospi(u), sn = (sgn < 0 ? -1.0 : 1.0) * or_sinpi(u);
+            for (long b = 0; b < M; b += len) {
+                long p0 = b + k, q0 = p0 + half;
+                double tr = re[q0] * c - im[q0] * sn;
+                double ti = re[q0] * sn + im[q0] * c;
+                re[q0] = re[p0] - tr;
+                im[q0] = im[p0] - ti;
+                re[p0] += tr;
+                im[p0] += ti;
+            }
+        }
+    }
+}
+
+/* R(f) on an integer lattice as a Toeplitz operator: with o_n = t_n - t_0
+ * and S = o_{N-1}, (R v)_n = sum_m h(o_n - o_m) v_m, h(j) = sin(2 pi f j)/(pi j),
+ * i.e. the linear convolution of h (lags -S..S) with v placed on the lattice
+ * (zeros at the missing points), sampled at the o_n.  A circular
+ * convolution of length M >= 2 S + 1 holds it exactly; H = FFT(h) is
+ * computed once per operator. */
+typedef struct {
+    long N, S, M;
+    long *o;
+    double *Hr, *Hi, *wr, *wi;
+} toep_op;
+
+static int toep_init(toep_op *op, const double *t, long N, double f)
+{
+    memset(op, 0, sizeof(*op));
+    for (long n = 0; n < N; ++n)
+        if (t[n] != nearbyint(t[n]) || fabs(t[n]) > 1e15) return OR_ERR_ARG;
+    for (long n = 1; n < N; ++n)
+        if (!(t[n] > t[n - 1])) return OR_ERR_T_ORDER;
+    long S = (long)(t[N - 1] - t[0]);
+    long M = 1;
+    while (M < 2 * S + 1) M <<= 1;
+    op->N = N;
+    op->S = S;
+    op->M = M;
+    op->o = (long *)malloc(sizeof(long) * (size_t)N);
+    op->Hr = (double *)calloc((size_t)M, sizeof(double));
+    op->Hi = (double *)calloc((size_t)M, sizeof(double));
+    op->wr = (double *)malloc(sizeof(double) * (size_t)M);
+    op->wi = (double *)malloc(sizeof(double) * (size_t)M);
+    for (long n = 0; n < N; ++n) op->o[n] = (long)(t[n] - t[0]);
+    op->Hr[0] = sinc_kernel(f, 0.0);
+    for (long j = 1; j <= S; ++j) {
+        double h = sinc_kernel(f, (double)j);
+        op->Hr[j] = h;
+        op->Hr[M - j] = h;
+    }
+    or_fft(op->Hr, op->Hi, M, -1);
+    return OR_OK;
+}
+
+static void toep_apply(const toep_op *op, const double *v, long stride, double *y, long ystride)
+{
+    const long M = op->M;
+    memset(op->wr, 0, sizeof(double) * (size_t)M);
+    memset(op->wi, 0, sizeof(double) * (size_t)M);
+    for (long n = 0; n < op->N; ++n) op->wr[op->o[n]] = v[n * stride];
+    or_fft(op->wr, op->wi, M, -1);
+    for (long k = 0; k < M; ++k) {
+        double a = op->wr[k], b = op->wi[k];
+        op->wr[k] = a * op->Hr[k] - b * op->Hi[k];
+        op->wi[k] = a * op->Hi[k] + b * op->Hr[k];
+    }
+    or_fft(op->wr, op->wi, M, +1);
+    for (long n = 0; n < op->N; ++n) y[n * ystride] = op->wr[op->o[n]] / (double)M;
+}
+
+static void toep_free(toep_op *op)
+{
+    free(op->o); free(op->Hr); free(op->Hi); free(op->wr); free(op->wi);
+    memset(op, 0, sizeof(*op));
+}
+
+/* Y (N x nv, row-major) = R(f) V for strictly increasing integer t, through
+ * the lattice Toeplitz operator.  Returns 0, or OR_ERR_ARG for non-integer t. */
+int or_apply_sinc_toeplitz(const double *t, long N, double f, const double *V,
+                           long nv, double *Y)
+{
+    toep_op op;
+    int st = toep_init(&op, t, N, f);
+    if (st) { toep_free(&op); return st; }
+    for (long c = 0; c < nv; ++c) toep_apply(&op, V + c, nv, Y + c, nv);
+    toep_free(&op);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Cholesky R = L L^T (lower, row-major, in place; upper part zeroed)  */
 /* returns 0 or -(index of the failing pivot + 1)                      */
 /* ------------------------------------------------------------------ */
@@ -340,26 +457,37 @@ static void fix_sign(const double *t, long N, double *w)
 /* ------------------------------------------------------------------ */
 /* Lanczos with full re-orthogonalisation for the largest eigenpairs of */
 /* C = L^{-1} R(A0) L^{-T}.  L == NULL means L = sqrt(cdiag) I.         */
+/* toeplitz != 0 (with L == NULL and integer t): R(A0) is applied as the */
+/* lattice Toeplitz convolution instead of the direct O(N^2) sum.       */
 /* Ritz pairs come from the Jacobi decomposition of the tridiagonal T.  */
 /* y is N x nwant row-major (column k = unit Ritz vector k).            */
 /* ------------------------------------------------------------------ */
 static void apply_C(const double *t, long N, double fw, const double *L,
-                    double cdiag, const double *v, double *out, double *tmp)
+                    double cdiag, const toep_op *op, const double *v, double *out,
+                    double *tmp)
 {
     memcpy(tmp, v, sizeof(double) * (size_t)N);
     if (L) back_subst_T(L, N, tmp, 1);
     else for (long n = 0; n < N; ++n) tmp[n] /= sqrt(cdiag);
-    or_apply_sinc(t, N, fw, tmp, 1, out);
+    if (op) toep_apply(op, tmp, 1, out, 1);
+    else or_apply_sinc(t, N, fw, tmp, 1, out);
     if (L) fwd_subst(L, N, out, 1);
     else for (long n = 0; n < N; ++n) out[n] /= sqrt(cdiag);
 }
 
 int or_lanczos(const double *t, long N, double fw, const double *L,
                double cdiag, int nwant, int mmax, double tol,
-               double *evals, double *y, uint64_t seed)
+               double *evals, double *y, uint64_t seed, int toeplitz)
 {
     if (mmax > N) mmax = (int)N;
     if (nwant > mmax) return OR_ERR_ARG;
+    toep_op op_store, *op = NULL;
+    if (toeplitz) {
+        if (L) return OR_ERR_ARG;
+        int st0 = toep_init(&op_store, t, N, fw);
+        if (st0) { toep_free(&op_store); return st0; }
+        op = &op_store;
+    }
     double *Q = (double *)calloc((size_t)(mmax + 1) * (size_t)N, sizeof(double));
     double *z = (double *)malloc(sizeof(double) * (size_t)N);
     double *tmp = (double *)malloc(sizeof(double) * (size_t)N);
@@ -384,7 +512,7 @@ int or_lanczos(const double *t, long N, double fw, const double *L,
     for (long n = 0; n < N; ++n) Q[n] /= nrm;
     for (int j = 0; j < mmax; ++j) {
         double *qj = Q + (size_t)j * N;
-        apply_C(t, N, fw, L, cdiag, qj, z, tmp);
+        apply_C(t, N, fw, L, cdiag, op, qj, z, tmp);
         double a = 0.0;
         for (long n = 0; n < N; ++n) a += qj[n] * z[n];
         alpha[j] = a;
@@ -434,13 +562,16 @@ int or_lanczos(const double *t, long N, double fw, const double *L,
         for (long n = 0; n < N; ++n) qn[n] = z[n] / b;
     }
     free(Q); free(z); free(tmp); free(alpha); free(beta); free(T); free(S); free(th);
+    if (op) toep_free(op);
     return status;
 }
 
 /* ------------------------------------------------------------------ */
 /* The K largest GPSS tapers at the nominal band A0 (f_c0 = 0):        */
 /*   R(A0) w = lambda R(B) w,  w_k^T R(B) w_k = 2 f_w.                 */
-/* method 0: dense reduction + Jacobi; 1: Lanczos.                     */
+/* method 0: dense reduction + Jacobi; 1: Lanczos; 2: Lanczos on an   */
+/* integer lattice with integer 2 f_max (R(B) = 2 f_max I, Toeplitz     */
+/* R(A0), no N x N matrix).                                            */
 /* w is K x N row-major, lam[K] descending.                            */
 /* ------------------------------------------------------------------ */
 long or_gpss_tapers(const double *t, long N, double fmax, double fw, int K,
@@ -448,6 +579,27 @@ long or_gpss_tapers(const double *t, long N, double fmax, double fw, int K,
 {
     int st = or_validate(t, N, fmax, fw, K);
     if (st) return st;
+    if (method == 2) {
+        /* integer lattice with integer 2 f_max: every off-diagonal
+         * sin(2 pi f_max tau) of R(B) is an exact zero, R(B) = 2 f_max I; the
+         * GEP is the standard problem of R(A0) / (2 f_max), solved by Lanczos
+         * with the Toeplitz operator (no N x N matrix is formed) */
+        double cB = 2.0 * fmax;
+        if (cB != nearbyint(cB) || cB < 1.0) return OR_ERR_ARG;
+        for (long n = 0; n < N; ++n)
+            if (t[n] != nearbyint(t[n]) || fabs(t[n]) > 1e15) return OR_ERR_ARG;
+        double *y = (double *)malloc(sizeof(double) * (size_t)N * (size_t)K);
+        int mmax = (int)((N < 400) ? N : 400);
+        int sw = or_lanczos(t, N, fw, NULL, cB, K, mmax, 1e-14, lam, y, 0x5EEDull, 1);
+        double *col = (double *)malloc(sizeof(double) * (size_t)N);
+        for (int k = 0; k < K; ++k) {
+            for (long n = 0; n < N; ++n) col[n] = y[n * K + k] / sqrt(cB) * sqrt(2.0 * fw);
+            fix_sign(t, N, col);
+            memcpy(w + (size_t)k * N, col, sizeof(double) * (size_t)N);
+        }
+        free(col); free(y);
+        return sw < 0 ? OR_ERR_NO_CONVERGE : 0;
+    }
     size_t NN = (size_t)N * (size_t)N;
     double *RB = (double *)malloc(sizeof(double) * NN);
     or_gpss_matrix(t, N, fmax, RB);
@@ -484,7 +636,7 @@ long or_gpss_tapers(const double *t, long N, double fmax, double fw, int K,
     } else {
         int mmax = (int)((N < 400) ? N : 400);
         int sw = or_lanczos(t, N, fw, diagonal ? NULL : RB, cdiag, K, mmax,
-                            1e-14, lam, y, 0x5EEDull);
+                            1e-14, lam, y, 0x5EEDull, 0);
         if (sw < 0) ret = OR_ERR_NO_CONVERGE;
     }
     /* w_k = sqrt(2 f_w) L^{-T} y_k  =>  w_k^T R(B) w_k = 2 f_w */

@@ -349,7 +349,7 @@ def m2nufft_psd(ctx: Context, t, x, w, lam, fmax, fw, f_lo, df, I, prec=M2N_FP64
                 nufft_tol=0.0, weights=None, want_E=True, want_J=False, stream=None,
                 out=None, check=True, want_F=False):
     """Table 3 steps 4-5 fused, plus the Appendix B suboptimality estimate and,
-    with want_F, the Thomson F-statistic (Sec. 3.4).  `out` is (P, E, J) or
+    with want_F, the Thomson F-statistic (Sec. 3.6).  `out` is (P, E, J) or
     (P, E, J, F).  Returns {"P": [I], "E": [I] or None, "J": [K, I] or None,
     "F": [I] or None}."""
     t, x, w = _dev(t), _dev(x), _dev(w)

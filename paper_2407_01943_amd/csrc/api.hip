@@ -85,6 +85,17 @@ int Ctx::pinned_info(size_t bytes) {
     return M2N_OK;
 }
 
+int Ctx::pinned_erec(size_t bytes) {
+    if (erec_bytes >= bytes) return M2N_OK;
+    // every earlier use of the records was followed by an event synchronise
+    if (erec) (void)hipHostFree(erec);
+    erec = nullptr;
+    erec_bytes = 0;
+    M2N_HIP(hipHostMalloc(&erec, bytes, hipHostMallocDefault));
+    erec_bytes = bytes;
+    return M2N_OK;
+}
+
 int Ctx::stage(hipStream_t st, const void* src, size_t bytes, void* dst_dev) {
     if (hstage_used) M2N_HIP(hipEventSynchronize(hstage_ev));
     if (hstage_bytes < bytes) {
@@ -206,6 +217,7 @@ void m2n_destroy(m2n_ctx* ctx) {
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->hstage_ev) (void)hipEventDestroy(ctx->hstage_ev);
     if (ctx->tcheck_ev) (void)hipEventDestroy(ctx->tcheck_ev);
+    if (ctx->erec) (void)hipHostFree(ctx->erec);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);

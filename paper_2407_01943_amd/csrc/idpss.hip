@@ -1,5 +1,5 @@
 // Interpolated-DPSS tapers (Table 3 step 3, the branch for a nominal band
-// centred at 0; Sec. 3.3 on approximating the GPSS tapers by DPSS):
+// centred at 0; Table 3 in Sec. 3.7, approximating the GPSS tapers by DPSS):
 //   (a) the DPSS of length N and half-bandwidth f_w D on the uniform grid
 //       u_m = t_1 + m D, D = (t_N - t_1) / (N - 1): the GPSS tapers of the
 //       integer lattice 0..N-1 with f_max = 1/2 (R(B) = I), computed by the

@@ -106,6 +106,7 @@ struct NuSeriesIn {
     void* E = nullptr;
     void* J = nullptr;
     void* F = nullptr;   // Thomson F-statistic [I] or NULL
+    double* hrec = nullptr;   // pinned record of the t check (set internally)
 };
 
 // FP64 complex FFT plan of length M (lattice convolution in the GEP)
@@ -158,16 +159,6 @@ struct GepIn {
 // many series: one t check for all, the lattice low-rank ones in one set of
 // launches, the rest one by one
 int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
-// what the t check found for one series: flags bit 0 a non-finite t_n, bit 1
-// a step t_n <= t_{n-1}, bit 2 a t_n that is not an integer; t_0 and t_{N-1}
-struct TSummary {
-    int flags = 0;
-    double t0 = 0, tN = 0;
-};
-// launch the t check of ns series on st and record `done` after it; *read
-// waits for `done` and fills one summary per series (gep.hip)
-int t_check_begin(Ctx* ctx, hipStream_t st, const double* const* t, const int64_t* N, int ns, hipEvent_t done,
-                  std::function<void(std::vector<TSummary>&)>* read);
 // Ehat of one series whose R(B) is not a multiple of the identity: D_k(i) by
 // quadrature of |W_k|^2 over every band's window (ehat.hip); span = t_N - t_1
 int ehat_general(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol, const NuSeriesIn& s, double span);
@@ -205,6 +196,9 @@ struct Ctx {
     // a second stream (default priority) and two events for work that
     // overlaps the caller's stream, created on first use
     hipEvent_t tcheck_ev = nullptr;     // marks the t check of an Ehat request
+    void* erec = nullptr;               // pinned records of that check
+    size_t erec_bytes = 0;
+    int pinned_erec(size_t bytes);
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork = nullptr, aux_join = nullptr;
     int aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);

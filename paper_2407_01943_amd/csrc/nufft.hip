@@ -227,6 +227,9 @@ struct NuSeries {
     double* wsp;   // [nwg][K] partial sums of w_k (for F)
     double* wsums; // [K] their totals, the tapers' DC gains W_k(0)
     int* diag;     // [1] R(B) = 2 f_max I
+    double* hrec;  // pinned host record of the t check, or NULL: [0] flags
+                   // (bit 0 non-finite, bit 1 not increasing, bit 2 a t_n
+                   // that is not an integer), [1] t_0, [2] t_{N-1}
     int64_t N;
     double f_lo, df, fmax, fw;
     int K, nwg, ppw, pad;
@@ -239,26 +242,7 @@ struct NuArgs {
     const void* tw;          // FFT twiddles
     const void* inv_phihat;  // deconvolution table
     unsigned* dev_err;
-    long long* stamp;        // phase clock of workgroup 0 (NULL: off)
 };
-
-// clock of a phase boundary in workgroup (0, 0), for kernel tuning
-__device__ __forceinline__ void phase_stamp(const NuArgs& a, int i) {
-    if (a.stamp && blockIdx.x == 0 && blockIdx.y == 0) {
-        __syncthreads();
-        if (threadIdx.x == 0) a.stamp[i] = clock64();
-    }
-}
-
-// start and end times (100 MHz device clock) of every workgroup of series 0
-// (kernel tuning):
-// stamp[base + 2 b], stamp[base + 2 b + 1], b < 2048
-__device__ __forceinline__ void wg_stamp(const NuArgs& a, int base, int end) {
-    if (a.stamp && blockIdx.y == 0 && blockIdx.x < 2048) {
-        if (end) __syncthreads();
-        if (threadIdx.x == 0) a.stamp[base + 2 * blockIdx.x + end] = (long long)__builtin_amdgcn_s_memrealtime();
-    }
-}
 
 // this workgroup's series
 __device__ __forceinline__ NuSeries series_of(const NuSeries& d0, const NuSeries* D) {
@@ -272,29 +256,44 @@ __global__ __launch_bounds__(NT) void k_hist(NuArgs a, NuSeries d0, const NuSeri
     const int wg = blockIdx.x;
     if (wg >= d.nwg) return;
     __shared__ int sh[MAX_BINS];
-    __shared__ int s_int, s_bad;
+    __shared__ int s_int, s_bad, s_ord;
     for (int b = threadIdx.x; b < a.nbins; b += NT) sh[b] = 0;
     if (threadIdx.x == 0) {
         s_int = 1;
         s_bad = 0;
+        s_ord = 0;
     }
     __syncthreads();
     const int64_t n0 = (int64_t)wg * d.ppw;
-    int my_int = 1, my_bad = 0;
+    int my_int = 1, my_bad = 0, my_ord = 0;
     for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= d.N) break;
-        Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, a.h, a.nf, a.w);
+        const double tn = d.t[n];
+        Geo g = point_geo(tn, d.x[n], d.f_lo, d.df, a.h, a.nf, a.w);
         my_int &= g.integral ? 1 : 0;
         my_bad |= g.ok ? 0 : 1;
+        if (d.hrec && n > 0 && !(tn > d.t[n - 1])) my_ord = 1;
         const int bin = (g.l0 & (a.N2 - 1)) / a.B;
         atomicAdd(&sh[bin], 1);
     }
     if (!my_int) atomicAnd(&s_int, 0);
     if (my_bad) atomicOr(&s_bad, 1);
+    if (my_ord) atomicOr(&s_ord, 1);
     __syncthreads();
     for (int b = threadIdx.x; b < a.nbins; b += NT) d.hist[(int64_t)wg * a.nbins + b] = sh[b];
-    if (threadIdx.x == 0) d.flags[wg] = (s_int ? 1 : 0) | (s_bad ? 2 : 0);
+    if (threadIdx.x == 0) d.flags[wg] = (s_int ? 1 : 0) | (s_bad ? 2 : 0) | (s_ord ? 4 : 0);
+}
+
+// the t check's record for the host (thread 0 of the series' last kernel
+// that has seen every sample)
+__device__ __forceinline__ void write_hrec(const NuSeries& d, bool integral, bool bad, bool ord) {
+    if (!d.hrec) return;
+    const int f = (bad ? 1 : 0) | (ord ? 2 : 0) | (integral ? 0 : 4);
+    d.hrec[0] = (double)f;
+    d.hrec[1] = d.t[0];
+    d.hrec[2] = d.t[d.N - 1];
+    __threadfence_system();
 }
 
 // K1b: one workgroup per series.  off[wg][b] = start of (wg, b) in bin-major
@@ -305,7 +304,7 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     const NuSeries d = series_of(d0, D);
     __shared__ int cnt[SCAN_LDS];
     __shared__ int tot[MAX_BINS + 1];
-    __shared__ int s_int, s_bad;
+    __shared__ int s_int, s_bad, s_ord;
     const int tid = threadIdx.x;
     const int nwg = d.nwg, nbins = a.nbins;
     // staged: the counts held bin-major, cnt[b * nwgp + g], with an odd row
@@ -316,6 +315,7 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     if (tid == 0) {
         s_int = 1;
         s_bad = 0;
+        s_ord = 0;
     }
     if (staged) {
         // all of a thread's loads in flight at once (blockDim.x = 1024)
@@ -358,13 +358,15 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
             tot[b] = s0;
         }
     }
-    int li = 1, lb = 0;
+    int li = 1, lb = 0, lo = 0;
     for (int g = tid; g < nwg; g += blockDim.x) {
         li &= d.flags[g] & 1;
         lb |= (d.flags[g] >> 1) & 1;
+        lo |= (d.flags[g] >> 2) & 1;
     }
     if (!li) atomicAnd(&s_int, 0);
     if (lb) atomicOr(&s_bad, 1);
+    if (lo) atomicOr(&s_ord, 1);
     __syncthreads();
     // exclusive scan over the bins (one wavefront, 64-wide chunks)
     if (tid < 64) {
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
         const int dg = (s_int && c == rint(c) && c >= 1.0) ? 1 : 0;
         d.diag[0] = dg;
         if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
+        write_hrec(d, s_int != 0, s_bad != 0, s_ord != 0);
     }
 }
 
@@ -578,8 +581,6 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
-    wg_stamp(a, 1024, 0);
-    phase_stamp(a, 0);
     for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
     if (threadIdx.x == 0) s_maxrow = -1;
     const R two_over_w = (R)2 / (R)w;
@@ -588,7 +589,6 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     const auto* cwk = gp((const cplx<R>*)d.cw + (int64_t)k * d.N);
     const auto* l0s = gp((const int*)d.l0s);
     const auto* binoff = gp((const int*)d.binoff);
-    phase_stamp(a, 1);
     // the points of bins blk - lookback .. blk, as one flat range of
     // segments so that every thread's loads are independent
     // (lookback + 1 <= MAXSEG is checked when the plan is built)
@@ -617,7 +617,6 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         }
         return j;
     };
-    phase_stamp(a, 5);
     // FP32: the length-N1 FFT twiddles are fetched now and stored to LDS
     // after the spread, so that their latency overlaps the point loads (in
     // FP64 the registers held across the spread cost more than they save)
@@ -766,9 +765,7 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
             d.wsums[k] = s1;
         }
     }
-    phase_stamp(a, 2);
     fft_lds<R, N1, B, NT1, LD>(tile, tw, 1, pruned);
-    phase_stamp(a, 3);
     // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, then
     // G[k][m1][l2].  A thread keeps one column cb and steps m1 by S = NT1 / B,
     // so its twiddle advances by the fixed factor exp(-2 pi i c S / nf): two
@@ -794,8 +791,6 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
             tr = nr;
         }
     }
-    phase_stamp(a, 4);
-    wg_stamp(a, 1024, 1);
 }
 
 // -------------------------------------------------------------- pass 2
@@ -828,8 +823,6 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     R* E = (R*)d.E;
     cplx<R>* J = (cplx<R>*)d.J;
     R* Fo = (R*)d.F;
-    wg_stamp(a, 8192, 0);
-    phase_stamp(a, 8);
     for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
     if (E && threadIdx.x < 64) {
         // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I (lane k)
@@ -890,9 +883,7 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             rows[r * LD + l2] = v[u];
         }
         __syncthreads();
-        phase_stamp(a, 9);
         fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1, false, nk * M);   // the nk tapers present
-        phase_stamp(a, 10);
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
             const int e = threadIdx.x + it * NT2;
@@ -938,8 +929,6 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             }
         }
     }
-    phase_stamp(a, 11);
-    wg_stamp(a, 8192, 1);
 }
 
 // ------------------------------------------------- single-workgroup path
@@ -949,10 +938,11 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
     constexpr int OUT_IT = (NF / 2 + NT - 1) / NT;
     __shared__ cplx<R> grid[NF];
     __shared__ double red[NT / 64];
-    __shared__ int s_int, s_bad;
+    __shared__ int s_int, s_bad, s_ord;
     if (threadIdx.x == 0) {
         s_int = 1;
         s_bad = 0;
+        s_ord = 0;
     }
     const int K = d.K, w = a.w;
     const int64_t I = a.I, h = a.h, N = d.N;
@@ -978,11 +968,13 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
         __syncthreads();
         const double* wk = d.w + (int64_t)k * N;
         double nrm = 0.0, wsum = 0.0;
-        int my_int = 1, my_bad = 0;
+        int my_int = 1, my_bad = 0, my_ord = 0;
         for (int64_t n = threadIdx.x; n < N; n += NT) {
-            const Geo g = point_geo(d.t[n], d.x[n], d.f_lo, d.df, h, NF, w);
+            const double tn = d.t[n];
+            const Geo g = point_geo(tn, d.x[n], d.f_lo, d.df, h, NF, w);
             my_int &= g.integral ? 1 : 0;
             my_bad |= g.ok ? 0 : 1;
+            if (k == 0 && d.hrec && n > 0 && !(tn > d.t[n - 1])) my_ord = 1;
             const double wv = wk[n];
             nrm += wv * wv;
             wsum += wv;
@@ -998,6 +990,7 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
         }
         if (!my_int) atomicAnd(&s_int, 0);
         if (my_bad) atomicOr(&s_bad, 1);
+        if (my_ord) atomicOr(&s_ord, 1);
         nrm = block_sum(nrm, red);   // contains barriers
         if (Fo) {
             wsum = block_sum(wsum, red);   // W_k(0), the taper's DC gain
@@ -1034,6 +1027,7 @@ __global__ __launch_bounds__(NT) void k_small(NuArgs a, NuSeries d0, const NuSer
     const R ev = diag ? (R)(esum / (double)K) : (R)NAN;
     if (threadIdx.x == 0) {
         if (s_bad) atomicOr(a.dev_err, (unsigned)DEVERR_NONFINITE);
+        write_hrec(d, s_int != 0, s_bad != 0, s_ord != 0);
     }
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) {
@@ -1189,9 +1183,6 @@ int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
 }
 
 // ---------------------------------------------------------- dispatchers
-// device buffer for the phase clocks of workgroup 0 (kernel tuning builds
-// that compile this file into a timing harness set it; NULL otherwise)
-long long* g_phase_stamp = nullptr;
 
 NuArgs make_args(Ctx* ctx, const NufftPlan& p) {
     NuArgs a{};
@@ -1211,7 +1202,6 @@ NuArgs make_args(Ctx* ctx, const NufftPlan& p) {
     a.tw = p.tw_fft.p;
     a.inv_phihat = p.inv_phihat.p;
     a.dev_err = ctx->dev_err;
-    a.stamp = g_phase_stamp;
     return a;
 }
 
@@ -1303,8 +1293,10 @@ struct Carver {
     }
 };
 
+// `checked` (or NULL) is recorded once the kernels that write the series'
+// host records of the t check (k_scan, k_small) are queued
 template <typename R>
-int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns) {
+int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns, hipEvent_t checked) {
     const NuArgs a = make_args(ctx, p);
     std::vector<NuSeries> ds(ns);
     int maxK = 0, maxwg = 0;
@@ -1324,6 +1316,7 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         d.E = s.E;
         d.J = s.J;
         d.F = s.F;
+        d.hrec = s.hrec;
         d.N = s.N;
         d.f_lo = s.f_lo;
         d.df = s.df;
@@ -1387,6 +1380,7 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         M2N_PROF(ctx, st, "k_small");
         M2N_TRY(launch_small<R>(p, st, dim3(1, ys), a, d0, D));
         M2N_HIP(hipGetLastError());
+        if (checked) M2N_HIP(hipEventRecord(checked, st));
         return M2N_OK;
     }
     {
@@ -1397,6 +1391,7 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         M2N_PROF(ctx, st, "k_scan");
         hipLaunchKernelGGL(k_scan, dim3(1, ys), dim3(1024), 0, st, a, d0, D);
     }
+    if (checked) M2N_HIP(hipEventRecord(checked, st));
     {
         M2N_PROF(ctx, st, "k_scatter");
         bool anyF = false;
@@ -1461,38 +1456,43 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
     M2N_TRY(get_plan(ctx, I, prec, tol, &p));
     // Ehat: where R(B) is a multiple of the identity the NuFFT pass writes
     // it (band-constant); elsewhere the window quadrature overwrites it.  The
-    // t check that tells them apart is launched first and read once the
-    // NuFFT is queued, so the device does not wait for the host.
+    // binning kernels record what they saw of t in pinned host memory; the
+    // host reads it once the whole NuFFT is queued, so the device does not
+    // wait for the host.
     std::vector<int> eidx;
     for (int i = 0; i < nseries; ++i)
         if (series[i].E) eidx.push_back(i);
-    std::function<void(std::vector<TSummary>&)> read_t;
-    if (!eidx.empty()) {
-        std::vector<const double*> tp;
-        std::vector<int64_t> Np;
-        for (int i : eidx) {
-            tp.push_back(series[i].t);
-            Np.push_back(series[i].N);
-        }
-        if (!ctx->tcheck_ev) M2N_HIP(hipEventCreateWithFlags(&ctx->tcheck_ev, hipEventDisableTiming));
-        M2N_TRY(t_check_begin(ctx, st, tp.data(), Np.data(), (int)eidx.size(), ctx->tcheck_ev, &read_t));
+    if (eidx.empty()) {
+        if (prec == M2N_FP32) return run_typed<float>(ctx, st, *p, series, nseries, nullptr);
+        return run_typed<double>(ctx, st, *p, series, nseries, nullptr);
     }
-    if (prec == M2N_FP32) M2N_TRY(run_typed<float>(ctx, st, *p, series, nseries));
-    else M2N_TRY(run_typed<double>(ctx, st, *p, series, nseries));
-    if (eidx.empty()) return M2N_OK;
-    std::vector<TSummary> ts;
-    read_t(ts);
-    for (size_t e = 0; e < eidx.size(); ++e) {
-        const NuSeriesIn& s = series[eidx[e]];
-        const TSummary& r = ts[e];
-        if (r.flags & 1) continue;   // non-finite t: flagged by the NuFFT kernels
-        if (r.flags & 2) {
-            set_error("series %d: Ehat needs strictly increasing sampling times", eidx[e]);
+    M2N_TRY(ctx->pinned_erec((size_t)nseries * 4 * sizeof(double)));
+    double* rec = (double*)ctx->erec;
+    std::vector<NuSeriesIn> ser(series, series + nseries);
+    for (int i : eidx) {
+        ser[i].hrec = rec + 4 * i;
+        rec[4 * i] = -1.0;
+    }
+    if (!ctx->tcheck_ev) M2N_HIP(hipEventCreateWithFlags(&ctx->tcheck_ev, hipEventDisableTiming));
+    if (prec == M2N_FP32) M2N_TRY(run_typed<float>(ctx, st, *p, ser.data(), nseries, ctx->tcheck_ev));
+    else M2N_TRY(run_typed<double>(ctx, st, *p, ser.data(), nseries, ctx->tcheck_ev));
+    M2N_HIP(hipEventSynchronize(ctx->tcheck_ev));
+    for (int i : eidx) {
+        const NuSeriesIn& s = series[i];
+        const double* r = rec + 4 * i;
+        const int flags = (int)r[0];
+        if (flags < 0) {
+            set_error("series %d: the t check left no record", i);
+            return M2N_ERR_HIP;
+        }
+        if (flags & 1) continue;   // non-finite t: reported by m2n_check
+        if (flags & 2) {
+            set_error("series %d: Ehat needs strictly increasing sampling times", i);
             return M2N_ERR_T_ORDER;
         }
         const double c = 2.0 * s.fmax;
-        const bool diag = !(r.flags & 4) && c == std::rint(c) && c >= 1.0;
-        if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, tol, s, s.N > 1 ? r.tN - r.t0 : 0.0));
+        const bool diag = !(flags & 4) && c == std::rint(c) && c >= 1.0;
+        if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, tol, s, s.N > 1 ? r[2] - r[1] : 0.0));
     }
     return M2N_OK;
 }

@@ -1,4 +1,4 @@
-"""Thomson F-statistic (Sec. 3.4) on the GPU against the oracle.
+"""Thomson F-statistic (Sec. 3.6) on the GPU against the oracle.
 
 The GPU fuses the statistic into the band average: S_JW = sum_k J_k W_k(0),
 S_JJ = sum_k |J_k|^2 and S_WW = sum_k W_k(0)^2, F = (K-1) q / (S_JJ - q) with

@@ -130,6 +130,51 @@ def test_lanczos_matches_jacobi(orc):
     np.testing.assert_allclose(w_l, w_j, atol=1e-9)
 
 
+def test_oracle_fft_is_the_dft(orc):
+    # the oracle's own radix-2 FFT against the DFT written out as a sum
+    rng = np.random.default_rng(31)
+    for M in (1, 2, 8, 64, 256):
+        x = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+        jk = np.outer(np.arange(M), np.arange(M)) % M
+        for sign in (-1, 1):
+            ref = (np.exp(sign * 2j * np.pi * jk / M) * x[None, :]).sum(axis=1)
+            assert np.abs(orc.fft(x, sign) - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_toeplitz_matvec_matches_direct_sum(orc):
+    # R(f) V on integer lattices by the Toeplitz convolution equals the direct
+    # sum of the sinc kernel (N up to 4096; gaps, a shifted origin, several f)
+    rng = np.random.default_rng(32)
+    for L, seed in ((700, 1), (2000, 2), (5200, 3)):
+        s = W.gapped_scaled(L, 3, 1024, seed=seed)
+        t = s.t + 17.0
+        assert s.N <= 4096
+        V = rng.standard_normal((s.N, 3))
+        for f in (s.fw, 0.5, 0.37):
+            A = orc.apply_sinc(t, f, V)
+            B = orc.apply_sinc_toeplitz(t, f, V)
+            assert np.abs(A - B).max() <= 1e-13 * np.abs(A).max()
+    with pytest.raises(orc.OracleError):
+        orc.apply_sinc_toeplitz(np.array([0.0, 1.5, 3.0]), 0.1, np.ones((3, 1)))
+
+
+def test_lattice_method_matches_jacobi_and_lanczos(orc):
+    # the lattice method (no N x N matrix, Toeplitz Lanczos) against the dense
+    # Jacobi solve and the direct-sum Lanczos
+    s = W.gapped_scaled(700, 4, 4096, seed=5)
+    w_j, lam_j = orc.gpss_tapers(s.t, 0.5, s.fw, 4, method="jacobi")
+    w_t, lam_t = orc.gpss_tapers(s.t, 0.5, s.fw, 4, method="lattice")
+    np.testing.assert_allclose(lam_t, lam_j, atol=1e-13)
+    np.testing.assert_allclose(w_t, w_j, atol=1e-9)
+    s = W.gapped_scaled(2600, 5, 4096, seed=6)
+    w_l, lam_l = orc.gpss_tapers(s.t, 1.0, s.fw, 5, method="lanczos")
+    w_t, lam_t = orc.gpss_tapers(s.t, 1.0, s.fw, 5, method="lattice")
+    np.testing.assert_allclose(lam_t, lam_l, atol=1e-13)
+    np.testing.assert_allclose(w_t, w_l, atol=1e-9)
+    with pytest.raises(orc.OracleError):
+        orc.gpss_tapers(s.t + 0.5, 0.5, s.fw, 5, method="lattice")
+
+
 # --------------------------------------------------------------------------
 # P1: closed forms at N = 1 and N = 2
 # --------------------------------------------------------------------------
@@ -364,7 +409,7 @@ def test_sinusoid_peak_band(orc):
 
 
 # --------------------------------------------------------------------------
-# Thomson F-test (Sec. 3.4)
+# Thomson F-test (Sec. 3.6)
 # --------------------------------------------------------------------------
 def _ftest_levels():
     import os
@@ -444,7 +489,7 @@ def test_ftest_detects_a_line_on_the_lattice(orc):
 
 
 def test_ftest_null_distribution(orc):
-    # white Gaussian noise: F ~ F(2, 2K-2) (Sec. 3.4).  Bands 4 f_w apart
+    # white Gaussian noise: F ~ F(2, 2K-2) (Sec. 3.6).  Bands 4 f_w apart
     # are nearly independent; the exceedance rate at p = 0.05 and the mean
     # nu / (nu - 2) are checked against binomial and sampling errors
     N, K, NW = 512, 6, 3.5
