@@ -15,10 +15,16 @@ adds the two one-line steps that are clearer in numpy:
 * ``m2nufft``: Table 3 steps 3 (GEP branch), 4 and 5 in order;
 * ``nudft_freqs``: eigencoefficients at an arbitrary list of band centres;
 * ``idpss_tapers``: the interpolated-DPSS tapers of Table 3 step 3 (fc0 = 0):
-  uniform-grid DPSS, natural cubic spline to t, R(B) normalisation;
+  uniform-grid DPSS (this oracle's GEP on the gap-free lattice), natural cubic
+  spline to t (or_natural_spline), R(B) normalisation;
 * ``subband_tapers``, ``subband_eigcoeffs``, ``fix_phase``: one sub-band of
   the multiband partition (Sec. 2.4, Sec. 3.1-3.2): complex tapers of the
-  nominal band at fc0 and their eigencoefficients on relative frequencies.
+  nominal band at fc0 (or_reduce_herm, Hermitian Lanczos with or_jacobi on
+  the tridiagonal) and their eigencoefficients on relative frequencies.
+
+No eigen-solver, factorisation or triangular solve of a library is used: the
+GEPs are the oracle's own Cholesky, Jacobi and Lanczos; numpy serves for
+matrix products, sums and the elementwise steps.
 
 Parity pins: tests/test_oracle_pins.py.  Readings where the paper is silent
 (sign of a taper, the suboptimality estimate) are stated at each function.
@@ -77,6 +83,12 @@ def lib():
         L.or_lanczos.argtypes = [_d, ctypes.c_long, ctypes.c_double, _d, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, _d, _d,
                                  ctypes.c_uint64, ctypes.c_int]
+        L.or_reduce_herm.restype = None
+        L.or_reduce_herm.argtypes = [_d, _d, _d, ctypes.c_long, _d, _d]
+        L.or_solve_LT.restype = None
+        L.or_solve_LT.argtypes = [_d, ctypes.c_long, _d, ctypes.c_long]
+        L.or_natural_spline.restype = None
+        L.or_natural_spline.argtypes = [_d, ctypes.c_long, _d, ctypes.c_long, _d, ctypes.c_long, _d]
         L.or_fft.restype = None
         L.or_fft.argtypes = [_d, _d, ctypes.c_long, ctypes.c_int]
         L.or_apply_sinc_toeplitz.restype = ctypes.c_int
@@ -250,26 +262,72 @@ def fix_sign(t, w):
     return out
 
 
+def natural_spline(u, v, x):
+    """Natural cubic spline through (u_m, v_m) (rows of v share the knots),
+    evaluated at x (or_natural_spline)."""
+    u, x = _f64(u), _f64(x)
+    v = _f64(np.atleast_2d(v))
+    out = np.empty((v.shape[0], x.shape[0]))
+    lib().or_natural_spline(_p(u), u.shape[0], _p(v), v.shape[0], _p(x), x.shape[0], _p(out))
+    return out
+
+
 def idpss_tapers(t, fmax, fw, K):
     """Interpolated-DPSS tapers (Table 3 step 3, the branch for fc0 = 0):
-    (a) the DPSS of length N and half-bandwidth f_w on the uniform grid
-    u_m = t_1 + m D, D = (t_N - t_1) / (N - 1) (scipy's tridiagonal solver;
-    half-bandwidth f_w D in cycles per grid step), (b) a natural cubic spline
-    from u to t (scipy), (c) the scale that makes w^T R(B) w = 2 f_w, with R(B)
-    from or_gpss_matrix; sign by ``fix_sign``.  Returns (w [K, N], lam [K]),
-    lam the concentrations of the uniform-grid DPSS."""
-    import scipy.signal.windows as sw
-    from scipy.interpolate import CubicSpline
+    (a) the DPSS of length N and half-bandwidth f_w D on the uniform grid
+    u_m = t_1 + m D, D = (t_N - t_1) / (N - 1): the unit-norm GPSS tapers of
+    the gap-free lattice 0..N-1 with f_max = 1/2 (R(B) = I there, so the GEP
+    is the standard eigenproblem of the sinc matrix of half-bandwidth f_w D,
+    whose eigenvectors are the DPSS), from this oracle's own GEP; (b) the
+    natural cubic spline from u to t (``natural_spline``); (c) the scale that
+    makes w^T R(B) w = 2 f_w, with R(B) from or_gpss_matrix; sign by
+    ``fix_sign``.  Returns (w [K, N], lam [K]), lam the concentrations of the
+    uniform-grid DPSS."""
     t = _f64(t)
     N = t.shape[0]
     D = (t[-1] - t[0]) / (N - 1)
     u = t[0] + D * np.arange(N)
-    v, lam = sw.dpss(N, N * fw * D, Kmax=K, return_ratios=True)
-    v = np.atleast_2d(v)
-    w = CubicSpline(u, v.T, bc_type="natural")(t).T
+    fwD = fw * D
+    g, lam = gpss_tapers(np.arange(N, dtype=np.float64), 0.5, fwD, K)
+    v = g / np.sqrt(2.0 * fwD)                  # unit-norm DPSS
+    w = natural_spline(u, v, t)
     q = np.einsum("kn,nm,km->k", w, gpss_matrix(t, fmax), w)
     w = w * np.sqrt(2.0 * fw / q)[:, None]
     return fix_sign(t, w), np.atleast_1d(lam).copy()
+
+
+def herm_lanczos(C, K, mmax=400, tol=1e-14, seed=0x5EED):
+    """The K largest eigenpairs of a complex Hermitian matrix C by Lanczos
+    with full re-orthogonalisation (two classical Gram-Schmidt passes), the
+    Ritz pairs from or_jacobi on the real tridiagonal T (Hermitian Lanczos
+    keeps alpha and beta real).  Convergence: |beta_m s_{m,k}| <= tol for
+    the K wanted Ritz pairs, checked every 8 steps.  Returns (theta [K]
+    descending, Z [N, K])."""
+    C = np.asarray(C, dtype=np.complex128)
+    N = C.shape[0]
+    mmax = min(mmax, N)
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(-1, 1, N) + 1j * rng.uniform(-1, 1, N)
+    Q = np.zeros((mmax + 1, N), dtype=np.complex128)
+    Q[0] = q / np.linalg.norm(q)
+    alpha, beta = np.zeros(mmax), np.zeros(mmax)
+    for j in range(mmax):
+        z = C @ Q[j]
+        alpha[j] = float(np.real(np.vdot(Q[j], z)))
+        for _ in range(2):
+            z -= Q[:j + 1].T @ (Q[:j + 1].conj() @ z)
+        b = float(np.linalg.norm(z))
+        beta[j] = b
+        m = j + 1
+        if m >= K and (m % 8 == 0 or m == mmax or b < 1e-300):
+            T = np.diag(alpha[:m]) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+            th, S = jacobi_eigh(T)
+            if np.max(np.abs(b * S[m - 1, :K])) <= tol or b < 1e-300 or m == mmax:
+                return th[:K].copy(), Q[:m].T @ S[:, :K]
+        if b < 1e-300:
+            break
+        Q[j + 1] = z / b
+    raise OracleError(-4, "herm_lanczos")
 
 
 def fix_phase(t, fc0, w):
@@ -303,21 +361,24 @@ def subband_tapers(t, fmin, fmax, fw, fc0, K):
 
     Steps: R(B^q) = L L^T (real Cholesky, or_cholesky); R(A0) is complex
     Hermitian (Sec. 3.2, e^{j 2 pi fc0 tau} times the sinc of f_w), and
-    C = L^{-1} R(A0) L^{-T} by two triangular solves (L is real, so L^{-T} is
-    also L^{-*}); the eigenpairs of C come from LAPACK's Hermitian solver;
-    w = sqrt(2 f_w) L^{-T} z.  Returns (w [K, N] complex, lam [K]).
+    C = L^{-1} R(A0) L^{-T} by triangular solves on its real and imaginary
+    parts (or_reduce_herm; L is real, so L^{-T} is also L^{-*}); the top
+    eigenpairs of C by Hermitian Lanczos (``herm_lanczos``);
+    w = sqrt(2 f_w) L^{-T} z (or_solve_LT).  Returns (w [K, N] complex, lam [K]).
     """
-    import scipy.linalg as sla
     t = _f64(t)
+    N = t.shape[0]
     L = cholesky(subband_matrix(t, fmin, fmax))
     RA = band_matrix(t, fc0, fw)
-    M = sla.solve_triangular(L, RA, lower=True)            # L^{-1} R(A0)
-    C = sla.solve_triangular(L, M.T, lower=True).T         # (L^{-1} M^T)^T = M L^{-T}
-    C = 0.5 * (C + C.conj().T)
-    th, Z = np.linalg.eigh(C)
-    idx = np.argsort(th)[::-1][:K]
-    w = np.sqrt(2.0 * fw) * sla.solve_triangular(L.T, Z[:, idx], lower=False)
-    return fix_phase(t, fc0, w.T), th[idx].copy()
+    Ar, Ai = _f64(RA.real.copy()), _f64(RA.imag.copy())
+    Cr, Ci = np.empty((N, N)), np.empty((N, N))
+    lib().or_reduce_herm(_p(L), _p(Ar), _p(Ai), N, _p(Cr), _p(Ci))
+    th, Z = herm_lanczos(Cr + 1j * Ci, K)
+    Xr, Xi = _f64(Z.real.copy()), _f64(Z.imag.copy())
+    lib().or_solve_LT(_p(L), N, _p(Xr), K)
+    lib().or_solve_LT(_p(L), N, _p(Xi), K)
+    w = np.sqrt(2.0 * fw) * (Xr + 1j * Xi)
+    return fix_phase(t, fc0, w.T), np.asarray(th, dtype=np.float64).copy()
 
 
 def subband_eigcoeffs(t, x, w, f_lo, df, I=None, bands=None):

@@ -26,6 +26,11 @@
  *                       rounding; O(S log S) instead of O(N^2))
  *   or_cholesky         R(B) = L L^T, unblocked, row oriented
  *   or_reduce           C = L^{-1} R(A0) L^{-T}  (GEP -> standard problem)
+ *   or_reduce_herm      the same for a complex Hermitian R(A0) = Ar + j Ai
+ *                       and real L (sub-band GEP)
+ *   or_solve_LT         X <- L^{-T} X (back substitution, several columns)
+ *   or_natural_spline   natural cubic spline through (u_m, v_m), evaluated at
+ *                       t_n (interpolated-DPSS tapers)
  *   or_jacobi           full eigen-decomposition by cyclic Jacobi
  *   or_lanczos          top eigenpairs of C by Lanczos with full
  *                       re-orthogonalisation (large N)
@@ -359,6 +364,90 @@ void or_reduce(const double *L, const double *RA, long N, double *C)
         for (long j = 0; j < N; ++j)
             C[i * N + j] = 0.5 * (M[i * N + j] + M[j * N + i]);
     free(M);
+}
+
+/* Complex Hermitian R(A0) = Ar + j Ai (Ar symmetric, Ai antisymmetric)
+ * with real L: C = L^{-1} R(A0) L^{-T} has real part L^{-1} Ar L^{-T}
+ * (symmetrised) and imaginary part L^{-1} Ai L^{-T} (antisymmetrised). */
+void or_reduce_herm(const double *L, const double *Ar, const double *Ai, long N,
+                    double *Cr, double *Ci)
+{
+    size_t NN = (size_t)N * (size_t)N;
+    double *M = (double *)malloc(sizeof(double) * NN);
+    for (int part = 0; part < 2; ++part) {
+        memcpy(M, part ? Ai : Ar, sizeof(double) * NN);
+#pragma omp parallel for schedule(static)
+        for (long c = 0; c < N; ++c) fwd_subst(L, N, M + c, N);
+#pragma omp parallel for schedule(static)
+        for (long r = 0; r < N; ++r) fwd_subst(L, N, M + r * N, 1);
+        double *C = part ? Ci : Cr;
+        double sg = part ? -1.0 : 1.0;
+        for (long i = 0; i < N; ++i)
+            for (long j = 0; j < N; ++j)
+                C[i * N + j] = 0.5 * (M[i * N + j] + sg * M[j * N + i]);
+    }
+    free(M);
+}
+
+/* X (N x nrhs, row-major) <- L^{-T} X */
+void or_solve_LT(const double *L, long N, double *X, long nrhs)
+{
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nrhs; ++c) back_subst_T(L, N, X + c, nrhs);
+}
+
+/* Natural cubic spline through (u_m, v_m), m < n (u strictly increasing,
+ * n >= 2), evaluated at x[0..nx): second derivatives M with M_0 = M_{n-1} = 0
+ * from the continuity of the first derivative at the interior knots,
+ *   h_{m-1} M_{m-1} + 2 (h_{m-1} + h_m) M_m + h_m M_{m+1}
+ *       = 6 ((v_{m+1} - v_m) / h_m - (v_m - v_{m-1}) / h_{m-1}),
+ * solved by forward elimination and back substitution (the system is
+ * tridiagonal and diagonally dominant); on [u_m, u_{m+1}] the cubic is
+ *   M_m (u_{m+1} - x)^3 / (6 h) + M_{m+1} (x - u_m)^3 / (6 h)
+ *   + (v_m / h - M_m h / 6) (u_{m+1} - x) + (v_{m+1} / h - M_{m+1} h / 6) (x - u_m).
+ * Points outside [u_0, u_{n-1}] use the end intervals' cubics.  nv series
+ * v[k * n + m] share the knots; out[k * nx + i]. */
+void or_natural_spline(const double *u, long n, const double *v, long nv,
+                       const double *x, long nx, double *out)
+{
+    double *M = (double *)calloc((size_t)n, sizeof(double));
+    double *cp = (double *)calloc((size_t)n, sizeof(double));
+    double *dp = (double *)calloc((size_t)n, sizeof(double));
+    for (long k = 0; k < nv; ++k) {
+        const double *vk = v + k * n;
+        for (long m = 0; m < n; ++m) M[m] = 0.0;
+        if (n > 2) {
+            /* unknowns M_1..M_{n-2}; row m: a M_{m-1} + b M_m + c M_{m+1} = d */
+            for (long m = 1; m <= n - 2; ++m) {
+                double h0 = u[m] - u[m - 1], h1 = u[m + 1] - u[m];
+                double a = h0, b = 2.0 * (h0 + h1), c = h1;
+                double d = 6.0 * ((vk[m + 1] - vk[m]) / h1 - (vk[m] - vk[m - 1]) / h0);
+                if (m > 1) {
+                    double den = b - a * cp[m - 1];
+                    cp[m] = c / den;
+                    dp[m] = (d - a * dp[m - 1]) / den;
+                } else {
+                    cp[m] = c / b;
+                    dp[m] = d / b;
+                }
+            }
+            M[n - 2] = dp[n - 2];
+            for (long m = n - 3; m >= 1; --m) M[m] = dp[m] - cp[m] * M[m + 1];
+        }
+        for (long i = 0; i < nx; ++i) {
+            double xi = x[i];
+            long lo = 0, hi = n - 1;            /* u[lo] <= xi < u[hi] */
+            while (hi - lo > 1) {
+                long mid = (lo + hi) / 2;
+                if (u[mid] <= xi) lo = mid; else hi = mid;
+            }
+            double h = u[hi] - u[lo], A = u[hi] - xi, B = xi - u[lo];
+            out[k * nx + i] = M[lo] * A * A * A / (6.0 * h) + M[hi] * B * B * B / (6.0 * h)
+                              + (vk[lo] / h - M[lo] * h / 6.0) * A
+                              + (vk[hi] / h - M[hi] * h / 6.0) * B;
+        }
+    }
+    free(M); free(cp); free(dp);
 }
 
 /* ------------------------------------------------------------------ */

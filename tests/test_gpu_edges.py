@@ -139,12 +139,21 @@ def test_largest_band_count_sampled(m2n, ctx, orc):
     # I = 2^21 (n_f = 2^22, the largest split of this build), sampled bands
     s = W.gapped_scaled(6000, 3, 2 ** 21, seed=45)
     w = np.random.default_rng(301).standard_normal((3, s.N)) * 0.05
-    bands = np.unique(np.concatenate([np.arange(0, 32), np.arange(s.I - 32, s.I),
-                                      np.random.default_rng(8).integers(0, s.I, 1024)]))
     _say(f"case I=2^21 N={s.N}")
+    out64 = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), None, s.fmax, s.fw, s.f_lo, s.df,
+                            s.I, prec=m2n.M2N_FP64, want_E=False, want_J=True)
+    P64 = out64["P"].cpu().numpy()
+    # both ends, 4,096 uniform draws and the 256 bands of largest P
+    bands = np.unique(np.concatenate([np.arange(0, 32), np.arange(s.I - 32, s.I),
+                                      np.random.default_rng(8).integers(0, s.I, 4096),
+                                      np.argsort(P64)[-256:]]))
     J_o = orc.nudft(s.t, s.x, w, s.f_lo, s.df, bands=bands)
     for prec, tol in ((m2n.M2N_FP64, 1e-10), (m2n.M2N_FP32, 1e-5)):
-        out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), None, s.fmax, s.fw, s.f_lo, s.df,
-                              s.I, prec=prec, want_E=False, want_J=True)
+        out = out64 if prec == m2n.M2N_FP64 else m2n.m2nufft_psd(
+            ctx, _dev(s.t), _dev(s.x), _dev(w), None, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=prec,
+            want_E=False, want_J=True)
         J = out["J"].cpu().numpy().astype(np.complex128)[:, bands]
-        assert normwise_rows(J, J_o) < 10 * tol
+        P = out["P"].cpu().numpy().astype(np.float64)[bands]
+        eJ, eP = normwise_rows(J, J_o), psd_err(P, orc.psd(J_o))
+        _say(f"  prec={prec}: J sampled {eJ:.3e}  P {eP:.3e}")
+        assert eJ < tol and eP < tol

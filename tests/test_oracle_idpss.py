@@ -54,3 +54,25 @@ def test_idpss_approximates_gpss_on_jittered_grids(orc):
         w0, _ = orc.gpss_tapers(s.t, 0.5, fw, 3, method="jacobi")
         errs.append(np.abs(w - w0).max() / np.abs(w0).max())
     assert errs[2] < 0.02 and errs[2] < errs[1] < errs[0]
+
+
+def test_natural_spline_end_conditions_and_library(orc):
+    # the oracle's natural cubic spline: it interpolates the knots, reproduces
+    # linear functions, has zero second derivative at both ends (central
+    # second differences of a cubic are exact, extrapolated linearly to the
+    # end knot), and equals scipy's natural CubicSpline on non-uniform knots
+    from scipy.interpolate import CubicSpline
+    rng = np.random.default_rng(77)
+    u = np.cumsum(rng.uniform(0.5, 1.5, 40))
+    v = rng.standard_normal((3, 40))
+    S = lambda x: orc.natural_spline(u, v, np.atleast_1d(np.asarray(x, dtype=np.float64)))
+    np.testing.assert_allclose(S(u), v, atol=1e-13)
+    lin = 0.3 * u - 1.7
+    np.testing.assert_allclose(orc.natural_spline(u, lin, u + 0.1)[0], 0.3 * (u + 0.1) - 1.7, atol=1e-12)
+    x = np.linspace(u[0], u[-1], 2001)
+    np.testing.assert_allclose(S(x), CubicSpline(u, v.T, bc_type="natural")(x).T, atol=1e-12)
+    for a, h in ((u[0], (u[1] - u[0]) / 8), (u[-1], -(u[-1] - u[-2]) / 8)):
+        p = S(a + h * np.arange(4)).T            # [4, 3]
+        d2_1 = (p[0] - 2 * p[1] + p[2]) / h ** 2  # S'' at a + h
+        d2_2 = (p[1] - 2 * p[2] + p[3]) / h ** 2  # S'' at a + 2 h
+        assert np.abs(2 * d2_1 - d2_2).max() < 1e-7 * max(1.0, np.abs(d2_1).max())
