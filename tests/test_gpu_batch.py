@@ -79,6 +79,24 @@ def test_batch_mixed_paths_and_band_counts(m2n, ctx):
     _compare(m2n, ctx, series[:2], [True, False], m2n.M2N_FP64)
 
 
+def test_batch_512_series_bitwise_tapers(m2n, ctx):
+    # the batched form's size (512 uneven series, more than 4,096 Gram chunks in
+    # all): every series' tapers and eigenvalues are bitwise those of its call
+    # alone, P within the FP32 NuFFT tolerance
+    series = [W.batched_series(s) for s in range(512)]
+    _say(f"case 512 batched_series: {sum(s.N for s in series)} samples, "
+         f"{sum((s.N + 63) // 64 for s in series)} Gram chunks")
+    outs = m2n.m2n_batch_psd(ctx, [_spec(s) for s in series], prec=m2n.M2N_FP32)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for s, o in zip(series, outs):
+        w, lam, P, _ = _single(m2n, ctx, s, m2n.M2N_FP32, False)
+        assert torch.equal(o["w"], w) and torch.equal(o["lam"], lam), s.name
+        worst = max(worst, psd_err(o["P"].double().cpu().numpy(), P.double().cpu().numpy()))
+    _say(f"  tapers bitwise for all 512; P batch-vs-single max {worst:.2e}")
+    assert worst < 2e-6
+
+
 def test_batch_against_oracle(m2n, ctx, orc):
     picks = [s for s in (W.batched_series(i) for i in range(40)) if s.N < 2500][:2]
     assert len(picks) == 2
