@@ -2,10 +2,11 @@
 """Benchmark of the M2NuFFT hot path on one MI355X.
 
 One step = the whole path for one gapped series: GPSS tapers by the GEP at the
-nominal band (validation, R(B)/R(A0), Cholesky reduction, subspace iteration,
-normalisation), then the type-1 NuFFT of the K tapered sequences onto the I
-band centres fused with the multitaper average P and the suboptimality
-estimate Ehat.  Inputs are resident in HBM before the timed region.
+nominal band (validation of t, R(B) = I detected on the lattice, R(A0) by its
+quadrature factor, the Gram matrix and its top-K eigen-solve, normalisation
+and sign), then the type-1 NuFFT of the K tapered sequences onto the I band
+centres fused with the multitaper average P and the suboptimality estimate
+Ehat.  Inputs are resident in HBM before the timed region.
 
 Workload (default): 20,480-sample unit grid with periodic 64-of-320 gaps and
 5 % random dropouts (N observed ~ 15.5k), AR(2) + 5 sinusoids, f_w = 4/20480,
@@ -14,7 +15,10 @@ K = 7, I = 2^18 bands; NuFFT in FP32 at tolerance 1e-6, GEP in FP64.
 value = N K I / (seconds per step) / 1e6   (NUDFT-equivalent Mpts*tapers*bands/s)
 plus PSDs/s, step latency p50/p99, the NuFFT-only rate, the dominant kernel's
 roofline (HIP events on the launch stream over a second timed pass) and the
-CPU FP64 oracle timed on a bounded sample of the same workload.
+CPU FP64 oracle timed on a bounded sample of the same workload (all threads
+and one thread).  `legs` repeats the step on the FP64 path of the same
+workload, on the 256-sample series (FP64) and on the 81,920-sample series
+(FP32), each with its parity against the oracle on sampled bands.
 """
 import argparse
 import json
@@ -154,7 +158,7 @@ def parse():
                     help="bands in the oracle's timed NUDFT sample")
     ap.add_argument("--batch-series", type=int, default=512,
                     help="series in the batched-form measurement (0: skip)")
-    ap.add_argument("--served-seconds", type=float, default=10.0,
+    ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served-form Poisson arrival trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0, help="arrivals per second")
     ap.add_argument("--gep-stress-n", type=int, default=16384,
@@ -162,6 +166,8 @@ def parse():
     ap.add_argument("--multiband-n", type=int, default=4096,
                     help="samples of the multiband form (0 skips it)")
     ap.add_argument("--no-idpss", action="store_true", help="skip the interpolated-DPSS form")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other workloads' step legs (FP64 gapped_20k, small_gapped, gapped_82k)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (byte-counter calibration)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
@@ -341,6 +347,80 @@ def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
 
 
 FP64_PEAK_TFLOPS = 78.6
+# the NuFFT settings of each precision (the library's defaults at tolerance 0:
+# kernel width ceil(-log10 tol) + 1, oversampling 2)
+NUFFT_LABEL = {"fp32": "fp32 tol 1e-6 w7 sigma2", "fp64": "fp64 tol 1e-12 w13 sigma2"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def step_leg(m2n, torch, workloads, ctx, name, prec_name, steps, warmup, oracle_bands=1024):
+    """The per-series step (tapers, then P and Ehat) on one workload and
+    precision: median step time over `steps` timed steps after `warmup`, and
+    P on sampled bands (both ends, uniform draws, the largest-P bands) and
+    lambda against the oracle (its own tapers through its direct NUDFT)."""
+    import numpy as np
+    s = getattr(workloads, name)()
+    prec = m2n.M2N_FP32 if prec_name == "fp32" else m2n.M2N_FP64
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(dev)
+    x = torch.from_numpy(s.x).to(dev)
+    w = torch.empty((s.K, s.N), dtype=torch.float64, device=dev)
+    lam = torch.empty((s.K,), dtype=torch.float64, device=dev)
+    rdt = torch.float32 if prec == m2n.M2N_FP32 else torch.float64
+    P = torch.empty((s.I,), dtype=rdt, device=dev)
+    E = torch.empty((s.I,), dtype=rdt, device=dev)
+
+    def step():
+        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K, out=(w, lam))
+        m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=prec,
+                        want_E=True, out=(P, E, None), check=False)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    ms = 1e3 * float(np.median(lat))
+    out = {"workload": name, "N": s.N, "K": s.K, "I": s.I, "prec": prec_name,
+           "nufft": NUFFT_LABEL[prec_name], "steps": steps, "ms_per_step": round(ms, 4),
+           "value": round(s.N * s.K * s.I / (ms * 1e-3) / 1e6, 1), "unit": "Mpts*tapers*bands/s",
+           "psds_per_s": round(1e3 / ms, 1),
+           "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
+                          "p99": round(1e3 * float(np.percentile(lat, 99)), 4)}}
+    import oracle
+    Pg = P.double().cpu().numpy()
+    rng = np.random.default_rng(5 + s.N)
+    nb = min(oracle_bands, s.I)
+    bands = np.unique(np.concatenate([[0, s.I - 1], rng.integers(0, s.I, nb),
+                                      np.argsort(Pg)[-min(64, s.I):]])).astype(np.int64)
+    w_o, lam_o = oracle.gpss_tapers(s.t, s.fmax, s.fw, s.K)
+    P_o = oracle.psd(oracle.nudft(s.t, s.x, w_o, s.f_lo, s.df, bands=bands))
+    E_o, _ = oracle.ehat(s.t, w_o, lam_o, s.fmax, s.fw, s.f_lo, s.df, bands=bands[:64]) \
+        if s.N <= 4096 else (None, None)
+    gate = 1e-5 if prec == m2n.M2N_FP32 else 1e-10
+    err = float(np.max(np.abs(Pg[bands] - P_o)) / np.max(P_o))
+    par = {"bands": int(bands.size), "P_rel_err": err,
+           "lambda_abs_err": float(np.max(np.abs(lam.cpu().numpy() - lam_o))), "gate": gate}
+    if E_o is not None:
+        par["Ehat_abs_err"] = float(np.max(np.abs(E.double().cpu().numpy()[bands[:64]] - E_o)))
+    par["pass"] = bool(err < gate and par["lambda_abs_err"] < 1e-12 and par.get("Ehat_abs_err", 0.0) < gate)
+    out["parity"] = par
+    return out
 
 
 def gep_stress(m2n, torch, workloads, ctx, n, reps=3):
@@ -571,46 +651,6 @@ def idpss_form(m2n, torch, workloads, ctx, s_main, reps=5):
     return out
 
 
-def schemes_form(m2n, torch, workloads, ctx, n_spectra=1000):
-    """The timing experiment's shape (Sec. 4): 1,000 spectra of 50-point
-    series, a quarter on each of the four sampling schemes (uniform, jitter,
-    missing data, arithmetic), f_w = 0.05, K = 4, 64 bands, one series per
-    call: interpolated-DPSS tapers then the FP64 NuFFT and average, and the
-    same with the GEP tapers.  Reports spectra per second (host round trips
-    included: each taper call waits for its t check) and, for the GEP tapers,
-    the series whose R(B) is numerically singular (samples denser than the
-    band needs, as in the arithmetic scheme): their Cholesky stops with
-    NOT_PD, while the interpolated branch needs no factorisation."""
-    dev = torch.device("cuda:0")
-    makers = [workloads.scheme_uniform, workloads.scheme_jitter, workloads.scheme_missing,
-              workloads.scheme_arithmetic]
-    series = [makers[i % 4](seed=100 + i) for i in range(n_spectra)]
-    data = [(torch.from_numpy(q.t).to(dev), torch.from_numpy(q.x).to(dev), q) for q in series]
-    out = {}
-    for label, taper in (("idpss", m2n.idpss_tapers), ("gep", m2n.gpss_tapers)):
-        def one(t, x, q):
-            try:
-                w, lam = taper(ctx, t, q.fmax, q.fw, q.K)
-            except m2n.M2NError as e:
-                if e.code != m2n.M2N_ERR_NOT_PD:
-                    raise
-                return 0
-            m2n.m2nufft_psd(ctx, t, x, w, lam, q.fmax, q.fw, q.f_lo, q.df, q.I, prec=m2n.M2N_FP64,
-                            want_E=False, check=False)
-            return 1
-        for t, x, q in data[:8]:
-            one(t, x, q)
-        torch.cuda.synchronize()
-        h0 = time.perf_counter()
-        done = sum(one(t, x, q) for t, x, q in data)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - h0
-        out[label] = {"seconds": round(sec, 4), "spectra": done, "not_pd": n_spectra - done,
-                      "spectra_per_s": round(done / sec, 1)}
-    return {"spectra": n_spectra, "N": 50, "K": 4, "fw": 0.05, "I": 64,
-            "schemes": ["uniform", "jitter", "missing", "arithmetic"], **out}
-
-
 def psd_at_form(m2n, torch, ctx, s, w, n_centres=4096, reps=10):
     """P at an arbitrary list of band centres (direct FP64 summation) on the
     main workload's tapers: time per call and the rate in sample-centre pairs
@@ -802,19 +842,34 @@ def main():
         nb = min(a.cpu_bands, I)
         bands = np.linspace(0, I - 1, nb).round().astype(np.int64)
         tc0 = time.perf_counter()
-        w_o, lam_o = oracle.gpss_tapers(s.t, s.fmax, s.fw, K, method="lanczos")
+        w_o, lam_o = oracle.gpss_tapers(s.t, s.fmax, s.fw, K)
         tc1 = time.perf_counter()
         J_o = oracle.nudft(s.t, s.x, w_o, s.f_lo, s.df, bands=bands)
         P_o = oracle.psd(J_o)
         tc2 = time.perf_counter()
         t_gep, t_nudft = tc1 - tc0, tc2 - tc1
         t_full = t_gep + t_nudft * I / nb
+        # the same on one thread, on a quarter of the bands
+        nthreads = oracle.num_threads()
+        oracle.set_threads(1)
+        nb1 = max(1, nb // 4)
+        tc3 = time.perf_counter()
+        oracle.gpss_tapers(s.t, s.fmax, s.fw, K)
+        tc4 = time.perf_counter()
+        oracle.nudft(s.t, s.x, w_o, s.f_lo, s.df, bands=bands[::4][:nb1])
+        tc5 = time.perf_counter()
+        oracle.set_threads(nthreads)
+        t1_full = (tc4 - tc3) + (tc5 - tc4) * I / nb1
         cpu = {"value": round(N * K * I / t_full / 1e6, 3), "unit": "Mpts*tapers*bands/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": (f"GEP by Lanczos on the full series ({t_gep:.2f} s) + direct NUDFT "
-                          f"and average on {nb} of {I} bands ({t_nudft:.2f} s), "
-                          f"extrapolated to all bands"),
-               "seconds_per_psd": round(t_full, 3)}
+               "cores": nthreads, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": (f"GEP by Lanczos with the lattice Toeplitz operator on the full series "
+                          f"({t_gep:.2f} s) + direct NUDFT and average on {nb} of {I} bands "
+                          f"({t_nudft:.2f} s), extrapolated to all bands"),
+               "seconds_per_psd": round(t_full, 3),
+               "single_thread": {"value": round(N * K * I / t1_full / 1e6, 3),
+                                 "seconds_per_psd": round(t1_full, 3),
+                                 "sample": (f"GEP {tc4 - tc3:.2f} s + NUDFT on {nb1} bands "
+                                            f"{tc5 - tc4:.2f} s, extrapolated")}}
         Pg = P.double().cpu().numpy()[bands]
         err = float(np.max(np.abs(Pg - P_o)) / np.max(P_o))
         lam_err = float(np.max(np.abs(lam.cpu().numpy() - lam_o)))
@@ -857,19 +912,21 @@ def main():
         print(f"bench: idpss {idpss['main']['idpss_ms']} ms (GEP {idpss['main']['gep_ms']} ms) on {s.name}",
               file=sys.stderr, flush=True)
 
-    schemes = None
-    if not a.no_idpss:
-        print("bench: sampling-scheme spectra", file=sys.stderr, flush=True)
-        schemes = schemes_form(m2n, torch, workloads, ctx)
-        print(f"bench: schemes {schemes['idpss']['spectra_per_s']} spectra/s (interpolated DPSS), "
-              f"{schemes['gep']['spectra_per_s']} (GEP)", file=sys.stderr, flush=True)
-
     print("bench: band-centre list", file=sys.stderr, flush=True)
     wl = torch.empty((s.K, s.N), dtype=torch.float64, device=torch.device("cuda:0"))
     ll = torch.empty((s.K,), dtype=torch.float64, device=torch.device("cuda:0"))
     m2n.gpss_tapers(ctx, torch.from_numpy(s.t).cuda(), s.fmax, s.fw, s.K, out=(wl, ll))
     psd_at = psd_at_form(m2n, torch, ctx, s, wl)
     print(f"bench: band-centre list {psd_at['ms']} ms for {psd_at['centres']} centres", file=sys.stderr, flush=True)
+
+    legs = []
+    if not a.no_legs:
+        for wl, pr, st_, wu in (("gapped_20k", "fp64", 20, 5), ("small_gapped", "fp64", 50, 10),
+                                ("gapped_82k", "fp32", 10, 3)):
+            print(f"bench: leg {wl} {pr}", file=sys.stderr, flush=True)
+            legs.append(step_leg(m2n, torch, workloads, ctx, wl, pr, st_, wu))
+            print(f"bench: leg {wl} {pr} {legs[-1]['ms_per_step']} ms per step, "
+                  f"parity {legs[-1]['parity']['pass']}", file=sys.stderr, flush=True)
 
     value = N * K * I / (ms_step * 1e-3) / 1e6
     line = {
@@ -886,7 +943,7 @@ def main():
         "dtype": "f32" if prec == m2n.M2N_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": s.name, "N": N, "grid_len": s.grid_len, "K": K, "I": I,
-                   "fw": s.fw, "fmax": s.fmax, "nufft": a.prec + " tol 1e-6 w7 sigma2",
+                   "fw": s.fw, "fmax": s.fmax, "nufft": NUFFT_LABEL[a.prec],
                    "gep": "fp64"},
         "psds_per_s": round(1e3 / ms_step, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
@@ -907,8 +964,8 @@ def main():
         "gep_stress": stress,
         "multiband": multiband,
         "idpss": idpss,
-        "schemes_1000": schemes,
         "psd_at": psd_at,
+        "legs": legs,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -61,6 +61,8 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         L.or_num_threads.restype = ctypes.c_int
         L.or_num_threads.argtypes = []
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_validate.restype = ctypes.c_int
         L.or_validate.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.or_sinpi.restype = ctypes.c_double
@@ -117,6 +119,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the oracle's parallel loops (timing only)."""
+    lib().or_set_threads(int(n))
 
 
 def validate(t, fmax, fw, K):

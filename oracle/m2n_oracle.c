@@ -64,8 +64,9 @@
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
-/* number of OpenMP threads the parallel loops use */
+/* number of OpenMP threads the parallel loops use, and its setter */
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 /* ------------------------------------------------------------------ */
 /* argument checks (Table 3 step 1: t_n strictly increasing, 0<fw<fmax) */
