@@ -337,13 +337,42 @@ def batched_form(m2n, torch, workloads, ctx, nser, reps=5):
     ts = time.perf_counter() - t0
     dP = max(float((a.double() - sp["P"].double()).abs().max() / sp["P"].double().abs().max())
              for a, sp in zip(P_batch, specs[:8]))
+    # the replayable batch: one HIP graph per batch, NuFFT schedule by the
+    # autotuner or the default rule, against the same launches issued eagerly
+    replay = {}
+    for label, graph, tune in (("graph_tuned", True, True), ("graph_default", True, False),
+                               ("eager_tuned", False, True)):
+        bspecs = [{k: v for k, v in sp.items() if k not in ("w", "lam", "P", "E")} for sp in specs]
+        b = m2n.Batch(ctx, bspecs, prec=m2n.M2N_FP32, graph=graph, tune=tune)
+        b.launch()
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            b.launch()
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t0)
+        tm = float(np.median(tt))
+        inf = b.info()
+        dPg = max(float((o["P"].double() - a.double()).abs().max() / a.double().abs().max())
+                  for o, a in zip(b.outputs[:8], P_batch))
+        b.close()
+        replay[label] = {"ms_per_batch": round(tm * 1e3, 3), "psds_per_s": round(nser / tm, 1),
+                         "value": round(work / tm / 1e6, 1), "P_rel_vs_batch_psd": dPg,
+                         "graph_nodes": inf["graph_nodes"], "tuned": bool(inf["tuned"]),
+                         "schedule": {"log2_N1": inf["l1"], "B": inf["B"], "M": inf["M"]}
+                         if inf["tuned"] else "default rule",
+                         "tuner": {"from_cache": bool(inf["from_cache"]), "candidates": inf["candidates"],
+                                   "nufft_ms_default": round(inf["nufft_ms_default"], 4),
+                                   "nufft_ms_tuned": round(inf["nufft_ms_tuned"], 4)} if inf["tuned"] else None}
     return {"series": nser, "N_range": [min(s.N for s in series), max(s.N for s in series)],
             "K_range": [min(s.K for s in series), max(s.K for s in series)], "I": series[0].I,
             "ms_per_batch": round(tb * 1e3, 3), "psds_per_s": round(nser / tb, 1),
             "value": round(work / tb / 1e6, 1), "unit": "Mpts*tapers*bands/s",
             "per_series_ms": round(ts * 1e3, 3), "per_series_psds_per_s": round(nser / ts, 1),
             "speedup_vs_per_series": round(ts / tb, 2),
-            "batch_vs_per_series_P_rel": dP, "kernels_ms": kern, "roofline_nufft": roof}
+            "batch_vs_per_series_P_rel": dP, "kernels_ms": kern, "roofline_nufft": roof,
+            "replayable": replay}
 
 
 FP64_PEAK_TFLOPS = 78.6

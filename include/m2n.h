@@ -367,6 +367,62 @@ int m2n_batch_psd(m2n_ctx *ctx, void *stream, const m2n_series *series, int nser
                   int prec, double nufft_tol);
 
 /*
+ * Replayable batches -- m2n_batch_psd for the same series launched many
+ * times (fixed batch shapes: the same t, new x between launches is fine),
+ * prepared once:
+ *   m2n_batch_create  checks every series' t (one host round trip; each must
+ *                     take the lattice path: integer t, integer 2 f_max and
+ *                     quadrature rank Q + 2 <= 64, else M2N_ERR_UNSUPPORTED
+ *                     naming the series), creates a child context of ctx that
+ *                     owns every workspace, plan and staging block of the
+ *                     batch, and runs one warm-up pass (results written).
+ *                     With M2N_BATCH_TUNE it first times every NuFFT schedule
+ *                     this build has kernels for at each band count of the
+ *                     batch (column FFT length, pass-1 column block, pass-2
+ *                     rows per workgroup; HIP events, median of three) and
+ *                     keeps the fastest; the choice is appended to a text
+ *                     file ($M2N_TUNE_CACHE, else
+ *                     ${XDG_CACHE_HOME:-$HOME/.cache}/m2n/nufft_schedules.txt;
+ *                     M2N_TUNE_CACHE="" disables it) keyed by device, band
+ *                     count, precision, kernel width and the batch's size
+ *                     class, and read back by later batches of that class.
+ *                     With M2N_BATCH_GRAPH one more pass is captured into a
+ *                     HIP graph (private capture stream).
+ *   m2n_batch_launch  recomputes tapers, lambda, P, Ehat (and J, F when
+ *                     given) of every series from the current contents of the
+ *                     inputs: one hipGraphLaunch on `stream` with a graph,
+ *                     else the same launches one by one.  No host round trip,
+ *                     no allocation.  Launches on one batch must be ordered.
+ *   m2n_batch_destroy waits for the device and frees the batch.
+ * The series array and the device buffers it points to must outlive the
+ * batch; results equal m2n_batch_psd's (tapers bitwise; P, Ehat within the
+ * NuFFT tolerance when the autotuner chose another schedule).
+ */
+#define M2N_BATCH_GRAPH 1
+#define M2N_BATCH_TUNE 2
+typedef struct m2n_batch m2n_batch;
+typedef struct {
+    int graph;               /* 1 when launches replay a HIP graph           */
+    int graph_nodes;         /* nodes of that graph                           */
+    int tuned;               /* 1 when the autotuner ran                      */
+    int from_cache;          /* 1 when a schedule came from the file          */
+    int candidates;          /* schedules timed                               */
+    int l1, B, M;            /* schedule kept for the last band count
+                                (log2 N1, pass-1 block, pass-2 rows; 0 = the
+                                default rule)                                  */
+    double nufft_ms_default; /* NuFFT time of the default schedule (summed
+                                over band counts; 0 when from the file)       */
+    double nufft_ms_tuned;   /* the same for the kept schedules               */
+    int series, band_counts;
+} m2n_batch_info;
+
+int m2n_batch_create(m2n_ctx *ctx, void *stream, const m2n_series *series, int nseries,
+                     int prec, double nufft_tol, int flags, m2n_batch **out);
+int m2n_batch_launch(m2n_batch *batch, void *stream);
+int m2n_batch_get_info(const m2n_batch *batch, m2n_batch_info *info);
+int m2n_batch_destroy(m2n_batch *batch);
+
+/*
  * Request queue with continuous batching (the served form).
  *
  * Requests carry HOST inputs, which m2n_submit copies before it returns, and

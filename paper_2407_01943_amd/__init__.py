@@ -41,7 +41,10 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
             "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at",
-            "m2nufft_psd_at_noalloc"]
+            "m2nufft_psd_at_noalloc", "m2n_batch_create", "m2n_batch_launch",
+            "m2n_batch_get_info", "m2n_batch_destroy"]
+M2N_BATCH_GRAPH = 1
+M2N_BATCH_TUNE = 2
 
 
 class M2NSubBand(ctypes.Structure):
@@ -58,6 +61,15 @@ class M2NSeries(ctypes.Structure):
                 ("weights", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("lam", ctypes.c_void_p), ("P", ctypes.c_void_p), ("E", ctypes.c_void_p),
                 ("J", ctypes.c_void_p), ("F", ctypes.c_void_p)]
+
+
+class M2NBatchInfo(ctypes.Structure):
+    """m2n_batch_info of include/m2n.h."""
+    _fields_ = [("graph", ctypes.c_int), ("graph_nodes", ctypes.c_int), ("tuned", ctypes.c_int),
+                ("from_cache", ctypes.c_int), ("candidates", ctypes.c_int), ("l1", ctypes.c_int),
+                ("B", ctypes.c_int), ("M", ctypes.c_int), ("nufft_ms_default", ctypes.c_double),
+                ("nufft_ms_tuned", ctypes.c_double), ("series", ctypes.c_int),
+                ("band_counts", ctypes.c_int)]
 
 
 class M2NQueueCfg(ctypes.Structure):
@@ -128,6 +140,14 @@ def _load():
     L.m2nufft_psd.restype = i
     L.m2n_batch_psd.argtypes = [vp, vp, ctypes.POINTER(M2NSeries), i, i, d]
     L.m2n_batch_psd.restype = i
+    L.m2n_batch_create.argtypes = [vp, vp, ctypes.POINTER(M2NSeries), i, i, d, i, ctypes.POINTER(vp)]
+    L.m2n_batch_create.restype = i
+    L.m2n_batch_launch.argtypes = [vp, vp]
+    L.m2n_batch_launch.restype = i
+    L.m2n_batch_get_info.argtypes = [vp, ctypes.POINTER(M2NBatchInfo)]
+    L.m2n_batch_get_info.restype = i
+    L.m2n_batch_destroy.argtypes = [vp]
+    L.m2n_batch_destroy.restype = i
     L.m2n_queue_create.argtypes = [vp, ctypes.POINTER(M2NQueueCfg), ctypes.POINTER(vp)]
     L.m2n_queue_create.restype = i
     L.m2n_submit.argtypes = [vp, ctypes.POINTER(M2NRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -422,6 +442,44 @@ def m2n_batch_psd(ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, want_E=Tru
     if check:
         ctx.check(stream)
     return outs
+
+
+class Batch:
+    """m2n_batch: the batched form prepared once (t checked, workspaces sized,
+    optionally the NuFFT schedule tuned and the launches captured into a HIP
+    graph) and launched many times.  `series` is as for m2n_batch_psd; the
+    tensors must outlive the batch.  `outputs` lists the output tensors."""
+
+    def __init__(self, ctx: Context, series, prec=M2N_FP32, nufft_tol=0.0, graph=True, tune=False,
+                 want_E=True, want_J=False, want_F=False, stream=None):
+        self.ctx = ctx
+        self._series = series
+        self._arr, self.outputs = batch_descriptors(series, prec, want_E, want_J, want_F)
+        flags = (M2N_BATCH_GRAPH if graph else 0) | (M2N_BATCH_TUNE if tune else 0)
+        h = ctypes.c_void_p()
+        _err(lib.m2n_batch_create(ctx.handle, _stream(stream), self._arr, len(self.outputs), int(prec),
+                                  float(nufft_tol), flags, ctypes.byref(h)), "m2n_batch_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _err(lib.m2n_batch_launch(self.handle, _stream(stream)), "m2n_batch_launch")
+        return self.outputs
+
+    def info(self):
+        inf = M2NBatchInfo()
+        _err(lib.m2n_batch_get_info(self.handle, ctypes.byref(inf)), "m2n_batch_get_info")
+        return {f[0]: getattr(inf, f[0]) for f in M2NBatchInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            lib.m2n_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Queue:

@@ -97,6 +97,20 @@ int Ctx::pinned_erec(size_t bytes) {
 }
 
 int Ctx::stage(hipStream_t st, const void* src, size_t bytes, void* dst_dev) {
+    if (stage_fixed) {
+        if (stage_cursor == stage_blocks.size()) {
+            void* b = nullptr;
+            M2N_HIP(hipHostMalloc(&b, bytes, hipHostMallocDefault));
+            stage_blocks.push_back({b, bytes});
+        } else if (stage_blocks[stage_cursor].second < bytes) {
+            set_error("replayed launch sequence staged more bytes than its first pass");
+            return M2N_ERR_HIP;
+        }
+        void* b = stage_blocks[stage_cursor++].first;
+        std::memcpy(b, src, bytes);
+        M2N_HIP(hipMemcpyAsync(dst_dev, b, bytes, hipMemcpyHostToDevice, st));
+        return M2N_OK;
+    }
     if (hstage_used) M2N_HIP(hipEventSynchronize(hstage_ev));
     if (hstage_bytes < bytes) {
         if (hstage) (void)hipHostFree(hstage);
@@ -218,6 +232,7 @@ void m2n_destroy(m2n_ctx* ctx) {
     if (ctx->hstage_ev) (void)hipEventDestroy(ctx->hstage_ev);
     if (ctx->tcheck_ev) (void)hipEventDestroy(ctx->tcheck_ev);
     if (ctx->erec) (void)hipHostFree(ctx->erec);
+    for (auto& b : ctx->stage_blocks) (void)hipHostFree(b.first);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);

@@ -89,6 +89,7 @@ struct NufftPlan {
     int tw_len = 0;
     DevBuf inv_phihat;     // 1 / phihat(|k|), |k| <= kmax
     int64_t kmax = 0;
+    int M_force = 0;       // pass-2 rows per workgroup forced by a schedule (0: by occupancy)
 };
 
 // One series of a NuFFT launch, as the host describes it (all pointers are
@@ -107,6 +108,15 @@ struct NuSeriesIn {
     void* J = nullptr;
     void* F = nullptr;   // Thomson F-statistic [I] or NULL
     double* hrec = nullptr;   // pinned record of the t check (set internally)
+    bool e_diag_known = false;  // R(B) = c I established by the caller: Ehat
+                                // needs no routing (no host wait)
+};
+
+// NuFFT schedule of a plan (the autotuner's choices): log2 of the column
+// FFT length N1 (0: default), pass-1 column block B (0: default), pass-2 rows
+// per workgroup M (0: default)
+struct NuSchedule {
+    int l1 = 0, B = 0, M = 0;
 };
 
 // FP64 complex FFT plan of length M (lattice convolution in the GEP)
@@ -135,6 +145,12 @@ int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
 // many series with one band count I and precision in one set of launches
 int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
                     const NuSeriesIn* series, int nseries);
+// the kernel width a tolerance gives, and every schedule this build has
+// kernels for at (I, prec, width); the first entry is the default one
+int nufft_width(int prec, double tol);
+int nufft_schedules(int64_t I, int prec, double tol, std::vector<NuSchedule>& out);
+// forget the plan of (I, prec, tol) so that the next call builds it anew
+void nufft_drop_plan(Ctx* ctx, int64_t I, int prec, double tol);
 
 // GEP entries (defined in gep.hip)
 int gep_run(Ctx* ctx, hipStream_t st, const double* t_dev, int64_t N,
@@ -159,6 +175,12 @@ struct GepIn {
 // many series: one t check for all, the lattice low-rank ones in one set of
 // launches, the rest one by one
 int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
+// a replayable batch: one t check, every series on the lattice low-rank path
+// (gep.hip); then the tapers' launches alone
+int gep_batch_check_lattice(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<double>& t0,
+                            std::vector<double>& tN);
+int gep_batch_enqueue_lattice(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, const double* t0,
+                              const double* tN);
 // Ehat of one series whose R(B) is not a multiple of the identity: D_k(i) by
 // quadrature of |W_k|^2 over every band's window (ehat.hip); span = t_N - t_1
 int ehat_general(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol, const NuSeriesIn& s, double span);
@@ -169,6 +191,14 @@ struct Ctx {
     size_t budget = 0;         // 0 = unlimited
     size_t held = 0;           // bytes currently allocated
     std::map<std::tuple<int64_t, int, int>, std::unique_ptr<NufftPlan>> plans;
+    // schedules forced for plans built from now on, by (I, prec, width)
+    std::map<std::tuple<int64_t, int, int>, NuSchedule> schedule;
+    // staging for replayable batches: every stage() call takes the next block
+    // of its own (allocated on the first pass, reused in the same order), so
+    // that a captured copy reads a block nothing else overwrites
+    bool stage_fixed = false;
+    std::vector<std::pair<void*, size_t>> stage_blocks;
+    size_t stage_cursor = 0;
     std::map<int64_t, std::unique_ptr<FftPlan64>> fft64;   // by length
     std::map<std::string, DevBuf> ws;   // named grow-only workspaces
     unsigned* dev_err = nullptr;        // sticky device error word

@@ -1090,9 +1090,13 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
     if (p.single) {
         Nt = p.nf;
     } else {
+        NuSchedule sch;
+        auto si = ctx->schedule.find(std::make_tuple(p.I, p.prec, p.w));
+        if (si != ctx->schedule.end()) sch = si->second;
         int L = p.log_nf;
         int l1 = L / 2;
         if (l1 > 10) l1 = 10;
+        if (sch.l1 > 0) l1 = sch.l1;
         p.N1 = 1 << l1;
         p.N2 = p.nf / p.N1;
         if (p.N2 > 4096) {
@@ -1109,6 +1113,7 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
         if (p.B > p.N2 / 2) p.B = p.N2 / 2;
         if (p.B < 8 && sizeof(R) == 4) p.B = 8;
         if (p.B < 4) p.B = 4;
+        if (sch.B > 0) p.B = sch.B;
         p.lookback = (p.w - 1 + p.B - 1) / p.B;
         if (p.lookback >= p.N2 / p.B || p.N2 / p.B > MAX_BINS || p.lookback + 1 > MAXSEG) {
             set_error("unsupported grid split (N2 = %d, B = %d, w = %d)", p.N2, p.B, p.w);
@@ -1121,6 +1126,7 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
         p.KC = rows_max < 8 ? rows_max : 8;
         p.M = rows_max / p.KC;
         if (p.M > 4) p.M = 4;
+        if (sch.M > 0) p.M_force = sch.M;
         Nt = p.N1 > p.N2 ? p.N1 : p.N2;
     }
     p.tw_len = Nt;
@@ -1148,12 +1154,17 @@ int build_plan(Ctx* ctx, NufftPlan& p) {
     return M2N_OK;
 }
 
-int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
+int width_of(int prec, double tol) {
     if (tol <= 0.0) tol = (prec == M2N_FP32) ? 1e-6 : 1e-12;
     int w = (int)std::ceil(-std::log10(tol)) + 1;
     if (w < 4) w = 4;
     if (prec == M2N_FP32 && w > 8) w = 8;
     if (w > 16) w = 16;
+    return w;
+}
+
+int get_plan(Ctx* ctx, int64_t I, int prec, double tol, NufftPlan** out) {
+    const int w = width_of(prec, tol);
     auto key = std::make_tuple(I, prec, w);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
@@ -1241,8 +1252,10 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a,
     }
     if constexpr (sizeof(R) == 4) {
         M2N_P1(64, 32) M2N_P1(128, 32) M2N_P1(256, 16) M2N_P1(512, 8) M2N_P1(1024, 8)
+        M2N_P1(256, 8) M2N_P1(512, 16)
     } else {
         M2N_P1(64, 32) M2N_P1(128, 16) M2N_P1(256, 8) M2N_P1(512, 4) M2N_P1(1024, 4)
+        M2N_P1(256, 4) M2N_P1(512, 8)
     }
 #undef M2N_P1
     set_error("no pass-1 kernel for N1 = %d, B = %d", p.N1, p.B);
@@ -1252,6 +1265,7 @@ int launch_pass1(const NufftPlan& p, hipStream_t st, dim3 grid, const NuArgs& a,
 // rows-per-workgroup choice for pass 2: largest M the LDS budget allows that
 // still gives at least two workgroups per compute unit (counting a batch)
 inline int pass2_rows(const NufftPlan& p, int cu_count, int nseries) {
+    if (p.M_force > 0) return p.M_force;
     int M = p.M;
     while (M > 1 && (int64_t)(p.N1 / M) * nseries < 2 * cu_count) M /= 2;
     return M;
@@ -1461,7 +1475,7 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
     // wait for the host.
     std::vector<int> eidx;
     for (int i = 0; i < nseries; ++i)
-        if (series[i].E) eidx.push_back(i);
+        if (series[i].E && !series[i].e_diag_known) eidx.push_back(i);
     if (eidx.empty()) {
         if (prec == M2N_FP32) return run_typed<float>(ctx, st, *p, series, nseries, nullptr);
         return run_typed<double>(ctx, st, *p, series, nseries, nullptr);
@@ -1518,6 +1532,73 @@ int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_
     s.J = J;
     s.F = F;
     return nufft_run_batch(ctx, st, I, prec, tol, &s, 1);
+}
+
+int nufft_width(int prec, double tol) { return width_of(prec, tol); }
+
+// Every (N1, B, M) this build has pass-1 and pass-2 kernels for at a band
+// count, the default schedule first (the autotuner's candidates).  Mirrors
+// the feasibility rules of build_plan.
+int nufft_schedules(int64_t I, int prec, double tol, std::vector<NuSchedule>& out) {
+    out.clear();
+    const int w = width_of(prec, tol);
+    int64_t nf = 64;
+    while (nf < 2 * I) nf *= 2;
+    while (nf < 4 * w) nf *= 2;
+    const int cs = prec == M2N_FP32 ? 8 : 16;
+    if (nf <= (prec == M2N_FP32 ? 8192 : 4096)) {
+        out.push_back(NuSchedule());   // single workgroup: nothing to choose
+        return M2N_OK;
+    }
+    const int L = ilog2i(nf);
+    const int p1f[][2] = {{64, 32}, {128, 32}, {256, 16}, {512, 8}, {1024, 8}, {256, 8}, {512, 16}};
+    const int p1d[][2] = {{64, 32}, {128, 16}, {256, 8}, {512, 4}, {1024, 4}, {256, 4}, {512, 8}};
+    // pass-2 kernels: (N2, M, KC)
+    const int p2f[][3] = {{128, 1, 8}, {128, 2, 8}, {128, 4, 8}, {256, 1, 8}, {256, 2, 8}, {256, 4, 8},
+                          {512, 1, 8}, {512, 2, 8}, {512, 4, 8}, {1024, 1, 8}, {1024, 2, 8},
+                          {2048, 1, 8}, {4096, 1, 2}};
+    const int p2d[][3] = {{128, 1, 8}, {128, 2, 8}, {128, 4, 8}, {256, 1, 8}, {256, 2, 8}, {256, 4, 8},
+                          {512, 1, 8}, {512, 2, 8}, {1024, 1, 8}, {2048, 1, 2}, {4096, 1, 1}};
+    int l1d = L / 2;
+    if (l1d > 10) l1d = 10;
+    std::vector<NuSchedule> cand;
+    for (int l1 : {l1d, l1d - 1, l1d + 1}) {
+        if (l1 < 6 || l1 > 10) continue;
+        const int N1 = 1 << l1, N2 = (int)(nf >> l1);
+        if (N2 < 128 || N2 > 4096) continue;
+        int rows_max = 1;
+        while (2 * rows_max * (N2 + 1) * cs + N2 * cs <= 160000) rows_max *= 2;
+        const int KC = rows_max < 8 ? rows_max : 8;
+        for (int bi = 0; bi < 7; ++bi) {
+            const int n1b = prec == M2N_FP32 ? p1f[bi][0] : p1d[bi][0];
+            const int B = prec == M2N_FP32 ? p1f[bi][1] : p1d[bi][1];
+            if (n1b != N1) continue;
+            const int lookback = (w - 1 + B - 1) / B;
+            if (lookback >= N2 / B || N2 / B > MAX_BINS || lookback + 1 > MAXSEG) continue;
+            const int n2k = prec == M2N_FP32 ? 13 : 11;
+            for (int mi = 0; mi < n2k; ++mi) {
+                const int* e = prec == M2N_FP32 ? p2f[mi] : p2d[mi];
+                if (e[0] != N2 || e[2] != KC) continue;
+                NuSchedule sc;
+                sc.l1 = l1;
+                sc.B = B;
+                sc.M = e[1];
+                cand.push_back(sc);
+            }
+        }
+    }
+    out.push_back(NuSchedule());   // the default: build_plan's own choices
+    out.insert(out.end(), cand.begin(), cand.end());
+    return M2N_OK;
+}
+
+void nufft_drop_plan(Ctx* ctx, int64_t I, int prec, double tol) {
+    auto it = ctx->plans.find(std::make_tuple(I, prec, width_of(prec, tol)));
+    if (it == ctx->plans.end()) return;
+    (void)hipDeviceSynchronize();
+    ctx->release(it->second->tw_fft);
+    ctx->release(it->second->inv_phihat);
+    ctx->plans.erase(it);
 }
 
 }  // namespace m2n

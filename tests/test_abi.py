@@ -87,7 +87,8 @@ def _struct_fields(tag):
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libm2n.so not built")
-@pytest.mark.parametrize("tag,cls", [("m2n_series", "M2NSeries"), ("m2n_subband", "M2NSubBand")])
+@pytest.mark.parametrize("tag,cls", [("m2n_series", "M2NSeries"), ("m2n_subband", "M2NSubBand"),
+                                     ("m2n_batch_info", "M2NBatchInfo")])
 def test_structs_match_header(tag, cls):
     # the ctypes mirrors of the header's structs have its fields, in order
     import paper_2407_01943_amd as m2n
