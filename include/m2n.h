@@ -445,6 +445,12 @@ typedef struct {
     int slots;               /* batches in flight (0 = 2, at most 4)       */
     int prec;                /* M2N_FP32 (also when 0) or M2N_FP64         */
     double nufft_tol;        /* as in m2nufft_psd                          */
+    int outputs_pinned;      /* 1: every request's host outputs are pinned
+                                memory (hipHostMalloc, or a torch tensor made
+                                with pin_memory=True); results are copied
+                                from the device straight into them, with no
+                                staging block and no host memcpy.  0: any
+                                host memory, through a pinned staging block */
 } m2n_queue_cfg;
 
 typedef struct {

@@ -74,7 +74,8 @@ class M2NBatchInfo(ctypes.Structure):
 
 class M2NQueueCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
-                ("slots", ctypes.c_int), ("prec", ctypes.c_int), ("nufft_tol", ctypes.c_double)]
+                ("slots", ctypes.c_int), ("prec", ctypes.c_int), ("nufft_tol", ctypes.c_double),
+                ("outputs_pinned", ctypes.c_int)]
 
 
 class M2NRequest(ctypes.Structure):
@@ -488,28 +489,44 @@ class Queue:
     this object until the request is collected."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes=0, max_batch=0, slots=0,
-                 prec=M2N_FP32, nufft_tol=0.0):
+                 prec=M2N_FP32, nufft_tol=0.0, pinned_outputs=False):
         import numpy as np
         self._np = np
         self.ctx = ctx
         self.prec = prec
-        cfg = M2NQueueCfg(hbm_budget_bytes, max_batch, slots, prec, nufft_tol)
+        self.pinned = bool(pinned_outputs)
+        cfg = M2NQueueCfg(hbm_budget_bytes, max_batch, slots, prec, nufft_tol, 1 if self.pinned else 0)
         h = ctypes.c_void_p()
         _err(lib.m2n_queue_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)),
              "m2n_queue_create")
         self.handle = h
         self._out = {}
 
-    def submit(self, t, x, fmax, fw, K, f_lo, df, I, want_E=True):
+    def submit(self, t, x, fmax, fw, K, f_lo, df, I, want_E=True, want_w=True, out=None):
+        """`out` (optional): the caller's output arrays {"P", "E", "lam", "w"}
+        (pinned memory when the queue was made with pinned_outputs), e.g. views
+        of a pool the caller reuses; "E" and "w" may be None."""
         np = self._np
         t = np.ascontiguousarray(t, dtype=np.float64)
         x = np.ascontiguousarray(x, dtype=np.float64)
         N = t.shape[0]
-        rdt = np.float32 if self.prec == M2N_FP32 else np.float64
-        out = {"w": np.empty((K, N)), "lam": np.empty(K), "P": np.empty(I, dtype=rdt),
-               "E": np.empty(I, dtype=rdt) if want_E else None}
+        if out is not None:
+            out = dict(out)
+        elif self.pinned:
+            # pinned host tensors (torch's pinned allocator), handed out as numpy views
+            rdt = torch.float32 if self.prec == M2N_FP32 else torch.float64
+
+            def buf(shape, dt):
+                return torch.empty(shape, dtype=dt, pin_memory=True).numpy()
+            out = {"w": buf((K, N), torch.float64) if want_w else None, "lam": buf((K,), torch.float64),
+                   "P": buf((I,), rdt), "E": buf((I,), rdt) if want_E else None}
+        else:
+            rdt = np.float32 if self.prec == M2N_FP32 else np.float64
+            out = {"w": np.empty((K, N)) if want_w else None, "lam": np.empty(K),
+                   "P": np.empty(I, dtype=rdt), "E": np.empty(I, dtype=rdt) if want_E else None}
         req = M2NRequest(t.ctypes.data, x.ctypes.data, N, int(K), float(fmax), float(fw),
-                         float(f_lo), float(df), int(I), out["w"].ctypes.data,
+                         float(f_lo), float(df), int(I),
+                         None if out["w"] is None else out["w"].ctypes.data,
                          out["lam"].ctypes.data, out["P"].ctypes.data,
                          None if out["E"] is None else out["E"].ctypes.data)
         tk = ctypes.c_uint64()

@@ -125,7 +125,7 @@ int run_batch(m2n_queue* q, Slot& s, std::vector<Req*>& batch) {
         s.dev_bytes = want;
     }
     M2N_TRY(grow_pinned(&s.pin_in, &s.pin_in_bytes, in_bytes));
-    M2N_TRY(grow_pinned(&s.pin_out, &s.pin_out_bytes, out_bytes));
+    if (!q->cfg.outputs_pinned) M2N_TRY(grow_pinned(&s.pin_out, &s.pin_out_bytes, out_bytes));
     char* din = (char*)s.dev;
     char* dout = din + in_bytes;
     char* hin = (char*)s.pin_in;
@@ -161,6 +161,23 @@ int run_batch(m2n_queue* q, Slot& s, std::vector<Req*>& batch) {
     int st = m2n_batch_psd(s.ctx, s.st, ser.data(), (int)ser.size(), prec, q->cfg.nufft_tol);
     if (st == M2N_OK) st = m2n_check(s.ctx, s.st);
     if (st != M2N_OK) return st;
+    if (q->cfg.outputs_pinned) {
+        // straight into the callers' pinned buffers: one copy per output
+        for (size_t j = 0; j < batch.size(); ++j) {
+            Req* r = batch[j];
+            const m2n_series& d = ser[j];
+            if (r->w_out)
+                M2N_HIP(hipMemcpyAsync(r->w_out, d.w, sizeof(double) * r->K * r->N, hipMemcpyDeviceToHost, s.st));
+            if (r->lam_out)
+                M2N_HIP(hipMemcpyAsync(r->lam_out, d.lambda, sizeof(double) * r->K, hipMemcpyDeviceToHost, s.st));
+            if (r->P_out) M2N_HIP(hipMemcpyAsync(r->P_out, d.P, rs * r->I, hipMemcpyDeviceToHost, s.st));
+            if (r->want_E && r->E_out)
+                M2N_HIP(hipMemcpyAsync(r->E_out, d.E, rs * r->I, hipMemcpyDeviceToHost, s.st));
+        }
+        M2N_HIP(hipStreamSynchronize(s.st));
+        for (Req* r : batch) r->res.status = M2N_OK;
+        return M2N_OK;
+    }
     M2N_HIP(hipMemcpyAsync(s.pin_out, dout, out_bytes, hipMemcpyDeviceToHost, s.st));
     M2N_HIP(hipStreamSynchronize(s.st));
     const char* hout = (const char*)s.pin_out;

@@ -85,6 +85,28 @@ def test_queue_same_alone_and_in_mix(m2n, ctx):
     q.close()
 
 
+def test_queue_pinned_outputs(m2n, ctx):
+    # results copied from the device straight into pinned host buffers: the
+    # same as alone; requests without tapers leave w out
+    series = [W.batched_series(s) for s in range(60, 76)]
+    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP32, pinned_outputs=True)
+    tk = [q.submit(s.t, s.x, s.fmax, s.fw, s.K, s.f_lo, s.df, s.I, want_w=(i % 2 == 0))
+          for i, s in enumerate(series)]
+    res = [_wait(q, t) for t in tk]
+    worst = 0.0
+    for i, (s, r) in enumerate(zip(series, res)):
+        if i % 2 == 0:
+            worst = max(worst, _check(m2n, ctx, s, r, m2n.M2N_FP32))
+        else:
+            assert r["w"] is None
+            w, lam, P, E = _alone(m2n, ctx, s, m2n.M2N_FP32)
+            assert np.array_equal(r["lam"], lam)
+            assert float(np.max(np.abs(r["P"].astype(np.float64) - P)) / np.max(np.abs(P))) < 2e-6
+    _say(f"case pinned outputs: 16 requests, batch sizes {sorted(r['batch_size'] for r in res)}, "
+         f"worst P {worst:.2e}")
+    q.close()
+
+
 def test_queue_failing_request_is_isolated(m2n, ctx):
     good = [W.batched_series(s) for s in (30, 31, 32)]
     bad = W.batched_series(33)
