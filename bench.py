@@ -721,9 +721,10 @@ def idpss_form(m2n, torch, workloads, ctx, s_main, reps=5):
 
 
 def psd_at_form(m2n, torch, ctx, s, w, n_centres=4096, reps=10):
-    """P at an arbitrary list of band centres (direct FP64 summation) on the
-    main workload's tapers: time per call and the rate in sample-centre pairs
-    per second (each pair one reduced sincos and 2K FMAs)."""
+    """P at an arbitrary list of band centres on the main workload's tapers:
+    the direct FP64 summation (time per call and the rate in sample-centre
+    pairs per second, each pair one reduced sincos and 2K FMAs) and the
+    type-3 NuFFT at the same and at 2^18 centres."""
     import numpy as np
     dev = torch.device("cuda:0")
     t = torch.from_numpy(s.t).to(dev)
@@ -741,8 +742,27 @@ def psd_at_form(m2n, torch, ctx, s, w, n_centres=4096, reps=10):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     pairs = float(s.N) * n_centres
-    return {"workload": s.name, "N": s.N, "K": int(w.shape[0]), "centres": n_centres, "ms": round(ms, 4),
-            "pairs_per_s": round(pairs / (ms * 1e-3), 1)}
+    out = {"workload": s.name, "N": s.N, "K": int(w.shape[0]), "centres": n_centres, "ms": round(ms, 4),
+           "pairs_per_s": round(pairs / (ms * 1e-3), 1)}
+    # the type-3 NuFFT (m2nufft_psd_freqs) at the same and at many more
+    # centres; wall time per call (it reads the span back: one round trip)
+    t3 = []
+    for nc in (n_centres, 2 ** 18):
+        fr = torch.from_numpy(np.random.default_rng(8).uniform(-0.5, 0.5, nc)).to(dev)
+        for prec in (m2n.M2N_FP32, m2n.M2N_FP64):
+            m2n.m2nufft_psd_freqs(ctx, t, x, w, fr, prec=prec, check=False)
+            torch.cuda.synchronize()
+            tt = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                m2n.m2nufft_psd_freqs(ctx, t, x, w, fr, prec=prec, check=False)
+                torch.cuda.synchronize()
+                tt.append(time.perf_counter() - t0)
+            msn = 1e3 * float(np.median(tt))
+            t3.append({"centres": nc, "prec": "fp32" if prec == m2n.M2N_FP32 else "fp64",
+                       "ms": round(msn, 4), "centres_per_s": round(nc / (msn * 1e-3), 1)})
+    out["type3"] = t3
+    return out
 
 
 def algorithmic_bytes(name, s, N, K, I, plan, prec_bytes):

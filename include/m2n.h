@@ -113,7 +113,8 @@ int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
  * modest number of centres (for many equally spaced ones use m2nufft_psd).
  *
  *   t, x    [N]     device, FP64
- *   w       [K*N]   device, FP64 real tapers, 1 <= K <= 16
+ *   w       [K*N]   device, FP64 real tapers, 1 <= K <= 64 (summed in groups
+ *                   of 16 tapers)
  *   freqs   [I]     device, FP64 band centres, any order, repeats allowed
  *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
  *   P       [I]     device out, FP64
@@ -126,6 +127,36 @@ int m2nufft_psd_at(m2n_ctx *ctx, void *stream, const double *t, const double *x,
                    int64_t I, const double *weights, double *P, void *J);
 
 /*
+ * m2nufft_psd_freqs -- the same quantities at an arbitrary list of band
+ * centres by a type-3 NuFFT, for many centres: with t_c an integer centre of
+ * the span and X the half-span, the samples are divided by the Fourier
+ * transform of an exponential-of-semicircle kernel psi of w cells of a
+ * frequency grid of spacing d = 1/(4 X), the library's type-1 NuFFT puts
+ * them on the grid covering [min f_i, max f_i] (about 4 X (max f_i - min f_i)
+ * bands), and each centre interpolates w grid values with psi (FP64) and
+ * takes the phase e^{-j 2 pi f_i t_c}.  The kernel width is
+ * ceil(-log10 tol) + 2 and the inner NuFFT runs a decade tighter, so J and P
+ * hold tol relative to their largest values.
+ *
+ *   t, x    [N]     device, FP64 (any order)
+ *   w       [K*N]   device, FP64 real tapers, 1 <= K <= 64
+ *   freqs   [I]     device, FP64 band centres, any order, repeats allowed
+ *   prec            M2N_FP32 (P float, J float2; inner NuFFT FP32) or
+ *                   M2N_FP64 (double, double2)
+ *   nufft_tol       requested accuracy (<= 0: 1e-6 FP32, 1e-12 FP64)
+ *   weights [K]     device, FP64 d_k, or NULL for d_k = 1/K
+ *   P       [I]     device out; J [K*I] device out or NULL
+ *
+ * One host round trip (the span of t and of the centres sizes the grid).
+ * Errors: M2N_ERR_ARG, M2N_ERR_UNSUPPORTED (grid above 2^21 bands:
+ * 4 X (max f_i - min f_i) too large).
+ */
+int m2nufft_psd_freqs(m2n_ctx *ctx, void *stream, const double *t, const double *x,
+                      int64_t N, const double *w, int K, const double *freqs,
+                      int64_t I, int prec, double nufft_tol, const double *weights,
+                      void *P, void *J);
+
+/*
  * m2nufft_psd_at_noalloc -- m2nufft_psd_at for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, layouts and results (the sample
@@ -136,8 +167,8 @@ int m2nufft_psd_at(m2n_ctx *ctx, void *stream, const double *t, const double *x,
  * process ends; the call allocates nothing, grows no workspace and records no
  * timing events.
  *
- * Limits and sharing: K * I * 16 bytes must not exceed the array (K = 16
- * allows I <= 65536), else M2N_ERR_ARG.  Every call on one GPU uses the same
+ * Limits and sharing: min(K, 16) * I * 16 bytes must not exceed the array
+ * (I <= 65536 for any K), else M2N_ERR_ARG.  Every call on one GPU uses the same
  * array: calls that overlap on one GPU (different streams, threads or
  * contexts without ordering between them) race and give wrong results.
  * Stream-ordered and asynchronous.  Errors: M2N_ERR_ARG.

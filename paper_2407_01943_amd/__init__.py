@@ -42,7 +42,7 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
             "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at",
             "m2nufft_psd_at_noalloc", "m2n_batch_create", "m2n_batch_launch",
-            "m2n_batch_get_info", "m2n_batch_destroy"]
+            "m2n_batch_get_info", "m2n_batch_destroy", "m2nufft_psd_freqs"]
 M2N_BATCH_GRAPH = 1
 M2N_BATCH_TUNE = 2
 
@@ -125,6 +125,8 @@ def _load():
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
     L.m2nufft_psd_at.restype = i
     L.m2nufft_psd_at.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
+    L.m2nufft_psd_freqs.restype = i
+    L.m2nufft_psd_freqs.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, i, d, vp, vp, vp]
     L.m2nufft_psd_at_noalloc.restype = i
     L.m2nufft_psd_at_noalloc.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
     L.gpss_tapers_multiband.restype = i
@@ -256,6 +258,27 @@ def m2nufft_psd_at(ctx: Context, t, x, w, freqs, weights=None, want_J=False, str
         weights = _dev(weights)
     _err(lib.m2nufft_psd_at(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w), K, _ptr(freqs), I,
                             _ptr(weights), _ptr(P), _ptr(J)), "m2nufft_psd_at")
+    if check:
+        ctx.check(stream)
+    return {"P": P, "J": J}
+
+
+def m2nufft_psd_freqs(ctx: Context, t, x, w, freqs, prec=M2N_FP64, nufft_tol=0.0, weights=None, want_J=False,
+                      stream=None, check=True):
+    """P (and J) at an arbitrary list of band centres by the type-3 NuFFT.
+    Returns {"P": [I], "J": [K, I] or None}."""
+    t, x, w, freqs = _dev(t), _dev(x), _dev(w), _dev(freqs)
+    K, N = w.shape
+    I = freqs.shape[0]
+    rdt = torch.float32 if prec == M2N_FP32 else torch.float64
+    cdt = torch.complex64 if prec == M2N_FP32 else torch.complex128
+    P = torch.empty((I,), dtype=rdt, device=t.device)
+    J = torch.empty((K, I), dtype=cdt, device=t.device) if want_J else None
+    if weights is not None:
+        weights = _dev(weights)
+    _err(lib.m2nufft_psd_freqs(ctx.handle, _stream(stream), _ptr(t), _ptr(x), N, _ptr(w), K, _ptr(freqs), I,
+                               int(prec), float(nufft_tol), _ptr(weights), _ptr(P), _ptr(J)),
+         "m2nufft_psd_freqs")
     if check:
         ctx.check(stream)
     return {"P": P, "J": J}

@@ -20,6 +20,9 @@ int nudft_list_run_noalloc(Ctx* ctx, hipStream_t st, const double* t, const doub
                            int K, const double* freqs, int64_t I, const double* weights, double* P, void* J);
 // device address of that array, looked up once per device (device current)
 int noalloc_scratch_init(int device);
+// eigencoefficients at a list of band centres by a type-3 NuFFT (nufft3.hip)
+int nufft3_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
+               const double* freqs, int64_t I, int prec, double tol, const double* weights, void* P, void* J);
 // interpolated-DPSS tapers (idpss.hip)
 int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
               double* w, double* lambda);
@@ -344,6 +347,17 @@ int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x,
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
+}
+
+int m2nufft_psd_freqs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N, const double* w,
+                      int K, const double* freqs, int64_t I, int prec, double nufft_tol, const double* weights,
+                      void* P, void* J) {
+    if (!ctx) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return nufft3_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, prec, nufft_tol, weights, P, J);
 }
 
 int m2nufft_psd_at_noalloc(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,

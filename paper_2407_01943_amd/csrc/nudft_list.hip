@@ -78,14 +78,17 @@ __global__ __launch_bounds__(LT) void k_nudft_list(const double* __restrict__ t,
     }
 }
 
-// J_k(i) = sum over the chunks in order; P_i = sum_k d_k |J_k(i)|^2
+// J_k(i) = sum over the chunks in order; P_i = sum_k d_k |J_k(i)|^2 over the
+// K tapers of this group (tapers k0 .. k0 + K - 1 of Ktot), added to P when
+// accum (the groups after the first)
 __global__ __launch_bounds__(LT) void k_nudft_reduce(const cplx<double>* __restrict__ part, int nchunk, int K,
                                                      int64_t I, const double* __restrict__ weights,
-                                                     double* __restrict__ P, cplx<double>* __restrict__ J) {
+                                                     double* __restrict__ P, cplx<double>* __restrict__ J,
+                                                     int k0, int Ktot, int accum) {
     const int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x;
     if (i >= I) return;
-    const double d0 = 1.0 / K;
-    double p = 0.0;
+    const double d0 = 1.0 / Ktot;
+    double p = accum ? P[i] : 0.0;
     for (int k = 0; k < K; ++k) {
         double re = 0.0, im = 0.0;
         for (int c = 0; c < nchunk; ++c) {
@@ -93,13 +96,13 @@ __global__ __launch_bounds__(LT) void k_nudft_reduce(const cplx<double>* __restr
             re += v.x;
             im += v.y;
         }
-        const double d = weights ? weights[k] : d0;
+        const double d = weights ? weights[k0 + k] : d0;
         p += d * (re * re + im * im);
         if (J) {
             cplx<double> v;
             v.x = re;
             v.y = im;
-            J[(int64_t)k * I + i] = v;
+            J[(int64_t)(k0 + k) * I + i] = v;
         }
     }
     P[i] = p;
@@ -125,21 +128,26 @@ void chunking(int64_t N, int64_t I, int64_t max_chunks, int64_t* nchunk_out, int
 
 int check_args(const double* t, const double* x, const double* w, const double* freqs, const double* P, int64_t N,
                int K, int64_t I) {
-    if (!t || !x || !w || !freqs || !P || N < 1 || K < 1 || K > LK || I < 1) {
-        set_error("bad argument (N = %lld, K = %d (<= %d), I = %lld)", (long long)N, K, LK, (long long)I);
+    if (!t || !x || !w || !freqs || !P || N < 1 || K < 1 || K > 64 || I < 1) {
+        set_error("bad argument (N = %lld, K = %d (<= 64), I = %lld)", (long long)N, K, (long long)I);
         return M2N_ERR_ARG;
     }
     return M2N_OK;
 }
 
+// the tapers in groups of LK, one sum and one reduction per group (the
+// partial sums of a group are reduced before the next group writes them)
 void launch_list(hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
                  const double* freqs, int64_t I, const double* weights, double* P, void* J, int64_t nchunk,
                  int64_t nc, cplx<double>* part) {
     const int64_t bx = (I + LT - 1) / LT;
-    hipLaunchKernelGGL(k_nudft_list, dim3((unsigned)bx, (unsigned)nchunk), dim3(LT), 0, st, t, x, w, N, K, freqs, I,
-                       nc, part);
-    hipLaunchKernelGGL(k_nudft_reduce, dim3((unsigned)bx), dim3(LT), 0, st, (const cplx<double>*)part, (int)nchunk, K,
-                       I, weights, P, (cplx<double>*)J);
+    for (int k0 = 0; k0 < K; k0 += LK) {
+        const int kg = K - k0 < LK ? K - k0 : LK;
+        hipLaunchKernelGGL(k_nudft_list, dim3((unsigned)bx, (unsigned)nchunk), dim3(LT), 0, st, t, x,
+                           w + (int64_t)k0 * N, N, kg, freqs, I, nc, part);
+        hipLaunchKernelGGL(k_nudft_reduce, dim3((unsigned)bx), dim3(LT), 0, st, (const cplx<double>*)part,
+                           (int)nchunk, kg, I, weights, P, (cplx<double>*)J, k0, K, k0 > 0 ? 1 : 0);
+    }
 }
 
 // ------------------------------------------------ allocation-free variant
@@ -182,7 +190,8 @@ int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, i
     int64_t nchunk, nc;
     chunking(N, I, INT64_MAX, &nchunk, &nc);
     void* vp;
-    M2N_TRY(ctx->workspace("nl_part", sizeof(cplx<double>) * (size_t)nchunk * K * I, &vp));
+    const int kg = K < LK ? K : LK;
+    M2N_TRY(ctx->workspace("nl_part", sizeof(cplx<double>) * (size_t)nchunk * kg * I, &vp));
     {
         M2N_PROF(ctx, st, "k_nudft_list");
         launch_list(st, t, x, N, w, K, freqs, I, weights, P, J, nchunk, nc, (cplx<double>*)vp);
@@ -193,15 +202,16 @@ int nudft_list_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, i
 
 // The same sums with the partial results in the per-device scratch array: no
 // allocation, no workspace growth, no timing events.  Fewer sample chunks
-// when K I nchunk complex values would not fit (the reduction order is still
-// the chunk order).
+// when min(K, 16) I nchunk complex values would not fit (the reduction order
+// is still the chunk order).
 int nudft_list_run_noalloc(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w,
                            int K, const double* freqs, int64_t I, const double* weights, double* P, void* J) {
     M2N_TRY(check_args(t, x, w, freqs, P, N, K, I));
-    const size_t per_chunk = sizeof(cplx<double>) * (size_t)K * (size_t)I;
+    const int kg = K < LK ? K : LK;   // tapers per group of the sums
+    const size_t per_chunk = sizeof(cplx<double>) * (size_t)kg * (size_t)I;
     if (per_chunk > NOALLOC_SCRATCH_BYTES) {
-        set_error("K I = %lld complex partial sums exceed the %zu-byte scratch of the allocation-free call",
-                  (long long)K * (long long)I, NOALLOC_SCRATCH_BYTES);
+        set_error("min(K, 16) I = %lld complex partial sums exceed the %zu-byte scratch of the allocation-free call",
+                  (long long)kg * (long long)I, NOALLOC_SCRATCH_BYTES);
         return M2N_ERR_ARG;
     }
     void* ptr = ctx->device >= 0 && ctx->device < MAX_DEVICES ? g_scratch_ptr[ctx->device] : nullptr;
