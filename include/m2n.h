@@ -106,6 +106,30 @@ int gpss_tapers(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
                 double *w, double *lambda);
 
 /*
+ * gpss_tapers_rr -- gpss_tapers when R(B) may be numerically singular (the
+ * GEP of Sec. 3.2 assumes it positive definite): a rank-revealing reduction.
+ * A diagonally pivoted Cholesky of R(B) takes, one at a time, the sample
+ * with the largest remaining Schur diagonal (ties within 1e-12 relative to
+ * the smallest index) until every remaining one is below rank_tol * 2 f_max;
+ * the tapers are those of gpss_tapers on the kept samples t_S (increasing
+ * order; sign reading on t_S) and are zero on the others, so that
+ * w_k^T R(B) w_k = 2 f_w with the full R(B).  When R(B) is a multiple of the
+ * identity (integer t, integer 2 f_max) every sample is kept.
+ *
+ *   t, N, fmax, fw, K, w, lambda   as in gpss_tapers (fc0 = 0)
+ *   rank_tol        relative pivot floor in (0, 1); <= 0: 1e-8.  The GEP of
+ *                   t_S then has cond(R(B)_SS) of order 1 / rank_tol, which
+ *                   bounds its forward error
+ *   rank    [1]     HOST out: the number of samples kept
+ *
+ * Blocks (the pivot steps read a stop flag every 16 steps).  N <= 32768.
+ * Errors: as gpss_tapers; M2N_ERR_NOT_PD when fewer than K samples are kept.
+ */
+int gpss_tapers_rr(m2n_ctx *ctx, void *stream, const double *t, int64_t N,
+                   double fmax, double fw, int K, double rank_tol,
+                   double *w, double *lambda, int64_t *rank);
+
+/*
  * m2nufft_psd_at -- Table 3 steps 4 and 5 at an arbitrary list of band
  * centres (Sec. 3.2; the centres need not be equally spaced), by direct FP64
  * summation: J_k(i) = sum_n w_k(t_n) x(t_n) e^{-j 2 pi f_i t_n} and

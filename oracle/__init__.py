@@ -91,6 +91,9 @@ def lib():
         L.or_solve_LT.argtypes = [_d, ctypes.c_long, _d, ctypes.c_long]
         L.or_natural_spline.restype = None
         L.or_natural_spline.argtypes = [_d, ctypes.c_long, _d, ctypes.c_long, _d, ctypes.c_long, _d]
+        L.or_rr_select.restype = ctypes.c_long
+        L.or_rr_select.argtypes = [_d, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_int), _d]
         L.or_fft.restype = None
         L.or_fft.argtypes = [_d, _d, ctypes.c_long, ctypes.c_int]
         L.or_apply_sinc_toeplitz.restype = ctypes.c_int
@@ -252,6 +255,36 @@ def gpss_tapers(t, fmax, fw, K, method="auto"):
     if st < 0:
         raise OracleError(st, "gpss_tapers")
     return w, lam
+
+
+def rr_select(t, fmax, tau):
+    """The samples a rank-revealing (diagonally pivoted) Cholesky of R(B)
+    takes before every remaining Schur diagonal is below tau * 2 f_max
+    (or_rr_select).  Returns (sorted indices, largest remaining diagonal)."""
+    t = _f64(t)
+    N = t.shape[0]
+    sel = np.zeros(N, dtype=np.int32)
+    mr = np.zeros(1)
+    lib().or_rr_select(_p(t), N, float(fmax), float(tau), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       _p(mr))
+    return np.nonzero(sel)[0], float(mr[0])
+
+
+def gpss_tapers_rr(t, fmax, fw, K, tau, method="auto"):
+    """GPSS tapers when R(B) may be numerically singular (the paper assumes it
+    positive definite): the rank-revealing reduction keeps the samples S that
+    a diagonally pivoted Cholesky of R(B) takes down to tau * 2 f_max, and
+    solves the GEP of the sub-series t_S (R(B)_SS is positive definite with
+    its pivots >= tau * 2 f_max; sign reading on t_S); the tapers are zero on
+    the other samples.  Returns (w [K, N], lam [K], S)."""
+    t = _f64(t)
+    S, _ = rr_select(t, fmax, tau)
+    if S.shape[0] < K:
+        raise OracleError(ERR_ARG, "gpss_tapers_rr (rank below K)")
+    wS, lam = gpss_tapers(t[S], fmax, fw, K, method=method)
+    w = np.zeros((K, t.shape[0]))
+    w[:, S] = wS      # the sign reading is that of the sub-series t_S
+    return w, lam, S
 
 
 def fix_sign(t, w):

@@ -37,6 +37,10 @@
  *   or_gpss_tapers      the K largest solutions of R(A0) w = lambda R(B) w,
  *                       scaled to w^T R(B) w = 2 f_w    (Sec. 3.2 GEP at A0,
  *                       Sec. 2.2 normalisation requirement, Table 3 step 3)
+ *   or_rr_select        rank-revealing reduction of a numerically singular
+ *                       R(B): diagonally pivoted Cholesky, stopped when every
+ *                       remaining Schur diagonal is below tau * 2 f_max; the
+ *                       pivots are the samples the tapers are supported on
  *   or_nudft            J_k(A_i) = sum_n w_k(t_n) x(t_n) e^{-j 2 pi df_i t_n},
  *                       df_i = f_lo + i*df              (Sec. 3.2 eigencoeff.,
  *                       Table 3 step 4), by direct summation
@@ -741,6 +745,56 @@ long or_gpss_tapers(const double *t, long N, double fmax, double fw, int K,
     }
     free(col); free(y); free(RB);
     return ret;
+}
+
+/* ------------------------------------------------------------------ */
+/* Rank-revealing reduction (no positive-definiteness assumed):         */
+/* R(B) = P L L^T P^T + S with diagonal pivoting; at each step the       */
+/* sample with the largest remaining Schur diagonal d_i is taken (ties,   */
+/* i.e. d_i >= (1 - 1e-12) max d, go to the smallest index), and the      */
+/* process stops when max d < tau * 2 f_max.  sel[n] = 1 for the taken     */
+/* samples; returns their number r; *maxrem = the largest remaining d.   */
+/* The columns of L are formed from their definition,                     */
+/*   l_{i,j} = (R_{i,p} - sum_{k<j} l_{i,k} l_{p,k}) / sqrt(d_p).          */
+/* ------------------------------------------------------------------ */
+long or_rr_select(const double *t, long N, double fmax, double tau, int *sel, double *maxrem)
+{
+    double *d = (double *)malloc(sizeof(double) * (size_t)N);
+    double *L = (double *)calloc((size_t)N * (size_t)N, sizeof(double));   /* column j at L + j N */
+    long *piv = (long *)malloc(sizeof(long) * (size_t)N);
+    const double dmax0 = 2.0 * fmax;
+    for (long i = 0; i < N; ++i) { d[i] = dmax0; sel[i] = 0; }
+    long r = 0;
+    for (long j = 0; j < N; ++j) {
+        double mx = -1.0;
+        for (long i = 0; i < N; ++i)
+            if (!sel[i] && d[i] > mx) mx = d[i];
+        if (!(mx >= tau * dmax0)) break;
+        long p = -1;
+        for (long i = 0; i < N && p < 0; ++i)
+            if (!sel[i] && d[i] >= (1.0 - 1e-12) * mx) p = i;
+        sel[p] = 1;
+        piv[j] = p;
+        const double sp = sqrt(d[p]);
+        double *lj = L + (size_t)j * (size_t)N;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < N; ++i) {
+            if (sel[i] && i != p) { lj[i] = 0.0; continue; }
+            double v = sinc_kernel(fmax, t[i] - t[p]);
+            for (long k = 0; k < j; ++k) v -= L[(size_t)k * N + i] * L[(size_t)k * N + p];
+            lj[i] = v / sp;
+        }
+        for (long i = 0; i < N; ++i)
+            if (!sel[i]) d[i] -= lj[i] * lj[i];
+        d[p] = 0.0;
+        r = j + 1;
+    }
+    double mr = 0.0;
+    for (long i = 0; i < N; ++i)
+        if (!sel[i] && d[i] > mr) mr = d[i];
+    *maxrem = mr;
+    free(d); free(L); free(piv);
+    return r;
 }
 
 /* ------------------------------------------------------------------ */

@@ -42,7 +42,7 @@ EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes"
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
             "idpss_tapers", "gpss_tapers_multiband", "m2nufft_psd_at",
             "m2nufft_psd_at_noalloc", "m2n_batch_create", "m2n_batch_launch",
-            "m2n_batch_get_info", "m2n_batch_destroy", "m2nufft_psd_freqs"]
+            "m2n_batch_get_info", "m2n_batch_destroy", "m2nufft_psd_freqs", "gpss_tapers_rr"]
 M2N_BATCH_GRAPH = 1
 M2N_BATCH_TUNE = 2
 
@@ -125,6 +125,8 @@ def _load():
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
     L.m2nufft_psd_at.restype = i
     L.m2nufft_psd_at.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, vp, vp, vp]
+    L.gpss_tapers_rr.restype = i
+    L.gpss_tapers_rr.argtypes = [vp, vp, vp, i64, d, d, i, d, vp, vp, ctypes.POINTER(ctypes.c_int64)]
     L.m2nufft_psd_freqs.restype = i
     L.m2nufft_psd_freqs.argtypes = [vp, vp, vp, vp, i64, vp, i, vp, i64, i, d, vp, vp, vp]
     L.m2nufft_psd_at_noalloc.restype = i
@@ -261,6 +263,19 @@ def m2nufft_psd_at(ctx: Context, t, x, w, freqs, weights=None, want_J=False, str
     if check:
         ctx.check(stream)
     return {"P": P, "J": J}
+
+
+def gpss_tapers_rr(ctx: Context, t, fmax, fw, K, rank_tol=0.0, stream=None):
+    """Tapers after the rank-revealing reduction of R(B): (w [K, N], lam [K],
+    number of samples kept)."""
+    t = _dev(t)
+    N = t.shape[0]
+    w = torch.empty((K, N), dtype=torch.float64, device=t.device)
+    lam = torch.empty((K,), dtype=torch.float64, device=t.device)
+    r = ctypes.c_int64(0)
+    _err(lib.gpss_tapers_rr(ctx.handle, _stream(stream), _ptr(t), N, float(fmax), float(fw), int(K),
+                            float(rank_tol), _ptr(w), _ptr(lam), ctypes.byref(r)), "gpss_tapers_rr")
+    return w, lam, int(r.value)
 
 
 def m2nufft_psd_freqs(ctx: Context, t, x, w, freqs, prec=M2N_FP64, nufft_tol=0.0, weights=None, want_J=False,

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "nufft.hip", "gep.hip", "queue.hip", "subband.hip", "idpss.hip", "nudft_list.hip", "ehat.hip", "graph.hip", "nufft3.hip"]
+SOURCES = ["api.hip", "nufft.hip", "gep.hip", "queue.hip", "subband.hip", "idpss.hip", "nudft_list.hip", "ehat.hip", "graph.hip", "nufft3.hip", "rankrev.hip"]
 LIB = os.path.join(HERE, "libm2n.so")
 ARCH = os.environ.get("M2N_OFFLOAD_ARCH", "gfx950")
 

@@ -23,6 +23,9 @@ int noalloc_scratch_init(int device);
 // eigencoefficients at a list of band centres by a type-3 NuFFT (nufft3.hip)
 int nufft3_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N, const double* w, int K,
                const double* freqs, int64_t I, int prec, double tol, const double* weights, void* P, void* J);
+// tapers after a rank-revealing reduction of R(B) (rankrev.hip)
+int gep_rr(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K, double tau,
+           double* w, double* lambda, int64_t* rank);
 // interpolated-DPSS tapers (idpss.hip)
 int idpss_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double fmax, double fw, int K,
               double* w, double* lambda);
@@ -347,6 +350,16 @@ int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x,
     }
     M2N_HIP(hipSetDevice(ctx->device));
     return nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
+}
+
+int gpss_tapers_rr(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,
+                   double rank_tol, double* w, double* lambda, int64_t* rank) {
+    if (!ctx) {
+        set_error("NULL argument");
+        return M2N_ERR_ARG;
+    }
+    M2N_HIP(hipSetDevice(ctx->device));
+    return gep_rr(ctx, (hipStream_t)stream, t, N, fmax, fw, K, rank_tol, w, lambda, rank);
 }
 
 int m2nufft_psd_freqs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N, const double* w,

@@ -531,3 +531,56 @@ def test_nudft_freqs_matches_progression_and_fft(orc):
     x = rng.standard_normal(N)
     J2 = orc.nudft_freqs(t, x, np.ones((1, N)), np.arange(N) / N)
     assert np.abs(J2[0] - np.fft.fft(x)).max() < 1e-12 * np.abs(np.fft.fft(x)).max()
+
+
+# --------------------------------------------------------------------------
+# Rank-revealing reduction for a numerically singular R(B)
+# --------------------------------------------------------------------------
+
+def test_rr_full_rank_is_the_gep(orc):
+    # a well-conditioned grid keeps every sample: the plain GEP's tapers
+    s = W.jitter_stress(n=200, seed=8, K=4)
+    w, lam, S = orc.gpss_tapers_rr(s.t, s.fmax, 4.0 / 200, 4, 1e-12)
+    w0, lam0 = orc.gpss_tapers(s.t, s.fmax, 4.0 / 200, 4)
+    assert S.shape[0] == s.N
+    assert np.array_equal(w, w0) and np.array_equal(lam, lam0)
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6])
+def test_rr_schur_complement_bound(orc, tau):
+    # t = 5n/6 (R(B) numerically singular): the kept block is positive
+    # definite and the Schur complement of the left-out samples, formed
+    # independently with a dense solve, is bounded by the largest remaining
+    # pivot, which is below tau * 2 f_max
+    s = W.scheme_missing(L=480, n_keep=400, seed=3)
+    S, maxrem = orc.rr_select(s.t, s.fmax, tau)
+    R = orc.gpss_matrix(s.t, s.fmax)
+    out = np.setdiff1d(np.arange(s.N), S)
+    assert 0 < S.shape[0] < s.N and maxrem < tau * 2 * s.fmax
+    orc.cholesky(R[np.ix_(S, S)])                                 # positive definite
+    Sc = R[np.ix_(out, out)] - R[np.ix_(out, S)] @ np.linalg.solve(R[np.ix_(S, S)], R[np.ix_(S, out)])
+    assert np.abs(Sc).max() <= maxrem * (1 + 1e-6) + 1e-14
+    assert abs(np.diag(Sc).max() - maxrem) <= 1e-6 * maxrem + 1e-14
+
+
+def test_rr_near_duplicate_sample(orc):
+    # a sample repeated 1e-7 later makes R(B) singular to rounding: one of the
+    # pair is left out and the result is the GEP of the series without it
+    s = W.jitter_stress(n=120, seed=9, K=4)
+    t2 = np.sort(np.concatenate([s.t, [s.t[10] + 1e-7]]))
+    w, lam, S = orc.gpss_tapers_rr(t2, s.fmax, 4.0 / 120, 4, 1e-8)
+    _, lam0 = orc.gpss_tapers(s.t, s.fmax, 4.0 / 120, 4)
+    assert S.shape[0] == s.N and (10 not in S or 11 not in S)
+    np.testing.assert_allclose(lam, lam0, atol=1e-6)
+
+
+def test_rr_taper_properties(orc):
+    # tapers vanish off the kept samples, are R(B)-orthonormal with the full
+    # R(B) (2 f_w delta_kl) and their lambda lie in [0, 1]
+    for s in [W.scheme_arithmetic(seed=sd) for sd in (21, 30, 38, 43)]:   # plain GEP: NOT_PD
+        w, lam, S = orc.gpss_tapers_rr(s.t, s.fmax, s.fw, s.K, 1e-8)
+        out = np.setdiff1d(np.arange(s.N), S)
+        assert np.all(w[:, out] == 0.0)
+        G = w @ orc.gpss_matrix(s.t, s.fmax) @ w.T
+        assert np.abs(G - 2 * s.fw * np.eye(s.K)).max() < 1e-8
+        assert lam.min() >= -1e-12 and lam.max() <= 1 + 1e-12
