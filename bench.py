@@ -433,7 +433,7 @@ def cpu_model():
 
 
 def step_leg(m2n, torch, workloads, ctx, name, prec_name, steps, warmup, oracle_bands=1024):
-    """The per-series step (tapers, then P and Ehat) on one workload and
+    """The per-series step (tapers, P and Ehat in one fused call) on one workload and
     precision: median step time over `steps` timed steps after `warmup`, and
     P on sampled bands (both ends, uniform draws, the largest-P bands) and
     lambda against the oracle (its own tapers through its direct NUDFT)."""
@@ -449,10 +449,12 @@ def step_leg(m2n, torch, workloads, ctx, name, prec_name, steps, warmup, oracle_
     P = torch.empty((s.I,), dtype=rdt, device=dev)
     E = torch.empty((s.I,), dtype=rdt, device=dev)
 
+    spec = [{"t": t, "x": x, "fmax": s.fmax, "fw": s.fw, "K": s.K, "f_lo": s.f_lo, "df": s.df, "I": s.I,
+             "w": w, "lam": lam, "P": P, "E": E}]
+    prepared = m2n.batch_descriptors(spec, prec, True, False, False)
+
     def step():
-        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K, out=(w, lam))
-        m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=prec,
-                        want_E=True, out=(P, E, None), check=False)
+        m2n.m2n_batch_psd(ctx, spec, prec=prec, prepared=prepared, check=False)
 
     for _ in range(warmup):
         step()
@@ -808,10 +810,14 @@ def main():
     E = torch.empty((I,), dtype=rdt, device=dev)
     stream = torch.cuda.current_stream()
 
+    # one step: the fused boundary call (t check, tapers, NuFFT, P and Ehat)
+    # on a batch of this one series
+    spec = [{"t": t, "x": x, "fmax": s.fmax, "fw": s.fw, "K": K, "f_lo": s.f_lo, "df": s.df, "I": I,
+             "w": w, "lam": lam, "P": P, "E": E}]
+    prepared = m2n.batch_descriptors(spec, prec, True, False, False)
+
     def step():
-        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, K, out=(w, lam))
-        m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, I, prec=prec,
-                        want_E=True, out=(P, E, None), check=False)
+        m2n.m2n_batch_psd(ctx, spec, prec=prec, prepared=prepared, check=False)
 
     def nufft_only():
         m2n.m2nufft_psd(ctx, t, x, w, lam, s.fmax, s.fw, s.f_lo, s.df, I, prec=prec,

@@ -237,6 +237,7 @@ void m2n_destroy(m2n_ctx* ctx) {
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->hstage_ev) (void)hipEventDestroy(ctx->hstage_ev);
     if (ctx->tcheck_ev) (void)hipEventDestroy(ctx->tcheck_ev);
+    if (ctx->gcheck_ev) (void)hipEventDestroy(ctx->gcheck_ev);
     if (ctx->erec) (void)hipHostFree(ctx->erec);
     for (auto& b : ctx->stage_blocks) (void)hipHostFree(b.first);
     for (auto& r : ctx->pending) {
@@ -503,9 +504,13 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
     }
     M2N_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    M2N_TRY(gep_run_batch(ctx, st, g.data(), nseries));
-    // one NuFFT batch per distinct band count
-    std::map<int64_t, std::vector<NuSeriesIn>> groups;
+    // one NuFFT batch per distinct band count; Ehat is routed here from the
+    // taper solve's t check (R(B) = c I or not), so the NuFFT never waits
+    struct Entry {
+        int idx;
+        NuSeriesIn in;
+    };
+    std::map<int64_t, std::vector<Entry>> groups;
     for (int i = 0; i < nseries; ++i) {
         const m2n_series& s = series[i];
         NuSeriesIn n;
@@ -524,10 +529,46 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
         n.E = s.E;
         n.J = s.J;
         n.F = s.F;
-        groups[s.I].push_back(n);
+        n.e_diag_known = true;
+        groups[s.I].push_back({i, n});
     }
-    for (auto& kv : groups)
-        M2N_TRY(nufft_run_batch(ctx, st, kv.first, prec, nufft_tol, kv.second.data(), (int)kv.second.size()));
+    auto ins_of = [](const std::vector<Entry>& v) {
+        std::vector<NuSeriesIn> r;
+        r.reserve(v.size());
+        for (const Entry& e : v) r.push_back(e.in);
+        return r;
+    };
+    // the t check, then the binning of the first band count (it needs t
+    // alone) while the host waits for the check's records
+    GepCheck* chk = nullptr;
+    M2N_TRY(gep_check_begin(ctx, st, g.data(), nseries, &chk));
+    std::unique_ptr<GepCheck, void (*)(GepCheck*)> chk_own(chk, gep_check_free);
+    std::vector<NuSeriesIn> first = ins_of(groups.begin()->second);
+    NuPending* pend = nullptr;
+    M2N_TRY(nufft_begin(ctx, st, groups.begin()->first, prec, nufft_tol, first.data(), (int)first.size(), &pend));
+    std::unique_ptr<NuPending, void (*)(NuPending*)> pend_own(pend, nufft_pending_free);
+    M2N_TRY(gep_check_wait(ctx, chk));
+    M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
+    for (auto it = groups.begin(); it != groups.end(); ++it) {
+        const int64_t I = it->first;
+        if (it == groups.begin()) {
+            M2N_TRY(nufft_finish(ctx, st, pend_own.release()));
+        } else {
+            std::vector<NuSeriesIn> v = ins_of(it->second);
+            M2N_TRY(nufft_run_batch(ctx, st, I, prec, nufft_tol, v.data(), (int)v.size()));
+        }
+        // Ehat where R(B) is not a multiple of the identity (the NuFFT wrote
+        // the band-constant value, which the quadrature overwrites)
+        for (const Entry& e : it->second) {
+            if (!e.in.E) continue;
+            int flags = 0;
+            double t0 = 0.0, tN = 0.0;
+            gep_check_info(chk, e.idx, &flags, &t0, &tN);
+            const double c = 2.0 * e.in.fmax;
+            const bool diag = !(flags & 4) && c == std::rint(c) && c >= 1.0;
+            if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, nufft_tol, e.in, e.in.N > 1 ? tN - t0 : 0.0));
+        }
+    }
     return M2N_OK;
 }
 

@@ -145,6 +145,17 @@ int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x,
 // many series with one band count I and precision in one set of launches
 int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
                     const NuSeriesIn* series, int nseries);
+// The same in two halves: nufft_begin queues the binning (it reads t
+// alone), nufft_finish the rest (scatter with the tapers, both passes,
+// outputs).  Ehat must be routed by the caller (e_diag_known set on every
+// series with E); the NuFFT's workspace stays reserved in between, so no
+// other NuFFT may run on this context until nufft_finish (or
+// nufft_pending_free) is called.
+struct NuPending;
+int nufft_begin(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol, const NuSeriesIn* series,
+                int nseries, NuPending** out);
+int nufft_finish(Ctx* ctx, hipStream_t st, NuPending* pending);   // frees pending
+void nufft_pending_free(NuPending* pending);
 // the kernel width a tolerance gives, and every schedule this build has
 // kernels for at (I, prec, width); the first entry is the default one
 int nufft_width(int prec, double tol);
@@ -175,6 +186,18 @@ struct GepIn {
 // many series: one t check for all, the lattice low-rank ones in one set of
 // launches, the rest one by one
 int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
+// The same with the t check split off: gep_check_begin queues the check and
+// marks its end with an event; gep_check_wait waits for that event alone
+// (work queued after the check keeps running) and reads the records;
+// gep_run_checked computes the tapers.  gep_check_info reports what the
+// check found for series i: flags (1 non-finite, 2 not increasing, 4 some t
+// not an integer), t_1 and t_N.
+struct GepCheck;
+int gep_check_begin(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, GepCheck** out);
+int gep_check_wait(Ctx* ctx, GepCheck* c);
+int gep_run_checked(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, const GepCheck* c);
+void gep_check_info(const GepCheck* c, int i, int* flags, double* t0, double* tN);
+void gep_check_free(GepCheck* c);
 // a replayable batch: one t check, every series on the lattice low-rank path
 // (gep.hip); then the tapers' launches alone
 int gep_batch_check_lattice(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<double>& t0,
@@ -225,6 +248,7 @@ struct Ctx {
 
     // a second stream (default priority) and two events for work that
     // overlaps the caller's stream, created on first use
+    hipEvent_t gcheck_ev = nullptr;     // marks the end of a taper solve's t check
     hipEvent_t tcheck_ev = nullptr;     // marks the t check of an Ehat request
     void* erec = nullptr;               // pinned records of that check
     size_t erec_bytes = 0;

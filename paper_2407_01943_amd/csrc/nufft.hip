@@ -30,6 +30,7 @@
 // as a device array indexed by blockIdx.y for a batch; NuArgs holds what the
 // plan fixes (band count, grid split, tables).
 #include <cmath>
+#include <memory>
 #include <cstdarg>
 #include <cstring>
 
@@ -1309,10 +1310,28 @@ struct Carver {
 
 // `checked` (or NULL) is recorded once the kernels that write the series'
 // host records of the t check (k_scan, k_small) are queued
+}  // namespace
+
+// A NuFFT batch whose binning (histogram and scan of the cells, which need
+// t alone) is queued and whose scatter, passes and outputs are not: the
+// tapers may still be in flight between the two halves.
+struct NuPending {
+    const NufftPlan* p = nullptr;
+    int prec = 0;
+    NuArgs a{};
+    std::vector<NuSeries> ds;
+    const NuSeries* D = nullptr;
+    int maxK = 0, maxwg = 0;
+};
+
+namespace {
+
 template <typename R>
-int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns, hipEvent_t checked) {
-    const NuArgs a = make_args(ctx, p);
-    std::vector<NuSeries> ds(ns);
+int begin_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns, NuPending& q) {
+    q.p = &p;
+    q.a = make_args(ctx, p);
+    std::vector<NuSeries>& ds = q.ds;
+    ds.assign(ns, NuSeries());
     int maxK = 0, maxwg = 0;
     // per-series binning geometry, then the workspace layout (two passes:
     // measure with a null base, then carve)
@@ -1353,6 +1372,8 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         maxK = std::max(maxK, s.K);
         maxwg = std::max(maxwg, d.nwg);
     }
+    q.maxK = maxK;
+    q.maxwg = maxwg;
     if (!p.single) {
         auto carve = [&](Carver& c) {
             for (int i = 0; i < ns; ++i) {
@@ -1381,51 +1402,74 @@ int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in
         c.base = (char*)wsp;
         carve(c);
     }
-    const NuSeries* D = nullptr;
+    q.D = nullptr;
     if (ns > 1) {
         void* vd;
         M2N_TRY(ctx->workspace("nu_desc", sizeof(NuSeries) * (size_t)ns, &vd));
         M2N_TRY(ctx->stage(st, ds.data(), sizeof(NuSeries) * (size_t)ns, vd));
-        D = (const NuSeries*)vd;
+        q.D = (const NuSeries*)vd;
     }
+    if (p.single) return M2N_OK;
     const NuSeries& d0 = ds[0];
+    const unsigned ys = (unsigned)ns;
+    {
+        M2N_PROF(ctx, st, "k_hist");
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, q.a, d0, q.D);
+    }
+    {
+        M2N_PROF(ctx, st, "k_scan");
+        hipLaunchKernelGGL(k_scan, dim3(1, ys), dim3(1024), 0, st, q.a, d0, q.D);
+    }
+    M2N_HIP(hipGetLastError());
+    return M2N_OK;
+}
+
+// the second half: scatter, the two passes (or the one-workgroup kernel for
+// small grids); `checked` (if given) is recorded once the t check of the
+// binning is done
+template <typename R>
+int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
+    const NufftPlan& p = *q.p;
+    const NuSeries& d0 = q.ds[0];
+    const NuSeries* D = q.D;
+    const int ns = (int)q.ds.size();
     const unsigned ys = (unsigned)ns;
     if (p.single) {
         M2N_PROF(ctx, st, "k_small");
-        M2N_TRY(launch_small<R>(p, st, dim3(1, ys), a, d0, D));
+        M2N_TRY(launch_small<R>(p, st, dim3(1, ys), q.a, d0, D));
         M2N_HIP(hipGetLastError());
         if (checked) M2N_HIP(hipEventRecord(checked, st));
         return M2N_OK;
     }
-    {
-        M2N_PROF(ctx, st, "k_hist");
-        hipLaunchKernelGGL(k_hist, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
-    }
-    {
-        M2N_PROF(ctx, st, "k_scan");
-        hipLaunchKernelGGL(k_scan, dim3(1, ys), dim3(1024), 0, st, a, d0, D);
-    }
+    const int nbins = p.N2 / p.B;
     if (checked) M2N_HIP(hipEventRecord(checked, st));
     {
         M2N_PROF(ctx, st, "k_scatter");
         bool anyF = false;
-        for (const NuSeries& d : ds) anyF = anyF || d.F != nullptr;
-        if (anyF) hipLaunchKernelGGL((k_scatter<R, true>), dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
-        else hipLaunchKernelGGL((k_scatter<R, false>), dim3((unsigned)maxwg, ys), dim3(NT), 0, st, a, d0, D);
+        for (const NuSeries& d : q.ds) anyF = anyF || d.F != nullptr;
+        if (anyF) hipLaunchKernelGGL((k_scatter<R, true>), dim3((unsigned)q.maxwg, ys), dim3(NT), 0, st, q.a, d0, D);
+        else hipLaunchKernelGGL((k_scatter<R, false>), dim3((unsigned)q.maxwg, ys), dim3(NT), 0, st, q.a, d0, D);
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass1");
-        M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(maxK * nbins), ys), a, d0, D));
+        M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(q.maxK * nbins), ys), q.a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass2");
         const int M = pass2_rows(p, ctx->cu_count, ns);
-        M2N_TRY(launch_pass2<R>(p, st, M, dim3((unsigned)(p.N1 / M), ys), a, d0, D));
+        M2N_TRY(launch_pass2<R>(p, st, M, dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
+}
+
+template <typename R>
+int run_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* in, int ns, hipEvent_t checked) {
+    NuPending q;
+    M2N_TRY(begin_typed<R>(ctx, st, p, in, ns, q));
+    return finish_typed<R>(ctx, st, q, checked);
 }
 
 int check_series(const NuSeriesIn& s, int64_t I) {
@@ -1510,6 +1554,42 @@ int nufft_run_batch(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol,
     }
     return M2N_OK;
 }
+
+int nufft_begin(Ctx* ctx, hipStream_t st, int64_t I, int prec, double tol, const NuSeriesIn* series,
+                int nseries, NuPending** out) {
+    *out = nullptr;
+    if (nseries < 1 || !series) {
+        set_error("empty batch");
+        return M2N_ERR_ARG;
+    }
+    if (prec != M2N_FP32 && prec != M2N_FP64) {
+        set_error("prec must be M2N_FP32 or M2N_FP64");
+        return M2N_ERR_ARG;
+    }
+    for (int i = 0; i < nseries; ++i) {
+        M2N_TRY(check_series(series[i], I));
+        if (series[i].E && !series[i].e_diag_known) {
+            set_error("series %d: a split NuFFT needs Ehat routed by its caller", i);
+            return M2N_ERR_ARG;
+        }
+    }
+    NufftPlan* p = nullptr;
+    M2N_TRY(get_plan(ctx, I, prec, tol, &p));
+    std::unique_ptr<NuPending> q(new NuPending());
+    q->prec = prec;
+    if (prec == M2N_FP32) M2N_TRY(begin_typed<float>(ctx, st, *p, series, nseries, *q));
+    else M2N_TRY(begin_typed<double>(ctx, st, *p, series, nseries, *q));
+    *out = q.release();
+    return M2N_OK;
+}
+
+int nufft_finish(Ctx* ctx, hipStream_t st, NuPending* q) {
+    std::unique_ptr<NuPending> own(q);
+    if (q->prec == M2N_FP32) return finish_typed<float>(ctx, st, *q, nullptr);
+    return finish_typed<double>(ctx, st, *q, nullptr);
+}
+
+void nufft_pending_free(NuPending* q) { delete q; }
 
 int nufft_run(Ctx* ctx, hipStream_t st, const double* t, const double* x, int64_t N,
               const double* w, int K, double f_lo, double df, int64_t I, int prec, double tol,
