@@ -434,7 +434,8 @@ def cpu_model():
 
 def step_leg(m2n, torch, workloads, ctx, name, prec_name, steps, warmup, oracle_bands=1024):
     """The per-series step (tapers, P and Ehat in one fused call) on one workload and
-    precision: median step time over `steps` timed steps after `warmup`, and
+    precision: step time over `steps` steps queued back to back after `warmup`
+    (and the latency of steps run one at a time), and
     P on sampled bands (both ends, uniform draws, the largest-P bands) and
     lambda against the oracle (its own tapers through its direct NUDFT)."""
     import numpy as np
@@ -460,13 +461,19 @@ def step_leg(m2n, torch, workloads, ctx, name, prec_name, steps, warmup, oracle_
         step()
     torch.cuda.synchronize()
     ctx.check()
+    # throughput: steps back to back between two synchronisations; latency:
+    # one step at a time from an idle device
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
     lat = []
     for _ in range(steps):
         t0 = time.perf_counter()
         step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
-    ms = 1e3 * float(np.median(lat))
     out = {"workload": name, "N": s.N, "K": s.K, "I": s.I, "prec": prec_name,
            "nufft": NUFFT_LABEL[prec_name], "steps": steps, "ms_per_step": round(ms, 4),
            "value": round(s.N * s.K * s.I / (ms * 1e-3) / 1e6, 1), "unit": "Mpts*tapers*bands/s",
@@ -839,18 +846,24 @@ def main():
     ctx.check()
     print("bench: warmup done", file=sys.stderr, flush=True)
 
-    # ---- timed pass 1: whole steps
-    lat = []
+    # ---- timed pass 1: K whole steps back to back on the stream (the call
+    # waits for nothing in between, so step i + 1 is queued while step i runs),
+    # bracketed by synchronisations: whole-job throughput
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / a.steps
+    # ---- latency: the same steps one at a time, each from an idle device to
+    # its results
+    lat = []
     for _ in range(a.steps):
         ts = time.perf_counter()
         step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = 1e3 * elapsed / a.steps
     lat_ms = np.array(lat) * 1e3
 
     # ---- NuFFT + average only (tapers resident), HIP events on the stream
@@ -863,7 +876,8 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms_nufft = e0.elapsed_time(e1) / reps
-    print(f"bench: step {ms_step:.3f} ms, nufft {ms_nufft:.4f} ms", file=sys.stderr, flush=True)
+    print(f"bench: step {ms_step:.3f} ms (p50 latency {float(np.percentile(lat_ms, 50)):.3f} ms), "
+          f"nufft {ms_nufft:.4f} ms", file=sys.stderr, flush=True)
 
     # ---- the same with the Thomson F-statistic fused into the average
     Fb = torch.empty((I,), dtype=rdt, device=dev)

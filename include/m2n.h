@@ -388,11 +388,22 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
 
 /*
  * m2n_batch_psd -- gpss_tapers followed by m2nufft_psd for many series, in
- * batched launches: one check of all sampling times (one host round trip),
- * the tapers of every series whose R(B) is a multiple of the identity in
- * one set of launches (the others one by one), then one NuFFT launch set per
- * distinct band count I.  Results equal the per-series calls within the
- * NuFFT tolerance (the tapers are bitwise equal).
+ * batched launches: one check of all sampling times, the tapers of every
+ * series whose R(B) is a multiple of the identity in one set of launches
+ * (the others one by one), then one NuFFT launch set per distinct band count
+ * I.  Results equal the per-series calls within the NuFFT tolerance (the
+ * tapers are bitwise equal).
+ *
+ * Host round trip: the taper path of a series depends on what the check
+ * finds (t integer or not, t_1, t_N).  The first call on given t buffers
+ * (pointer and N) waits for the check while the NuFFT binning runs; the
+ * context keeps the records, and later calls on the same buffers queue
+ * everything on them at once and compare them with the real check when all
+ * is queued (by then it has long finished).  If they differ (the contents
+ * changed t_1, t_N or the lattice property) the call computes everything
+ * again with the real records before it returns, so results are always
+ * those of the real check; an invalid t is reported as always.  Output
+ * buffers hold unspecified values when a call returns an error.
  *
  *   series  [nseries] HOST array of descriptors; every pointer inside is a
  *           device pointer with the layout of the per-series calls:
@@ -403,7 +414,8 @@ int m2nufft_psd(m2n_ctx *ctx, void *stream, const double *t, const double *x,
  *
  * Errors name the offending series in m2n_last_error().  Stream-ordered
  * after the t check, except for series that take the dense or wide-band
- * taper path (see gpss_tapers), which block.
+ * taper path (see gpss_tapers), which block.  Calls on one context must not
+ * run concurrently (as for every entry point).
  */
 typedef struct {
     const double *t, *x;

@@ -250,6 +250,8 @@ void m2n_destroy(m2n_ctx* ctx) {
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->aux_fork) (void)hipEventDestroy(ctx->aux_fork);
     if (ctx->aux_join) (void)hipEventDestroy(ctx->aux_join);
+    if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+    if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
     if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
 }
@@ -538,36 +540,66 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
         for (const Entry& e : v) r.push_back(e.in);
         return r;
     };
-    // the t check, then the binning of the first band count (it needs t
-    // alone) while the host waits for the check's records
+    // The t check, then the binning of the first band count (it needs t
+    // alone), both on a side stream.  When the last call on the same t buffers left its records,
+    // everything is queued at once on those and the real check (done long
+    // before the host looks) is compared at the end: the parameters of the
+    // taper path (lattice or not, t_1, t_N) depend on nothing else, so equal
+    // records mean the queued results are the right ones; otherwise they are
+    // computed again with the real records.  Without them the host waits
+    // for the check alone while the binning runs.
+    // The check and the binning go to the context's side stream, forked
+    // from `stream` (after everything queued on it before) and joined back
+    // before the NuFFT's second half, so that they run beside the tapers (the
+    // taper kernels read t themselves; only their launch parameters come from
+    // the check).
+    hipStream_t side = nullptr;
+    hipEvent_t af = nullptr, aj = nullptr;
+    M2N_TRY(ctx->aux_stream(&side, &af, &aj));
+    if (!ctx->side_fork) M2N_HIP(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming));
+    if (!ctx->side_join) M2N_HIP(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming));
+    M2N_HIP(hipEventRecord(ctx->side_fork, st));
+    M2N_HIP(hipStreamWaitEvent(side, ctx->side_fork, 0));
     GepCheck* chk = nullptr;
-    M2N_TRY(gep_check_begin(ctx, st, g.data(), nseries, &chk));
+    M2N_TRY(gep_check_begin(ctx, side, g.data(), nseries, &chk));
     std::unique_ptr<GepCheck, void (*)(GepCheck*)> chk_own(chk, gep_check_free);
+    const bool guessed = gep_check_guess(ctx, chk, g.data(), nseries);
     std::vector<NuSeriesIn> first = ins_of(groups.begin()->second);
     NuPending* pend = nullptr;
-    M2N_TRY(nufft_begin(ctx, st, groups.begin()->first, prec, nufft_tol, first.data(), (int)first.size(), &pend));
+    M2N_TRY(nufft_begin(ctx, side, groups.begin()->first, prec, nufft_tol, first.data(), (int)first.size(), &pend));
     std::unique_ptr<NuPending, void (*)(NuPending*)> pend_own(pend, nufft_pending_free);
-    M2N_TRY(gep_check_wait(ctx, chk));
-    M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
-    for (auto it = groups.begin(); it != groups.end(); ++it) {
-        const int64_t I = it->first;
-        if (it == groups.begin()) {
-            M2N_TRY(nufft_finish(ctx, st, pend_own.release()));
-        } else {
-            std::vector<NuSeriesIn> v = ins_of(it->second);
-            M2N_TRY(nufft_run_batch(ctx, st, I, prec, nufft_tol, v.data(), (int)v.size()));
+    M2N_HIP(hipEventRecord(ctx->side_join, side));
+    if (!guessed) M2N_TRY(gep_check_wait(ctx, chk, g.data(), nseries));
+    auto rest = [&](bool first_pending) -> int {
+        M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
+        M2N_HIP(hipStreamWaitEvent(st, ctx->side_join, 0));
+        for (auto it = groups.begin(); it != groups.end(); ++it) {
+            const int64_t I = it->first;
+            if (it == groups.begin() && first_pending) {
+                M2N_TRY(nufft_finish(ctx, st, pend_own.release()));
+            } else {
+                std::vector<NuSeriesIn> v = ins_of(it->second);
+                M2N_TRY(nufft_run_batch(ctx, st, I, prec, nufft_tol, v.data(), (int)v.size()));
+            }
+            // Ehat where R(B) is not a multiple of the identity (the NuFFT
+            // wrote the band-constant value, which the quadrature overwrites)
+            for (const Entry& e : it->second) {
+                if (!e.in.E) continue;
+                int flags = 0;
+                double t0 = 0.0, tN = 0.0;
+                gep_check_info(chk, e.idx, &flags, &t0, &tN);
+                const double c = 2.0 * e.in.fmax;
+                const bool diag = !(flags & 4) && c == std::rint(c) && c >= 1.0;
+                if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, nufft_tol, e.in, e.in.N > 1 ? tN - t0 : 0.0));
+            }
         }
-        // Ehat where R(B) is not a multiple of the identity (the NuFFT wrote
-        // the band-constant value, which the quadrature overwrites)
-        for (const Entry& e : it->second) {
-            if (!e.in.E) continue;
-            int flags = 0;
-            double t0 = 0.0, tN = 0.0;
-            gep_check_info(chk, e.idx, &flags, &t0, &tN);
-            const double c = 2.0 * e.in.fmax;
-            const bool diag = !(flags & 4) && c == std::rint(c) && c >= 1.0;
-            if (!diag) M2N_TRY(ehat_general(ctx, st, I, prec, nufft_tol, e.in, e.in.N > 1 ? tN - t0 : 0.0));
-        }
+        return M2N_OK;
+    };
+    M2N_TRY(rest(true));
+    if (guessed) {
+        bool same = true;
+        M2N_TRY(gep_check_confirm(ctx, chk, g.data(), nseries, &same));
+        if (!same) M2N_TRY(rest(false));
     }
     return M2N_OK;
 }

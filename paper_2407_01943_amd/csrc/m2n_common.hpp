@@ -194,10 +194,20 @@ int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
 // not an integer), t_1 and t_N.
 struct GepCheck;
 int gep_check_begin(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, GepCheck** out);
-int gep_check_wait(Ctx* ctx, GepCheck* c);
+int gep_check_wait(Ctx* ctx, GepCheck* c, const GepIn* in, int nseries);
 int gep_run_checked(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, const GepCheck* c);
 void gep_check_info(const GepCheck* c, int i, int* flags, double* t0, double* tN);
 void gep_check_free(GepCheck* c);
+// Speculation on the record of the last check of the same t buffers:
+// gep_check_guess fills the records from ctx->tcache (returns false, and
+// leaves them unset, unless every series has an entry that did not fail a
+// guess since it last repeated); gep_check_confirm waits for the real
+// check, compares, keeps the real records and reports whether they equal
+// the guess (an entry that fails is not guessed on again until a waited
+// check finds the same records twice in a row).  gep_check_wait also
+// updates the cache.
+bool gep_check_guess(Ctx* ctx, GepCheck* c, const GepIn* in, int nseries);
+int gep_check_confirm(Ctx* ctx, GepCheck* c, const GepIn* in, int nseries, bool* same);
 // a replayable batch: one t check, every series on the lattice low-rank path
 // (gep.hip); then the tapers' launches alone
 int gep_batch_check_lattice(Ctx* ctx, hipStream_t st, const GepIn* in, int ns, std::vector<double>& t0,
@@ -249,6 +259,10 @@ struct Ctx {
     // a second stream (default priority) and two events for work that
     // overlaps the caller's stream, created on first use
     hipEvent_t gcheck_ev = nullptr;     // marks the end of a taper solve's t check
+    // what the last t check found per (t pointer, N): flags, t_1, t_N, and
+    // whether a guess on it has failed since the records last repeated; the
+    // fused call queues its tapers on these and confirms them at its end
+    std::map<std::pair<const double*, int64_t>, std::tuple<int, double, double, bool>> tcache;
     hipEvent_t tcheck_ev = nullptr;     // marks the t check of an Ehat request
     void* erec = nullptr;               // pinned records of that check
     size_t erec_bytes = 0;
@@ -256,6 +270,9 @@ struct Ctx {
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork = nullptr, aux_join = nullptr;
     int aux_stream(hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);
+    // the fused call's fork to the side stream (t check and NuFFT binning
+    // beside the tapers) and its join before the NuFFT's second half
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
     // child contexts (own workspace, streams and pinned records) and their
     // streams for sub-bands solved at once; created on first use
     std::vector<Ctx*> subs;

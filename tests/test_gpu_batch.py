@@ -1,7 +1,10 @@
 """Batched form: many uneven series through m2n_batch_psd (one t check, the
 lattice tapers of all series in one set of launches, one NuFFT launch set per
 band count) give the same tapers bit for bit and the same P / Ehat within the
-NuFFT tolerance as the per-series calls, and match the CPU FP64 oracle."""
+NuFFT tolerance as the per-series calls, and match the CPU FP64 oracle.
+Calls on the same t buffers reuse the last t-check records and confirm them
+at the end: in-place changes of t (span, lattice, validity) give a fresh
+context's results (tapers bitwise) or its error."""
 import numpy as np
 import pytest
 
@@ -127,3 +130,62 @@ def test_batch_error_names_series(m2n, ctx):
         m2n.m2n_batch_psd(ctx, [_spec(good), _spec(bad)], prec=m2n.M2N_FP32)
     assert ei.value.code == m2n.M2N_ERR_T_ORDER
     assert "series 1" in str(ei.value)
+
+
+def _same_result(got, ref, label):
+    # tapers and eigenvalues bit for bit; P and Ehat within the FP32 NuFFT
+    # tolerance (the spreading sums points in an order set by LDS atomics)
+    assert torch.equal(got["w"], ref["w"]) and torch.equal(got["lam"], ref["lam"]), label
+    dP = psd_err(got["P"].double().cpu().numpy(), ref["P"].double().cpu().numpy())
+    assert dP < 2e-6, (label, dP)
+    assert torch.allclose(got["E"].double(), ref["E"].double(), rtol=0, atol=1e-7), label
+
+
+def _run_on(m2n, c, spec, prec):
+    o = m2n.m2n_batch_psd(c, [spec], prec=prec)[0]
+    torch.cuda.synchronize()
+    return {k: (v.clone() if v is not None else None) for k, v in o.items()}
+
+
+@pytest.mark.parametrize("name", ["small_gapped", "batched_series_3"])
+def test_batch_check_records_reused_and_confirmed(m2n, ctx, name):
+    # Calls on the same t buffer queue their tapers on the previous call's
+    # t-check records and compare them with the real check at the end.  Each
+    # case below changes the buffer in place between calls: results must
+    # equal those of a fresh context (which has no records to reuse), and an
+    # invalid t must still be reported.
+    s = W.small_gapped() if name == "small_gapped" else W.batched_series(3)
+    t0 = s.t.copy()
+    t, x = _dev(t0), _dev(s.x)
+    spec = {"t": t, "x": x, "fmax": s.fmax, "fw": s.fw, "K": s.K, "f_lo": s.f_lo, "df": s.df,
+            "I": s.I, "want_E": True}
+    prec = m2n.M2N_FP32
+    cases = [("same contents", t0),
+             ("t shifted by 7 (t_1, t_N change)", t0 + 7.0),
+             ("one sample off the integers (dense path)", t0 + np.where(np.arange(s.N) == 5, 0.5, 0.0)),
+             ("back to the first contents", t0)]
+    _run_on(m2n, ctx, spec, prec)   # leaves the records of t0
+    for label, tv in cases:
+        t.copy_(torch.from_numpy(tv))
+        torch.cuda.synchronize()
+        got = _run_on(m2n, ctx, spec, prec)
+        c2 = m2n.Context(0)
+        ref = _run_on(m2n, c2, spec, prec)
+        c2.close()
+        _say(f"case {name}: {label}")
+        _same_result(got, ref, label)
+    # an invalid t after valid records: the real check wins
+    bad = t0.copy()
+    bad[[3, 4]] = bad[[4, 3]]
+    t.copy_(torch.from_numpy(bad))
+    torch.cuda.synchronize()
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.m2n_batch_psd(ctx, [spec], prec=prec)
+    assert ei.value.code == m2n.M2N_ERR_T_ORDER
+    t.copy_(torch.from_numpy(t0))
+    torch.cuda.synchronize()
+    got = _run_on(m2n, ctx, spec, prec)
+    c2 = m2n.Context(0)
+    ref = _run_on(m2n, c2, spec, prec)
+    c2.close()
+    _same_result(got, ref, "valid again after the error")
