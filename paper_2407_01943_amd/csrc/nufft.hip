@@ -562,7 +562,11 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     const int blk = blockIdx.x % nblk;
     const int k = blockIdx.x / nblk;
     if (k >= d.K) return;
-    constexpr int LD = N1 + 1;
+    // the column FFTs' intermediate stages use the layout with a gap every 32
+    // elements (the tile stays small enough for four workgroups per compute
+    // unit)
+    constexpr int PSH = N1 >= 64 ? 5 : 0;
+    constexpr int LD = N1 + (PSH ? N1 / 32 : 0) + 1;
     constexpr int G = 64 / B;                               // tile rows per wavefront task
     constexpr int TASKS = N1 * B / NT1;                     // tile cells each thread owns
     // points sorted per chunk: the sorted list lives in the tile's storage,
@@ -733,8 +737,9 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         if (!pruned) {
             tile[cb * LD + row] = acc[u];
         } else if (row < N1 / 8) {
+            // the first stage's output, in the layout of the stages after it
 #pragma unroll
-            for (int q = 0; q < 8; ++q) tile[cb * LD + 8 * row + q] = acc[u];
+            for (int q = 0; q < 8; ++q) tile[cb * LD + fft_pad(8 * row + q, N1 > 8 ? PSH : 0)] = acc[u];
         }
     }
     if constexpr (TW_EARLY) {
@@ -766,7 +771,7 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
             d.wsums[k] = s1;
         }
     }
-    fft_lds<R, N1, B, NT1, LD>(tile, tw, 1, pruned);
+    fft_lds<R, N1, B, NT1, LD, PSH>(tile, tw, 1, pruned);
     // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, then
     // G[k][m1][l2].  A thread keeps one column cb and steps m1 by S = NT1 / B,
     // so its twiddle advances by the fixed factor exp(-2 pi i c S / nf): two
@@ -801,8 +806,12 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
 template <typename R, int N2, int M, int KC>
 __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
-    constexpr int LD = N2 + 1;
     constexpr int ROWS = KC * M;
+    // the FFTs' intermediate stages use the padded layout when the longer
+    // rows still fit the LDS of a compute unit
+    constexpr bool PAD = ROWS * (N2 + N2 / 8 + 1) * (int)sizeof(cplx<R>) + N2 * (int)sizeof(cplx<R>) <= 160000;
+    constexpr int PSH = PAD ? 3 : 0;
+    constexpr int LD = PAD ? N2 + N2 / 8 + 1 : N2 + 1;
     constexpr int OUT_IT = (M * (N2 / 2 + 2) + NT2 - 1) / NT2;
     __shared__ cplx<R> rows[ROWS * LD];
     __shared__ cplx<R> tw[N2];
@@ -818,7 +827,10 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
     const int m1_0 = bid * M;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
-    const cplx<R>* inter = (const cplx<R>*)d.inter;
+    // global address space: plain global loads, which the LDS-only
+    // barriers of the FFT do not wait for
+    typedef R R2 __attribute__((ext_vector_type(2)));
+    const auto* inter = gp((const R2*)d.inter);
     const R* inv_phihat = (const R*)a.inv_phihat;
     R* P = (R*)d.P;
     R* E = (R*)d.E;
@@ -861,22 +873,35 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
         sjj[it] = (R)0;
         sjw[it] = {(R)0, (R)0};
     }
-    for (int kc0 = 0; kc0 < K; kc0 += KC) {
+    // a group's rows, all loads in flight together (a row never straddles a
+    // wavefront: the taper test is uniform per wavefront); the next group's
+    // loads are issued before this group's FFTs, so that they arrive while
+    // the LDS work runs
+    constexpr int LIT = ROWS * N2 / NT2;
+    static_assert(ROWS * N2 % NT2 == 0, "pass-2 tile");
+    auto load_group = [&](int kc0, cplx<R> (&v)[LIT]) {
         const int nk = K - kc0 < KC ? K - kc0 : KC;
-        // all loads first, then the LDS stores, so that they are in flight
-        // together (a row never straddles a wavefront: the taper test is
-        // uniform per wavefront)
-        constexpr int LIT = ROWS * N2 / NT2;
-        static_assert(ROWS * N2 % NT2 == 0, "pass-2 tile");
-        cplx<R> v[LIT];
 #pragma unroll
         for (int u = 0; u < LIT; ++u) {
             const int e = threadIdx.x + u * NT2;
             const int r = e / N2, l2 = e - r * N2;
             const int kq = r / M, mm = r - kq * M;
             v[u] = {(R)0, (R)0};
-            if (kq < nk) v[u] = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
+            if (kq < nk) {
+                const R2 g = inter[(int64_t)(kc0 + kq) * nf + (int64_t)(m1_0 + mm) * N2 + l2];
+                v[u] = {g.x, g.y};
+            }
         }
+    };
+    // (registers for two groups only with groups of at most four rows; the
+    // larger groups load in place)
+    constexpr bool PREF = ROWS <= 4;
+    constexpr int LITN = PREF ? LIT : 1;
+    cplx<R> v[LIT], vn[LITN];
+    if constexpr (PREF) load_group(0, v);
+    for (int kc0 = 0; kc0 < K; kc0 += KC) {
+        const int nk = K - kc0 < KC ? K - kc0 : KC;
+        if constexpr (!PREF) load_group(kc0, v);
 #pragma unroll
         for (int u = 0; u < LIT; ++u) {
             const int e = threadIdx.x + u * NT2;
@@ -884,7 +909,10 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             rows[r * LD + l2] = v[u];
         }
         __syncthreads();
-        fft_lds<R, N2, ROWS, NT2, LD>(rows, tw, 1, false, nk * M);   // the nk tapers present
+        if constexpr (PREF) {
+            if (kc0 + KC < K) load_group(kc0 + KC, vn);
+        }
+        fft_lds<R, N2, ROWS, NT2, LD, PSH>(rows, tw, 1, false, nk * M);   // the nk tapers present
 #pragma unroll
         for (int it = 0; it < OUT_IT; ++it) {
             const int e = threadIdx.x + it * NT2;
@@ -913,6 +941,10 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
             }
         }
         __syncthreads();
+        if constexpr (PREF) {
+#pragma unroll
+            for (int u = 0; u < LIT; ++u) v[u] = vn[u];
+        }
     }
 #pragma unroll
     for (int it = 0; it < OUT_IT; ++it) {
@@ -1272,11 +1304,17 @@ inline int pass2_rows(const NufftPlan& p, int cu_count, int nseries) {
     return M;
 }
 
+// Taper group of a pass-2 launch: with one row per workgroup and more than
+// four tapers, groups of four (half the LDS of eight, so more workgroups per
+// compute unit, and a second group whose loads overlap the first group's
+// FFTs); else the plan's.
+inline int pass2_group(const NufftPlan& p, int M, int maxK) { return M == 1 && maxK > 4 && p.KC > 4 ? 4 : p.KC; }
+
 template <typename R>
-int launch_pass2(const NufftPlan& p, hipStream_t st, int M, dim3 grid, const NuArgs& a,
+int launch_pass2(const NufftPlan& p, hipStream_t st, int M, int KC, dim3 grid, const NuArgs& a,
                  const NuSeries& d0, const NuSeries* D) {
 #define M2N_P2(N2V, MV, KCV)                                                               \
-    if (p.N2 == N2V && M == MV && p.KC == KCV) {                                           \
+    if (p.N2 == N2V && M == MV && KC == KCV) {                                             \
         hipLaunchKernelGGL((k_pass2<R, N2V, MV, KCV>), grid, dim3(NT2), 0, st, a, d0, D);  \
         return M2N_OK;                                                                     \
     }
@@ -1286,14 +1324,16 @@ int launch_pass2(const NufftPlan& p, hipStream_t st, int M, dim3 grid, const NuA
         M2N_P2(512, 1, 8) M2N_P2(512, 2, 8) M2N_P2(512, 4, 8)
         M2N_P2(1024, 1, 8) M2N_P2(1024, 2, 8)
         M2N_P2(2048, 1, 8) M2N_P2(4096, 1, 2)
+        M2N_P2(128, 1, 4) M2N_P2(256, 1, 4) M2N_P2(512, 1, 4) M2N_P2(1024, 1, 4) M2N_P2(2048, 1, 4)
     } else {
         M2N_P2(128, 1, 8) M2N_P2(128, 2, 8) M2N_P2(128, 4, 8)
         M2N_P2(256, 1, 8) M2N_P2(256, 2, 8) M2N_P2(256, 4, 8)
         M2N_P2(512, 1, 8) M2N_P2(512, 2, 8)
         M2N_P2(1024, 1, 8) M2N_P2(2048, 1, 2) M2N_P2(4096, 1, 1)
+        M2N_P2(128, 1, 4) M2N_P2(256, 1, 4) M2N_P2(512, 1, 4) M2N_P2(1024, 1, 4)
     }
 #undef M2N_P2
-    set_error("no pass-2 kernel for N2 = %d, M = %d, KC = %d", p.N2, M, p.KC);
+    set_error("no pass-2 kernel for N2 = %d, M = %d, KC = %d", p.N2, M, KC);
     return M2N_ERR_UNSUPPORTED;
 }
 
@@ -1459,7 +1499,7 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
     {
         M2N_PROF(ctx, st, "k_pass2");
         const int M = pass2_rows(p, ctx->cu_count, ns);
-        M2N_TRY(launch_pass2<R>(p, st, M, dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
+        M2N_TRY(launch_pass2<R>(p, st, M, pass2_group(p, M, q.maxK), dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
