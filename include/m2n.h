@@ -91,13 +91,17 @@ size_t m2n_workspace_bytes(const m2n_ctx *ctx);
  *                   sum_n (tbar - t_n) w_k(t_n) is positive, tbar = (t_1+t_N)/2
  *   lambda  [K]     device, FP64 out, descending, in [0, 1]
  *
- * The call first checks t on the device and waits for that check (one short
- * round trip; t is never copied to the host).  When R(B) is a multiple of
- * the identity (t on an integer lattice, 2 f_max a positive integer) the rest
- * is stream-ordered and the call returns before the tapers are complete;
- * otherwise (dense R(B), or the subspace-iteration fallback for wide bands)
- * it blocks until they are, since it reads back the Cholesky or convergence
- * status.  Errors: M2N_ERR_ARG (non-finite t), M2N_ERR_T_ORDER,
+ * The call checks t on the device (t is never copied to the host); the
+ * path depends on what the check finds (t on an integer lattice or not, t_1,
+ * t_N).  The first call on given t buffers (pointer and N) waits for the
+ * check; the context keeps its records, and later calls on the same buffers
+ * queue the tapers on them and compare them with the real check once all is
+ * queued, recomputing on a difference (as m2n_batch_psd).  When R(B) is a
+ * multiple of the identity (t on an integer lattice, 2 f_max a positive
+ * integer) the tapers are stream-ordered and the call returns before they
+ * are complete; otherwise (dense R(B), or the subspace-iteration fallback
+ * for wide bands) it blocks until they are, since it reads back the
+ * Cholesky or convergence status.  Errors: M2N_ERR_ARG (non-finite t), M2N_ERR_T_ORDER,
  * M2N_ERR_NOT_PD (Cholesky pivot <= 0; no silent regularisation),
  * M2N_ERR_NO_CONVERGE, M2N_ERR_UNSUPPORTED (dense N > 65536).
  */

@@ -189,3 +189,36 @@ def test_batch_check_records_reused_and_confirmed(m2n, ctx, name):
     ref = _run_on(m2n, c2, spec, prec)
     c2.close()
     _same_result(got, ref, "valid again after the error")
+
+
+def test_gpss_tapers_check_records_reused_and_confirmed(m2n, ctx):
+    # the per-series taper call follows the same scheme: in-place changes of
+    # t between calls give a fresh context's tapers bit for bit, and an
+    # invalid t is still reported
+    s = W.batched_series(5)
+    t0 = s.t.copy()
+    t = _dev(t0)
+    w = torch.empty((s.K, s.N), dtype=torch.float64, device="cuda")
+    lam = torch.empty((s.K,), dtype=torch.float64, device="cuda")
+    cases = [("same contents", t0), ("t shifted by 3", t0 + 3.0), ("same again", t0 + 3.0),
+             ("one sample off the integers (dense path)", t0 + np.where(np.arange(s.N) == 7, 0.25, 0.0)),
+             ("the first contents", t0)]
+    m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K, out=(w, lam))
+    for label, tv in cases:
+        t.copy_(torch.from_numpy(tv))
+        torch.cuda.synchronize()
+        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K, out=(w, lam))
+        torch.cuda.synchronize()
+        c2 = m2n.Context(0)
+        w2, lam2 = m2n.gpss_tapers(c2, t, s.fmax, s.fw, s.K)
+        torch.cuda.synchronize()
+        c2.close()
+        _say(f"case gpss_tapers: {label}")
+        assert torch.equal(w, w2) and torch.equal(lam, lam2), label
+    bad = t0.copy()
+    bad[[10, 11]] = bad[[11, 10]]
+    t.copy_(torch.from_numpy(bad))
+    torch.cuda.synchronize()
+    with pytest.raises(m2n.M2NError) as ei:
+        m2n.gpss_tapers(ctx, t, s.fmax, s.fw, s.K, out=(w, lam))
+    assert ei.value.code == m2n.M2N_ERR_T_ORDER
