@@ -1061,7 +1061,15 @@ def main():
                   "extra_ms": round(ms_nufft_f - ms_nufft, 5),
                   "note": "Thomson F-statistic fused into the band average (pass 2)"},
         "nufft_only": {"ms": round(ms_nufft, 5),
-                       "value": round(N * K * I / (ms_nufft * 1e-3) / 1e6, 1)},
+                       "value": round(N * K * I / (ms_nufft * 1e-3) / 1e6, 1),
+                       # bytes the NuFFT cannot avoid (read t, x and the K
+                       # tapers once, write P and Ehat once) over its time:
+                       # how far the two-pass grid round trip is from them
+                       "compulsory": {"bytes": N * (8 + 8 + 8 * K) + I * 2 * (4 if a.prec == "fp32" else 8),
+                                      "GB_per_s": round((N * (8 + 8 + 8 * K) + I * 2 * (4 if a.prec == "fp32" else 8))
+                                                        / (ms_nufft * 1e-3) / 1e9, 1),
+                                      "frac_of_8TBps": round((N * (8 + 8 + 8 * K) + I * 2 * (4 if a.prec == "fp32" else 8))
+                                                             / (ms_nufft * 1e-3) / 8e12, 5)}},
         "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "dominant_kernel": dom,
         "roofline": roofline,
