@@ -221,12 +221,11 @@ struct NuSeries {
     int* flags;    // [nwg]
     int* l0s;      // [N] binned first cells
     void* dels;    // [N] R offsets
-    void* cw;      // [K][N] cplx<R> tapered pre-phased samples, bin order
+    double* cx;    // [N][2] pre-phased samples x_n e^{-j 2 pi (f_lo + h df) t_n}, bin order
+    int* perm;     // [N] sample index n of each binned point
     void* inter;   // [K][nf] cplx<R> after pass 1
-    double* nrm;   // [nwg][K] partial sums of w_k^2 (for E)
-    double* norms; // [K] their totals
-    double* wsp;   // [nwg][K] partial sums of w_k (for F)
-    double* wsums; // [K] their totals, the tapers' DC gains W_k(0)
+    double* nrm;   // [nbins][K] pass 1's per-block shares of sum_n w_k^2 (for E)
+    double* wsp;   // [nbins][K] the same for sum_n w_k (for F)
     int* diag;     // [1] R(B) = 2 f_max I
     double* hrec;  // pinned host record of the t check, or NULL: [0] flags
                    // (bit 0 non-finite, bit 1 not increasing, bit 2 a t_n
@@ -407,13 +406,13 @@ __global__ __launch_bounds__(1024) void k_scan(NuArgs a, NuSeries d0, const NuSe
     }
 }
 
-// K1c: scatter the points into bin order, with the K tapered samples
-// cw[k][pos] = w_k(t_n) x_n e^{-j 2 pi (f_lo + h df) t_n} so that pass 1
-// reads its taper's values without a dependent gather.
-// SW: the batch asks for the F-statistic, so the sums of w_k are needed too
-// (a separate instance keeps their registers out of the common case)
-template <typename R, bool SW>
-__global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuSeries* D) {
+// K1c: scatter the points into bin order: first cell, offset, the
+// pre-phased sample x_n e^{-j 2 pi (f_lo + h df) t_n} in FP64 (pass 1 forms
+// each tapered value from it with one rounding) and the sample's index, by
+// which pass 1 gathers its taper's values.  Nothing here depends on the
+// tapers, so it runs with the binning, while they are still being computed.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_bin_geo(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     const int wg = blockIdx.x;
     if (wg >= d.nwg) return;
@@ -421,20 +420,7 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
     for (int b = threadIdx.x; b < a.nbins; b += NT) cur[b] = 0;
     __syncthreads();
     R* dels = (R*)d.dels;
-    cplx<R>* cw = (cplx<R>*)d.cw;
     const int64_t n0 = (int64_t)wg * d.ppw;
-    // with Ê or the F-statistic and at most KR tapers, this workgroup's
-    // shares of sum_n w_k(t_n)^2 and sum_n w_k(t_n) are accumulated while
-    // the tapers are read
-    constexpr int KR = 16;
-    constexpr int KW = SW ? KR : 1;
-    const bool need = d.E || d.F;
-    const bool fuse = need && d.K <= KR;
-    double sq[KR], sw[KW];
-#pragma unroll
-    for (int k = 0; k < KR; ++k) sq[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < KW; ++k) sw[k] = 0.0;
     for (int j = threadIdx.x; j < d.ppw; j += NT) {
         const int64_t n = n0 + j;
         if (n >= d.N) break;
@@ -443,69 +429,9 @@ __global__ __launch_bounds__(NT) void k_scatter(NuArgs a, NuSeries d0, const NuS
         const int pos = d.off[(int64_t)wg * a.nbins + bin] + atomicAdd(&cur[bin], 1);
         d.l0s[pos] = g.l0;
         dels[pos] = (R)g.del;
-        if (fuse) {
-#pragma unroll
-            for (int k = 0; k < KR; ++k) {
-                if (k < d.K) {
-                    const double wv = d.w[(int64_t)k * d.N + n];
-                    cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
-                    sq[k] += wv * wv;
-                    if constexpr (SW) sw[k] += wv;
-                }
-            }
-        } else {
-            for (int k = 0; k < d.K; ++k) {
-                const double wv = d.w[(int64_t)k * d.N + n];
-                cw[(int64_t)k * d.N + pos] = {(R)(g.cre * wv), (R)(g.cim * wv)};
-            }
-        }
-    }
-    if (fuse) {
-        // wavefront sums, then the wavefronts in order
-        __shared__ double redk[NT / 64][KR], redw[NT / 64][KR];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-        for (int k = 0; k < KR; ++k) {
-            if (k < d.K) {
-                const double v = wave_sum_to63(sq[k]);
-                if (lane == 63) redk[wv][k] = v;
-                if constexpr (SW) {
-                    const double u = wave_sum_to63(sw[k]);
-                    if (lane == 63) redw[wv][k] = u;
-                }
-            }
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < d.K) {
-            double v = 0.0, u = 0.0;
-#pragma unroll
-            for (int i = 0; i < NT / 64; ++i) {
-                v += redk[i][threadIdx.x];
-                if constexpr (SW) u += redw[i][threadIdx.x];
-            }
-            d.nrm[(int64_t)wg * d.K + threadIdx.x] = v;
-            if constexpr (SW) d.wsp[(int64_t)wg * d.K + threadIdx.x] = u;
-        }
-    } else if (need) {
-        // this workgroup's shares of sum_n w_k(t_n)^2 and sum_n w_k(t_n),
-        // summed in a fixed order
-        __shared__ double red[NT / 64];
-        for (int k = 0; k < d.K; ++k) {
-            double sq = 0.0, s1 = 0.0;
-            for (int j = threadIdx.x; j < d.ppw; j += NT) {
-                const int64_t n = n0 + j;
-                if (n >= d.N) break;
-                const double wv = d.w[(int64_t)k * d.N + n];
-                sq += wv * wv;
-                s1 += wv;
-            }
-            sq = block_sum(sq, red);
-            s1 = block_sum(s1, red);
-            if (threadIdx.x == 0) {
-                d.nrm[(int64_t)wg * d.K + k] = sq;
-                d.wsp[(int64_t)wg * d.K + k] = s1;
-            }
-        }
+        d.cx[2 * (int64_t)pos] = g.cre;
+        d.cx[2 * (int64_t)pos + 1] = g.cim;
+        d.perm[pos] = (int)n;
     }
 }
 
@@ -590,9 +516,27 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     if (threadIdx.x == 0) s_maxrow = -1;
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
+    typedef double D2 __attribute__((ext_vector_type(2)));
     const auto* dels = gp((const R*)d.dels);
-    const auto* cwk = gp((const cplx<R>*)d.cw + (int64_t)k * d.N);
+    const auto* cxs = gp((const D2*)d.cx);
+    const auto* perm = gp((const int*)d.perm);
+    const auto* wk = gp(d.w + (int64_t)k * d.N);
     const auto* l0s = gp((const int*)d.l0s);
+    // with E or the F-statistic: this block's shares of sum_n w_k(t_n)^2
+    // and sum_n w_k(t_n), over a contiguous range of samples (summed in a
+    // fixed order; pass 2 adds the blocks' shares)
+    const bool need = d.E || d.F;
+    double sq = 0.0, s1 = 0.0;
+    if (need) {
+        const int64_t per = (d.N + nblk - 1) / nblk;
+        const int64_t n0 = (int64_t)blk * per;
+        const int64_t n1 = n0 + per < d.N ? n0 + per : d.N;
+        for (int64_t n = n0 + threadIdx.x; n < n1; n += NT1) {
+            const double wv = wk[n];
+            sq += wv * wv;
+            s1 += wv;
+        }
+    }
     const auto* binoff = gp((const int*)d.binoff);
     // the points of bins blk - lookback .. blk, as one flat range of
     // segments so that every thread's loads are independent
@@ -649,21 +593,34 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     __syncthreads();   // rows[] is zero before the first count
     const int nchunks = (total + CAP - 1) / CAP;
     for (int ch = 0; ch < nchunks; ++ch) {
-        // this thread's points of the chunk: all loads first
-        int pl0[PPT];
+        // this thread's points of the chunk: all loads first, then the
+        // taper's values at the points' sample indices,
+        // c = (R)(x_n e^{-j 2 pi (f_lo + h df) t_n} w_k(t_n))
+        int pl0[PPT], pn[PPT];
         R pdel[PPT];
-        cplx<R> pcv[PPT];
+        D2 pcx[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const int f = ch * CAP + p * NT1 + threadIdx.x;
             pl0[p] = -1;
+            pn[p] = -1;
             pdel[p] = (R)0;
-            pcv[p] = {(R)0, (R)0};
+            pcx[p] = D2{0.0, 0.0};
             if (f < total) {
                 const int j = locate(f);
                 pl0[p] = l0s[j];
                 pdel[p] = dels[j];
-                pcv[p] = {cwk[j].x, cwk[j].y};
+                pcx[p] = cxs[j];
+                pn[p] = perm[j];
+            }
+        }
+        cplx<R> pcv[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            pcv[p] = {(R)0, (R)0};
+            if (pn[p] >= 0) {
+                const double wv = wk[pn[p]];
+                pcv[p] = {(R)(pcx[p].x * wv), (R)(pcx[p].y * wv)};
             }
         }
         // target row of each point and its slot in that row, packed as
@@ -751,25 +708,25 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     } else {
         for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     }
+    __shared__ double s_red[2][NT1 / 64];
+    if (need) {
+        sq = wave_sum_to63(sq);
+        s1 = wave_sum_to63(s1);
+        if (lane == 63) {
+            s_red[0][wv] = sq;
+            s_red[1][wv] = s1;
+        }
+    }
     __syncthreads();
-    if ((d.E || d.F) && blk == 0 && threadIdx.x < 64) {
-        // norms[k] and wsums[k] = the binning workgroups' partial sums of
-        // w_k^2 and of w_k, in order
-        const auto* nrm = gp((const double*)d.nrm);
-        const auto* wsp = gp((const double*)d.wsp);
-        double sq = 0.0, s1 = 0.0;
-        for (int g = threadIdx.x; g < d.nwg; g += 64) {
-            sq += nrm[(int64_t)g * d.K + k];
-            s1 += wsp[(int64_t)g * d.K + k];
+    if (need && threadIdx.x == 0) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT1 / 64; ++i) {
+            a0 += s_red[0][i];
+            a1 += s_red[1][i];
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            sq += __shfl_xor(sq, o, 64);
-            s1 += __shfl_xor(s1, o, 64);
-        }
-        if (threadIdx.x == 0) {
-            d.norms[k] = sq;
-            d.wsums[k] = s1;
-        }
+        d.nrm[(int64_t)blk * d.K + k] = a0;
+        d.wsp[(int64_t)blk * d.K + k] = a1;
     }
     fft_lds<R, N1, B, NT1, LD, PSH>(tile, tw, 1, pruned);
     // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, then
@@ -837,26 +794,6 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     cplx<R>* J = (cplx<R>*)d.J;
     R* Fo = (R*)d.F;
     for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
-    if (E && threadIdx.x < 64) {
-        // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I (lane k)
-        double e = 0.0;
-        const int k = threadIdx.x;
-        if (k < K) {
-            const double c = 2.0 * d.fmax;
-            e = fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * d.norms[k]));
-        }
-        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
-        if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
-    }
-    if (Fo && threadIdx.x < 64) {
-        // the tapers' DC gains W_k(0) and sum_k W_k(0)^2 (lane k)
-        const int k = threadIdx.x;
-        const double wk = k < K ? d.wsums[k] : 0.0;
-        s_wk[k] = (R)wk;
-        double ww = wk * wk;
-        for (int o = 32; o > 0; o >>= 1) ww += __shfl_xor(ww, o, 64);
-        if (threadIdx.x == 0) s_sww = (R)ww;
-    }
     // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
     if (npos > N2) npos = N2;
@@ -899,6 +836,49 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     constexpr int LITN = PREF ? LIT : 1;
     cplx<R> v[LIT], vn[LITN];
     if constexpr (PREF) load_group(0, v);
+    if (E || Fo) {
+        // |w_k|^2 and W_k(0) = sum_n w_k(t_n): pass 1's per-block shares
+        // summed in a fixed order (wavefront v takes tapers v, v + 8, ...),
+        // while the first rows are on their way
+        __shared__ double s_nrm[64], s_wsm[64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const auto* nrm = gp((const double*)d.nrm);
+        const auto* wsp = gp((const double*)d.wsp);
+        for (int k = wv; k < K; k += NT2 / 64) {
+            double sq = 0.0, s1 = 0.0;
+            for (int b = lane; b < a.nbins; b += 64) {
+                sq += nrm[(int64_t)b * K + k];
+                s1 += wsp[(int64_t)b * K + k];
+            }
+            sq = wave_sum_to63(sq);
+            s1 = wave_sum_to63(s1);
+            if (lane == 63) {
+                s_nrm[k] = sq;
+                s_wsm[k] = s1;
+            }
+        }
+        __syncthreads();
+        if (E && threadIdx.x < 64) {
+            // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I (lane k)
+            double e = 0.0;
+            const int k = threadIdx.x;
+            if (k < K) {
+                const double c = 2.0 * d.fmax;
+                e = fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * s_nrm[k]));
+            }
+            for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+            if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
+        }
+        if (Fo && threadIdx.x < 64) {
+            // the tapers' DC gains W_k(0) and sum_k W_k(0)^2 (lane k)
+            const int k = threadIdx.x;
+            const double wk = k < K ? s_wsm[k] : 0.0;
+            s_wk[k] = (R)wk;
+            double ww = wk * wk;
+            for (int o = 32; o > 0; o >>= 1) ww += __shfl_xor(ww, o, 64);
+            if (threadIdx.x == 0) s_sww = (R)ww;
+        }
+    }
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
         const int nk = K - kc0 < KC ? K - kc0 : KC;
         if constexpr (!PREF) load_group(kc0, v);
@@ -1425,12 +1405,11 @@ int begin_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* 
                 d.flags = (int*)c.take(sizeof(int) * (size_t)d.nwg);
                 d.l0s = (int*)c.take(sizeof(int) * N);
                 d.dels = c.take(sizeof(R) * N);
-                d.cw = c.take(sizeof(cplx<R>) * (size_t)d.K * N);
+                d.cx = (double*)c.take(2 * sizeof(double) * N);
+                d.perm = (int*)c.take(sizeof(int) * N);
                 d.inter = c.take(sizeof(cplx<R>) * (size_t)d.K * p.nf);
-                d.nrm = (double*)c.take(sizeof(double) * (size_t)d.nwg * d.K);
-                d.norms = (double*)c.take(sizeof(double) * (size_t)d.K);
-                d.wsp = (double*)c.take(sizeof(double) * (size_t)d.nwg * d.K);
-                d.wsums = (double*)c.take(sizeof(double) * (size_t)d.K);
+                d.nrm = (double*)c.take(sizeof(double) * (size_t)nbins * d.K);
+                d.wsp = (double*)c.take(sizeof(double) * (size_t)nbins * d.K);
                 d.diag = (int*)c.take(64);
             }
         };
@@ -1460,6 +1439,10 @@ int begin_typed(Ctx* ctx, hipStream_t st, const NufftPlan& p, const NuSeriesIn* 
         M2N_PROF(ctx, st, "k_scan");
         hipLaunchKernelGGL(k_scan, dim3(1, ys), dim3(1024), 0, st, q.a, d0, q.D);
     }
+    {
+        M2N_PROF(ctx, st, "k_bin_geo");
+        hipLaunchKernelGGL(k_bin_geo<R>, dim3((unsigned)maxwg, ys), dim3(NT), 0, st, q.a, d0, q.D);
+    }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
 }
@@ -1483,14 +1466,6 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
     }
     const int nbins = p.N2 / p.B;
     if (checked) M2N_HIP(hipEventRecord(checked, st));
-    {
-        M2N_PROF(ctx, st, "k_scatter");
-        bool anyF = false;
-        for (const NuSeries& d : q.ds) anyF = anyF || d.F != nullptr;
-        if (anyF) hipLaunchKernelGGL((k_scatter<R, true>), dim3((unsigned)q.maxwg, ys), dim3(NT), 0, st, q.a, d0, D);
-        else hipLaunchKernelGGL((k_scatter<R, false>), dim3((unsigned)q.maxwg, ys), dim3(NT), 0, st, q.a, d0, D);
-    }
-    M2N_HIP(hipGetLastError());
     {
         M2N_PROF(ctx, st, "k_pass1");
         M2N_TRY(launch_pass1<R>(p, st, dim3((unsigned)(q.maxK * nbins), ys), q.a, d0, D));

@@ -7,7 +7,7 @@ import bench
 
 
 def test_kernel_families():
-    for k in ("k_pass1", "k_pass2", "k_hist", "k_scan", "k_scatter"):
+    for k in ("k_pass1", "k_pass2", "k_hist", "k_scan", "k_bin_geo"):
         assert bench.kernel_sources(k) is bench.NUFFT_SOURCES, k
     for k in ("k_sym_topk", "k_gram_mfma", "k_lr_basis", "k_t_analyze", "k_syrk"):
         assert bench.kernel_sources(k) is bench.GEP_SOURCES, k
