@@ -685,19 +685,13 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
             __syncthreads();
         }
     }
-    // when every point lies in the first N1 / 8 rows, the first radix-8 FFT
-    // stage only replicates each row; store its output directly
-    const bool pruned = N1 >= 8 && s_maxrow < N1 / 8;
+    // when every point lies in the first N1 / 8 rows, only those rows are
+    // stored and the FFT skips its first stage (which would only repeat them)
+    const bool pruned = N1 >= 64 && s_maxrow < N1 / 8;
 #pragma unroll
     for (int u = 0; u < TASKS; ++u) {
         const int row = (u * (NT1 / 64) + wv) * G + rsub;
-        if (!pruned) {
-            tile[cb * LD + row] = acc[u];
-        } else if (row < N1 / 8) {
-            // the first stage's output, in the layout of the stages after it
-#pragma unroll
-            for (int q = 0; q < 8; ++q) tile[cb * LD + fft_pad(8 * row + q, N1 > 8 ? PSH : 0)] = acc[u];
-        }
+        if (!pruned || row < N1 / 8) tile[cb * LD + row] = acc[u];
     }
     if constexpr (TW_EARLY) {
 #pragma unroll
@@ -793,7 +787,15 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     R* E = (R*)d.E;
     cplx<R>* J = (cplx<R>*)d.J;
     R* Fo = (R*)d.F;
-    for (int j = threadIdx.x; j < N2; j += NT2) tw[j] = tw_g[j * a.tws2];
+    // the twiddle table is loaded now and stored to LDS once the first
+    // rows' loads are in flight too
+    constexpr int TWN = (N2 + NT2 - 1) / NT2;
+    cplx<R> twr[TWN];
+#pragma unroll
+    for (int q = 0; q < TWN; ++q) {
+        const int j = threadIdx.x + q * NT2;
+        twr[q] = j < N2 ? tw_g[j * a.tws2] : cplx<R>{(R)0, (R)0};
+    }
     // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
     int npos = (int)((I - h + N1 - 1) / N1);
     if (npos > N2) npos = N2;
@@ -836,6 +838,11 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
     constexpr int LITN = PREF ? LIT : 1;
     cplx<R> v[LIT], vn[LITN];
     if constexpr (PREF) load_group(0, v);
+#pragma unroll
+    for (int q = 0; q < TWN; ++q) {
+        const int j = threadIdx.x + q * NT2;
+        if (j < N2) tw[j] = twr[q];
+    }
     if (E || Fo) {
         // |w_k|^2 and W_k(0) = sum_n w_k(t_n): pass 1's per-block shares
         // summed in a fixed order (wavefront v takes tapers v, v + 8, ...),
@@ -941,6 +948,109 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
                 if (Fo) Fo[i] = f_statistic<R>(sjw[it], sjj[it], s_sww, K);
             }
         }
+    }
+}
+
+// Pass 2 with wavefront-private row transforms: a workgroup owns one row m1
+// and its eight wavefronts take the tapers in turn (wavefront v: tapers v,
+// v + 8, ...); each transforms its row alone (wave_fft: no workgroup
+// barrier between stages) and accumulates d_k |J_k|^2 for the 16 modes
+// l + 64 m its lane holds.  The wavefronts' sums are added in a fixed order
+// at the end.  Rows of N2 = 512 or 1024, P and E only (batches that ask for
+// the eigencoefficients or the F-statistic take the general kernel).
+template <typename R, int N2>
+__global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const NuSeries* D) {
+    const NuSeries d = series_of(d0, D);
+    using W = WavePlan<N2>;
+    using T = WaveTw<N2>;
+    constexpr int E = W::E, WLD = N2 + (N2 >> W::PSH), NW = NT2 / 64;
+    static_assert(NW * N2 * sizeof(R) <= NW * WLD * sizeof(cplx<R>), "sums fit the transform space");
+    __shared__ __attribute__((aligned(16))) cplx<R> wbuf[NW * WLD];
+    __shared__ cplx<R> twt[T::NB + T::NC];
+    __shared__ R s_eval;
+    const int K = d.K, N1 = a.N1, nf = a.nf;
+    const int64_t I = a.I, h = a.h;
+    // rows dealt to the 8 XCDs in contiguous ranges, as in k_pass2
+    int bid = blockIdx.x;
+    const int nwg = gridDim.x;
+    if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    const int m1 = bid;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    typedef R R2 __attribute__((ext_vector_type(2)));
+    const auto* inter = gp((const R2*)d.inter);
+    const cplx<R>* tw_g = (const cplx<R>*)a.tw;
+    const R* inv_phihat = (const R*)a.inv_phihat;
+    R* P = (R*)d.P;
+    R* Ep = (R*)d.E;
+    cplx<R> v[E];
+    auto load_row = [&](int k) {
+        const auto* src = inter + (int64_t)k * nf + (int64_t)m1 * N2 + lane;
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const R2 g = src[64 * t];
+            v[t] = {g.x, g.y};
+        }
+    };
+    if (wv < K) load_row(wv);
+    for (int e = threadIdx.x; e < T::NB + T::NC; e += NT2) twt[e] = tw_g[T::index(e) * a.tws2];
+    if (Ep) {
+        // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I: |w_k|^2 from pass 1's
+        // per-block shares, summed in a fixed order (wavefront v takes
+        // tapers v, v + 8, ...)
+        __shared__ double s_nrm[64];
+        const auto* nrm = gp((const double*)d.nrm);
+        for (int k = wv; k < K; k += NW) {
+            double sq = 0.0;
+            for (int b = lane; b < a.nbins; b += 64) sq += nrm[(int64_t)b * K + k];
+            sq = wave_sum_to63(sq);
+            if (lane == 63) s_nrm[k] = sq;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            double e = 0.0;
+            const int k = threadIdx.x;
+            if (k < K) {
+                const double c = 2.0 * d.fmax;
+                e = fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * s_nrm[k]));
+            }
+            for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+            if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
+        }
+    }
+    __syncthreads();   // twiddle table
+    // modes kept: m2 in [0, npos) (i' >= 0) and [m2neg0, N2) (i' < 0)
+    int npos = (int)((I - h + N1 - 1) / N1);
+    if (npos > N2) npos = N2;
+    int m2neg0 = (int)((nf - h) / N1);
+    if (m2neg0 < npos) m2neg0 = npos;
+    R acc[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[m] = (R)0;
+    cplx<R>* wb = wbuf + wv * WLD;
+    for (int k = wv; k < K; k += NW) {
+        if (k != wv) load_row(k);
+        wave_fft<R, N2>(v, wb, twt);
+        const R dd = d.dk ? (R)d.dk[k] : (R)1 / (R)K;
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[m] += dd * (v[m].x * v[m].x + v[m].y * v[m].y);
+    }
+    __syncthreads();   // every wavefront is done with its region
+    R* red = reinterpret_cast<R*>(wbuf);
+#pragma unroll
+    for (int m = 0; m < E; ++m) red[wv * N2 + lane + 64 * m] = acc[m];
+    __syncthreads();
+    for (int m2 = threadIdx.x; m2 < N2; m2 += NT2) {
+        if (!(m2 < npos || m2 >= m2neg0)) continue;
+        const int64_t mm = (int64_t)m1 + (int64_t)N1 * m2;
+        const int64_t kk = mm < nf / 2 ? mm : mm - nf;
+        const int64_t i = kk + h;
+        if (i < 0 || i >= I) continue;
+        R sum = (R)0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += red[w * N2 + m2];
+        const R sc = inv_phihat[kk < 0 ? -kk : kk];
+        if (P) P[i] = sum * (sc * sc);
+        if (Ep) Ep[i] = s_eval;
     }
 }
 
@@ -1474,7 +1584,19 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
     {
         M2N_PROF(ctx, st, "k_pass2");
         const int M = pass2_rows(p, ctx->cu_count, ns);
-        M2N_TRY(launch_pass2<R>(p, st, M, pass2_group(p, M, q.maxK), dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
+        bool anyJF = false;
+        for (const NuSeries& d : q.ds) anyJF = anyJF || d.F != nullptr || d.J != nullptr;
+        bool wave_rows = false;
+        if constexpr (sizeof(R) == 4) {
+            // one row per workgroup, P and E only: wavefront-private row FFTs
+            if (M == 1 && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
+                wave_rows = true;
+                if (p.N2 == 1024) hipLaunchKernelGGL((k_pass2w<R, 1024>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
+                else hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
+            }
+        }
+        if (!wave_rows)
+            M2N_TRY(launch_pass2<R>(p, st, M, pass2_group(p, M, q.maxK), dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
     }
     M2N_HIP(hipGetLastError());
     return M2N_OK;
