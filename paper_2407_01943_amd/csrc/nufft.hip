@@ -507,13 +507,17 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     __shared__ int rows[N1 + 1];
     __shared__ int wtot[NT1 / 64];
     __shared__ int s_maxrow;   // largest tile row any point reaches
+    __shared__ int s_maxrot;   // the same after the rotation by one row
     __shared__ cplx<R> tw[N1];
     SpreadRec<R>* list = reinterpret_cast<SpreadRec<R>*>(tile);
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
     for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
-    if (threadIdx.x == 0) s_maxrow = -1;
+    if (threadIdx.x == 0) {
+        s_maxrow = -1;
+        s_maxrot = -1;
+    }
     const R two_over_w = (R)2 / (R)w;
     const R beta = (R)a.beta;
     typedef double D2 __attribute__((ext_vector_type(2)));
@@ -627,7 +631,7 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         // slot << 16 | row << 6 | (s + 16)  (slot < 2048, row < 1024,
         // -16 < s < 32), -1 for a point that reaches no column of the block
         int pk[PPT];
-        int mr = -1;
+        int mr = -1, mrot = -1;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             pk[p] = -1;
@@ -643,11 +647,18 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
                     const int slot = atomicAdd(&rows[row], 1);
                     pk[p] = (slot << 16) | (row << 6) | (sc + 16);
                     mr = max(mr, row);
+                    mrot = max(mrot, (row + 1) & (N1 - 1));
                 }
             }
         }
-        for (int o = 32; o > 0; o >>= 1) mr = max(mr, __shfl_xor(mr, o, 64));
-        if (lane == 0 && mr >= 0) atomicMax(&s_maxrow, mr);   // one LDS atomic per wavefront
+        for (int o = 32; o > 0; o >>= 1) {
+            mr = max(mr, __shfl_xor(mr, o, 64));
+            mrot = max(mrot, __shfl_xor(mrot, o, 64));
+        }
+        if (lane == 0 && mr >= 0) {   // one LDS atomic per wavefront
+            atomicMax(&s_maxrow, mr);
+            atomicMax(&s_maxrot, mrot);
+        }
         __syncthreads();
         scan_counts<N1>(rows, wtot);
 #pragma unroll
@@ -685,12 +696,16 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
             __syncthreads();
         }
     }
-    // when every point lies in the first N1 / 8 rows, only those rows are
-    // stored and the FFT skips its first stage (which would only repeat them)
-    const bool pruned = N1 >= 64 && s_maxrow < N1 / 8;
+    // Each column enters its FFT rotated by one row (row r at r + 1 mod N1):
+    // points whose support wraps below cell 0 reach the last row, which the
+    // rotation brings next to the first ones.  The FFT then carries a factor
+    // exp(-2 pi i m1 / N1), undone in the four-step twiddle below.  When every
+    // rotated row lies in the first N1 / 8, only those are stored and the FFT
+    // skips its first stage (which would only repeat them).
+    const bool pruned = N1 >= 64 && s_maxrot < N1 / 8;
 #pragma unroll
     for (int u = 0; u < TASKS; ++u) {
-        const int row = (u * (NT1 / 64) + wv) * G + rsub;
+        const int row = ((u * (NT1 / 64) + wv) * G + rsub + 1) & (N1 - 1);
         if (!pruned || row < N1 / 8) tile[cb * LD + row] = acc[u];
     }
     if constexpr (TW_EARLY) {
@@ -723,19 +738,22 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         d.wsp[(int64_t)blk * d.K + k] = a1;
     }
     fft_lds<R, N1, B, NT1, LD, PSH>(tile, tw, 1, pruned);
-    // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, then
-    // G[k][m1][l2].  A thread keeps one column cb and steps m1 by S = NT1 / B,
-    // so its twiddle advances by the fixed factor exp(-2 pi i c S / nf): two
-    // sine-cosine pairs per thread and a complex product per element, all in
-    // FP64 (the product chain adds about IT ulps)
+    // four-step twiddle exp(-2 pi i c m1 / nf), c = c0 + cb, times
+    // exp(2 pi i m1 / N1) for the rotation: exp(-2 pi i (c - N2) m1 / nf),
+    // then G[k][m1][l2].  A thread keeps one column cb and steps m1 by
+    // S = NT1 / B, so its twiddle advances by the fixed factor
+    // exp(-2 pi i (c - N2) S / nf): two sine-cosine pairs per thread and a
+    // complex product per element, all in FP64 (the product chain adds about
+    // IT ulps)
     cplx<R>* out = (cplx<R>*)d.inter + (int64_t)k * nf;
     {
         constexpr int S = NT1 / B, IT = B * N1 / NT1;
         const int cb = threadIdx.x % B, m0 = threadIdx.x / B;
         const int c = c0 + cb;
+        const int cr = c + nf - N2;   // c - N2 modulo nf
         const double two_nf = 2.0 / (double)nf;
-        const double xt = (double)((c * m0) & (nf - 1)) * two_nf;
-        const double xr = (double)((c * S) & (nf - 1)) * two_nf;
+        const double xt = (double)((cr * m0) & (nf - 1)) * two_nf;
+        const double xr = (double)((cr * S) & (nf - 1)) * two_nf;
         double tr = cospi(xt), ti = -sinpi(xt);
         const double fr = cospi(xr), fi = -sinpi(xr);
 #pragma unroll 4
@@ -978,7 +996,7 @@ __global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     typedef R R2 __attribute__((ext_vector_type(2)));
     const auto* inter = gp((const R2*)d.inter);
-    const cplx<R>* tw_g = (const cplx<R>*)a.tw;
+    const auto* tw_g = gp((const R2*)a.tw);
     const R* inv_phihat = (const R*)a.inv_phihat;
     R* P = (R*)d.P;
     R* Ep = (R*)d.E;
@@ -991,19 +1009,48 @@ __global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const 
             v[t] = {g.x, g.y};
         }
     };
-    if (wv < K) load_row(wv);
-    for (int e = threadIdx.x; e < T::NB + T::NC; e += NT2) twt[e] = tw_g[T::index(e) * a.tws2];
+    // Every load is issued up front, branch-free (a clamped index or a valid
+    // stand-in address), in the order the values are needed: loads return in
+    // issue order, so the twiddle table and E can be finished while the row
+    // is still on its way.  Pass 1's shares of |w_k|^2 are preloaded when
+    // each wavefront has one taper and there are at most 128 blocks.
+    const auto* nrm = gp((const double*)d.nrm);
+    const bool pre = K <= NW && a.nbins <= 128;
+    const int kw = wv < K ? wv : K - 1;
+    const double nq0 = nrm[(int64_t)(lane < a.nbins ? lane : 0) * K + kw];
+    const double nq1 = nrm[(int64_t)(lane + 64 < a.nbins ? lane + 64 : 0) * K + kw];
+    const double lam = gp(d.lambda ? d.lambda : (const double*)d.nrm)[lane < K ? lane : 0];
+    const int diag = gp((const int*)d.diag)[0];
+    const double dkv = gp(d.dk ? d.dk : (const double*)d.nrm)[kw];
+    constexpr int TWR = (T::NB + T::NC + NT2 - 1) / NT2;
+    cplx<R> twr[TWR];
+#pragma unroll
+    for (int q = 0; q < TWR; ++q) {
+        const int e = threadIdx.x + q * NT2;
+        const R2 g = tw_g[T::index(e < T::NB + T::NC ? e : 0) * a.tws2];
+        twr[q] = {g.x, g.y};
+    }
+    load_row(kw);
+#pragma unroll
+    for (int q = 0; q < TWR; ++q) {
+        const int e = threadIdx.x + q * NT2;
+        if (e < T::NB + T::NC) twt[e] = twr[q];
+    }
     if (Ep) {
         // D_k = 2 f_max |w_k|^2 when R(B) = 2 f_max I: |w_k|^2 from pass 1's
         // per-block shares, summed in a fixed order (wavefront v takes
         // tapers v, v + 8, ...)
         __shared__ double s_nrm[64];
-        const auto* nrm = gp((const double*)d.nrm);
-        for (int k = wv; k < K; k += NW) {
-            double sq = 0.0;
-            for (int b = lane; b < a.nbins; b += 64) sq += nrm[(int64_t)b * K + k];
-            sq = wave_sum_to63(sq);
-            if (lane == 63) s_nrm[k] = sq;
+        if (pre) {
+            const double sq = wave_sum_to63((lane < a.nbins ? nq0 : 0.0) + (lane + 64 < a.nbins ? nq1 : 0.0));
+            if (lane == 63 && wv < K) s_nrm[wv] = sq;
+        } else {
+            for (int k = wv; k < K; k += NW) {
+                double sq = 0.0;
+                for (int b = lane; b < a.nbins; b += 64) sq += nrm[(int64_t)b * K + k];
+                sq = wave_sum_to63(sq);
+                if (lane == 63) s_nrm[k] = sq;
+            }
         }
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -1011,10 +1058,10 @@ __global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const 
             const int k = threadIdx.x;
             if (k < K) {
                 const double c = 2.0 * d.fmax;
-                e = fabs(d.lambda[k] - 2.0 * d.fw * d.lambda[k] / (c * s_nrm[k]));
+                e = fabs(lam - 2.0 * d.fw * lam / (c * s_nrm[k]));
             }
             for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
-            if (threadIdx.x == 0) s_eval = d.diag[0] ? (R)(e / (double)K) : (R)NAN;
+            if (threadIdx.x == 0) s_eval = diag ? (R)(e / (double)K) : (R)NAN;
         }
     }
     __syncthreads();   // twiddle table
@@ -1030,7 +1077,7 @@ __global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const 
     for (int k = wv; k < K; k += NW) {
         if (k != wv) load_row(k);
         wave_fft<R, N2>(v, wb, twt);
-        const R dd = d.dk ? (R)d.dk[k] : (R)1 / (R)K;
+        const R dd = d.dk ? (R)(k == wv ? dkv : d.dk[k]) : (R)1 / (R)K;
 #pragma unroll
         for (int m = 0; m < E; ++m) acc[m] += dd * (v[m].x * v[m].x + v[m].y * v[m].y);
     }
