@@ -513,6 +513,8 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     const int N2 = a.N2, log_N2 = a.log_N2, nf = a.nf, w = a.w;
     const int c0 = blk * B;
     const cplx<R>* tw_g = (const cplx<R>*)a.tw;
+    typedef R R2 __attribute__((ext_vector_type(2)));
+    const auto* tw_gv = gp((const R2*)a.tw);
     for (int e = threadIdx.x; e <= N1; e += NT1) rows[e] = 0;
     if (threadIdx.x == 0) {
         s_maxrow = -1;
@@ -526,38 +528,57 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
     const auto* perm = gp((const int*)d.perm);
     const auto* wk = gp(d.w + (int64_t)k * d.N);
     const auto* l0s = gp((const int*)d.l0s);
+    // The first loads go out together, branch-free (clamped indices), in the
+    // order their values are needed, since they return in issue order: the
+    // bin bounds of the window, the FFT twiddles (FP32), and this thread's
+    // first two taper values for the sums below.
+    // The points of bins blk - lookback .. blk form one flat range of
+    // segments, so that every thread's point loads are independent
+    // (lookback + 1 <= MAXSEG is checked when the plan is built).
+    // (one load per lane: lane q < MAXSEG the start of segment q, lane
+    // MAXSEG + q its end; segments past the lookback repeat the last one)
+    const auto* binoff = gp((const int*)d.binoff);
+    static_assert(2 * MAXSEG <= 64, "segment bounds in one wavefront load");
+    int bv;
+    {
+        const int ln = threadIdx.x & 63;
+        const int lq = ln < MAXSEG ? ln : (ln < 2 * MAXSEG ? ln - MAXSEG : 0);
+        int bb = blk - (lq <= a.lookback ? lq : a.lookback);
+        if (bb < 0) bb += nblk;
+        bv = binoff[bb + (ln >= MAXSEG && ln < 2 * MAXSEG ? 1 : 0)];
+    }
+    // FP32: the length-N1 FFT twiddles are fetched now and stored to LDS
+    // after the spread, so that their latency overlaps the point loads (in
+    // FP64 the registers held across the spread cost more than they save)
+    constexpr bool TW_EARLY = sizeof(R) == 4;
+    constexpr int TWP = (N1 + NT1 - 1) / NT1;
+    cplx<R> twp[TWP];
+    if constexpr (TW_EARLY) {
+#pragma unroll
+        for (int q = 0; q < TWP; ++q) {
+            const int j = threadIdx.x + q * NT1;
+            const R2 g = tw_gv[(j < N1 ? j : 0) * a.tws1];
+            twp[q] = {g.x, g.y};
+        }
+    }
     // with E or the F-statistic: this block's shares of sum_n w_k(t_n)^2
     // and sum_n w_k(t_n), over a contiguous range of samples (summed in a
     // fixed order; pass 2 adds the blocks' shares)
     const bool need = d.E || d.F;
-    double sq = 0.0, s1 = 0.0;
-    if (need) {
-        const int64_t per = (d.N + nblk - 1) / nblk;
-        const int64_t n0 = (int64_t)blk * per;
-        const int64_t n1 = n0 + per < d.N ? n0 + per : d.N;
-        for (int64_t n = n0 + threadIdx.x; n < n1; n += NT1) {
-            const double wv = wk[n];
-            sq += wv * wv;
-            s1 += wv;
-        }
-    }
-    const auto* binoff = gp((const int*)d.binoff);
-    // the points of bins blk - lookback .. blk, as one flat range of
-    // segments so that every thread's loads are independent
-    // (lookback + 1 <= MAXSEG is checked when the plan is built)
+    const int64_t per = (d.N + nblk - 1) / nblk;
+    const int64_t n0 = (int64_t)blk * per;
+    const int64_t n1 = n0 + per < d.N ? n0 + per : d.N;
+    const int64_t na = n0 + threadIdx.x, nb = na + NT1;
+    const double wa = wk[na < d.N ? na : d.N - 1];
+    const double wb = wk[nb < d.N ? nb : d.N - 1];
+    // the bounds are uniform: kept in scalar registers
     int sb[MAXSEG], sl[MAXSEG];
     int total = 0;
 #pragma unroll
     for (int q = 0; q < MAXSEG; ++q) {
-        sb[q] = 0;
-        sl[q] = 0;
-        if (q <= a.lookback) {
-            int bb = blk - q;
-            if (bb < 0) bb += nblk;
-            sb[q] = binoff[bb];
-            sl[q] = binoff[bb + 1] - sb[q];
-            total += sl[q];
-        }
+        sb[q] = __builtin_amdgcn_readlane(bv, q);
+        sl[q] = q <= a.lookback ? __builtin_amdgcn_readlane(bv, MAXSEG + q) - sb[q] : 0;
+        total += sl[q];
     }
     auto locate = [&](int f) {
         int j = -1, r0 = f;
@@ -570,19 +591,6 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         }
         return j;
     };
-    // FP32: the length-N1 FFT twiddles are fetched now and stored to LDS
-    // after the spread, so that their latency overlaps the point loads (in
-    // FP64 the registers held across the spread cost more than they save)
-    constexpr bool TW_EARLY = sizeof(R) == 4;
-    constexpr int TWP = (N1 + NT1 - 1) / NT1;
-    cplx<R> twp[TWP];
-    if constexpr (TW_EARLY) {
-#pragma unroll
-        for (int q = 0; q < TWP; ++q) {
-            const int j = threadIdx.x + q * NT1;
-            twp[q] = j < N1 ? tw_g[j * a.tws1] : cplx<R>{(R)0, (R)0};
-        }
-    }
     // Owner-computes spreading, chunk by chunk (one chunk holds CAP points,
     // normally the whole window): each chunk's points are counting-sorted by
     // the tile row they reach (integer LDS atomics), then every thread sums,
@@ -718,7 +726,21 @@ __global__ __launch_bounds__(NT1, sizeof(R) == 4 ? (N1 <= 512 ? 4 : 2) : 1) void
         for (int j = threadIdx.x; j < N1; j += NT1) tw[j] = tw_g[j * a.tws1];
     }
     __shared__ double s_red[2][NT1 / 64];
+    double sq = 0.0, s1 = 0.0;
     if (need) {
+        if (na < n1) {
+            sq += wa * wa;
+            s1 += wa;
+        }
+        if (nb < n1) {
+            sq += wb * wb;
+            s1 += wb;
+        }
+        for (int64_t n = nb + NT1; n < n1; n += NT1) {
+            const double wv = wk[n];
+            sq += wv * wv;
+            s1 += wv;
+        }
         sq = wave_sum_to63(sq);
         s1 = wave_sum_to63(s1);
         if (lane == 63) {
