@@ -98,6 +98,39 @@ def test_nufft_large_grid_sampled(m2n, ctx, orc, prec, tol):
     assert eJ < tol and eP < tol
 
 
+@pytest.mark.parametrize("I,K,weighted", [(2 ** 16, 5, False), (2 ** 17, 9, True), (2 ** 18, 7, False)])
+def test_psd_only_wavefront_rows(m2n, ctx, orc, I, K, weighted):
+    # P and E without J or F in FP32: rows of 512 (I = 2^16, 2^17) or 1024
+    # (I = 2^18) take the pass-2 form with one wavefront per taper row; with
+    # K = 9 a wavefront takes two tapers (and their weights).  P against the
+    # oracle's direct NUDFT on sampled bands (both ends, uniform draws, the
+    # largest-P bands); E, band-constant on a lattice, against the oracle's
+    # Ehat for tapers and lambda that do not solve the GEP, so that it is not
+    # zero and every taper's norm enters it.
+    s = W.gapped_scaled(12000, K, I, seed=37)
+    rng = np.random.default_rng(106)
+    w = rng.standard_normal((K, s.N)) * 0.02
+    lam = rng.uniform(0.5, 1.0, K)
+    d = rng.uniform(0.5, 1.5, K) / K if weighted else None
+    _say(f"case psd-only N={s.N} K={K} I={I} weighted={weighted}")
+    out = m2n.m2nufft_psd(ctx, _dev(s.t), _dev(s.x), _dev(w), _dev(lam), s.fmax, s.fw, s.f_lo,
+                          s.df, s.I, prec=1, weights=None if d is None else _dev(d), want_E=True,
+                          want_J=False)
+    P = out["P"].cpu().numpy().astype(np.float64)
+    E = out["E"].cpu().numpy().astype(np.float64)
+    bands = np.unique(np.concatenate([np.arange(0, 32), np.arange(s.I - 32, s.I),
+                                      np.random.default_rng(8).integers(0, s.I, 2048),
+                                      np.argsort(P)[-128:]]))
+    ref_P = orc.psd(orc.nudft(s.t, s.x, w, s.f_lo, s.df, bands=bands), weights=d)
+    eP = psd_err(P[bands], ref_P)
+    eb = bands[[0, 1, len(bands) // 2, -1]]
+    E_ref, _ = orc.ehat(s.t, w, lam, s.fmax, s.fw, s.f_lo, s.df, bands=eb)
+    eE = float(np.abs(E[eb] - E_ref).max() / np.abs(E_ref).max())
+    _say(f"  P sampled {eP:.3e}  E {eE:.3e} (E_ref {E_ref[0]:.4e})")
+    assert eP < 1e-5 and eE < 1e-6
+    assert np.all(E == E[0])
+
+
 def test_ehat_two_pass_lattice(m2n, ctx, orc):
     # Ehat through the two-pass path on a lattice (R(B) = I): identically ~0
     s = W.gapped_scaled(3000, 5, 2 ** 14, seed=36)
