@@ -157,8 +157,8 @@ def profile_summary(a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="gapped_20k",
                     choices=["gapped_20k", "gapped_82k", "small_gapped"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
