@@ -1657,8 +1657,9 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
         for (const NuSeries& d : q.ds) anyJF = anyJF || d.F != nullptr || d.J != nullptr;
         bool wave_rows = false;
         if constexpr (sizeof(R) == 4) {
-            // one row per workgroup, P and E only: wavefront-private row FFTs
-            if (M == 1 && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
+            // P and E only, rows of 512 or 1024: wavefront-private row FFTs,
+            // one row per workgroup (unless a tuned schedule fixed the rows)
+            if ((M == 1 || p.M_force == 0) && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
                 wave_rows = true;
                 if (p.N2 == 1024) hipLaunchKernelGGL((k_pass2w<R, 1024>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
                 else hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
