@@ -559,19 +559,26 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
     if (!ctx->side_fork) M2N_HIP(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming));
     if (!ctx->side_join) M2N_HIP(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming));
     M2N_HIP(hipEventRecord(ctx->side_fork, st));
-    M2N_HIP(hipStreamWaitEvent(side, ctx->side_fork, 0));
-    GepCheck* chk = nullptr;
-    M2N_TRY(gep_check_begin(ctx, side, g.data(), nseries, &chk));
-    std::unique_ptr<GepCheck, void (*)(GepCheck*)> chk_own(chk, gep_check_free);
+    // with the records of the last check on the same t buffers, the tapers go
+    // on the stream first (they need nothing from the side stream), then the
+    // check and the binning beside them
+    std::unique_ptr<GepCheck, void (*)(GepCheck*)> chk_own(gep_check_new(), gep_check_free);
+    GepCheck* chk = chk_own.get();
     const bool guessed = gep_check_guess(ctx, chk, g.data(), nseries);
+    if (guessed) M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
+    M2N_HIP(hipStreamWaitEvent(side, ctx->side_fork, 0));
+    M2N_TRY(gep_check_launch(ctx, side, chk, g.data(), nseries));
     std::vector<NuSeriesIn> first = ins_of(groups.begin()->second);
     NuPending* pend = nullptr;
     M2N_TRY(nufft_begin(ctx, side, groups.begin()->first, prec, nufft_tol, first.data(), (int)first.size(), &pend));
     std::unique_ptr<NuPending, void (*)(NuPending*)> pend_own(pend, nufft_pending_free);
     M2N_HIP(hipEventRecord(ctx->side_join, side));
-    if (!guessed) M2N_TRY(gep_check_wait(ctx, chk, g.data(), nseries));
-    auto rest = [&](bool first_pending) -> int {
+    if (!guessed) {
+        M2N_TRY(gep_check_wait(ctx, chk, g.data(), nseries));
         M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
+    }
+    // the NuFFT (its first band count's binning already queued) and Ehat
+    auto rest = [&](bool first_pending) -> int {
         M2N_HIP(hipStreamWaitEvent(st, ctx->side_join, 0));
         for (auto it = groups.begin(); it != groups.end(); ++it) {
             const int64_t I = it->first;
@@ -599,7 +606,12 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
     if (guessed) {
         bool same = true;
         M2N_TRY(gep_check_confirm(ctx, chk, g.data(), nseries, &same));
-        if (!same) M2N_TRY(rest(false));
+        if (!same) {
+            // the guess was wrong: the tapers and the NuFFT again on the real
+            // records
+            M2N_TRY(gep_run_checked(ctx, st, g.data(), nseries, chk));
+            M2N_TRY(rest(false));
+        }
     }
     return M2N_OK;
 }

@@ -194,6 +194,10 @@ int gep_run_batch(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries);
 // not an integer), t_1 and t_N.
 struct GepCheck;
 int gep_check_begin(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, GepCheck** out);
+// the two halves of gep_check_begin: an empty check (for gep_check_guess
+// before anything is queued), then the check queued on st
+GepCheck* gep_check_new();
+int gep_check_launch(Ctx* ctx, hipStream_t st, GepCheck* c, const GepIn* in, int nseries);
 int gep_check_wait(Ctx* ctx, GepCheck* c, const GepIn* in, int nseries);
 int gep_run_checked(Ctx* ctx, hipStream_t st, const GepIn* in, int nseries, const GepCheck* c);
 void gep_check_info(const GepCheck* c, int i, int* flags, double* t0, double* tN);
