@@ -14,14 +14,19 @@
 // a length-nf FFT, and division by the kernel's Fourier transform phihat(i').
 //
 // Grid layout for nf = N1 * N2 (two passes): cell l = l2 + N2 l1.
-//   pass 1: a workgroup owns B consecutive columns l2 of one taper, spreads the
-//           points that reach them into an LDS tile, runs the N1-point column
-//           FFTs, multiplies by exp(-2 pi i l2 m1 / nf) and writes G[k][m1][l2].
+//   pass 1: a workgroup owns B consecutive columns l2 of one taper, gathers the
+//           taper's values of the points that reach them by sample index,
+//           spreads them into an LDS tile, runs the N1-point column FFTs,
+//           multiplies by exp(-2 pi i l2 m1 / nf) and writes G[k][m1][l2].
 //   pass 2: a workgroup owns M consecutive rows m1, loops over the tapers,
 //           runs the N2-point row FFTs (mode m = m1 + N1 m2), deconvolves,
-//           keeps the I wanted modes and accumulates P (and J, E) in registers.
+//           keeps the I wanted modes and accumulates P (and J, E) in registers;
+//           for P and E alone on rows of 512 or 1024 (FP32), one wavefront
+//           transforms each taper's row by itself (k_pass2w).
 // Points are binned by the column block of their first cell (counting sort:
-// per-workgroup histograms, one scan, scatter) so pass 1 reads contiguous runs.
+// per-workgroup histograms, one scan, then the binned geometry with each
+// point's sample index), so pass 1 reads contiguous runs.  The binning needs
+// only t and x and can run before the tapers exist.
 // Small grids (nf <= 8192 FP32 / 4096 FP64) run the whole transform in one
 // workgroup's LDS.
 //
