@@ -922,7 +922,7 @@ def main():
     plan = {"nf": nf}
     pb = 4 if prec == m2n.M2N_FP32 else 8
     # roofline of the dominant kernel.  The lattice GEP's eigen-solver
-    # (k_sym_topk: one wavefront on the Q x Q quadrature Gram matrix) is
+    # (k_sym_topk: one workgroup on the Q x Q quadrature Gram matrix) is
     # FP64 ALU work priced against the chip's FP64 vector peak, with the
     # textbook flop count of a dense symmetric top-K eigenproblem
     # (Householder tridiagonalisation 4/3 Q^3 plus the back-transformation
@@ -942,7 +942,7 @@ def main():
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(ach / FP64_PEAK_TFLOPS, 8), "traffic": measured_traffic(name),
                     "algorithmic_flops": fl, "Q": Q, "avg_ms": round(avg, 5), "launches": cnt_k,
-                    "note": "one wavefront (1 of 1024 SIMDs): latency of the serial eigen-solve"}
+                    "note": "one workgroup of four wavefronts (4 of 1024 SIMDs): latency of the serial eigen-solve"}
         byts = algorithmic_bytes(name, s, N, K, I, plan, pb)
         ach = byts / (avg * 1e-3) / 1e9
         tr = measured_traffic(name)
