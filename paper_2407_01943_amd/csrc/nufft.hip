@@ -21,7 +21,7 @@
 //   pass 2: a workgroup owns M consecutive rows m1, loops over the tapers,
 //           runs the N2-point row FFTs (mode m = m1 + N1 m2), deconvolves,
 //           keeps the I wanted modes and accumulates P (and J, E) in registers;
-//           for P and E alone on rows of 512 or 1024 (FP32), one wavefront
+//           for P and E alone on rows of 512 or 1024, one wavefront
 //           transforms each taper's row by itself (k_pass2w).
 // Points are binned by the column block of their first cell (counting sort:
 // per-workgroup histograms, one scan, then the binned geometry with each
@@ -1002,9 +1002,10 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
 // barrier between stages) and accumulates d_k |J_k|^2 for the 16 modes
 // l + 64 m its lane holds.  The wavefronts' sums are added in a fixed order
 // at the end.  Rows of N2 = 512 or 1024, P and E only (batches that ask for
-// the eigencoefficients or the F-statistic take the general kernel).
+// the eigencoefficients or the F-statistic take the general kernel); FP32
+// with four waves per SIMD, FP64 with two (156 KB of LDS at N2 = 1024).
 template <typename R, int N2>
-__global__ __launch_bounds__(NT2, 4) void k_pass2w(NuArgs a, NuSeries d0, const NuSeries* D) {
+__global__ __launch_bounds__(NT2, sizeof(R) == 4 ? 4 : 2) void k_pass2w(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     using W = WavePlan<N2>;
     using T = WaveTw<N2>;
@@ -1661,14 +1662,12 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
         bool anyJF = false;
         for (const NuSeries& d : q.ds) anyJF = anyJF || d.F != nullptr || d.J != nullptr;
         bool wave_rows = false;
-        if constexpr (sizeof(R) == 4) {
-            // P and E only, rows of 512 or 1024: wavefront-private row FFTs,
-            // one row per workgroup (unless a tuned schedule fixed the rows)
-            if ((M == 1 || p.M_force == 0) && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
-                wave_rows = true;
-                if (p.N2 == 1024) hipLaunchKernelGGL((k_pass2w<R, 1024>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
-                else hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
-            }
+        // P and E only, rows of 512 or 1024: wavefront-private row FFTs, one
+        // row per workgroup (unless a tuned schedule fixed the rows)
+        if ((M == 1 || p.M_force == 0) && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
+            wave_rows = true;
+            if (p.N2 == 1024) hipLaunchKernelGGL((k_pass2w<R, 1024>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
+            else hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
         }
         if (!wave_rows)
             M2N_TRY(launch_pass2<R>(p, st, M, pass2_group(p, M, q.maxK), dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));
