@@ -209,9 +209,37 @@ __device__ __forceinline__ void dft16(cplx<R>* u) {
     }
 }
 
+// forward radix-32 butterfly in place: length-16 DFTs of the even and odd
+// inputs, combined with w32^k = (cos(pi k / 16), -sin(pi k / 16))
+template <typename R>
+__device__ __forceinline__ void dft32(cplx<R>* u) {
+    cplx<R> e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        e[i] = u[2 * i];
+        o[i] = u[2 * i + 1];
+    }
+    dft16(e);
+    dft16(o);
+    // cos(pi k / 16), k = 0 .. 8
+    const R c[9] = {(R)1.0, (R)0.98078528040323044913, (R)0.92387953251128675613, (R)0.83146961230254523708,
+                    (R)0.70710678118654752440, (R)0.55557023301960222474, (R)0.38268343236508977173,
+                    (R)0.19509032201612826785, (R)0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        // w32^k = cos(pi k / 16) - i sin(pi k / 16); sin(pi k / 16) = cos(pi (8 - k) / 16)
+        const R cr = k <= 8 ? c[k] : -c[16 - k];
+        const R si = k <= 8 ? c[8 - k] : c[k - 8];
+        const cplx<R> t = k == 0 ? o[0] : cmul(o[k], cplx<R>{cr, -si});
+        u[k] = cadd(e[k], t);
+        u[k + 16] = csub(e[k], t);
+    }
+}
+
 template <typename R, int RAD>
 __device__ __forceinline__ void dft_r(cplx<R>* u) {
-    if constexpr (RAD == 16) dft16(u);
+    if constexpr (RAD == 32) dft32(u);
+    else if constexpr (RAD == 16) dft16(u);
     else if constexpr (RAD == 8) dft8(u);
     else if constexpr (RAD == 4) dft4(u);
     else dft2(u[0], u[1]);
@@ -230,9 +258,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // whole transform, E values per lane, and exchanges them through its own LDS
 // region (N + N / 2^PSH slots), so no workgroup barrier is involved.  Three
 // Stockham stages: A (radix E, span 1, straight from the registers), B
-// (radix RB, span E, one butterfly per lane) and C (radix RC, span E RB,
-// E / RC butterflies per lane); RB RC = 64.  The padding puts the stage-A
-// stores (64 lanes E apart) and the stage-B stores on distinct banks.
+// (radix RB, span E, E / RB butterflies per lane) and C (radix RC, span
+// E RB, E / RC butterflies per lane); RB RC = 64.  The padding puts the
+// stage-A stores (64 lanes E apart) and the stage-B stores on distinct
+// banks.
 template <int N>
 struct WavePlan;
 template <>
@@ -242,6 +271,10 @@ struct WavePlan<512> {
 template <>
 struct WavePlan<1024> {
     static constexpr int E = 16, RB = 16, RC = 4, PSH = 4;
+};
+template <>
+struct WavePlan<2048> {
+    static constexpr int E = 32, RB = 16, RC = 4, PSH = 5;
 };
 
 // Twiddle tables of a wavefront transform, tw = exp(-2 pi i j / N):
@@ -282,18 +315,28 @@ __device__ __forceinline__ void wave_fft(cplx<R> (&v)[WavePlan<N>::E], cplx<R>* 
     for (int q = 0; q < E; ++q) wb[fft_pad(l * E + q, PSH)] = v[q];
     wave_lds_sync();
     {
-        const int k = l & (E - 1);
-        cplx<R> u[RB];
+        // every butterfly's inputs are read before any output is stored
+        constexpr int SB = E / RB, QB = N / RB;
+        cplx<R> u[SB][RB];
 #pragma unroll
-        for (int t = 0; t < RB; ++t) {
-            u[t] = wb[fft_pad(l + 64 * t, PSH)];
-            if (t > 0) u[t] = cmul(u[t], twB[(t - 1) * E + k]);
+        for (int s = 0; s < SB; ++s) {
+            const int j = l + 64 * s, k = j & (E - 1);
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+                u[s][t] = wb[fft_pad(j + QB * t, PSH)];
+                if (t > 0) u[s][t] = cmul(u[s][t], twB[(t - 1) * E + k]);
+            }
         }
-        dft_r<R, RB>(u);
-        wave_lds_sync();
-        const int base = (l - k) * RB + k;
 #pragma unroll
-        for (int q = 0; q < RB; ++q) wb[fft_pad(base + q * E, PSH)] = u[q];
+        for (int s = 0; s < SB; ++s) dft_r<R, RB>(u[s]);
+        wave_lds_sync();
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+            const int j = l + 64 * s, k = j & (E - 1);
+            const int base = (j - k) * RB + k;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) wb[fft_pad(base + q * E, PSH)] = u[s][q];
+        }
     }
     wave_lds_sync();
 #pragma unroll

@@ -21,7 +21,7 @@
 //   pass 2: a workgroup owns M consecutive rows m1, loops over the tapers,
 //           runs the N2-point row FFTs (mode m = m1 + N1 m2), deconvolves,
 //           keeps the I wanted modes and accumulates P (and J, E) in registers;
-//           for P and E alone on rows of 512 or 1024, one wavefront
+//           for P and E alone on rows of 512, 1024 or 2048, one wavefront
 //           transforms each taper's row by itself (k_pass2w).
 // Points are binned by the column block of their first cell (counting sort:
 // per-workgroup histograms, one scan, then the binned geometry with each
@@ -1001,11 +1001,12 @@ __global__ __launch_bounds__(NT2) void k_pass2(NuArgs a, NuSeries d0, const NuSe
 // v + 8, ...); each transforms its row alone (wave_fft: no workgroup
 // barrier between stages) and accumulates d_k |J_k|^2 for the 16 modes
 // l + 64 m its lane holds.  The wavefronts' sums are added in a fixed order
-// at the end.  Rows of N2 = 512 or 1024, P and E only (batches that ask for
-// the eigencoefficients or the F-statistic take the general kernel); FP32
-// with four waves per SIMD, FP64 with two (156 KB of LDS at N2 = 1024).
+// at the end.  Rows of N2 = 512, 1024 or 2048 (FP32 only), P and E only
+// (batches that ask for the eigencoefficients or the F-statistic take the
+// general kernel); FP32 rows up to 1024 with four waves per SIMD, the rest
+// with two (152-156 KB of LDS at the largest rows).
 template <typename R, int N2>
-__global__ __launch_bounds__(NT2, sizeof(R) == 4 ? 4 : 2) void k_pass2w(NuArgs a, NuSeries d0, const NuSeries* D) {
+__global__ __launch_bounds__(NT2, sizeof(R) == 4 && N2 <= 1024 ? 4 : 2) void k_pass2w(NuArgs a, NuSeries d0, const NuSeries* D) {
     const NuSeries d = series_of(d0, D);
     using W = WavePlan<N2>;
     using T = WaveTw<N2>;
@@ -1041,12 +1042,14 @@ __global__ __launch_bounds__(NT2, sizeof(R) == 4 ? 4 : 2) void k_pass2w(NuArgs a
     // stand-in address), in the order the values are needed: loads return in
     // issue order, so the twiddle table and E can be finished while the row
     // is still on its way.  Pass 1's shares of |w_k|^2 are preloaded when
-    // each wavefront has one taper and there are at most 128 blocks.
+    // each wavefront has one taper and there are at most 64 NQ blocks.
+    constexpr int NQ = N2 >= 2048 ? 4 : 2;
     const auto* nrm = gp((const double*)d.nrm);
-    const bool pre = K <= NW && a.nbins <= 128;
+    const bool pre = K <= NW && a.nbins <= 64 * NQ;
     const int kw = wv < K ? wv : K - 1;
-    const double nq0 = nrm[(int64_t)(lane < a.nbins ? lane : 0) * K + kw];
-    const double nq1 = nrm[(int64_t)(lane + 64 < a.nbins ? lane + 64 : 0) * K + kw];
+    double nq[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) nq[u] = nrm[(int64_t)(lane + 64 * u < a.nbins ? lane + 64 * u : 0) * K + kw];
     const double lam = gp(d.lambda ? d.lambda : (const double*)d.nrm)[lane < K ? lane : 0];
     const int diag = gp((const int*)d.diag)[0];
     const double dkv = gp(d.dk ? d.dk : (const double*)d.nrm)[kw];
@@ -1070,7 +1073,10 @@ __global__ __launch_bounds__(NT2, sizeof(R) == 4 ? 4 : 2) void k_pass2w(NuArgs a
         // tapers v, v + 8, ...)
         __shared__ double s_nrm[64];
         if (pre) {
-            const double sq = wave_sum_to63((lane < a.nbins ? nq0 : 0.0) + (lane + 64 < a.nbins ? nq1 : 0.0));
+            double sq = 0.0;
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) sq += lane + 64 * u < a.nbins ? nq[u] : 0.0;
+            sq = wave_sum_to63(sq);
             if (lane == 63 && wv < K) s_nrm[wv] = sq;
         } else {
             for (int k = wv; k < K; k += NW) {
@@ -1664,10 +1670,13 @@ int finish_typed(Ctx* ctx, hipStream_t st, NuPending& q, hipEvent_t checked) {
         bool wave_rows = false;
         // P and E only, rows of 512 or 1024: wavefront-private row FFTs, one
         // row per workgroup (unless a tuned schedule fixed the rows)
-        if ((M == 1 || p.M_force == 0) && !anyJF && (p.N2 == 512 || p.N2 == 1024)) {
+        // (rows of 2048 in FP32 only: the FP64 regions exceed the LDS)
+        if ((M == 1 || p.M_force == 0) && !anyJF &&
+            (p.N2 == 512 || p.N2 == 1024 || (p.N2 == 2048 && sizeof(R) == 4))) {
             wave_rows = true;
             if (p.N2 == 1024) hipLaunchKernelGGL((k_pass2w<R, 1024>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
-            else hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
+            else if (p.N2 == 512) hipLaunchKernelGGL((k_pass2w<R, 512>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
+            else if constexpr (sizeof(R) == 4) hipLaunchKernelGGL((k_pass2w<R, 2048>), dim3((unsigned)p.N1, ys), dim3(NT2), 0, st, q.a, d0, D);
         }
         if (!wave_rows)
             M2N_TRY(launch_pass2<R>(p, st, M, pass2_group(p, M, q.maxK), dim3((unsigned)(p.N1 / M), ys), q.a, d0, D));

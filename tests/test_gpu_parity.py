@@ -100,10 +100,12 @@ def test_nufft_large_grid_sampled(m2n, ctx, orc, prec, tol):
 
 @pytest.mark.parametrize("I,K,weighted,prec,tol_P,tol_E", [
     (2 ** 16, 5, False, 1, 1e-5, 1e-6), (2 ** 17, 9, True, 1, 1e-5, 1e-6), (2 ** 18, 7, False, 1, 1e-5, 1e-6),
-    (2 ** 16, 5, True, 2, 1e-10, 1e-12), (2 ** 18, 9, False, 2, 1e-10, 1e-12)])
+    (2 ** 16, 5, True, 2, 1e-10, 1e-12), (2 ** 18, 9, False, 2, 1e-10, 1e-12),
+    (2 ** 20, 7, False, 1, 1e-5, 1e-6), (2 ** 20, 9, True, 1, 1e-5, 1e-6)])
 def test_psd_only_wavefront_rows(m2n, ctx, orc, I, K, weighted, prec, tol_P, tol_E):
-    # P and E without J or F: rows of 512 (I = 2^16, 2^17) or 1024
-    # (I = 2^18) take the pass-2 form with one wavefront per taper row; with
+    # P and E without J or F: rows of 512 (I = 2^16, 2^17), 1024 (I = 2^18)
+    # or 2048 (I = 2^20, FP32) take the pass-2 form with one wavefront per
+    # taper row; with
     # K = 9 a wavefront takes two tapers (and their weights).  P against the
     # oracle's direct NUDFT on sampled bands (both ends, uniform draws, the
     # largest-P bands); E, band-constant on a lattice, against the oracle's
