@@ -197,8 +197,9 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
     reqs = [workloads.served_request(r) for r in range(len(arr))]
     n = len(reqs)
     # results (P, Ehat, lambda; the tapers are not returned) are copied from
-    # the device straight into pinned host buffers
-    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP32, pinned_outputs=True)
+    # the device straight into pinned host buffers; the request arrays are
+    # borrowed until the results are collected (reqs keeps them alive)
+    q = m2n.Queue(ctx, prec=m2n.M2N_FP32, pinned_outputs=True, borrow_inputs=True)
     warm = [reqs[0]] + [r for r in reqs if r.I == 2 ** 20][:1]
     for r in warm:
         q.wait(q.submit(r.t, r.x, r.fmax, r.fw, r.K, r.f_lo, r.df, r.I, want_w=False))
@@ -237,14 +238,16 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
     # output buffers of the burst: views of one pinned pool, made once (a
     # server keeps such a pool and reuses it)
     rdt_t = torch.float32
-    tot = sum(2 * r.I + 2 * r.K for r in reqs[:nb])
+    # P and E of each request in turn, eigenvalues in a pool of their own,
+    # so that the queue copies each kind of a batch back in one piece
+    tot = sum(2 * r.I for r in reqs[:nb])
     pool = torch.empty(tot, dtype=rdt_t, pin_memory=True).numpy()
     lam_pool = torch.empty(sum(r.K for r in reqs[:nb]), dtype=torch.float64, pin_memory=True).numpy()
     outs, o, ol = [], 0, 0
     for r in reqs[:nb]:
         outs.append({"P": pool[o:o + r.I], "E": pool[o + r.I:o + 2 * r.I], "lam": lam_pool[ol:ol + r.K],
                      "w": None})
-        o += 2 * r.I + 2 * r.K
+        o += 2 * r.I
         ol += r.K
 
     def burst(qq, pinned):
@@ -260,13 +263,18 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
     burst(q, True)                     # once to warm the slots' arenas
     b_wall, bres = burst(q, True)
     q.close()
+    # the inputs copied at submit instead of borrowed
+    q = m2n.Queue(ctx, prec=m2n.M2N_FP32, pinned_outputs=True)
+    burst(q, True)
+    c_wall, cres = burst(q, True)
+    q.close()
     # the same burst with the staging path (any host memory, tapers returned)
-    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP32)
+    q = m2n.Queue(ctx, prec=m2n.M2N_FP32)
     s_wall, sres = burst(q, False)
     q.close()
     # and with an HBM budget of 256 MiB for the requests in flight
     budget = 256 << 20
-    q = m2n.Queue(ctx, hbm_budget_bytes=budget, slots=2, prec=m2n.M2N_FP32, pinned_outputs=True)
+    q = m2n.Queue(ctx, hbm_budget_bytes=budget, prec=m2n.M2N_FP32, pinned_outputs=True, borrow_inputs=True)
     g_wall, gres = burst(q, True)
     q.close()
     print(f"bench: served trace done, burst of {nb} in {b_wall:.2f} s", file=sys.stderr, flush=True)
@@ -305,7 +313,11 @@ def served_form(m2n, torch, workloads, ctx, rate, seconds):
             "mean_batch": round(float(np.mean(bsz)), 2), "max_batch": int(np.max(bsz)),
             "burst": {"requests": nb, "psds_per_s": round(nb / b_wall, 1),
                       "mean_batch": round(float(np.mean([r["batch_size"] for r in bres])), 1),
-                      "outputs": "a reused pool of pinned host buffers, P + Ehat + lambda"},
+                      "outputs": "a reused pool of pinned host buffers, P + Ehat + lambda",
+                      "inputs": "borrowed until the results are collected"},
+            "burst_copied_inputs": {"requests": nb, "psds_per_s": round(nb / c_wall, 1),
+                                    "mean_batch": round(float(np.mean([r["batch_size"] for r in cres])), 1),
+                                    "inputs": "copied at submit"},
             "burst_staged_outputs": {"requests": nb, "psds_per_s": round(nb / s_wall, 1),
                                      "mean_batch": round(float(np.mean([r["batch_size"] for r in sres])), 1),
                                      "outputs": "pageable host buffers through a pinned staging "

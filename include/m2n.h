@@ -496,9 +496,9 @@ int m2n_batch_destroy(m2n_batch *batch);
 /*
  * Request queue with continuous batching (the served form).
  *
- * Requests carry HOST inputs, which m2n_submit copies before it returns, and
- * HOST output buffers, which must stay valid until m2n_poll or m2n_wait has
- * reported the request done.  `slots` worker threads, each with its own
+ * Requests carry HOST inputs, which m2n_submit copies before it returns
+ * (unless the queue borrows them, below), and HOST output buffers, which must
+ * stay valid until m2n_poll or m2n_wait has reported the request done.  `slots` worker threads, each with its own
  * context and stream, take the pending requests in arrival order -- as many
  * as max_batch and the HBM budget admit -- and run them as one batch
  * (m2n_batch_psd); while one slot's batch is on the GPU the next admits what
@@ -512,8 +512,8 @@ typedef struct {
     size_t hbm_budget_bytes; /* cap on the estimated device bytes of the
                                 requests in flight (0 = no cap); a request
                                 larger than the cap runs alone              */
-    int max_batch;           /* requests per batch (0 = 512)               */
-    int slots;               /* batches in flight (0 = 2, at most 4)       */
+    int max_batch;           /* requests per batch (0 = 128)               */
+    int slots;               /* batches in flight (0 = 4, at most 4)       */
     int prec;                /* M2N_FP32 (also when 0) or M2N_FP64         */
     double nufft_tol;        /* as in m2nufft_psd                          */
     int outputs_pinned;      /* 1: every request's host outputs are pinned
@@ -522,10 +522,16 @@ typedef struct {
                                 from the device straight into them, with no
                                 staging block and no host memcpy.  0: any
                                 host memory, through a pinned staging block */
+    int inputs_borrowed;     /* 1: m2n_submit keeps the request's t and x
+                                pointers instead of copying them; the caller
+                                keeps both valid and unchanged until
+                                m2n_poll or m2n_wait has reported the
+                                request done (or m2n_queue_destroy returned).
+                                0: copied at submit                         */
 } m2n_queue_cfg;
 
 typedef struct {
-    const double *t, *x;     /* HOST [N], copied by m2n_submit               */
+    const double *t, *x;     /* HOST [N], copied by m2n_submit (or borrowed) */
     int64_t N;
     int K;
     double fmax, fw;

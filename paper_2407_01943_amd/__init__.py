@@ -75,7 +75,7 @@ class M2NBatchInfo(ctypes.Structure):
 class M2NQueueCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
                 ("slots", ctypes.c_int), ("prec", ctypes.c_int), ("nufft_tol", ctypes.c_double),
-                ("outputs_pinned", ctypes.c_int)]
+                ("outputs_pinned", ctypes.c_int), ("inputs_borrowed", ctypes.c_int)]
 
 
 class M2NRequest(ctypes.Structure):
@@ -527,13 +527,18 @@ class Queue:
     this object until the request is collected."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes=0, max_batch=0, slots=0,
-                 prec=M2N_FP32, nufft_tol=0.0, pinned_outputs=False):
+                 prec=M2N_FP32, nufft_tol=0.0, pinned_outputs=False, borrow_inputs=False):
+        """borrow_inputs: t and x are not copied at submit; this object keeps
+        the arrays it was given alive until the result is collected, and the
+        caller must not change them meanwhile."""
         import numpy as np
         self._np = np
         self.ctx = ctx
         self.prec = prec
         self.pinned = bool(pinned_outputs)
-        cfg = M2NQueueCfg(hbm_budget_bytes, max_batch, slots, prec, nufft_tol, 1 if self.pinned else 0)
+        self.borrow = bool(borrow_inputs)
+        cfg = M2NQueueCfg(hbm_budget_bytes, max_batch, slots, prec, nufft_tol, 1 if self.pinned else 0,
+                          1 if self.borrow else 0)
         h = ctypes.c_void_p()
         _err(lib.m2n_queue_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)),
              "m2n_queue_create")
@@ -569,11 +574,15 @@ class Queue:
                          None if out["E"] is None else out["E"].ctypes.data)
         tk = ctypes.c_uint64()
         _err(lib.m2n_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)), "m2n_submit")
+        if self.borrow:
+            out["_inputs"] = (t, x)     # alive until the result is collected
         self._out[tk.value] = out
         return tk.value
 
     def _finish(self, ticket, code, res):
         out = self._out.pop(ticket, None)
+        if out is not None:
+            out.pop("_inputs", None)
         _err(code, "m2n_wait")
         out.update(status=res.status, batch_size=res.batch_size, latency_us=res.latency_us,
                    service_us=res.service_us)

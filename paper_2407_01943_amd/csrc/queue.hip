@@ -1,6 +1,7 @@
 // Request queue with continuous batching (the served form).
 //
-// m2n_submit copies a request's host inputs and returns a ticket at once.
+// m2n_submit copies a request's host inputs (or, on a queue made to borrow
+// them, keeps the caller's pointers) and returns a ticket at once.
 // Worker threads, one per in-flight slot, each with its own context (plans,
 // workspace) and stream, take the pending requests in arrival order -- as
 // many as the slot's batch limit and the queue's HBM budget admit -- stage
@@ -27,7 +28,9 @@ using clk = std::chrono::steady_clock;
 
 struct Req {
     uint64_t ticket = 0;
-    std::vector<double> t, x;
+    std::vector<double> t, x;  // copies of the inputs (empty when borrowed)
+    const double* tp = nullptr;  // the inputs: the copies or the caller's
+    const double* xp = nullptr;
     int64_t N = 0, I = 0;
     int K = 0;
     double fmax = 0, fw = 0, f_lo = 0, df = 0;
@@ -98,16 +101,26 @@ int grow_pinned(void** p, size_t* have, size_t want) {
 
 // Run one batch on a slot.  Returns the batch status; per-request statuses
 // are set in the requests.
+//
+// Device arena: the inputs (t, x per request), then the outputs by kind, each
+// kind in request order -- P and E of every request, the tapers, then the
+// eigenvalues packed at 8 bytes -- so that the copies back to the host merge
+// wherever the callers' buffers are contiguous too (a server's pool of
+// outputs: one copy per kind and batch instead of one per output and request;
+// each copy costs ~10 us of fixed overhead on top of its bytes).
 int run_batch(m2n_queue* q, Slot& s, std::vector<Req*>& batch) {
     const int prec = q->cfg.prec;
     const size_t rs = prec == M2N_FP32 ? 4 : 8;
-    // layout: inputs (t, x) then outputs (w, lambda, P, E) per request
-    size_t in_bytes = 0, out_bytes = 0;
+    const size_t nb = batch.size();
+    size_t in_bytes = 0, pe_bytes = 0, w_bytes = 0, l_bytes = 0;
     for (Req* r : batch) {
         in_bytes += 2 * al256(sizeof(double) * r->N);
-        out_bytes += al256(sizeof(double) * r->K * r->N) + al256(sizeof(double) * r->K) +
-                     2 * al256(rs * r->I);
+        pe_bytes += (r->want_E ? 2 : 1) * al256(rs * r->I);
+        w_bytes += al256(sizeof(double) * r->K * r->N);
+        l_bytes += sizeof(double) * r->K;
     }
+    l_bytes = al256(l_bytes);
+    const size_t out_bytes = pe_bytes + w_bytes + l_bytes;
     if (s.dev_bytes < in_bytes + out_bytes) {
         if (s.dev) {
             M2N_HIP(hipStreamSynchronize(s.st));
@@ -127,18 +140,20 @@ int run_batch(m2n_queue* q, Slot& s, std::vector<Req*>& batch) {
     M2N_TRY(grow_pinned(&s.pin_in, &s.pin_in_bytes, in_bytes));
     if (!q->cfg.outputs_pinned) M2N_TRY(grow_pinned(&s.pin_out, &s.pin_out_bytes, out_bytes));
     char* din = (char*)s.dev;
-    char* dout = din + in_bytes;
+    char* dpe = din + in_bytes;
+    char* dw = dpe + pe_bytes;
+    char* dl = dw + w_bytes;
     char* hin = (char*)s.pin_in;
-    std::vector<m2n_series> ser(batch.size());
-    size_t oi = 0, oo = 0;
-    for (size_t j = 0; j < batch.size(); ++j) {
+    std::vector<m2n_series> ser(nb);
+    size_t oi = 0, ope = 0, ow = 0, ol = 0;
+    for (size_t j = 0; j < nb; ++j) {
         Req* r = batch[j];
         m2n_series& d = ser[j];
         std::memset(&d, 0, sizeof(d));
-        std::memcpy(hin + oi, r->t.data(), sizeof(double) * r->N);
+        std::memcpy(hin + oi, r->tp, sizeof(double) * r->N);
         d.t = (const double*)(din + oi);
         oi += al256(sizeof(double) * r->N);
-        std::memcpy(hin + oi, r->x.data(), sizeof(double) * r->N);
+        std::memcpy(hin + oi, r->xp, sizeof(double) * r->N);
         d.x = (const double*)(din + oi);
         oi += al256(sizeof(double) * r->N);
         d.N = r->N;
@@ -148,49 +163,65 @@ int run_batch(m2n_queue* q, Slot& s, std::vector<Req*>& batch) {
         d.f_lo = r->f_lo;
         d.df = r->df;
         d.I = r->I;
-        d.w = (double*)(dout + oo);
-        oo += al256(sizeof(double) * r->K * r->N);
-        d.lambda = (double*)(dout + oo);
-        oo += al256(sizeof(double) * r->K);
-        d.P = dout + oo;
-        oo += al256(rs * r->I);
-        d.E = r->want_E ? (void*)(dout + oo) : nullptr;
-        oo += al256(rs * r->I);
+        d.P = dpe + ope;
+        ope += al256(rs * r->I);
+        d.E = nullptr;
+        if (r->want_E) {
+            d.E = dpe + ope;
+            ope += al256(rs * r->I);
+        }
+        d.w = (double*)(dw + ow);
+        ow += al256(sizeof(double) * r->K * r->N);
+        d.lambda = (double*)(dl + ol);
+        ol += sizeof(double) * r->K;
     }
     M2N_HIP(hipMemcpyAsync(din, hin, in_bytes, hipMemcpyHostToDevice, s.st));
-    int st = m2n_batch_psd(s.ctx, s.st, ser.data(), (int)ser.size(), prec, q->cfg.nufft_tol);
+    int st = m2n_batch_psd(s.ctx, s.st, ser.data(), (int)nb, prec, q->cfg.nufft_tol);
     if (st == M2N_OK) st = m2n_check(s.ctx, s.st);
     if (st != M2N_OK) return st;
     if (q->cfg.outputs_pinned) {
-        // straight into the callers' pinned buffers: one copy per output
-        for (size_t j = 0; j < batch.size(); ++j) {
+        // straight into the callers' pinned buffers, runs that are contiguous
+        // on both sides merged into one copy
+        struct Cp {
+            char* dst;
+            const char* src;
+            size_t n;
+        };
+        std::vector<Cp> cps;
+        cps.reserve(4 * nb);
+        auto add = [&cps](void* dst, const void* src, size_t n) {
+            char* d = (char*)dst;
+            const char* sp = (const char*)src;
+            if (!cps.empty() && cps.back().dst + cps.back().n == d && cps.back().src + cps.back().n == sp)
+                cps.back().n += n;
+            else
+                cps.push_back({d, sp, n});
+        };
+        for (size_t j = 0; j < nb; ++j) {
             Req* r = batch[j];
-            const m2n_series& d = ser[j];
-            if (r->w_out)
-                M2N_HIP(hipMemcpyAsync(r->w_out, d.w, sizeof(double) * r->K * r->N, hipMemcpyDeviceToHost, s.st));
-            if (r->lam_out)
-                M2N_HIP(hipMemcpyAsync(r->lam_out, d.lambda, sizeof(double) * r->K, hipMemcpyDeviceToHost, s.st));
-            if (r->P_out) M2N_HIP(hipMemcpyAsync(r->P_out, d.P, rs * r->I, hipMemcpyDeviceToHost, s.st));
-            if (r->want_E && r->E_out)
-                M2N_HIP(hipMemcpyAsync(r->E_out, d.E, rs * r->I, hipMemcpyDeviceToHost, s.st));
+            if (r->P_out) add(r->P_out, ser[j].P, rs * r->I);
+            if (r->want_E && r->E_out) add(r->E_out, ser[j].E, rs * r->I);
         }
+        for (size_t j = 0; j < nb; ++j)
+            if (batch[j]->w_out) add(batch[j]->w_out, ser[j].w, sizeof(double) * batch[j]->K * batch[j]->N);
+        for (size_t j = 0; j < nb; ++j)
+            if (batch[j]->lam_out) add(batch[j]->lam_out, ser[j].lambda, sizeof(double) * batch[j]->K);
+        for (const Cp& c : cps) M2N_HIP(hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToHost, s.st));
         M2N_HIP(hipStreamSynchronize(s.st));
         for (Req* r : batch) r->res.status = M2N_OK;
         return M2N_OK;
     }
-    M2N_HIP(hipMemcpyAsync(s.pin_out, dout, out_bytes, hipMemcpyDeviceToHost, s.st));
+    M2N_HIP(hipMemcpyAsync(s.pin_out, dpe, out_bytes, hipMemcpyDeviceToHost, s.st));
     M2N_HIP(hipStreamSynchronize(s.st));
     const char* hout = (const char*)s.pin_out;
-    oo = 0;
-    for (Req* r : batch) {
-        if (r->w_out) std::memcpy(r->w_out, hout + oo, sizeof(double) * r->K * r->N);
-        oo += al256(sizeof(double) * r->K * r->N);
-        if (r->lam_out) std::memcpy(r->lam_out, hout + oo, sizeof(double) * r->K);
-        oo += al256(sizeof(double) * r->K);
-        if (r->P_out) std::memcpy(r->P_out, hout + oo, rs * r->I);
-        oo += al256(rs * r->I);
-        if (r->want_E && r->E_out) std::memcpy(r->E_out, hout + oo, rs * r->I);
-        oo += al256(rs * r->I);
+    for (size_t j = 0; j < nb; ++j) {
+        Req* r = batch[j];
+        const m2n_series& d = ser[j];
+        auto host = [&](const void* dev_ptr) { return hout + ((const char*)dev_ptr - dpe); };
+        if (r->w_out) std::memcpy(r->w_out, host(d.w), sizeof(double) * r->K * r->N);
+        if (r->lam_out) std::memcpy(r->lam_out, host(d.lambda), sizeof(double) * r->K);
+        if (r->P_out) std::memcpy(r->P_out, host(d.P), rs * r->I);
+        if (r->want_E && r->E_out) std::memcpy(r->E_out, host(d.E), rs * r->I);
         r->res.status = M2N_OK;
     }
     return M2N_OK;
@@ -276,8 +307,8 @@ int m2n_queue_create(m2n_ctx* ctx, const m2n_queue_cfg* cfg, m2n_queue** out) {
     *out = nullptr;
     m2n_queue_cfg c{};
     if (cfg) c = *cfg;
-    if (c.max_batch <= 0) c.max_batch = 512;
-    if (c.slots <= 0) c.slots = 2;
+    if (c.max_batch <= 0) c.max_batch = 128;
+    if (c.slots <= 0) c.slots = 4;
     if (c.slots > 4) c.slots = 4;
     if (c.prec == 0) c.prec = M2N_FP32;
     if (c.prec != M2N_FP32 && c.prec != M2N_FP64) {
@@ -312,8 +343,15 @@ int m2n_submit(m2n_queue* q, const m2n_request* r, uint64_t* ticket) {
         return M2N_ERR_OOM;
     }
     Req& d = *q_req;
-    d.t.assign(r->t, r->t + r->N);
-    d.x.assign(r->x, r->x + r->N);
+    if (q->cfg.inputs_borrowed) {
+        d.tp = r->t;
+        d.xp = r->x;
+    } else {
+        d.t.assign(r->t, r->t + r->N);
+        d.x.assign(r->x, r->x + r->N);
+        d.tp = d.t.data();
+        d.xp = d.x.data();
+    }
     d.N = r->N;
     d.K = r->K;
     d.I = r->I;

@@ -107,6 +107,57 @@ def test_queue_pinned_outputs(m2n, ctx):
     q.close()
 
 
+@pytest.mark.parametrize("borrow", [False, True])
+def test_queue_pinned_pool_merged_copies(m2n, ctx, borrow):
+    # outputs as back-to-back views of one pinned pool (P, E of each request
+    # in turn; eigenvalues and tapers in pools of their own), so that the
+    # copies of a batch merge; requests without E, without tapers and one
+    # band count whose P is not a multiple of 256 bytes break the runs; the
+    # inputs copied at submit or borrowed until the results are collected
+    series = [W.batched_series(s) for s in range(80, 92)]
+    series[5].I = 1000
+    want_E = [i % 4 != 3 for i in range(len(series))]
+    want_w = [i % 3 == 0 for i in range(len(series))]
+    pin = dict(pin_memory=True)
+    pe = torch.empty(sum((2 if e else 1) * s.I for s, e in zip(series, want_E)), dtype=torch.float32, **pin)
+    lp = torch.empty(sum(s.K for s in series), dtype=torch.float64, **pin)
+    wp = torch.empty(sum(s.K * s.N for s, f in zip(series, want_w) if f), dtype=torch.float64, **pin)
+    pe, lp, wp = pe.numpy(), lp.numpy(), wp.numpy()
+    outs, o, ol, ow = [], 0, 0, 0
+    for s, e, f in zip(series, want_E, want_w):
+        ob = {"P": pe[o:o + s.I], "E": None, "lam": lp[ol:ol + s.K], "w": None}
+        o += s.I
+        if e:
+            ob["E"] = pe[o:o + s.I]
+            o += s.I
+        if f:
+            ob["w"] = wp[ow:ow + s.K * s.N].reshape(s.K, s.N)
+            ow += s.K * s.N
+        ol += s.K
+        outs.append(ob)
+    q = m2n.Queue(ctx, slots=1, prec=m2n.M2N_FP32, pinned_outputs=True, borrow_inputs=borrow)
+    # fresh copies of t and x, referenced by nothing but the queue object:
+    # a borrowed input must be kept alive by it until its result is taken
+    tk = [q.submit(s.t.copy(), s.x.copy(), s.fmax, s.fw, s.K, s.f_lo, s.df, s.I, out=ob)
+          for s, ob in zip(series, outs)]
+    res = [_wait(q, t) for t in tk]
+    worst = 0.0
+    for i, (s, r) in enumerate(zip(series, res)):
+        assert r["status"] == m2n.M2N_OK and "_inputs" not in r
+        w, lam, P, E = _alone(m2n, ctx, s, m2n.M2N_FP32)
+        assert np.array_equal(r["lam"], lam), i
+        if want_w[i]:
+            assert np.array_equal(r["w"], w), i
+        dP = float(np.max(np.abs(r["P"].astype(np.float64) - P)) / np.max(np.abs(P)))
+        assert dP < 2e-6, (i, dP)
+        worst = max(worst, dP)
+        if want_E[i]:
+            assert np.max(np.abs(r["E"].astype(np.float64) - E)) < 1e-7, i
+    _say(f"case pinned pool (borrowed inputs {borrow}): 12 requests, batch sizes {sorted(r['batch_size'] for r in res)}, "
+         f"worst P {worst:.2e}")
+    q.close()
+
+
 def test_queue_failing_request_is_isolated(m2n, ctx):
     good = [W.batched_series(s) for s in (30, 31, 32)]
     bad = W.batched_series(33)
