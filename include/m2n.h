@@ -29,7 +29,7 @@
  *    eigencoefficients J are K x I complex (interleaved re, im).
  *  - Sizes are int64_t; N >= 1, 1 <= K <= min(N, 64), 1 <= I <= 2^21.
  *  - Errors are returned as m2n_status codes; nothing aborts and no C++
- *    exception crosses the ABI.  m2n_last_error() gives a text for the last
+ *    exception crosses the ABI.  m2n_last_error(ctx) gives a text for the last
  *    failure on the calling thread.
  *  - A context is not thread-safe: one host thread at a time per context.
  *    Its workspace is reused from call to call, so calls on one context
@@ -70,8 +70,9 @@ int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx **out);
 /* Free everything the context owns (waits for its streams' work first). */
 void m2n_destroy(m2n_ctx *ctx);
 
-/* Text of the last failure on the calling thread ("" if none). */
-const char *m2n_last_error(void);
+/* Text of the last failure on the calling thread ("" if none).  The text is
+ * kept per thread, not per context: `ctx` is not read and may be NULL. */
+const char *m2n_last_error(const m2n_ctx *ctx);
 
 /* Bytes of device workspace the context currently holds. */
 size_t m2n_workspace_bytes(const m2n_ctx *ctx);
@@ -574,7 +575,14 @@ int m2n_profile_read(m2n_ctx *ctx, char *names, size_t names_len, double *total_
                      int64_t *launches, int max_entries);
 
 /* Wait for `stream` and report the first device-side data error flagged by
- * the library's kernels since the last check (M2N_ERR_ARG for non-finite t). */
+ * the library's kernels since the last check (M2N_ERR_ARG for non-finite t),
+ * clearing it.  The compute calls are stream-ordered and return before their
+ * kernels run, so such errors surface here.  Synchronous mode -- the library
+ * built with -DM2N_SYNC=1, or a context created while the environment holds
+ * M2N_SYNC=1 -- makes every compute call (and m2n_batch_launch on a batch made
+ * from such a context) end with this wait and return that error itself.
+ * m2n_check is the same call under its earlier name. */
+int m2n_stream_status(m2n_ctx *ctx, void *stream);
 int m2n_check(m2n_ctx *ctx, void *stream);
 
 #ifdef __cplusplus

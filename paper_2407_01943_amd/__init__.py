@@ -36,7 +36,7 @@ M2N_FP32 = 1
 M2N_FP64 = 2
 
 EXPORTED = ["m2n_create", "m2n_destroy", "m2n_last_error", "m2n_workspace_bytes",
-            "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check",
+            "gpss_tapers", "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check", "m2n_stream_status",
             "m2n_profile_enable", "m2n_profile_reset", "m2n_profile_read",
             "m2n_batch_psd", "m2n_queue_create", "m2n_submit", "m2n_poll", "m2n_wait",
             "m2n_queue_destroy", "gpss_tapers_subband", "m2nufft_psd_subband",
@@ -106,7 +106,7 @@ def _load():
     L.m2n_create.restype = i
     L.m2n_destroy.argtypes = [vp]
     L.m2n_destroy.restype = None
-    L.m2n_last_error.argtypes = []
+    L.m2n_last_error.argtypes = [vp]
     L.m2n_last_error.restype = ctypes.c_char_p
     L.m2n_workspace_bytes.argtypes = [vp]
     L.m2n_workspace_bytes.restype = ctypes.c_size_t
@@ -120,6 +120,8 @@ def _load():
     L.m2n_profile_read.restype = i
     L.m2n_check.argtypes = [vp, vp]
     L.m2n_check.restype = i
+    L.m2n_stream_status.argtypes = [vp, vp]
+    L.m2n_stream_status.restype = i
     L.gpss_tapers.argtypes = [vp, vp, vp, i64, d, d, d, i, vp, vp]
     L.gpss_tapers.restype = i
     L.m2nufft_eigcoeffs.argtypes = [vp, vp, vp, vp, i64, vp, i, d, d, i64, i, d, vp]
@@ -171,7 +173,7 @@ lib = _load()
 
 def _err(code, where):
     if code != M2N_OK:
-        raise M2NError(code, where, lib.m2n_last_error().decode(errors="replace"))
+        raise M2NError(code, where, lib.m2n_last_error(None).decode(errors="replace"))
 
 
 def _ptr(x):
@@ -231,7 +233,7 @@ class Context:
         return {nm: (ms[i], int(cnt[i])) for i, nm in enumerate(names)}
 
     def check(self, stream=None):
-        _err(lib.m2n_check(self.handle, _stream(stream)), "m2n_check")
+        _err(lib.m2n_stream_status(self.handle, _stream(stream)), "m2n_stream_status")
 
 
 def gpss_tapers(ctx: Context, t, fmax, fw, K, fc0=0.0, stream=None, out=None):

@@ -1,6 +1,7 @@
 // C-ABI entry points, context, workspace and error state.
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "m2n_common.hpp"
@@ -174,9 +175,29 @@ int Ctx::prof_flush() {
 using namespace m2n;
 
 
+#ifndef M2N_SYNC
+#define M2N_SYNC 0
+#endif
+
+namespace {
+
+// The status a compute call returns: in synchronous mode (built with
+// M2N_SYNC=1, or a context created while the environment has M2N_SYNC=1) the
+// call waits for its stream and reports the device-side errors its kernels
+// flagged; otherwise they surface at the next m2n_stream_status.
+int sync_ret(m2n_ctx* ctx, void* stream, int st) {
+    if (st == M2N_OK && ctx->sync) return m2n_stream_status(ctx, stream);
+    return st;
+}
+
+}  // namespace
+
 extern "C" {
 
-const char* m2n_last_error(void) { return g_err; }
+const char* m2n_last_error(const m2n_ctx* ctx) {
+    (void)ctx;   // the text is kept per calling thread
+    return g_err;
+}
 
 int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx** out) {
     if (!out) {
@@ -198,6 +219,8 @@ int m2n_create(int hip_device, size_t hbm_budget_bytes, m2n_ctx** out) {
     }
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
+    const char* sync_env = std::getenv("M2N_SYNC");
+    c->sync = M2N_SYNC || (sync_env && std::strcmp(sync_env, "1") == 0);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
     void* e = nullptr;
@@ -303,7 +326,9 @@ int m2n_profile_read(m2n_ctx* ctx, char* names, size_t names_len, double* total_
     return n;
 }
 
-int m2n_check(m2n_ctx* ctx, void* stream) {
+int m2n_check(m2n_ctx* ctx, void* stream) { return m2n_stream_status(ctx, stream); }
+
+int m2n_stream_status(m2n_ctx* ctx, void* stream) {
     if (!ctx) {
         set_error("ctx is NULL");
         return M2N_ERR_ARG;
@@ -342,7 +367,7 @@ int gpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double f
         return M2N_ERR_UNSUPPORTED;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
+    return sync_ret(ctx, stream, gep_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda));
 }
 
 int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N, const double* w,
@@ -352,7 +377,7 @@ int m2nufft_psd_at(m2n_ctx* ctx, void* stream, const double* t, const double* x,
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
+    return sync_ret(ctx, stream, nudft_list_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J));
 }
 
 int gpss_tapers_rr(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,
@@ -362,7 +387,7 @@ int gpss_tapers_rr(m2n_ctx* ctx, void* stream, const double* t, int64_t N, doubl
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return gep_rr(ctx, (hipStream_t)stream, t, N, fmax, fw, K, rank_tol, w, lambda, rank);
+    return sync_ret(ctx, stream, gep_rr(ctx, (hipStream_t)stream, t, N, fmax, fw, K, rank_tol, w, lambda, rank));
 }
 
 int m2nufft_psd_freqs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N, const double* w,
@@ -373,7 +398,7 @@ int m2nufft_psd_freqs(m2n_ctx* ctx, void* stream, const double* t, const double*
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return nufft3_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, prec, nufft_tol, weights, P, J);
+    return sync_ret(ctx, stream, nufft3_run(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, prec, nufft_tol, weights, P, J));
 }
 
 int m2nufft_psd_at_noalloc(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
@@ -384,7 +409,7 @@ int m2nufft_psd_at_noalloc(m2n_ctx* ctx, void* stream, const double* t, const do
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return nudft_list_run_noalloc(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J);
+    return sync_ret(ctx, stream, nudft_list_run_noalloc(ctx, (hipStream_t)stream, t, x, N, w, K, freqs, I, weights, P, J));
 }
 
 int idpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmax, double fw, int K,
@@ -394,7 +419,7 @@ int idpss_tapers(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double 
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return idpss_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda);
+    return sync_ret(ctx, stream, idpss_run(ctx, (hipStream_t)stream, t, N, fmax, fw, K, w, lambda));
 }
 
 int gpss_tapers_subband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fmin,
@@ -419,7 +444,7 @@ int gpss_tapers_subband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, 
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return gep_subband(ctx, (hipStream_t)stream, t, N, fmin, fmax, fw, fc0, K, w, lambda);
+    return sync_ret(ctx, stream, gep_subband(ctx, (hipStream_t)stream, t, N, fmin, fmax, fw, fc0, K, w, lambda));
 }
 
 int gpss_tapers_multiband(m2n_ctx* ctx, void* stream, const double* t, int64_t N, double fw, int K,
@@ -435,7 +460,7 @@ int gpss_tapers_multiband(m2n_ctx* ctx, void* stream, const double* t, int64_t N
         }
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return multiband_run(ctx, (hipStream_t)stream, t, N, fw, K, sb, Q);
+    return sync_ret(ctx, stream, multiband_run(ctx, (hipStream_t)stream, t, N, fw, K, sb, Q));
 }
 
 int m2nufft_psd_subband(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
@@ -446,8 +471,8 @@ int m2nufft_psd_subband(m2n_ctx* ctx, void* stream, const double* t, const doubl
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return subband_psd_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol, weights, P,
-                           J);
+    return sync_ret(ctx, stream, subband_psd_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol, weights, P,
+                           J));
 }
 
 int m2nufft_eigcoeffs(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
@@ -458,8 +483,8 @@ int m2nufft_eigcoeffs(m2n_ctx* ctx, void* stream, const double* t, const double*
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
-                     nullptr, nullptr, 0.0, 0.0, nullptr, nullptr, J, nullptr);
+    return sync_ret(ctx, stream, nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
+                     nullptr, nullptr, 0.0, 0.0, nullptr, nullptr, J, nullptr));
 }
 
 int m2nufft_psd(m2n_ctx* ctx, void* stream, const double* t, const double* x, int64_t N,
@@ -471,8 +496,8 @@ int m2nufft_psd(m2n_ctx* ctx, void* stream, const double* t, const double* x, in
         return M2N_ERR_ARG;
     }
     M2N_HIP(hipSetDevice(ctx->device));
-    return nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
-                     weights, lambda, fmax, fw, P, E, J, F);
+    return sync_ret(ctx, stream, nufft_run(ctx, (hipStream_t)stream, t, x, N, w, K, f_lo, df, I, prec, nufft_tol,
+                     weights, lambda, fmax, fw, P, E, J, F));
 }
 
 int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nseries, int prec,
@@ -613,7 +638,7 @@ int m2n_batch_psd(m2n_ctx* ctx, void* stream, const m2n_series* series, int nser
             M2N_TRY(rest(false));
         }
     }
-    return M2N_OK;
+    return sync_ret(ctx, stream, M2N_OK);
 }
 
 }  // extern "C"

@@ -291,6 +291,7 @@ int m2n_batch_create(m2n_ctx* ctx, void* stream, const m2n_series* series, int n
     }
     rc = m2n_create(ctx->device, ctx->budget, &b->child);
     if (rc != M2N_OK) return fail(rc);
+    b->child->sync = ctx->sync;
     // the t check (one host round trip): every series on the lattice path
     rc = gep_batch_check_lattice(b->child, st, b->gin.data(), nseries, b->t0, b->tN);
     if (rc != M2N_OK) return fail(rc);
@@ -349,11 +350,16 @@ int m2n_batch_launch(m2n_batch* b, void* stream) {
     }
     M2N_HIP(hipSetDevice(b->device));
     hipStream_t st = (hipStream_t)stream;
+    int rc;
     if (b->exec) {
         M2N_HIP(hipGraphLaunch(b->exec, st));
-        return M2N_OK;
+        rc = M2N_OK;
+    } else {
+        rc = batch_enqueue(b, st);
     }
-    return batch_enqueue(b, st);
+    // synchronous mode (as the context the batch was made from)
+    if (rc == M2N_OK && b->child->sync) rc = m2n_stream_status(b->child, stream);
+    return rc;
 }
 
 int m2n_batch_get_info(const m2n_batch* b, m2n_batch_info* info) {

@@ -240,6 +240,7 @@ struct Ctx {
     std::map<std::string, DevBuf> ws;   // named grow-only workspaces
     unsigned* dev_err = nullptr;        // sticky device error word
     int cu_count = 256;
+    bool sync = false;         // every compute call waits and reports device-side errors
     void* hinfo = nullptr;              // pinned host record of the t checks
     size_t hinfo_bytes = 0;
     std::map<int, DevBuf> gl;           // Gauss-Legendre nodes/weights by order

@@ -109,7 +109,7 @@ int multiband_run(Ctx* ctx, hipStream_t st, const double* t, int64_t N, double f
             }
             rc[q] = gep_subband(ctx->subs[q], ctx->sub_streams[q], t, N, sb[q].fmin, sb[q].fmax, fw, sb[q].fc0,
                                 K, sb[q].w, sb[q].lambda);
-            if (rc[q] != M2N_OK) msg[q] = m2n_last_error();   // the worker's own error text
+            if (rc[q] != M2N_OK) msg[q] = m2n_last_error(nullptr);   // the worker's own error text
         });
     }
     for (auto& x : th) x.join();

@@ -23,7 +23,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("m2n_create", "m2n_destroy", "m2n_last_error", "gpss_tapers",
-              "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check"):
+              "m2nufft_eigcoeffs", "m2nufft_psd", "m2n_check", "m2n_stream_status"):
         assert n in names
 
 
@@ -47,7 +47,8 @@ def test_binding_names_match_header():
 def test_last_error_is_empty_string_initially():
     lib = ctypes.CDLL(LIB)
     lib.m2n_last_error.restype = ctypes.c_char_p
-    assert isinstance(lib.m2n_last_error(), bytes)
+    lib.m2n_last_error.argtypes = [ctypes.c_void_p]
+    assert isinstance(lib.m2n_last_error(None), bytes)
 
 
 def _header_src():

@@ -320,3 +320,39 @@ def test_errors(m2n, ctx):
         m2n.m2nufft_psd(ctx, _dev(np.arange(4.0)), x, w, None, 0.5, 0.1, -0.5, 1 / 64, 64,
                         want_E=False)
     assert ei.value.code == m2n.M2N_ERR_ARG
+
+
+def test_sync_mode_returns_device_errors(m2n, ctx, monkeypatch):
+    # a context created while M2N_SYNC=1: the call waits and returns the error
+    # its kernels flagged (non-finite x); on the default context the same call
+    # returns at once and the error surfaces at the next m2n_stream_status
+    monkeypatch.setenv("M2N_SYNC", "1")
+    sctx = m2n.Context(0)
+    monkeypatch.delenv("M2N_SYNC")
+    try:
+        t = _dev(np.arange(4.0))
+        x = _dev(np.array([1.0, np.nan, 2.0, 3.0]))
+        w = _dev(np.ones((1, 4)))
+        args = (t, x, w, None, 0.5, 0.1, -0.5, 1 / 64, 64)
+        with pytest.raises(m2n.M2NError) as ei:
+            m2n.m2nufft_psd(sctx, *args, want_E=False, check=False)
+        assert ei.value.code == m2n.M2N_ERR_ARG
+        sctx.check()                       # reported once, then cleared
+        m2n.m2nufft_psd(ctx, *args, want_E=False, check=False)
+        with pytest.raises(m2n.M2NError) as ei:
+            ctx.check()
+        assert ei.value.code == m2n.M2N_ERR_ARG
+        ctx.check()
+        # a clean series: the same tapers and spectrum bit for bit in both modes
+        s = W.small_gapped()
+        outs = []
+        for c in (ctx, sctx):
+            tt, xx = _dev(s.t), _dev(s.x)
+            wk, lam = m2n.gpss_tapers(c, tt, s.fmax, s.fw, s.K)
+            o = m2n.m2nufft_psd(c, tt, xx, wk, lam, s.fmax, s.fw, s.f_lo, s.df, s.I, prec=2)
+            outs.append([wk.cpu().numpy(), lam.cpu().numpy(), o["P"].cpu().numpy(), o["E"].cpu().numpy()])
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+        _say("case sync mode: error returned by the call; results bitwise equal to the default mode")
+    finally:
+        sctx.close()
