@@ -85,6 +85,26 @@ def test_queue_same_alone_and_in_mix(m2n, ctx):
     q.close()
 
 
+def test_queue_fp64(m2n, ctx):
+    # the FP64 queue: the same tapers bit for bit, and P and Ehat within the
+    # FP64 NuFFT tolerance, as the series alone
+    series = [W.batched_series(s) for s in range(110, 118)]
+    q = m2n.Queue(ctx, slots=2, prec=m2n.M2N_FP64)
+    tk = [_submit(q, s) for s in series]
+    res = [_wait(q, t) for t in tk]
+    worst = 0.0
+    for s, r in zip(series, res):
+        w, lam, P, E = _alone(m2n, ctx, s, m2n.M2N_FP64)
+        assert r["status"] == m2n.M2N_OK and r["P"].dtype == np.float64
+        assert np.array_equal(r["w"], w) and np.array_equal(r["lam"], lam)
+        dP = float(np.max(np.abs(r["P"] - P)) / np.max(np.abs(P)))
+        assert dP < 1e-11, dP
+        assert np.max(np.abs(r["E"] - E)) < 1e-12
+        worst = max(worst, dP)
+    _say(f"case FP64 queue: 8 requests, batch sizes {sorted(r['batch_size'] for r in res)}, worst P {worst:.2e}")
+    q.close()
+
+
 def test_queue_pinned_outputs(m2n, ctx):
     # results copied from the device straight into pinned host buffers: the
     # same as alone; requests without tapers leave w out
