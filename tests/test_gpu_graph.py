@@ -132,3 +132,31 @@ def test_batch_refuses_series_off_the_lattice_path(m2n, ctx):
         m2n.Batch(ctx, specs)
     assert ei.value.code == m2n.M2N_ERR_UNSUPPORTED
     assert "series 1" in str(ei.value)
+
+
+def test_graph_launch_in_sync_mode(m2n, ctx, monkeypatch):
+    # a batch made from a context in synchronous mode: each launch waits and
+    # returns the device-side error its kernels flagged (a non-finite sample
+    # written into x between launches), and launches cleanly once it is gone
+    monkeypatch.setenv("M2N_SYNC", "1")
+    sctx = m2n.Context(0)
+    monkeypatch.delenv("M2N_SYNC")
+    try:
+        series = [W.batched_series(s) for s in range(120, 124)]
+        specs = _specs(series)
+        ref = _reference(m2n, ctx, specs, m2n.M2N_FP32)
+        b = m2n.Batch(sctx, specs, prec=m2n.M2N_FP32, graph=True)
+        _check(b.launch(), ref, 2e-6)
+        x0 = specs[2]["x"][7].item()
+        specs[2]["x"][7] = float("nan")
+        torch.cuda.synchronize()
+        with pytest.raises(m2n.M2NError) as ei:
+            b.launch()
+        assert ei.value.code == m2n.M2N_ERR_ARG
+        specs[2]["x"][7] = x0
+        torch.cuda.synchronize()
+        _check(b.launch(), ref, 2e-6)
+        _say("case graph batch in sync mode: the flagged launch returned M2N_ERR_ARG, the next one clean")
+        b.close()
+    finally:
+        sctx.close()
