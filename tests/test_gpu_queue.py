@@ -178,12 +178,15 @@ def test_queue_pinned_pool_merged_copies(m2n, ctx, borrow):
     q.close()
 
 
-def test_queue_failing_request_is_isolated(m2n, ctx):
+@pytest.mark.parametrize("borrow", [False, True])
+def test_queue_failing_request_is_isolated(m2n, ctx, borrow):
+    # the batch holding the bad request fails and is rerun one request at a
+    # time (with borrowed inputs, from the callers' arrays again)
     good = [W.batched_series(s) for s in (30, 31, 32)]
     bad = W.batched_series(33)
     bad.x = bad.x.copy()
     bad.x[5] = np.nan
-    q = m2n.Queue(ctx, slots=1, prec=m2n.M2N_FP32)
+    q = m2n.Queue(ctx, slots=1, prec=m2n.M2N_FP32, borrow_inputs=borrow)
     tk = [_submit(q, s) for s in good[:2]] + [_submit(q, bad)] + [_submit(q, good[2])]
     out = []
     for t in tk:
